@@ -1,0 +1,390 @@
+"""Benchmark of the P1 assembly hot path on one MI355X.
+
+Step (timed): the whole assembly of the 2048 x 2048-cell unit square
+(8,388,608 triangles, jitter 0.2 h, random vertex relabelling, FP64 values,
+int32 indices) from (q, me) resident in HBM:
+    fem_pattern                symbolic phase (CSR pattern + triangle lists)
+    fem_assemble_stiff_mass    stiffness S and mass M, one fused pass
+    fem_assemble_wmass         weighted mass, w = 1 + x^2 + y^2 at the vertices
+    fem_elas_pattern           2x2-block elasticity pattern
+    fem_assemble_elas          elasticity stiffness, lambda = 1, mu = 0.5
+value = triangles / step time (M triangles per second).
+
+Also reported: per-call HIP-event times and roofline of each numeric kernel
+(algorithmic bytes per triangle), the batched block-diagonal assembly of 512
+meshes (one graph-captured launch) against a per-mesh launch loop, the
+forward + backward / forward ratio of the differentiable assembly, and the
+CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+METRIC = "M triangles/s & % HBM peak, P1 K+M FP64 @8.4M tris; batched vs looped"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(nq, nme, nnz):
+    """Bytes the method must move per call (inputs once, outputs once)."""
+    me, q, w = 12 * nme, 16 * nq, 8 * nq
+    vals = 8 * nnz
+    return {
+        "pattern": me + 4 * (nq + 1) + 4 * nnz,          # me -> row_ptr, col_idx
+        "stiff_mass": me + q + 2 * vals,
+        "wmass": me + q + w + vals,
+        "elas": me + q + 4 * vals,
+    }
+
+
+class Step:
+    """Preallocated buffers and the raw C calls of one assembly step."""
+
+    def __init__(self, fem, lib, torch, m, w, lam, mu):
+        dev = torch.device("cuda:0")
+        self.torch, self.fem, self.lib = torch, fem, lib
+        self.nq, self.nme = m.nq, m.nme
+        self.q = torch.from_numpy(m.q).to(dev)
+        self.me = torch.from_numpy(m.me).to(dev)
+        self.w = torch.from_numpy(w).to(dev)
+        self.lam, self.mu = lam, mu
+        ws = C.c_size_t(0)
+        fem._lib.check(lib.fem_pattern_workspace(m.nq, m.nme, C.byref(ws)))
+        self.ws = int(ws.value)
+        self.cap = int(lib.fem_nnz_bound(m.nq, m.nme))
+        i32 = dict(dtype=torch.int32, device=dev)
+        self.row_ptr = torch.empty(m.nq + 1, **i32)
+        self.col_idx = torch.empty(self.cap, **i32)
+        self.inc_ptr = torch.empty(m.nq + 1, **i32)
+        self.inc = torch.empty(3 * m.nme, **i32)
+        self.inc_pos = torch.empty(3 * m.nme, **i32)
+        self.work = torch.empty(self.ws, dtype=torch.uint8, device=dev)
+        self.rpe = torch.empty(2 * m.nq + 1, **i32)
+        self.nnz = None
+        self.pattern()
+        torch.cuda.synchronize()
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.S = torch.empty(self.nnz, **f64)
+        self.M = torch.empty(self.nnz, **f64)
+        self.Mw = torch.empty(self.nnz, **f64)
+        self.K = torch.empty(4 * self.nnz, **f64)
+        self.cie = torch.empty(4 * self.nnz, **i32)
+        self.stream = torch.cuda.current_stream().cuda_stream
+
+    def pattern(self):
+        n = C.c_int64(0)
+        s = self.torch.cuda.current_stream().cuda_stream
+        self.fem._lib.check(self.lib.fem_pattern(
+            self.nq, self.nme, self.me.data_ptr(), self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+            self.cap, self.inc_ptr.data_ptr(), self.inc.data_ptr(), self.inc_pos.data_ptr(), None,
+            self.work.data_ptr(), self.ws, C.byref(n), s))
+        self.nnz = int(n.value)
+
+    def _pat(self):
+        return (self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.inc_ptr.data_ptr(),
+                self.inc_pos.data_ptr(), None)
+
+    def stiff_mass(self):
+        self.fem._lib.check(self.lib.fem_assemble_stiff_mass(
+            self.nq, self.nme, self.nnz, self.q.data_ptr(), self.me.data_ptr(), *self._pat(),
+            self.S.data_ptr(), self.M.data_ptr(), 0, self.stream))
+
+    def wmass(self):
+        self.fem._lib.check(self.lib.fem_assemble_wmass(
+            self.nq, self.nme, self.nnz, self.q.data_ptr(), self.me.data_ptr(), *self._pat(),
+            self.w.data_ptr(), self.Mw.data_ptr(), 0, self.stream))
+
+    def elas(self):
+        self.fem._lib.check(self.lib.fem_elas_pattern(
+            self.nq, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.rpe.data_ptr(),
+            self.cie.data_ptr(), self.stream))
+        self.fem._lib.check(self.lib.fem_assemble_elas(
+            self.nq, self.nme, self.nnz, self.q.data_ptr(), self.me.data_ptr(), *self._pat(),
+            self.lam, self.mu, self.K.data_ptr(), 0, self.stream))
+
+    PARTS = ("pattern", "stiff_mass", "wmass", "elas")
+
+
+def run_main(torch, fem, args):
+    from paper_1305_3122_amd import meshgen as mg
+    lib = fem._lib.load()
+    t0 = time.time()
+    m = mg.config_mesh(2)
+    w = mg.weight_quadratic(m.q)
+    log(f"[bench] cfg2 mesh nq={m.nq} nme={m.nme} built in {time.time() - t0:.1f}s")
+    st = Step(fem, lib, torch, m, w, 1.0, 0.5)
+    log(f"[bench] nnz={st.nnz}")
+    for _ in range(args.warmup):
+        for p in Step.PARTS:
+            getattr(st, p)()
+    torch.cuda.synchronize()
+    ev = {p: [] for p in Step.PARTS}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for p in Step.PARTS:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            getattr(st, p)()
+            b.record()
+            ev[p].append((a, b))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ab = algorithmic_bytes(m.nq, m.nme, st.nnz)
+    kern = {}
+    for p in Step.PARTS:
+        us = float(np.mean([a.elapsed_time(b) for a, b in ev[p]])) * 1e3
+        gbs = ab[p] / (us * 1e-6) / 1e9
+        kern[p] = {"us": round(us, 2), "alg_bytes": ab[p], "alg_GBps": round(gbs, 1),
+                   "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "Mtri_per_s": round(m.nme / us, 1)}
+    log(f"[bench] step {ms_per_step:.3f} ms; " +
+        ", ".join(f"{p} {kern[p]['us']:.0f}us" for p in Step.PARTS))
+    return m, st, ms_per_step, kern
+
+
+def run_batched(torch, fem, args):
+    """512 meshes: one graph-captured batched launch vs a per-mesh launch loop."""
+    from paper_1305_3122_amd import meshgen as mg
+    lib = fem._lib.load()
+    t0 = time.time()
+    b = mg.config_mesh(4)
+    dev = torch.device("cuda:0")
+    log(f"[bench] cfg4 batch nb={b.nb} nq={b.q.shape[0]} nme={b.me.shape[0]} built in {time.time() - t0:.1f}s")
+    q = torch.from_numpy(b.q).to(dev)
+    me_g = fem.fem_batch_globalize(torch.from_numpy(b.me_local).to(dev),
+                                   torch.from_numpy(b.vtx_off).to(dev),
+                                   torch.from_numpy(b.elem_off).to(dev))
+    nq_all = int(b.vtx_off[-1])
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    pat = fem.fem_pattern(me_g, nq_all)
+    torch.cuda.synchronize()
+    t_pat_batched = time.perf_counter() - tp0
+    from paper_1305_3122_amd import autotune
+    tune, table = autotune.tune_batched(fem, torch, pat, q, b.nb)
+    S = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+    M = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+    side = torch.cuda.Stream()
+    g = fem.Graph(side)
+    with torch.cuda.stream(side):
+        with g.capture():
+            fem.fem_assemble_stiff_mass_batched(pat, q, b.nb, tune=tune, out_S=S, out_M=M, stream=side)
+    # per-mesh patterns and buffers (setup, untimed)
+    per = []
+    tp0 = time.perf_counter()
+    for i in range(b.nb):
+        v0, v1 = int(b.vtx_off[i]), int(b.vtx_off[i + 1])
+        e0, e1 = int(b.elem_off[i]), int(b.elem_off[i + 1])
+        pm = fem.fem_pattern(torch.from_numpy(b.me_local[e0:e1]).to(dev), v1 - v0)
+        per.append((pm, q[v0:v1], torch.empty(pm.nnz, dtype=torch.float64, device=dev),
+                    torch.empty(pm.nnz, dtype=torch.float64, device=dev)))
+    torch.cuda.synchronize()
+    t_pat_loop = time.perf_counter() - tp0
+    s_ptr = side.cuda_stream
+
+    def looped():
+        for pm, qm, Sm, Mm in per:
+            fem._lib.check(lib.fem_assemble_stiff_mass(
+                pm.nq, pm.nme, pm.nnz, qm.data_ptr(), None, pm.row_ptr.data_ptr(),
+                pm.col_idx.data_ptr(), pm.inc_ptr.data_ptr(), pm.inc_pos.data_ptr(), None,
+                Sm.data_ptr(), Mm.data_ptr(), 0, s_ptr))
+
+    def batched():
+        g.replay(side)
+
+    res = {}
+    for name, fn in (("batched_graph", batched), ("looped", looped)):
+        for _ in range(3):
+            fn()
+        side.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        c = torch.cuda.Event(enable_timing=True)
+        reps = 10
+        a.record(side)
+        for _ in range(reps):
+            fn()
+        c.record(side)
+        side.synchronize()
+        res[name] = a.elapsed_time(c) * 1e3 / reps
+    # looped, captured in one graph (secondary)
+    g2 = fem.Graph(side)
+    with torch.cuda.stream(side):
+        with g2.capture():
+            looped()
+    for _ in range(3):
+        g2.replay(side)
+    side.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    c = torch.cuda.Event(enable_timing=True)
+    a.record(side)
+    for _ in range(10):
+        g2.replay(side)
+    c.record(side)
+    side.synchronize()
+    res["looped_graph"] = a.elapsed_time(c) * 1e3 / 10
+    # results agree block by block
+    ok = True
+    for i in (0, b.nb // 2, b.nb - 1):
+        pm, qm, Sm, Mm = per[i]
+        e0 = int(pat.row_ptr[int(b.vtx_off[i])])
+        ok &= bool(torch.equal(S[e0:e0 + pm.nnz], Sm)) and bool(torch.equal(M[e0:e0 + pm.nnz], Mm))
+    nme = int(b.elem_off[-1])
+    out = {
+        "workload": f"{b.nb} unit-square meshes, cells per side log-uniform in [8,512], S+M FP64",
+        "nme": nme, "nnz": pat.nnz,
+        "batched_graph_us": round(res["batched_graph"], 1),
+        "looped_us": round(res["looped"], 1),
+        "looped_graph_us": round(res["looped_graph"], 1),
+        "speedup_vs_looped": round(res["looped"] / res["batched_graph"], 2),
+        "batched_Mtri_per_s": round(nme / res["batched_graph"], 1),
+        "pattern_batched_ms": round(t_pat_batched * 1e3, 1),
+        "pattern_looped_ms": round(t_pat_loop * 1e3, 1),
+        "tune": {"lds_entries": tune.lds_entries, "grid_blocks": tune.grid_blocks},
+        "tune_table_us": table,
+        "blocks_bitwise_equal": ok,
+    }
+    log(f"[bench] batched {out['batched_graph_us']}us vs looped {out['looped_us']}us "
+        f"(x{out['speedup_vs_looped']})")
+    return out
+
+
+def run_adjoint(torch, fem, args):
+    from paper_1305_3122_amd import meshgen as mg
+    dev = torch.device("cuda:0")
+    m = mg.config_mesh(5)
+    w = mg.weight_uniform(m.nq, 0.5, 2.0, seed=mg.BASE_SEED + 5)
+    q = torch.from_numpy(m.q).to(dev)
+    wd = torch.from_numpy(w).to(dev)
+    pat = fem.fem_pattern(torch.from_numpy(m.me).to(dev), m.nq)
+    fem.fem_transpose_map(pat)
+    G = torch.from_numpy(mg.normal_seed(pat.nnz, seed=mg.BASE_SEED + 55)).to(dev)
+    S = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+    Mw = torch.empty_like(S)
+    dq = torch.empty((m.nq, 2), dtype=torch.float64, device=dev)
+    dw = torch.empty(m.nq, dtype=torch.float64, device=dev)
+
+    def fwd():
+        fem.fem_assemble_stiff_wmass(pat, q, wd, out_S=S, out_M=Mw)
+
+    def bwd():
+        fem.fem_adjoint_stiff_wmass(pat, q, wd, G, G, dq=dq, dw=dw)
+
+    def t(fn, reps=50):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        c = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        c.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(c) * 1e3 / reps
+
+    tf = t(fwd)
+    tfb = t(lambda: (fwd(), bwd()))
+    out = {"workload": "unit square 512x512, S + Mw forward, adjoint of <G, S + Mw> (dq, dw)",
+           "fwd_us": round(tf, 1), "fwd_bwd_us": round(tfb, 1), "ratio": round(tfb / tf, 2)}
+    log(f"[bench] adjoint fwd {tf:.1f}us fwd+bwd {tfb:.1f}us ratio {tfb / tf:.2f}")
+    return out
+
+
+def run_cpu_baseline(args):
+    """The oracle, as it stands, on a bounded sample: the same recipe at
+    1448 x 1448 cells (half of the workload), one full step."""
+    import oracle
+    from paper_1305_3122_amd import meshgen as mg
+    n = args.cpu_cells
+    m = mg.unit_square(n, seed=mg.BASE_SEED + 2)
+    w = mg.weight_quadratic(m.q)
+    t0 = time.perf_counter()
+    P = oracle.pattern(m.nq, m.me)
+    oracle.assemble("stiff", m.q, m.me, P.slot, P.nnz)
+    oracle.assemble("mass", m.q, m.me, P.slot, P.nnz)
+    oracle.assemble("wmass", m.q, m.me, P.slot, P.nnz, w=w)
+    rpe, cie, se = oracle.pattern_elas(m.nq, m.me)
+    oracle.assemble("elas", m.q, m.me, se, int(rpe[-1]), lam=1.0, mu=0.5)
+    dt = time.perf_counter() - t0
+    log(f"[bench] cpu oracle {n}x{n}: {dt:.2f}s")
+    return {"value": round(m.nme / dt / 1e6, 4), "unit": "Mtri/s", "cores": 1, "kind": "oracle",
+            "sample": f"same recipe at {n}x{n} cells ({m.nme} triangles), one full step "
+                      f"(pattern, S, M, Mw, elasticity pattern and values), {dt:.2f} s wall, "
+                      f"single-threaded C (-O2 -ffp-contract=off)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-cells", type=int, default=1448)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (the assembly of one mesh runs on one "
+              "GPU; a multi-GPU split is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    import paper_1305_3122_amd as fem
+    m, st, ms, kern = run_main(torch, fem, args)
+    extras = {}
+    if not args.no_extras:
+        extras["batched"] = run_batched(torch, fem, args)
+        extras["adjoint"] = run_adjoint(torch, fem, args)
+    numeric = ("stiff_mass", "wmass", "elas")
+    dom = max(kern, key=lambda p: kern[p]["us"])
+    dom_num = max(numeric, key=lambda p: kern[p]["us"])
+
+    def roof(p):
+        k = kern[p]
+        return {"kernel": p, "bound": "hbm", "achieved": k["alg_GBps"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(k["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": None}
+
+    line = {
+        "metric": METRIC,
+        "value": round(m.nme / (ms * 1e-3) / 1e6, 2),
+        "unit": "Mtri/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "unit square 2048x2048 cells (jitter 0.2h, random vertex relabelling), "
+                               "full assembly: pattern + S+M fused + Mw (w=1+x^2+y^2) + elasticity "
+                               "(lambda=1, mu=0.5); FP64 values, int32 indices",
+                   "nq": m.nq, "nme": m.nme, "nnz": st.nnz},
+        "roofline": roof(dom if dom in numeric else dom_num),
+        "roofline_stiff_mass": roof("stiff_mass"),
+        "dominant_call": dom,
+        "kernels": kern,
+    }
+    line.update(extras)
+    if not args.no_cpu:
+        line["cpu_baseline"] = run_cpu_baseline(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

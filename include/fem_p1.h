@@ -1,0 +1,259 @@
+/*
+ * fem_p1.h -- C ABI of the MI355X (gfx950) P1 finite element assembly library.
+ *
+ * The library assembles the global sparse matrices of P1 Lagrange elements on
+ * a 2D triangle mesh, after Cuvelier, Japhet and Scarella, "An efficient way
+ * to perform the assembly of finite element matrices in Matlab and Octave"
+ * (INRIA RR-8305, 2013):
+ *   M    mass            M_ij    = int phi_i phi_j            (eq. MassElem)
+ *   Mw   weighted mass   Mw_ij   = int w phi_i phi_j, w P1    (eq. MassWElem)
+ *   S    stiffness       S_ij    = int grad phi_i . grad phi_j (eq. StiffMatElem)
+ *   K    elasticity      K_ml    = int eps(psi_m)^T C eps(psi_l)
+ *                        (linear elasticity section; Hooke's law, Lame
+ *                        parameters lambda, mu with lambda + mu > 0)
+ *
+ * Inputs follow the paper's problem statement (Notations section), 0-based:
+ *   q  : [nq][2]  double, vertex coordinates (the paper's 2 x nq array q)
+ *   me : [nme][3] int32,  connectivity; me[k][a] is the a-th vertex of
+ *                 triangle k (the paper's 3 x nme array me, minus one)
+ *   w  : [nq]     double, the weight sampled at the vertices (Tw)
+ * Triangle areas are computed from q (the paper passes them in).
+ *
+ * Output format: CSR (row_ptr, col_idx, values) with rows ascending, columns
+ * ascending and unique inside each row.  The pattern is structural: it holds
+ * every (i, j) with i and j in a common triangle, including entries whose
+ * value happens to be zero (Matlab's sparse() would drop those).  All four
+ * matrices share one scalar pattern; the elasticity matrix uses the derived
+ * 2 x 2 block layout below.
+ *
+ * Memory and streams.  Every array argument is a DEVICE pointer unless
+ * marked HOST.  The caller owns all memory; the library never allocates
+ * device memory.  Every call enqueues work on `stream` (a hipStream_t passed
+ * as void*; NULL is the default stream) and returns without waiting, except
+ * fem_pattern, which waits once for the number of nonzeros and the mesh
+ * checks.  Calls that overlap on the same output buffers race.
+ *
+ * Errors.  Every function returns a fem_status.  Argument checks run on the
+ * host before anything is enqueued; mesh checks (indices in range, distinct
+ * vertices per triangle) run on the device inside fem_pattern.  On error,
+ * fem_last_error() returns a message (thread-local, valid until the next
+ * call from the same thread).  Values of outputs are unspecified after an
+ * error.
+ */
+#ifndef FEM_P1_H
+#define FEM_P1_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fem_status {
+    FEM_OK = 0,
+    FEM_EINVAL = -1,       /* bad argument (NULL pointer, negative size, lambda + mu <= 0, ...) */
+    FEM_ERANGE = -2,       /* a vertex index of me outside [0, nq) */
+    FEM_EDEGEN = -3,       /* a triangle repeats a vertex */
+    FEM_ENOSPC = -4,       /* an output or workspace capacity is too small */
+    FEM_EOVERFLOW = -5,    /* a count does not fit the int32 index type */
+    FEM_EHIP = -6,         /* the HIP runtime reported an error */
+    FEM_EUNSUPPORTED = -8  /* a row longer than 65535 entries */
+} fem_status;
+
+/* flags of the numeric calls */
+enum {
+    FEM_DETERMINISTIC = 0, /* row-owner gather: every value summed by one lane in a fixed
+                              order; bitwise reproducible from run to run (default) */
+    FEM_ATOMIC = 1,        /* one lane per triangle, FP64 atomic adds through the slot map
+                              (needs me and slot); order of additions unspecified */
+    FEM_ACCUMULATE = 2     /* add into values instead of overwriting them */
+};
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *fem_last_error(void);
+
+/* Library ABI version (major * 100 + minor). */
+int fem_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Symbolic phase                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* HOST ONLY.  Bytes of device workspace fem_pattern needs for a mesh with nq
+ * vertices and nme triangles. */
+int fem_pattern_workspace(int32_t nq, int32_t nme, size_t *bytes /* HOST */);
+
+/* Upper bound of the number of nonzeros, nq + 6 nme (each triangle adds at
+ * most six off-diagonal entries); a safe col_cap. */
+int64_t fem_nnz_bound(int32_t nq, int32_t nme);
+
+/* Builds the CSR pattern of the scalar matrices (replaces the index arrays
+ * Ig = me([1 2 3 1 2 3 1 2 3], :), Jg = me([1 1 1 2 2 2 3 3 3], :) and the
+ * sort/compress inside sparse(Ig, Jg, Kg, nq, nq) of Section 5), plus the
+ * data the numeric calls read:
+ *
+ *   row_ptr [nq+1]       CSR row offsets
+ *   col_idx [col_cap]    CSR column indices; nnz of them are written
+ *   inc_ptr [nq+1]       offsets of the triangle lists of each vertex
+ *   inc     [3 nme]      for vertex v, the values 3k + a with me[k][a] == v, in
+ *                        ascending k (the triangles around v)
+ *   inc_pos [3 nme]      for the same entries, the positions inside row v
+ *                        (relative to row_ptr[v]) of me[k][(a+1)%3] (low 16
+ *                        bits) and me[k][(a+2)%3] (high 16 bits)
+ *   slot    [9][nme]     optional (NULL to skip): slot[(3b+a) nme + k] is the
+ *                        CSR position of entry (me[k][a], me[k][b]) -- local
+ *                        entry r = 3b + a of the column-wise element matrix
+ *   work    [work_bytes] device workspace, >= fem_pattern_workspace(nq, nme)
+ *   nnz_out HOST         number of nonzeros
+ *
+ * Requires nq >= 1, nme >= 0, 3 nme and nq + 6 nme within int32.  Returns
+ * FEM_ERANGE / FEM_EDEGEN for an invalid me, FEM_ENOSPC if col_cap < nnz,
+ * FEM_EUNSUPPORTED if a row would exceed 65535 entries.  Synchronises
+ * `stream` once (after the row lengths are known); the remaining work is
+ * enqueued asynchronously.  Integer results are identical on every run. */
+int fem_pattern(int32_t nq, int32_t nme, const int32_t *me,
+                int32_t *row_ptr, int32_t *col_idx, int64_t col_cap,
+                int32_t *inc_ptr, int32_t *inc, uint32_t *inc_pos,
+                int32_t *slot,
+                void *work, size_t work_bytes,
+                int64_t *nnz_out /* HOST */, void *stream);
+
+/* Transpose map: tpos[p] is the position of entry (j, i) for the entry
+ * p = (i, j), or -1 if the pattern has no entry (j, i) (every P1 mesh
+ * pattern is structurally symmetric, so -1 never occurs there). */
+int fem_transpose_map(int32_t nq, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                      int32_t *tpos, void *stream);
+
+/* Elasticity pattern over the 2 nq degrees of freedom psi_{2i} = (phi_i, 0),
+ * psi_{2i+1} = (0, phi_i) (the paper's interleaved basis, 0-based): row
+ * 2i + alpha holds columns 2j, 2j + 1 for every column j of scalar row i.
+ *   row_ptr_e [2nq+1]: row_ptr_e[2i] = 4 row_ptr[i],
+ *                      row_ptr_e[2i+1] = 4 row_ptr[i] + 2 len_i
+ *   col_idx_e [4 nnz]
+ * Entry (2i+alpha, 2j+beta), j the p-th column of row i, sits at
+ * 4 row_ptr[i] + 2 alpha len_i + 2 (p - row_ptr[i]) + beta. */
+int fem_elas_pattern(int32_t nq, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                     int32_t *row_ptr_e, int32_t *col_idx_e, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Numeric phase                                                             */
+/* ------------------------------------------------------------------------ */
+/* Common arguments: nq, nme, nnz and the arrays written by fem_pattern.
+ * FEM_DETERMINISTIC reads q (w), row_ptr, col_idx, inc_ptr, inc_pos; me and
+ * slot may be NULL.  FEM_ATOMIC reads q (w), me, slot (and row_ptr for the
+ * elasticity layout); it clears values first unless FEM_ACCUMULATE.  values
+ * has nnz entries (4 nnz for elasticity, in the layout of fem_elas_pattern).
+ * Element formulas: Section 2 (MassElem, MassWElem, StiffMatElem) and the
+ * elasticity section (K^e = |T| B^T C B); |T| = |det| / 2. */
+
+int fem_assemble_mass(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
+                      const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
+                      const uint32_t *inc_pos, const int32_t *slot,
+                      double *values, int flags, void *stream);
+
+int fem_assemble_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
+                       const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
+                       const uint32_t *inc_pos, const int32_t *slot, const double *w,
+                       double *values, int flags, void *stream);
+
+int fem_assemble_stiff(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
+                       const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
+                       const uint32_t *inc_pos, const int32_t *slot,
+                       double *values, int flags, void *stream);
+
+/* S and M in one pass over the mesh (shared gathers of q). */
+int fem_assemble_stiff_mass(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
+                            const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
+                            const uint32_t *inc_pos, const int32_t *slot,
+                            double *vals_S, double *vals_M, int flags, void *stream);
+
+/* S and Mw in one pass (the forward of the differentiable assembly). */
+int fem_assemble_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
+                             const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
+                             const uint32_t *inc_pos, const int32_t *slot, const double *w,
+                             double *vals_S, double *vals_Mw, int flags, void *stream);
+
+/* Elasticity stiffness (requires lambda + mu > 0); values_e [4 nnz] in the
+ * layout of fem_elas_pattern. */
+int fem_assemble_elas(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
+                      const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
+                      const uint32_t *inc_pos, const int32_t *slot, double lambda, double mu,
+                      double *values_e, int flags, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched assembly                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Globalises the connectivity of nb meshes stored back to back: triangles
+ * elem_off[b] .. elem_off[b+1]-1 index vertices local to mesh b, whose
+ * vertices are vtx_off[b] .. vtx_off[b+1]-1 of the concatenated q, so
+ * me_global[k][a] = me_local[k][a] + vtx_off[b].  vtx_off, elem_off: DEVICE
+ * [nb+1] int64, non-decreasing, elem_off[0] = 0, elem_off[nb] = nme (not
+ * checked).  fem_pattern on the result gives the block-diagonal CSR of the
+ * batch (block b = rows vtx_off[b] .. vtx_off[b+1]-1); its range check then
+ * covers the whole batch. */
+int fem_batch_globalize(int32_t nb, int32_t nme, const int64_t *vtx_off, const int64_t *elem_off,
+                        const int32_t *me_local, int32_t *me_global, void *stream);
+
+/* Tunable launch shape of the row-owner kernels. */
+typedef struct fem_tune {
+    int32_t lds_entries;   /* CSR entries staged in LDS per 64-row wave tile: 256..4096,
+                              multiple of 64 (0: library default) */
+    int32_t grid_blocks;   /* persistent grid: number of one-wave workgroups that loop over
+                              the tiles (0: one workgroup per tile) */
+} fem_tune;
+
+/* S and M of a batched (block-diagonal) pattern in ONE persistent launch;
+ * nq, nnz and the pattern arrays are those of the whole batch.  tune may be
+ * NULL (defaults).  Same semantics as fem_assemble_stiff_mass with
+ * FEM_DETERMINISTIC. */
+int fem_assemble_stiff_mass_batched(int32_t nb, int32_t nq, int64_t nnz, const double *q,
+                                    const int32_t *row_ptr, const int32_t *col_idx,
+                                    const int32_t *inc_ptr, const uint32_t *inc_pos,
+                                    double *vals_S, double *vals_M,
+                                    const fem_tune *tune /* HOST, nullable */, int flags,
+                                    void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* HIP graphs                                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Begins capturing `stream` (must not be the NULL stream).  Every numeric
+ * call enqueued on it until fem_graph_end is recorded instead of run
+ * (fem_pattern must not be captured: it synchronises). */
+int fem_graph_begin(void *stream);
+
+/* Ends the capture and instantiates it; *graph_out (HOST) receives an opaque
+ * handle for fem_graph_launch / fem_graph_destroy. */
+int fem_graph_end(void *stream, void **graph_out /* HOST */);
+
+/* Replays an instantiated graph on `stream`. */
+int fem_graph_launch(void *graph, void *stream);
+
+int fem_graph_destroy(void *graph);
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* HOST ONLY.  Bytes of device workspace for fem_adjoint_stiff_wmass. */
+int fem_adjoint_workspace(int64_t nnz, size_t *bytes /* HOST */);
+
+/* Gradient of L = sum_ij GS_ij S_ij(q) + sum_ij GM_ij Mw_ij(q, w) with
+ * respect to q and w (GS, GM [nnz] on the scalar pattern; either may be NULL
+ * to drop its term; w may be NULL only if GM is).  dq [nq][2] and dw [nq]
+ * are overwritten (FEM_ACCUMULATE adds into them).  tpos from
+ * fem_transpose_map, or NULL (then found by search).  Deterministic: two
+ * passes over the rows, no atomics. */
+int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
+                            const double *w, const int32_t *row_ptr, const int32_t *col_idx,
+                            const int32_t *inc_ptr, const uint32_t *inc_pos, const int32_t *tpos,
+                            const double *GS, const double *GM, double *dq, double *dw,
+                            void *work, size_t work_bytes, int flags, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEM_P1_H */

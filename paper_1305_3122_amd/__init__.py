@@ -1,0 +1,336 @@
+"""MI355X (gfx950) P1 finite element assembly.
+
+Python binding of ``libfem_p1.so`` (C ABI in ``include/fem_p1.h``).  Every
+function keeps the name of its C entry point and only marshals arguments:
+PyTorch provides device memory and the current HIP stream; every step of the
+assembly runs in the library's HIP kernels.  There is no CPU fallback: calls
+raise if the library is not built or no GPU is visible.
+
+Typical use::
+
+    import torch, paper_1305_3122_amd as fem
+    pat = fem.fem_pattern(me_dev, nq)                 # symbolic phase, once per mesh
+    S, M = fem.fem_assemble_stiff_mass(pat, q_dev)    # numeric phase
+    A = pat.csr(S)                                    # torch.sparse_csr_tensor view
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import Optional
+
+from . import _lib
+from ._lib import (FEM_ACCUMULATE, FEM_ATOMIC, FEM_DETERMINISTIC, FemError,  # noqa: F401
+                   fem_tune)
+
+__all__ = [
+    "Pattern", "FemError", "FEM_ATOMIC", "FEM_DETERMINISTIC", "FEM_ACCUMULATE", "fem_tune",
+    "fem_pattern", "fem_transpose_map", "fem_elas_pattern", "fem_assemble_mass",
+    "fem_assemble_wmass", "fem_assemble_stiff", "fem_assemble_stiff_mass",
+    "fem_assemble_stiff_wmass", "fem_assemble_elas", "fem_batch_globalize",
+    "fem_assemble_stiff_mass_batched", "Graph", "fem_adjoint_stiff_wmass", "AssembleStiffWMass",
+    "library_path",
+]
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev(t, dtype, name, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    return t
+
+
+@dataclasses.dataclass
+class Pattern:
+    """Result of fem_pattern: CSR pattern and triangle lists (device tensors)."""
+    nq: int
+    nme: int
+    nnz: int
+    me: object            # [nme][3] int32
+    row_ptr: object       # [nq+1]   int32
+    col_idx: object       # [nnz]    int32 (a view of the capacity buffer)
+    inc_ptr: object       # [nq+1]   int32
+    inc: object           # [3 nme]  int32  (3k + a)
+    inc_pos: object       # [3 nme]  uint32 stored as int32 (p1 | p2 << 16)
+    slot: object = None   # [9][nme] int32 or None
+    tpos: object = None   # [nnz]    int32 or None (fem_transpose_map)
+
+    def csr(self, values):
+        """torch.sparse_csr_tensor sharing row_ptr / col_idx / values."""
+        torch = _torch()
+        return torch.sparse_csr_tensor(self.row_ptr, self.col_idx, values, (self.nq, self.nq))
+
+    def args(self):
+        return (_ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.inc_ptr), _ptr(self.inc_pos),
+                _ptr(self.slot))
+
+
+def fem_pattern(me, nq: int, *, slot: bool = False, stream=None) -> Pattern:
+    """Symbolic phase (C: fem_pattern).  me: [nme][3] int32 on the GPU."""
+    torch = _torch()
+    lib = _lib.load()
+    _dev(me, torch.int32, "me")
+    if me.dim() != 2 or me.shape[1] != 3:
+        raise ValueError("me must have shape [nme, 3]")
+    nme = int(me.shape[0])
+    dev = me.device
+    ws = C.c_size_t(0)
+    _lib.check(lib.fem_pattern_workspace(int(nq), nme, C.byref(ws)))
+    cap = int(lib.fem_nnz_bound(int(nq), nme))
+    i32 = dict(dtype=torch.int32, device=dev)
+    row_ptr = torch.empty(nq + 1, **i32)
+    col_buf = torch.empty(max(cap, 1), **i32)
+    inc_ptr = torch.empty(nq + 1, **i32)
+    inc = torch.empty(max(3 * nme, 1), **i32)
+    inc_pos = torch.empty(max(3 * nme, 1), **i32)
+    sl = torch.empty(max(9 * nme, 1), **i32) if slot else None
+    work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
+    nnz = C.c_int64(0)
+    _lib.check(lib.fem_pattern(int(nq), nme, _ptr(me), _ptr(row_ptr), _ptr(col_buf), cap,
+                               _ptr(inc_ptr), _ptr(inc), _ptr(inc_pos), _ptr(sl), _ptr(work),
+                               int(ws.value), C.byref(nnz), _stream(stream)))
+    n = int(nnz.value)
+    return Pattern(int(nq), nme, n, me, row_ptr, col_buf[:n], inc_ptr, inc[:3 * nme],
+                   inc_pos[:3 * nme], None if sl is None else sl[:9 * nme].view(9, nme))
+
+
+def fem_transpose_map(pat: Pattern, *, stream=None):
+    torch = _torch()
+    tpos = torch.empty(max(pat.nnz, 1), dtype=torch.int32, device=pat.row_ptr.device)
+    _lib.check(_lib.load().fem_transpose_map(pat.nq, pat.nnz, _ptr(pat.row_ptr), _ptr(pat.col_idx),
+                                             _ptr(tpos), _stream(stream)))
+    pat.tpos = tpos[:pat.nnz]
+    return pat.tpos
+
+
+def fem_elas_pattern(pat: Pattern, *, stream=None):
+    """(row_ptr_e [2nq+1], col_idx_e [4nnz]) of the interleaved elasticity matrix."""
+    torch = _torch()
+    dev = pat.row_ptr.device
+    rpe = torch.empty(2 * pat.nq + 1, dtype=torch.int32, device=dev)
+    cie = torch.empty(max(4 * pat.nnz, 1), dtype=torch.int32, device=dev)
+    _lib.check(_lib.load().fem_elas_pattern(pat.nq, pat.nnz, _ptr(pat.row_ptr), _ptr(pat.col_idx),
+                                            _ptr(rpe), _ptr(cie), _stream(stream)))
+    return rpe, cie[:4 * pat.nnz]
+
+
+def _q(pat, q):
+    torch = _torch()
+    return _dev(q, torch.float64, "q", (pat.nq, 2))
+
+
+def _out(pat, out, n, name):
+    torch = _torch()
+    if out is None:
+        return torch.empty(max(n, 1), dtype=torch.float64, device=pat.row_ptr.device)[:n]
+    return _dev(out, torch.float64, name, (n,))
+
+
+def _head(pat, q):
+    return (pat.nq, pat.nme, pat.nnz, _ptr(_q(pat, q)), _ptr(pat.me))
+
+
+def fem_assemble_mass(pat: Pattern, q, *, out=None, flags: int = 0, stream=None):
+    v = _out(pat, out, pat.nnz, "out")
+    _lib.check(_lib.load().fem_assemble_mass(*_head(pat, q), *pat.args(), _ptr(v), flags,
+                                             _stream(stream)))
+    return v
+
+
+def fem_assemble_wmass(pat: Pattern, q, w, *, out=None, flags: int = 0, stream=None):
+    torch = _torch()
+    _dev(w, torch.float64, "w", (pat.nq,))
+    v = _out(pat, out, pat.nnz, "out")
+    _lib.check(_lib.load().fem_assemble_wmass(*_head(pat, q), *pat.args(), _ptr(w), _ptr(v), flags,
+                                              _stream(stream)))
+    return v
+
+
+def fem_assemble_stiff(pat: Pattern, q, *, out=None, flags: int = 0, stream=None):
+    v = _out(pat, out, pat.nnz, "out")
+    _lib.check(_lib.load().fem_assemble_stiff(*_head(pat, q), *pat.args(), _ptr(v), flags,
+                                              _stream(stream)))
+    return v
+
+
+def fem_assemble_stiff_mass(pat: Pattern, q, *, out_S=None, out_M=None, flags: int = 0,
+                            stream=None):
+    S = _out(pat, out_S, pat.nnz, "out_S")
+    M = _out(pat, out_M, pat.nnz, "out_M")
+    _lib.check(_lib.load().fem_assemble_stiff_mass(*_head(pat, q), *pat.args(), _ptr(S), _ptr(M),
+                                                   flags, _stream(stream)))
+    return S, M
+
+
+def fem_assemble_stiff_wmass(pat: Pattern, q, w, *, out_S=None, out_M=None, flags: int = 0,
+                             stream=None):
+    torch = _torch()
+    _dev(w, torch.float64, "w", (pat.nq,))
+    S = _out(pat, out_S, pat.nnz, "out_S")
+    M = _out(pat, out_M, pat.nnz, "out_M")
+    _lib.check(_lib.load().fem_assemble_stiff_wmass(*_head(pat, q), *pat.args(), _ptr(w), _ptr(S),
+                                                    _ptr(M), flags, _stream(stream)))
+    return S, M
+
+
+def fem_assemble_elas(pat: Pattern, q, lam: float, mu: float, *, out=None, flags: int = 0,
+                      stream=None):
+    v = _out(pat, out, 4 * pat.nnz, "out")
+    _lib.check(_lib.load().fem_assemble_elas(*_head(pat, q), *pat.args(), float(lam), float(mu),
+                                             _ptr(v), flags, _stream(stream)))
+    return v
+
+
+def fem_batch_globalize(me_local, vtx_off, elem_off, *, stream=None):
+    """Connectivity of a batch with global vertex ids (C: fem_batch_globalize).
+    vtx_off / elem_off: [nb+1] int64 GPU tensors."""
+    torch = _torch()
+    _dev(me_local, torch.int32, "me_local")
+    _dev(vtx_off, torch.int64, "vtx_off")
+    _dev(elem_off, torch.int64, "elem_off", (vtx_off.shape[0],))
+    nb = int(vtx_off.shape[0]) - 1
+    out = torch.empty_like(me_local)
+    _lib.check(_lib.load().fem_batch_globalize(nb, int(me_local.shape[0]), _ptr(vtx_off),
+                                               _ptr(elem_off), _ptr(me_local), _ptr(out),
+                                               _stream(stream)))
+    return out
+
+
+def fem_assemble_stiff_mass_batched(pat: Pattern, q, nb: int, *, tune: Optional[fem_tune] = None,
+                                    out_S=None, out_M=None, flags: int = 0, stream=None):
+    S = _out(pat, out_S, pat.nnz, "out_S")
+    M = _out(pat, out_M, pat.nnz, "out_M")
+    t = C.byref(tune) if tune is not None else None
+    _lib.check(_lib.load().fem_assemble_stiff_mass_batched(
+        int(nb), pat.nq, pat.nnz, _ptr(_q(pat, q)), _ptr(pat.row_ptr), _ptr(pat.col_idx),
+        _ptr(pat.inc_ptr), _ptr(pat.inc_pos), _ptr(S), _ptr(M), t, flags, _stream(stream)))
+    return S, M
+
+
+class Graph:
+    """HIP graph of library calls (C: fem_graph_begin / end / launch / destroy).
+
+        g = Graph(stream)
+        with g.capture():
+            fem_assemble_stiff_mass(pat, q, out_S=S, out_M=M, stream=stream)
+        g.replay()
+    """
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.handle = None
+
+    def capture(self):
+        g = self
+
+        class _Ctx:
+            def __enter__(self_):
+                _lib.check(_lib.load().fem_graph_begin(_stream(g.stream)))
+                return g
+
+            def __exit__(self_, et, ev, tb):
+                h = C.c_void_p()
+                st = _lib.load().fem_graph_end(_stream(g.stream), C.byref(h))
+                if et is None:
+                    _lib.check(st)
+                    g.handle = h.value
+                return False
+
+        return _Ctx()
+
+    def replay(self, stream=None):
+        _lib.check(_lib.load().fem_graph_launch(self.handle, _stream(stream or self.stream)))
+
+    def __del__(self):
+        if self.handle is not None and _lib._lib is not None:
+            _lib._lib.fem_graph_destroy(self.handle)
+            self.handle = None
+
+
+def fem_adjoint_stiff_wmass(pat: Pattern, q, w, GS, GM, *, dq=None, dw=None, flags: int = 0,
+                            stream=None):
+    """(dq [nq][2], dw [nq]) of L = <GS, S(q)> + <GM, Mw(q, w)>."""
+    torch = _torch()
+    lib = _lib.load()
+    dev = pat.row_ptr.device
+    _q(pat, q)
+    if GS is not None:
+        _dev(GS, torch.float64, "GS", (pat.nnz,))
+    if GM is not None:
+        _dev(GM, torch.float64, "GM", (pat.nnz,))
+        _dev(w, torch.float64, "w", (pat.nq,))
+    dq = torch.empty((pat.nq, 2), dtype=torch.float64, device=dev) if dq is None else dq
+    dw = torch.empty(pat.nq, dtype=torch.float64, device=dev) if dw is None else dw
+    ws = C.c_size_t(0)
+    _lib.check(lib.fem_adjoint_workspace(pat.nnz, C.byref(ws)))
+    work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
+    _lib.check(lib.fem_adjoint_stiff_wmass(pat.nq, pat.nme, pat.nnz, _ptr(q), _ptr(w),
+                                           _ptr(pat.row_ptr), _ptr(pat.col_idx), _ptr(pat.inc_ptr),
+                                           _ptr(pat.inc_pos), _ptr(pat.tpos), _ptr(GS), _ptr(GM),
+                                           _ptr(dq), _ptr(dw), _ptr(work), int(ws.value), flags,
+                                           _stream(stream)))
+    return dq, dw
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class AssembleStiffWMass(torch.autograd.Function):
+        """(S values, Mw values) = F(q, w) on a fixed pattern; backward runs the
+        hand-written adjoint kernels (fem_adjoint_stiff_wmass)."""
+
+        @staticmethod
+        def forward(ctx, q, w, pat):
+            S, M = fem_assemble_stiff_wmass(pat, q.contiguous(), w.contiguous())
+            ctx.pat = pat
+            ctx.save_for_backward(q, w)
+            return S, M
+
+        @staticmethod
+        def backward(ctx, gS, gM):
+            q, w = ctx.saved_tensors
+            gS = None if gS is None else gS.contiguous()
+            gM = None if gM is None else gM.contiguous()
+            dq, dw = fem_adjoint_stiff_wmass(ctx.pat, q.contiguous(), w.contiguous(), gS, gM)
+            return dq, (dw if gM is not None else None), None
+
+    return AssembleStiffWMass
+
+
+class _Lazy:
+    _fn = None
+
+    def apply(self, q, w, pat):
+        if _Lazy._fn is None:
+            _Lazy._fn = _autograd_function()
+        return _Lazy._fn.apply(q, w, pat)
+
+
+AssembleStiffWMass = _Lazy()

@@ -1,0 +1,313 @@
+// fem_adjoint.hip -- hand-written adjoint of the stiffness + weighted mass
+// assembly: gradient of L = <GS, S(q)> + <GM, Mw(q, w)> with respect to the
+// vertex coordinates q and the vertex weights w.
+//
+// Row-owner decomposition.  L = sum_i sum_{T around i} tau(i, T) where
+// tau(i, T) = sum_b GS[i, b] S^T_{ib} + GM[i, b] Mw^T_{ib} uses only row i of
+// GS and GM.  Pass 1 (one lane per row, the same tiling as the forward) walks
+// the triangles around i, differentiates tau(i, T) with respect to the three
+// vertices of T and the three weights, keeps the part for i in registers and
+// adds the parts for the two neighbours j into H[i, j] (LDS), then writes H
+// coalesced: H[i, j] = d(sum_T tau(i, T)) / d(q_j, w_j).  Pass 2 (one lane per
+// vertex u) sums column u of H: dL/d(q_u, w_u) = sum_v H[v, u], reading the
+// transposed positions.  No atomics; every sum has a fixed order, so the
+// result is bitwise reproducible.
+//
+// Derivatives for the triangle (x0, x1, x2) (cyclic rotation starting at i),
+// r0 = x1 - x2, r1 = x2 - x0, r2 = x0 - x1, D = (x1 - x0) x (x2 - x0),
+// d|D|/dx_c = sign(D) perp(r_c), perp(r) = (r_y, -r_x):
+//   stiffness  tau_S = N / (2|D|), N = <r0, R>, R = g0 r0 + g1 r1 + g2 r2
+//              dN/dx0 = (g2 - g1) r0, dN/dx1 = R + (g0 - g2) r0,
+//              dN/dx2 = -R + (g1 - g0) r0,
+//              dtau_S/dx_c = dN/dx_c / (2|D|) - N / (2|D|^2) d|D|/dx_c
+//   w-mass     tau_M = |D| P / 60, P = h0 (3w0+w1+w2) + h1 (w0+w1+w2/2)
+//                                      + h2 (w0+w1/2+w2)          (eq. MassWElem)
+//              dtau_M/dx_c = P / 60 d|D|/dx_c,
+//              dtau_M/dw = |D|/60 (3h0+h1+h2, h0+h1+h2/2, h0+h1/2+h2)
+// with g_b = GS[i, b], h_b = GM[i, b] for the columns b = (x0, x1, x2).
+#include "fem_internal.h"
+
+namespace fem {
+
+struct AdjGrad {
+    double gx[3], gy[3], gw[3];
+};
+
+template <bool HS, bool HM>
+__device__ __forceinline__ void adj_tau(double x0, double y0, double x1, double y1, double x2,
+                                        double y2, double w0, double w1, double w2, double g0,
+                                        double g1, double g2, double h0, double h1, double h2,
+                                        AdjGrad &o) {
+    const double r0x = x1 - x2, r0y = y1 - y2;
+    const double r1x = x2 - x0, r1y = y2 - y0;
+    const double r2x = x0 - x1, r2y = y0 - y1;
+    const double D = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
+    const double ad = fabs(D);
+    const double sg = D > 0.0 ? 1.0 : (D < 0.0 ? -1.0 : 0.0);
+    // d|D|/dx_c
+    const double dDx[3] = {sg * r0y, sg * r1y, sg * r2y};
+    const double dDy[3] = {-sg * r0x, -sg * r1x, -sg * r2x};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o.gx[c] = o.gy[c] = o.gw[c] = 0.0;
+    if constexpr (HS) {
+        const double Rx = g0 * r0x + g1 * r1x + g2 * r2x;
+        const double Ry = g0 * r0y + g1 * r1y + g2 * r2y;
+        const double N = r0x * Rx + r0y * Ry;
+        const double inv = 1.0 / (2.0 * ad);
+        const double k = N * inv / ad;
+        const double dNx[3] = {(g2 - g1) * r0x, Rx + (g0 - g2) * r0x, -Rx + (g1 - g0) * r0x};
+        const double dNy[3] = {(g2 - g1) * r0y, Ry + (g0 - g2) * r0y, -Ry + (g1 - g0) * r0y};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            o.gx[c] += dNx[c] * inv - k * dDx[c];
+            o.gy[c] += dNy[c] * inv - k * dDy[c];
+        }
+    }
+    if constexpr (HM) {
+        const double P = h0 * (3.0 * w0 + w1 + w2) + h1 * (w0 + w1 + 0.5 * w2) +
+                         h2 * (w0 + 0.5 * w1 + w2);
+        const double p60 = P / 60.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            o.gx[c] += p60 * dDx[c];
+            o.gy[c] += p60 * dDy[c];
+        }
+        const double a60 = ad / 60.0;
+        o.gw[0] = a60 * (3.0 * h0 + h1 + h2);
+        o.gw[1] = a60 * (h0 + h1 + 0.5 * h2);
+        o.gw[2] = a60 * (h0 + 0.5 * h1 + h2);
+    }
+}
+
+// Pass 1.  LDS tile per 64 rows: H accumulators (x, y, w) | qx | qy | w | GS | GM | col.
+template <bool HS, bool HM>
+__global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double *__restrict__ q,
+                                                   const double *__restrict__ w,
+                                                   const int32_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col_idx,
+                                                   const int32_t *__restrict__ inc_ptr,
+                                                   const uint32_t *__restrict__ inc_pos,
+                                                   const double *__restrict__ GS,
+                                                   const double *__restrict__ GM,
+                                                   double *__restrict__ H, int64_t nnz, int eb,
+                                                   int64_t ntiles) {
+    extern __shared__ double smem[];
+    double *s_hx = smem;
+    double *s_hy = s_hx + eb;
+    double *s_hw = s_hy + eb;
+    double *s_qx = s_hw + eb;
+    double *s_qy = s_qx + eb;
+    double *s_w = s_qy + eb;
+    double *s_gs = s_w + eb;
+    double *s_gm = s_gs + eb;
+    int32_t *s_col = reinterpret_cast<int32_t *>(s_gm + eb);
+    double *Hx = H, *Hy = H + nnz, *Hw = H + 2 * nnz;
+    const int lane = threadIdx.x;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * WAVE;
+        const int64_t r1 = (r0 + WAVE < nq) ? r0 + WAVE : nq;
+        const int64_t i = r0 + lane;
+        const bool active = i < nq;
+        const int32_t E0 = row_ptr[r0], E1 = row_ptr[r1], Ew = E1 - E0;
+        const int32_t rs = active ? row_ptr[i] : 0;
+        const int32_t len = active ? row_ptr[i + 1] - rs : 0;
+        if (Ew <= eb) {
+            for (int e = lane; e < Ew; e += WAVE) {
+                const int32_t c = col_idx[E0 + e];
+                s_col[e] = c;
+                const double2 qc = reinterpret_cast<const double2 *>(q)[c];
+                s_qx[e] = qc.x;
+                s_qy[e] = qc.y;
+                s_w[e] = HM ? w[c] : 0.0;
+                s_gs[e] = HS ? GS[E0 + e] : 0.0;
+                s_gm[e] = HM ? GM[E0 + e] : 0.0;
+                s_hx[e] = 0.0;
+                s_hy[e] = 0.0;
+                s_hw[e] = 0.0;
+            }
+            __syncthreads();
+            if (active && len > 0) {
+                const int32_t off = rs - E0;
+                int32_t pd = 0;
+                while (pd < len - 1 && s_col[off + pd] != (int32_t)i) ++pd;
+                const int32_t d0 = off + pd;
+                const double x0 = s_qx[d0], y0 = s_qy[d0], w0 = s_w[d0];
+                const double g0 = s_gs[d0], h0 = s_gm[d0];
+                double ox = 0.0, oy = 0.0, ow = 0.0;
+                const int32_t t1 = inc_ptr[i + 1];
+                for (int32_t t = inc_ptr[i]; t < t1; ++t) {
+                    const uint32_t pp = inc_pos[t];
+                    const int32_t p1 = off + (int32_t)(pp & 0xffffu);
+                    const int32_t p2 = off + (int32_t)(pp >> 16);
+                    AdjGrad o;
+                    adj_tau<HS, HM>(x0, y0, s_qx[p1], s_qy[p1], s_qx[p2], s_qy[p2], w0, s_w[p1],
+                                    s_w[p2], g0, s_gs[p1], s_gs[p2], h0, s_gm[p1], s_gm[p2], o);
+                    ox += o.gx[0];
+                    oy += o.gy[0];
+                    ow += o.gw[0];
+                    s_hx[p1] += o.gx[1];
+                    s_hy[p1] += o.gy[1];
+                    s_hw[p1] += o.gw[1];
+                    s_hx[p2] += o.gx[2];
+                    s_hy[p2] += o.gy[2];
+                    s_hw[p2] += o.gw[2];
+                }
+                s_hx[d0] += ox;
+                s_hy[d0] += oy;
+                s_hw[d0] += ow;
+            }
+            __syncthreads();
+            for (int e = lane; e < Ew; e += WAVE) {
+                Hx[E0 + e] = s_hx[e];
+                Hy[E0 + e] = s_hy[e];
+                Hw[E0 + e] = s_hw[e];
+            }
+            __syncthreads();
+        } else if (active && len > 0) {
+            // tile too large for LDS: own row in global memory, same order
+            for (int e = 0; e < len; ++e) {
+                Hx[rs + e] = 0.0;
+                Hy[rs + e] = 0.0;
+                Hw[rs + e] = 0.0;
+            }
+            const int32_t *cr = col_idx + rs;
+            int32_t pd = 0;
+            while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
+            const double x0 = q[2 * i], y0 = q[2 * i + 1], w0 = HM ? w[i] : 0.0;
+            const double g0 = HS ? GS[rs + pd] : 0.0, h0 = HM ? GM[rs + pd] : 0.0;
+            double ox = 0.0, oy = 0.0, ow = 0.0;
+            const int32_t t1 = inc_ptr[i + 1];
+            for (int32_t t = inc_ptr[i]; t < t1; ++t) {
+                const uint32_t pp = inc_pos[t];
+                const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
+                const int64_t j1 = cr[p1], j2 = cr[p2];
+                AdjGrad o;
+                adj_tau<HS, HM>(x0, y0, q[2 * j1], q[2 * j1 + 1], q[2 * j2], q[2 * j2 + 1], w0,
+                                HM ? w[j1] : 0.0, HM ? w[j2] : 0.0, g0, HS ? GS[rs + p1] : 0.0,
+                                HS ? GS[rs + p2] : 0.0, h0, HM ? GM[rs + p1] : 0.0,
+                                HM ? GM[rs + p2] : 0.0, o);
+                ox += o.gx[0];
+                oy += o.gy[0];
+                ow += o.gw[0];
+                Hx[rs + p1] += o.gx[1];
+                Hy[rs + p1] += o.gy[1];
+                Hw[rs + p1] += o.gw[1];
+                Hx[rs + p2] += o.gx[2];
+                Hy[rs + p2] += o.gy[2];
+                Hw[rs + p2] += o.gw[2];
+            }
+            Hx[rs + pd] += ox;
+            Hy[rs + pd] += oy;
+            Hw[rs + pd] += ow;
+        }
+    }
+}
+
+__device__ inline int32_t find_in_row(const int32_t *__restrict__ col_idx, int32_t rs, int32_t re,
+                                      int32_t x) {
+    int32_t lo = rs, hi = re;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (col_idx[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Pass 2: column sums of H, one lane per vertex u, ascending position in row u.
+__global__ __launch_bounds__(256) void k_adj_cols(int32_t nq, const int32_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ col_idx,
+                                                  const int32_t *__restrict__ tpos,
+                                                  const double *__restrict__ H, int64_t nnz,
+                                                  double *__restrict__ dq, double *__restrict__ dw,
+                                                  int accumulate) {
+    const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (u >= nq) return;
+    const double *Hx = H, *Hy = H + nnz, *Hw = H + 2 * nnz;
+    double gx = 0.0, gy = 0.0, gw = 0.0;
+    const int32_t rs = row_ptr[u], re = row_ptr[u + 1];
+    for (int32_t p = rs; p < re; ++p) {
+        int32_t t;
+        if (tpos) {
+            t = tpos[p];
+        } else {
+            const int32_t v = col_idx[p];
+            const int32_t re_v = row_ptr[v + 1];
+            t = find_in_row(col_idx, row_ptr[v], re_v, static_cast<int32_t>(u));
+            if (t >= re_v || col_idx[t] != (int32_t)u) t = -1;
+        }
+        if (t < 0) continue;   // no transposed entry (never for a P1 pattern)
+        gx += Hx[t];
+        gy += Hy[t];
+        gw += Hw[t];
+    }
+    if (accumulate) {
+        dq[2 * u] += gx;
+        dq[2 * u + 1] += gy;
+        if (dw) dw[u] += gw;
+    } else {
+        dq[2 * u] = gx;
+        dq[2 * u + 1] = gy;
+        if (dw) dw[u] = gw;
+    }
+}
+
+namespace {
+constexpr int ADJ_EB = 512;
+
+template <bool HS, bool HM>
+int launch_adj(int32_t nq, const double *q, const double *w, const int32_t *row_ptr,
+               const int32_t *col_idx, const int32_t *inc_ptr, const uint32_t *inc_pos,
+               const double *GS, const double *GM, double *H, int64_t nnz, hipStream_t s) {
+    const int64_t ntiles = (nq + WAVE - 1) / WAVE;
+    const size_t lds = (size_t)ADJ_EB * (8 * 8 + 4);
+    hipLaunchKernelGGL((k_adj_rows<HS, HM>), dim3((unsigned)ntiles), dim3(WAVE), lds, s, nq, q, w,
+                       row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, nnz, ADJ_EB, ntiles);
+    FEM_LAUNCH_CHECK();
+    return FEM_OK;
+}
+}  // namespace
+
+}  // namespace fem
+
+using namespace fem;
+
+extern "C" int fem_adjoint_workspace(int64_t nnz, size_t *bytes) {
+    clear_error();
+    FEM_REQUIRE(bytes && nnz >= 0, FEM_EINVAL, "fem_adjoint_workspace: bad arguments");
+    *bytes = (size_t)(3 * nnz > 0 ? 3 * nnz : 1) * sizeof(double);
+    return FEM_OK;
+}
+
+extern "C" int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
+                                       const double *w, const int32_t *row_ptr,
+                                       const int32_t *col_idx, const int32_t *inc_ptr,
+                                       const uint32_t *inc_pos, const int32_t *tpos,
+                                       const double *GS, const double *GM, double *dq, double *dw,
+                                       void *work, size_t work_bytes, int flags, void *stream) {
+    clear_error();
+    FEM_REQUIRE(nq >= 1 && nme >= 0 && nnz >= 0 && nnz <= INT32_MAX, FEM_EINVAL,
+                "fem_adjoint_stiff_wmass: bad sizes");
+    FEM_REQUIRE((flags & ~FEM_ACCUMULATE) == 0, FEM_EINVAL,
+                "fem_adjoint_stiff_wmass: only FEM_ACCUMULATE is supported");
+    FEM_REQUIRE(q && row_ptr && dq && work, FEM_EINVAL, "fem_adjoint_stiff_wmass: NULL q, row_ptr, dq or work");
+    FEM_REQUIRE(nnz == 0 || (col_idx && inc_ptr && inc_pos), FEM_EINVAL,
+                "fem_adjoint_stiff_wmass: NULL pattern array");
+    FEM_REQUIRE(!GM || (w && dw), FEM_EINVAL, "fem_adjoint_stiff_wmass: the GM term needs w and dw");
+    size_t need = 0;
+    fem_adjoint_workspace(nnz, &need);
+    FEM_REQUIRE(work_bytes >= need, FEM_ENOSPC, "fem_adjoint_stiff_wmass: workspace %zu < %zu",
+                work_bytes, need);
+    hipStream_t s = as_stream(stream);
+    double *H = static_cast<double *>(work);
+    int st;
+    if (GS && GM) st = launch_adj<true, true>(nq, q, w, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, nnz, s);
+    else if (GS) st = launch_adj<true, false>(nq, q, w, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, nnz, s);
+    else if (GM) st = launch_adj<false, true>(nq, q, w, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, nnz, s);
+    else st = fill_f64(H, 3 * nnz, 0.0, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_adj_cols, dim3(grid_for(nq, 256)), dim3(256), 0, s, nq, row_ptr, col_idx,
+                       tpos, H, nnz, dq, dw, (flags & FEM_ACCUMULATE) ? 1 : 0);
+    FEM_LAUNCH_CHECK();
+    return FEM_OK;
+}

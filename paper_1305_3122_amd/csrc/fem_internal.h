@@ -1,0 +1,99 @@
+// fem_internal.h -- shared host/device helpers of the gfx950 assembly library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "../../include/fem_p1.h"
+
+namespace fem {
+
+// ---------------------------------------------------------------- errors
+
+int set_error(int code, const char *fmt, ...);
+void clear_error();
+
+#define FEM_HIP_CHECK(expr)                                                              \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::fem::set_error(FEM_EHIP, "%s: %s (%s:%d)", #expr,                   \
+                                    hipGetErrorString(e_), __FILE__, __LINE__);          \
+    } while (0)
+
+#define FEM_LAUNCH_CHECK() FEM_HIP_CHECK(hipGetLastError())
+
+#define FEM_REQUIRE(cond, code, ...)                                                     \
+    do {                                                                                 \
+        if (!(cond))                                                                     \
+            return ::fem::set_error((code), __VA_ARGS__);                                \
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    return static_cast<unsigned>(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------- constants
+
+constexpr int WAVE = 64;
+
+// Device-side error bits of the symbolic phase.
+enum : int {
+    ERR_RANGE = 1,        // vertex index outside [0, nq)
+    ERR_DEGEN = 2,        // repeated vertex in a triangle
+    ERR_OVERFLOW = 4,     // a prefix sum exceeded int32
+    ERR_ROWLEN = 8,       // a row longer than 65535 entries
+};
+
+// Layout of the small counter block at the head of the pattern workspace.
+struct PatternCounters {
+    int err;              // OR of ERR_* bits
+    int wide_count;       // vertices routed to the workgroup-per-row path
+    int max_row_len;      // longest CSR row
+    int max_inc;          // most triangles around one vertex
+    long long total[4];   // totals written by the scans
+};
+
+// ---------------------------------------------------------------- device helpers
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+template <typename T>
+__device__ inline T wave_inclusive_scan(T v) {
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T u = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+// Zero / fill kernels (used instead of hipMemsetAsync so that captured
+// graphs replay correctly).
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v);
+__global__ void k_fill_f64(double *p, int64_t n, double v);
+
+int fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+int fill_f64(double *p, int64_t n, double v, hipStream_t s);
+
+// Exclusive scan of n int32 counts into out[0..n] (out[n] = total).  `part`
+// needs scan_partials(n) int64 slots.  The total is also stored to
+// *total_dev; ERR_OVERFLOW is OR-ed into *err_dev if it exceeds INT32_MAX.
+int64_t scan_partials(int64_t n);
+int exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, long long *part,
+                       long long *total_dev, int *err_dev, hipStream_t s);
+
+}  // namespace fem

@@ -1,0 +1,94 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/fem_p1.h, and rejects bad arguments on the host before
+touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1305_3122_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fem_p1.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fem_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1305_3122_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares a signature for each of them
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+
+
+def test_version_and_bounds(lib):
+    assert lib.fem_version() == 100
+    assert lib.fem_nnz_bound(10, 7) == 10 + 42
+    sz = C.c_size_t(0)
+    assert lib.fem_pattern_workspace(1089, 2048, C.byref(sz)) == 0
+    assert sz.value > 4 * (6 * 2048 + 1089)
+    assert lib.fem_pattern_workspace(0, 5, C.byref(sz)) == _lib.FEM_EINVAL
+    assert lib.fem_adjoint_workspace(100, C.byref(sz)) == 0 and sz.value == 2400
+
+
+def test_host_validation_before_any_launch(lib):
+    nnz = C.c_int64(0)
+    fake = C.c_void_p(0x1000)  # never dereferenced: the checks fail first
+    # nq < 1
+    st = lib.fem_pattern(0, 1, fake, fake, fake, 10, fake, fake, fake, None, fake, 1 << 20,
+                         C.byref(nnz), None)
+    assert st == _lib.FEM_EINVAL
+    assert b"nq" in lib.fem_last_error()
+    # nq + 6 nme beyond int32
+    st = lib.fem_pattern(10, 400_000_000, fake, fake, fake, 10, fake, fake, fake, None, fake,
+                         1 << 20, C.byref(nnz), None)
+    assert st == _lib.FEM_EOVERFLOW
+    # workspace too small
+    st = lib.fem_pattern(10, 4, fake, fake, fake, 100, fake, fake, fake, None, fake, 16,
+                         C.byref(nnz), None)
+    assert st == _lib.FEM_ENOSPC
+    # elasticity: lambda + mu must be positive (elasticity section)
+    st = lib.fem_assemble_elas(4, 2, 10, fake, fake, fake, fake, fake, fake, None, -1.0, 0.5,
+                               fake, 0, None)
+    assert st == _lib.FEM_EINVAL and b"lambda" in lib.fem_last_error()
+    # FEM_ATOMIC needs the slot map
+    st = lib.fem_assemble_stiff(4, 2, 10, fake, fake, fake, fake, fake, fake, None, fake,
+                                _lib.FEM_ATOMIC, None)
+    assert st == _lib.FEM_EINVAL
+    # unknown flag bits
+    st = lib.fem_assemble_mass(4, 2, 10, fake, fake, fake, fake, fake, fake, None, fake, 64, None)
+    assert st == _lib.FEM_EINVAL
+    # the weighted mass needs w
+    st = lib.fem_assemble_wmass(4, 2, 10, fake, fake, fake, fake, fake, fake, None, None, fake, 0,
+                                None)
+    assert st == _lib.FEM_EINVAL
+    # graphs cannot capture the NULL stream
+    assert lib.fem_graph_begin(None) == _lib.FEM_EINVAL
+    assert lib.fem_graph_destroy(None) == 0
+    # adjoint: the GM term needs w and dw
+    st = lib.fem_adjoint_stiff_wmass(4, 2, 10, fake, None, fake, fake, fake, fake, None, None,
+                                     fake, fake, None, fake, 1000, 0, None)
+    assert st == _lib.FEM_EINVAL
+
+
+def test_python_binding_refuses_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    import paper_1305_3122_amd as fem
+    me = torch.zeros((1, 3), dtype=torch.int32)
+    with pytest.raises(ValueError, match="GPU"):
+        fem.fem_pattern(me, 3)

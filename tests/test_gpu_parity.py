@@ -1,0 +1,268 @@
+"""GPU parity against the oracle, through the C ABI (Python binding).
+
+Integer outputs (pattern, triangle lists, slot map) must match bit for bit;
+FP64 values within 1e-13 relative per row (max norm).  Full-size workloads
+are checked on sampled rows that the oracle computes one by one, plus
+properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1305_3122_amd import meshgen as mg
+from tests.helpers import RTOL_ROW, fan_mesh, row_rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1305_3122_amd as fem  # noqa: E402
+
+DEV = torch.device("cuda:0")
+LAM, MU = 1.0, 0.5
+
+
+def _up(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _check_pattern(pat, P, me):
+    assert pat.nnz == P.nnz
+    np.testing.assert_array_equal(_np(pat.row_ptr), P.row_ptr)
+    np.testing.assert_array_equal(_np(pat.col_idx), P.col_idx)
+    np.testing.assert_array_equal(_np(pat.inc_ptr), P.inc_ptr)
+    np.testing.assert_array_equal(_np(pat.inc), P.inc)
+    if pat.slot is not None and me.shape[0] > 0:
+        np.testing.assert_array_equal(_np(pat.slot), P.slot)
+    # inc_pos: row-relative positions of the two cyclic successors
+    if me.shape[0] > 0:
+        pos = _np(pat.inc_pos).view(np.uint32)
+        p1 = (pos & 0xFFFF).astype(np.int64)
+        p2 = (pos >> 16).astype(np.int64)
+        v = np.repeat(np.arange(P.nq), np.diff(P.inc_ptr))
+        k, a = P.inc // 3, P.inc % 3
+        rs = P.row_ptr[v]
+        np.testing.assert_array_equal(P.col_idx[rs + p1], me[k, (a + 1) % 3])
+        np.testing.assert_array_equal(P.col_idx[rs + p2], me[k, (a + 2) % 3])
+
+
+def _check_values(m, pat, P, w, flags):
+    qd = _up(m.q)
+    wd = _up(w)
+    ref = {op: oracle.assemble(op, m.q, m.me, P.slot, P.nnz, w=w) for op in ("mass", "wmass", "stiff")}
+    got = {
+        "mass": fem.fem_assemble_mass(pat, qd, flags=flags),
+        "wmass": fem.fem_assemble_wmass(pat, qd, wd, flags=flags),
+        "stiff": fem.fem_assemble_stiff(pat, qd, flags=flags),
+    }
+    S2, M2 = fem.fem_assemble_stiff_mass(pat, qd, flags=flags)
+    S3, W3 = fem.fem_assemble_stiff_wmass(pat, qd, wd, flags=flags)
+    torch.cuda.synchronize()
+    for op in ref:
+        assert row_rel_err(P.row_ptr, _np(got[op]), ref[op]) <= RTOL_ROW, op
+    for op, t in (("stiff", S2), ("mass", M2), ("stiff", S3), ("wmass", W3)):
+        assert row_rel_err(P.row_ptr, _np(t), ref[op]) <= RTOL_ROW, op
+    if not (flags & fem.FEM_ATOMIC):
+        # fused and single-operator kernels sum in the same order
+        np.testing.assert_array_equal(_np(S2), _np(got["stiff"]))
+        np.testing.assert_array_equal(_np(M2), _np(got["mass"]))
+        np.testing.assert_array_equal(_np(W3), _np(got["wmass"]))
+    # elasticity: pattern derived from the scalar one, values vs the oracle
+    rpe, cie, se = oracle.pattern_elas(m.nq, m.me)
+    grpe, gcie = fem.fem_elas_pattern(pat)
+    np.testing.assert_array_equal(_np(grpe), rpe)
+    np.testing.assert_array_equal(_np(gcie), cie)
+    K = fem.fem_assemble_elas(pat, qd, LAM, MU, flags=flags)
+    Kref = oracle.assemble("elas", m.q, m.me, se, int(rpe[-1]), lam=LAM, mu=MU)
+    torch.cuda.synchronize()
+    assert row_rel_err(rpe, _np(K), Kref) <= RTOL_ROW
+
+
+def _meshes():
+    rng = np.random.default_rng(2024)
+    out = [("cfg1_square32", mg.config_mesh(1)),
+           ("square1", mg.unit_square(1, seed=3)),
+           ("square3_unjittered", mg.unit_square(3, jitter=0.0, seed=3)),
+           ("disk24", mg.unit_disk(24, seed=5))]
+    for s in range(3):
+        out.append((f"tiny{s}", mg.random_tiny_mesh(np.random.default_rng(rng.integers(1 << 30)), 40)))
+    for n_fan, extra in ((17, 0), (40, 3), (300, 5)):
+        q, me = fan_mesh(n_fan, extra, seed=n_fan)
+        out.append((f"fan{n_fan}", mg.Mesh(q, me, "fan")))
+    q = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    out.append(("one_triangle_cw", mg.Mesh(q, np.array([[0, 2, 1]], np.int32), "tri")))
+    return out
+
+
+MESHES = _meshes()
+
+
+@pytest.mark.parametrize("name,m", MESHES, ids=[n for n, _ in MESHES])
+def test_pattern_and_values_small(name, m):
+    print(f"[case] {name} nq={m.nq} nme={m.nme}", flush=True)
+    P = oracle.pattern(m.nq, m.me)
+    pat = fem.fem_pattern(_up(m.me), m.nq, slot=True)
+    torch.cuda.synchronize()
+    _check_pattern(pat, P, m.me)
+    w = np.random.default_rng(1).uniform(0.5, 2.0, size=m.nq)
+    _check_values(m, pat, P, w, 0)
+    _check_values(m, pat, P, w, fem.FEM_ATOMIC)
+
+
+def test_cfg5_square512_full_parity():
+    m = mg.config_mesh(5)
+    print(f"[case] cfg5 nq={m.nq} nme={m.nme}", flush=True)
+    P = oracle.pattern(m.nq, m.me)
+    pat = fem.fem_pattern(_up(m.me), m.nq, slot=True)
+    torch.cuda.synchronize()
+    _check_pattern(pat, P, m.me)
+    assert pat.nnz == 1_838_081          # nq + 2 (nq + nme - 1)
+    w = mg.weight_uniform(m.nq, seed=mg.BASE_SEED + 5)
+    _check_values(m, pat, P, w, 0)
+    _check_values(m, pat, P, w, fem.FEM_ATOMIC)
+
+
+def test_empty_mesh_and_unused_vertices():
+    me = np.zeros((0, 3), np.int32)
+    pat = fem.fem_pattern(torch.zeros((0, 3), dtype=torch.int32, device=DEV), 5, slot=True)
+    torch.cuda.synchronize()
+    assert pat.nnz == 0
+    np.testing.assert_array_equal(_np(pat.row_ptr), np.zeros(6, np.int32))
+    q = _up(np.zeros((5, 2)))
+    S, M = fem.fem_assemble_stiff_mass(pat, q)
+    K = fem.fem_assemble_elas(pat, q, 1.0, 1.0)
+    torch.cuda.synchronize()
+    assert S.numel() == 0 and K.numel() == 0
+    del me
+
+
+def test_deterministic_bitwise_and_accumulate():
+    m = mg.unit_disk(40, seed=9)
+    pat = fem.fem_pattern(_up(m.me), m.nq)
+    q = _up(m.q)
+    a = fem.fem_assemble_stiff_mass(pat, q)
+    b = fem.fem_assemble_stiff_mass(pat, q)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    S = a[0].clone()
+    fem.fem_assemble_stiff(pat, q, out=S, flags=fem.FEM_ACCUMULATE)
+    assert torch.equal(S, 2 * a[0])
+    K = fem.fem_assemble_elas(pat, q, 2.0, 1.0)
+    K2 = K.clone()
+    fem.fem_assemble_elas(pat, q, 2.0, 1.0, out=K2, flags=fem.FEM_ACCUMULATE)
+    assert torch.equal(K2, 2 * K)
+
+
+def test_small_lds_tile_takes_the_global_memory_path():
+    # lds_entries = 256 < 64 rows x ~7 entries: every tile uses the fallback
+    m = mg.unit_square(40, seed=2)
+    pat = fem.fem_pattern(_up(m.me), m.nq)
+    q = _up(m.q)
+    S0, M0 = fem.fem_assemble_stiff_mass(pat, q)
+    S1, M1 = fem.fem_assemble_stiff_mass_batched(pat, q, 1, tune=fem.fem_tune(256, 0))
+    S2, M2 = fem.fem_assemble_stiff_mass_batched(pat, q, 1, tune=fem.fem_tune(1024, 37))
+    assert torch.equal(S0, S1) and torch.equal(M0, M1)
+    assert torch.equal(S0, S2) and torch.equal(M0, M2)
+
+
+def test_error_paths():
+    bad = _up(np.array([[0, 1, 5]], np.int32))
+    with pytest.raises(fem.FemError) as e:
+        fem.fem_pattern(bad, 3)
+    assert e.value.status == -2
+    deg = _up(np.array([[0, 1, 2], [0, 1, 1]], np.int32))
+    with pytest.raises(fem.FemError) as e:
+        fem.fem_pattern(deg, 3)
+    assert e.value.status == -3
+    # and the library keeps working afterwards
+    m = mg.unit_square(2, seed=1)
+    pat = fem.fem_pattern(_up(m.me), m.nq)
+    assert pat.nnz == oracle.pattern(m.nq, m.me).nnz
+
+
+# ------------------------------------------------------------ full size, sampled
+
+def _sample_rows(n, rng, k=1500):
+    return np.unique(np.concatenate([[0, n - 1], rng.choice(n, size=k, replace=False)])).astype(np.int32)
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_full_size_sampled_rows(cfg):
+    m = mg.config_mesh(cfg)
+    print(f"[case] cfg{cfg} nq={m.nq} nme={m.nme}", flush=True)
+    lam, mu = (1.0, 0.5) if cfg == 2 else (2.0, 1.0)
+    w = mg.weight_quadratic(m.q)
+    qd, wd = _up(m.q), _up(w)
+    pat = fem.fem_pattern(_up(m.me), m.nq)
+    assert pat.nnz == m.nq + 2 * (m.nq + m.nme - 1)   # Euler, simply connected
+    rp = _np(pat.row_ptr)
+    ci = _np(pat.col_idx)
+    S, M = fem.fem_assemble_stiff_mass(pat, qd)
+    Mw = fem.fem_assemble_wmass(pat, qd, wd)
+    K = fem.fem_assemble_elas(pat, qd, lam, mu)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(cfg)
+    rows = _sample_rows(m.nq, rng)
+    for op, got in (("stiff", S), ("mass", M), ("wmass", Mw)):
+        ptr, cols, vals = oracle.rows(op, m.q, m.me, rows, w=w)
+        g = _np(got)
+        for s, r in enumerate(rows):
+            a, b = rp[r], rp[r + 1]
+            np.testing.assert_array_equal(ci[a:b], cols[ptr[s]:ptr[s + 1]])
+            ref = vals[ptr[s]:ptr[s + 1]]
+            assert np.max(np.abs(g[a:b] - ref)) <= RTOL_ROW * np.max(np.abs(ref)), (op, r)
+    erows = np.concatenate([2 * rows[:400], 2 * rows[:400] + 1]).astype(np.int32)
+    ptr, cols, vals = oracle.rows("elas", m.q, m.me, erows, lam=lam, mu=mu)
+    Kh = _np(K)
+    for s, r in enumerate(erows):
+        i, al = r // 2, r % 2
+        L = rp[i + 1] - rp[i]
+        a = 4 * rp[i] + 2 * al * L
+        ref = vals[ptr[s]:ptr[s + 1]]
+        assert np.max(np.abs(Kh[a:a + 2 * L] - ref)) <= RTOL_ROW * np.max(np.abs(ref)), ("elas", r)
+    # properties at full size
+    if cfg == 2:
+        assert float(M.sum()) == pytest.approx(1.0, rel=1e-12)
+    else:
+        N = 6 * 1024
+        assert float(M.sum()) == pytest.approx(N / 2 * np.sin(2 * np.pi / N), rel=1e-12)
+    rows_all = torch.repeat_interleave(torch.arange(m.nq, device=DEV), torch.diff(pat.row_ptr.long()))
+    rs = torch.zeros(m.nq, dtype=torch.float64, device=DEV).index_add_(0, rows_all, S).abs()
+    rmax = torch.zeros(m.nq, dtype=torch.float64, device=DEV)
+    rmax.scatter_reduce_(0, rows_all, S.abs(), reduce="amax")
+    assert float((rs / rmax).max()) < 1e-12
+    tp = fem.fem_transpose_map(pat)
+    assert int(tp.min()) >= 0
+    assert float(((S - S[tp.long()]).abs() / rmax[rows_all]).max()) < 1e-13
+
+
+def test_full_size_atomic_sampled_rows():
+    m = mg.config_mesh(2)
+    print(f"[case] cfg2 atomic nq={m.nq} nme={m.nme}", flush=True)
+    qd = _up(m.q)
+    pat = fem.fem_pattern(_up(m.me), m.nq, slot=True)
+    S, M = fem.fem_assemble_stiff_mass(pat, qd, flags=fem.FEM_ATOMIC)
+    torch.cuda.synchronize()
+    rp = _np(pat.row_ptr)
+    rows = _sample_rows(m.nq, np.random.default_rng(11), 800)
+    for op, got in (("stiff", S), ("mass", M)):
+        ptr, cols, vals = oracle.rows(op, m.q, m.me, rows)
+        g = _np(got)
+        for s, r in enumerate(rows):
+            a, b = rp[r], rp[r + 1]
+            ref = vals[ptr[s]:ptr[s + 1]]
+            assert np.max(np.abs(g[a:b] - ref)) <= RTOL_ROW * np.max(np.abs(ref)), (op, r)
+    # slot map consistency at full size (bit-exact property)
+    sl = _np(pat.slot)
+    ci = _np(pat.col_idx)
+    rows_of = np.repeat(np.arange(m.nq), np.diff(rp))
+    for b in range(3):
+        for a in range(3):
+            np.testing.assert_array_equal(ci[sl[3 * b + a]], m.me[:, b])
+            np.testing.assert_array_equal(rows_of[sl[3 * b + a]], m.me[:, a])
