@@ -368,8 +368,8 @@ int check_common(const char *fn, const Args &a, bool need_w, int nout) {
     FEM_REQUIRE(a.nnz <= INT32_MAX, FEM_EOVERFLOW, "%s: nnz exceeds int32", fn);
     FEM_REQUIRE((a.flags & ~(FEM_ATOMIC | FEM_ACCUMULATE)) == 0, FEM_EINVAL, "%s: unknown flags 0x%x", fn,
                 a.flags);
-    FEM_REQUIRE(a.q && a.row_ptr && a.out0 && (nout < 2 || a.out1), FEM_EINVAL,
-                "%s: NULL q, row_ptr or output", fn);
+    FEM_REQUIRE(a.q && a.row_ptr, FEM_EINVAL, "%s: NULL q or row_ptr", fn);
+    FEM_REQUIRE(a.nnz == 0 || (a.out0 && (nout < 2 || a.out1)), FEM_EINVAL, "%s: NULL output", fn);
     FEM_REQUIRE(!need_w || a.w, FEM_EINVAL, "%s: NULL w", fn);
     if (a.flags & FEM_ATOMIC) {
         FEM_REQUIRE(a.nme == 0 || (a.me && a.slot), FEM_EINVAL, "%s: FEM_ATOMIC needs me and slot", fn);
