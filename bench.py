@@ -3,18 +3,18 @@
 Step (timed): the whole assembly of the 2048 x 2048-cell unit square
 (8,388,608 triangles, jitter 0.2 h, random vertex relabelling, FP64 values,
 int32 indices) from (q, me) resident in HBM:
-    fem_pattern                symbolic phase (CSR pattern + triangle lists)
-    fem_assemble_stiff_mass    stiffness S and mass M, one fused pass
-    fem_assemble_wmass         weighted mass, w = 1 + x^2 + y^2 at the vertices
-    fem_elas_pattern           2x2-block elasticity pattern
-    fem_assemble_elas          elasticity stiffness, lambda = 1, mu = 0.5
+    fem_pattern        symbolic phase (CSR pattern + triangle lists)
+    fem_assemble       mass M, weighted mass Mw (w = 1 + x^2 + y^2) and
+                       stiffness S in one pass over the mesh
+    fem_assemble       elasticity K (lambda = 1, mu = 0.5), second pass
+    fem_elas_pattern   2x2-block elasticity pattern
 value = triangles / step time (M triangles per second).
 
-Also reported: per-call HIP-event times and roofline of each numeric kernel
-(algorithmic bytes per triangle), the batched block-diagonal assembly of 512
-meshes (one graph-captured launch) against a per-mesh launch loop, the
-forward + backward / forward ratio of the differentiable assembly, and the
-CPU oracle timed on a bounded sample.
+Also reported: per-call HIP-event times and the roofline of each numeric
+kernel (algorithmic bytes), the stiffness + mass pair alone, the batched
+block-diagonal assembly of 512 meshes (one graph-captured launch) against a
+per-mesh launch loop, the forward + backward / forward ratio of the
+differentiable assembly, and the CPU oracle timed on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
 """
@@ -46,10 +46,11 @@ def algorithmic_bytes(nq, nme, nnz):
     me, q, w = 12 * nme, 16 * nq, 8 * nq
     vals = 8 * nnz
     return {
-        "pattern": me + 4 * (nq + 1) + 4 * nnz,          # me -> row_ptr, col_idx
+        "pattern": me + 4 * (nq + 1) + 4 * nnz,           # me -> row_ptr, col_idx
+        "assemble_mws": me + q + w + 3 * vals,             # -> M, Mw, S
+        "assemble_k": me + q + 4 * vals,                   # -> K
+        "elas_pattern": 4 * (nq + 1) + 4 * nnz + 4 * (2 * nq + 1) + 16 * nnz,
         "stiff_mass": me + q + 2 * vals,
-        "wmass": me + q + w + vals,
-        "elas": me + q + 4 * vals,
     }
 
 
@@ -80,11 +81,14 @@ class Step:
         self.pattern()
         torch.cuda.synchronize()
         f64 = dict(dtype=torch.float64, device=dev)
-        self.S = torch.empty(self.nnz, **f64)
         self.M = torch.empty(self.nnz, **f64)
         self.Mw = torch.empty(self.nnz, **f64)
+        self.S = torch.empty(self.nnz, **f64)
         self.K = torch.empty(4 * self.nnz, **f64)
         self.cie = torch.empty(4 * self.nnz, **i32)
+        aw = C.c_size_t(0)
+        fem._lib.check(lib.fem_assemble_workspace(m.nq, 15, C.byref(aw)))
+        self.awork = torch.empty(max(int(aw.value), 1), dtype=torch.uint8, device=dev)
         self.stream = torch.cuda.current_stream().cuda_stream
 
     def pattern(self):
@@ -100,25 +104,42 @@ class Step:
         return (self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.inc_ptr.data_ptr(),
                 self.inc_pos.data_ptr(), None)
 
+    def assemble_mws(self):
+        self.fem._lib.check(self.lib.fem_assemble(
+            7, self.nq, self.nme, self.nnz, self.q.data_ptr(), self.w.data_ptr(), self.me.data_ptr(),
+            *self._pat(), 0.0, 0.0, self.M.data_ptr(), self.Mw.data_ptr(), self.S.data_ptr(),
+            None, self.awork.data_ptr(), self.awork.numel(), None, 0, self.stream))
+
+    def assemble_k(self):
+        self.fem._lib.check(self.lib.fem_assemble(
+            8, self.nq, self.nme, self.nnz, self.q.data_ptr(), None, self.me.data_ptr(),
+            *self._pat(), self.lam, self.mu, None, None, None, self.K.data_ptr(), None, 0, None, 0,
+            self.stream))
+
+    def elas_pattern(self):
+        self.fem._lib.check(self.lib.fem_elas_pattern(
+            self.nq, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.rpe.data_ptr(),
+            self.cie.data_ptr(), self.stream))
+
     def stiff_mass(self):
         self.fem._lib.check(self.lib.fem_assemble_stiff_mass(
             self.nq, self.nme, self.nnz, self.q.data_ptr(), self.me.data_ptr(), *self._pat(),
             self.S.data_ptr(), self.M.data_ptr(), 0, self.stream))
 
-    def wmass(self):
-        self.fem._lib.check(self.lib.fem_assemble_wmass(
-            self.nq, self.nme, self.nnz, self.q.data_ptr(), self.me.data_ptr(), *self._pat(),
-            self.w.data_ptr(), self.Mw.data_ptr(), 0, self.stream))
+    PARTS = ("pattern", "assemble_mws", "assemble_k", "elas_pattern")
 
-    def elas(self):
-        self.fem._lib.check(self.lib.fem_elas_pattern(
-            self.nq, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.rpe.data_ptr(),
-            self.cie.data_ptr(), self.stream))
-        self.fem._lib.check(self.lib.fem_assemble_elas(
-            self.nq, self.nme, self.nnz, self.q.data_ptr(), self.me.data_ptr(), *self._pat(),
-            self.lam, self.mu, self.K.data_ptr(), 0, self.stream))
 
-    PARTS = ("pattern", "stiff_mass", "wmass", "elas")
+def time_calls(torch, fn, reps):
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) * 1e3 / reps
 
 
 def run_main(torch, fem, args):
@@ -149,14 +170,16 @@ def run_main(torch, fem, args):
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     ab = algorithmic_bytes(m.nq, m.nme, st.nnz)
+    us = {p: float(np.mean([a.elapsed_time(b) for a, b in ev[p]])) * 1e3 for p in Step.PARTS}
+    # the stiffness + mass pair alone (not part of the step)
+    us["stiff_mass"] = time_calls(torch, st.stiff_mass, args.steps)
     kern = {}
-    for p in Step.PARTS:
-        us = float(np.mean([a.elapsed_time(b) for a, b in ev[p]])) * 1e3
-        gbs = ab[p] / (us * 1e-6) / 1e9
-        kern[p] = {"us": round(us, 2), "alg_bytes": ab[p], "alg_GBps": round(gbs, 1),
-                   "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "Mtri_per_s": round(m.nme / us, 1)}
+    for p, t in us.items():
+        gbs = ab[p] / (t * 1e-6) / 1e9
+        kern[p] = {"us": round(t, 2), "alg_bytes": ab[p], "alg_GBps": round(gbs, 1),
+                   "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "Mtri_per_s": round(m.nme / t, 1)}
     log(f"[bench] step {ms_per_step:.3f} ms; " +
-        ", ".join(f"{p} {kern[p]['us']:.0f}us" for p in Step.PARTS))
+        ", ".join(f"{p} {kern[p]['us']:.0f}us" for p in kern))
     return m, st, ms_per_step, kern
 
 
@@ -280,9 +303,11 @@ def run_adjoint(torch, fem, args):
     Mw = torch.empty_like(S)
     dq = torch.empty((m.nq, 2), dtype=torch.float64, device=dev)
     dw = torch.empty(m.nq, dtype=torch.float64, device=dev)
+    fwork = torch.empty(32 * m.nq, dtype=torch.uint8, device=dev)
+    ops = fem.FEM_OP_STIFF | fem.FEM_OP_WMASS
 
     def fwd():
-        fem.fem_assemble_stiff_wmass(pat, q, wd, out_S=S, out_M=Mw)
+        fem.fem_assemble(pat, q, ops, w=wd, out={"S": S, "Mw": Mw}, work=fwork)
 
     def bwd():
         fem.fem_adjoint_stiff_wmass(pat, q, wd, G, G, dq=dq, dw=dw)
@@ -339,6 +364,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-cells", type=int, default=1448)
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (the assembly of one mesh runs on one "
@@ -349,13 +376,20 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     import paper_1305_3122_amd as fem
+    if args.calib:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy of 1 GiB done")
+        del src, dst
     m, st, ms, kern = run_main(torch, fem, args)
     extras = {}
     if not args.no_extras:
         extras["batched"] = run_batched(torch, fem, args)
         extras["adjoint"] = run_adjoint(torch, fem, args)
-    numeric = ("stiff_mass", "wmass", "elas")
-    dom = max(kern, key=lambda p: kern[p]["us"])
+    numeric = ("assemble_mws", "assemble_k", "elas_pattern")
+    dom = max(Step.PARTS, key=lambda p: kern[p]["us"])
     dom_num = max(numeric, key=lambda p: kern[p]["us"])
 
     def roof(p):
@@ -372,8 +406,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "unit square 2048x2048 cells (jitter 0.2h, random vertex relabelling), "
-                               "full assembly: pattern + S+M fused + Mw (w=1+x^2+y^2) + elasticity "
-                               "(lambda=1, mu=0.5); FP64 values, int32 indices",
+                               "full assembly: pattern + one pass for M, Mw (w=1+x^2+y^2), S + one "
+                               "pass for elasticity (lambda=1, mu=0.5) + elasticity pattern; FP64 "
+                               "values, int32 indices",
                    "nq": m.nq, "nme": m.nme, "nnz": st.nnz},
         "roofline": roof(dom if dom in numeric else dom_num),
         "roofline_stiff_mass": roof("stiff_mass"),

@@ -70,6 +70,17 @@ enum {
     FEM_ACCUMULATE = 2     /* add into values instead of overwriting them */
 };
 
+/* Tunable launch shape of the row-owner kernels. */
+typedef struct fem_tune {
+    int32_t lds_entries;   /* CSR entries staged in LDS per 64-row wave tile (rounded to a
+                              compiled size in 256..1024, capped by 64 KiB of LDS; 0: 512) */
+    int32_t grid_blocks;   /* persistent grid: number of one-wave workgroups that loop over
+                              the tiles (0: one workgroup per tile) */
+    int32_t variant;       /* 0: row accumulators in registers for rows of <= 8 entries,
+                              longer rows per lane from global memory (default);
+                              1: row accumulators in LDS */
+} fem_tune;
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *fem_last_error(void);
 
@@ -162,6 +173,30 @@ int fem_assemble_stiff(int32_t nq, int32_t nme, int64_t nnz, const double *q, co
                        const uint32_t *inc_pos, const int32_t *slot,
                        double *values, int flags, void *stream);
 
+/* Operator bits of fem_assemble. */
+enum { FEM_OP_MASS = 1, FEM_OP_WMASS = 2, FEM_OP_STIFF = 4, FEM_OP_ELAS = 8 };
+
+/* HOST ONLY.  Optional workspace bytes of fem_assemble for the operator set
+ * `ops`: 32 nq when FEM_OP_WMASS is requested (packed (x, y, w) records, one
+ * random access per column instead of two), else 0. */
+int fem_assemble_workspace(int32_t nq, int ops, size_t *bytes /* HOST */);
+
+/* Any nonzero subset `ops` of {M, Mw, S, K} in ONE pass over the mesh: the
+ * gathers of q (and w) by column -- every one a random access on a
+ * relabelled mesh -- are shared by all requested operators.  Outputs of
+ * operators not in `ops` may be NULL; vals_K [4 nnz] uses the layout of
+ * fem_elas_pattern; lambda, mu are read only for FEM_OP_ELAS (then
+ * lambda + mu > 0 is required).  work / work_bytes: optional device
+ * workspace (fem_assemble_workspace), NULL allowed.  tune: optional launch
+ * shape of the row-owner kernel (NULL: defaults).  Other arguments and flags
+ * as in the single-operator calls below, which are this call with one bit. */
+int fem_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q, const double *w,
+                 const int32_t *me, const int32_t *row_ptr, const int32_t *col_idx,
+                 const int32_t *inc_ptr, const uint32_t *inc_pos, const int32_t *slot,
+                 double lambda, double mu, double *vals_M, double *vals_Mw, double *vals_S,
+                 double *vals_K, void *work, size_t work_bytes, const struct fem_tune *tune,
+                 int flags, void *stream);
+
 /* S and M in one pass over the mesh (shared gathers of q). */
 int fem_assemble_stiff_mass(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
                             const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
@@ -196,14 +231,6 @@ int fem_assemble_elas(int32_t nq, int32_t nme, int64_t nnz, const double *q, con
 int fem_batch_globalize(int32_t nb, int32_t nme, const int64_t *vtx_off, const int64_t *elem_off,
                         const int32_t *me_local, int32_t *me_global, void *stream);
 
-/* Tunable launch shape of the row-owner kernels. */
-typedef struct fem_tune {
-    int32_t lds_entries;   /* CSR entries staged in LDS per 64-row wave tile: 256..4096,
-                              multiple of 64 (0: library default) */
-    int32_t grid_blocks;   /* persistent grid: number of one-wave workgroups that loop over
-                              the tiles (0: one workgroup per tile) */
-} fem_tune;
-
 /* S and M of a batched (block-diagonal) pattern in ONE persistent launch;
  * nq, nnz and the pattern arrays are those of the whole batch.  tune may be
  * NULL (defaults).  Same semantics as fem_assemble_stiff_mass with
@@ -237,8 +264,10 @@ int fem_graph_destroy(void *graph);
 /* Adjoint                                                                   */
 /* ------------------------------------------------------------------------ */
 
-/* HOST ONLY.  Bytes of device workspace for fem_adjoint_stiff_wmass. */
-int fem_adjoint_workspace(int64_t nnz, size_t *bytes /* HOST */);
+/* HOST ONLY.  Bytes of device workspace for fem_adjoint_stiff_wmass:
+ * packed (x, y, w) vertex records (32 nq) and the per-entry partial
+ * derivatives (32 nnz). */
+int fem_adjoint_workspace(int32_t nq, int64_t nnz, size_t *bytes /* HOST */);
 
 /* Gradient of L = sum_ij GS_ij S_ij(q) + sum_ij GM_ij Mw_ij(q, w) with
  * respect to q and w (GS, GM [nnz] on the scalar pattern; either may be NULL

@@ -20,12 +20,13 @@ import dataclasses
 from typing import Optional
 
 from . import _lib
-from ._lib import (FEM_ACCUMULATE, FEM_ATOMIC, FEM_DETERMINISTIC, FemError,  # noqa: F401
-                   fem_tune)
+from ._lib import (FEM_ACCUMULATE, FEM_ATOMIC, FEM_DETERMINISTIC, FEM_OP_ELAS,  # noqa: F401
+                   FEM_OP_MASS, FEM_OP_STIFF, FEM_OP_WMASS, FemError, fem_tune)
 
 __all__ = [
     "Pattern", "FemError", "FEM_ATOMIC", "FEM_DETERMINISTIC", "FEM_ACCUMULATE", "fem_tune",
-    "fem_pattern", "fem_transpose_map", "fem_elas_pattern", "fem_assemble_mass",
+    "FEM_OP_MASS", "FEM_OP_WMASS", "FEM_OP_STIFF", "FEM_OP_ELAS",
+    "fem_pattern", "fem_transpose_map", "fem_elas_pattern", "fem_assemble", "fem_assemble_mass",
     "fem_assemble_wmass", "fem_assemble_stiff", "fem_assemble_stiff_mass",
     "fem_assemble_stiff_wmass", "fem_assemble_elas", "fem_batch_globalize",
     "fem_assemble_stiff_mass_batched", "Graph", "fem_adjoint_stiff_wmass", "AssembleStiffWMass",
@@ -155,6 +156,37 @@ def _out(pat, out, n, name):
 
 def _head(pat, q):
     return (pat.nq, pat.nme, pat.nnz, _ptr(_q(pat, q)), _ptr(pat.me))
+
+
+def fem_assemble(pat: Pattern, q, ops: int, *, w=None, lam: float = 0.0, mu: float = 0.0,
+                 out: Optional[dict] = None, work=None, tune: Optional[fem_tune] = None,
+                 flags: int = 0, stream=None) -> dict:
+    """Any subset of {M, Mw, S, K} in one pass (C: fem_assemble).  Returns a
+    dict with keys "M", "Mw", "S", "K" for the requested operators; `out` may
+    supply preallocated tensors under the same keys.  A packing workspace for
+    the weighted mass is allocated here unless `work` is given."""
+    torch = _torch()
+    lib = _lib.load()
+    out = dict(out or {})
+    names = (("M", FEM_OP_MASS, 1), ("Mw", FEM_OP_WMASS, 1), ("S", FEM_OP_STIFF, 1),
+             ("K", FEM_OP_ELAS, 4))
+    for key, bit, mult in names:
+        if ops & bit:
+            out[key] = _out(pat, out.get(key), mult * pat.nnz, key)
+    if ops & FEM_OP_WMASS:
+        _dev(w, torch.float64, "w", (pat.nq,))
+    ws = C.c_size_t(0)
+    _lib.check(lib.fem_assemble_workspace(pat.nq, int(ops), C.byref(ws)))
+    if work is None and ws.value > 0:
+        work = torch.empty(int(ws.value), dtype=torch.uint8, device=pat.row_ptr.device)
+    t = C.byref(tune) if tune is not None else None
+    _lib.check(lib.fem_assemble(int(ops), pat.nq, pat.nme, pat.nnz, _ptr(_q(pat, q)), _ptr(w),
+                                _ptr(pat.me), *pat.args(), float(lam), float(mu),
+                                _ptr(out.get("M")), _ptr(out.get("Mw")), _ptr(out.get("S")),
+                                _ptr(out.get("K")), _ptr(work),
+                                0 if work is None else work.numel() * work.element_size(), t,
+                                flags, _stream(stream)))
+    return {k: out[k] for k, bit, _ in names if ops & bit}
 
 
 def fem_assemble_mass(pat: Pattern, q, *, out=None, flags: int = 0, stream=None):
@@ -289,7 +321,7 @@ def fem_adjoint_stiff_wmass(pat: Pattern, q, w, GS, GM, *, dq=None, dw=None, fla
     dq = torch.empty((pat.nq, 2), dtype=torch.float64, device=dev) if dq is None else dq
     dw = torch.empty(pat.nq, dtype=torch.float64, device=dev) if dw is None else dw
     ws = C.c_size_t(0)
-    _lib.check(lib.fem_adjoint_workspace(pat.nnz, C.byref(ws)))
+    _lib.check(lib.fem_adjoint_workspace(pat.nq, pat.nnz, C.byref(ws)))
     work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
     _lib.check(lib.fem_adjoint_stiff_wmass(pat.nq, pat.nme, pat.nnz, _ptr(q), _ptr(w),
                                            _ptr(pat.row_ptr), _ptr(pat.col_idx), _ptr(pat.inc_ptr),
@@ -308,7 +340,8 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, q, w, pat):
-            S, M = fem_assemble_stiff_wmass(pat, q.contiguous(), w.contiguous())
+            r = fem_assemble(pat, q.contiguous(), FEM_OP_STIFF | FEM_OP_WMASS, w=w.contiguous())
+            S, M = r["S"], r["Mw"]
             ctx.pat = pat
             ctx.save_for_backward(q, w)
             return S, M

@@ -20,6 +20,11 @@ FEM_DETERMINISTIC = 0
 FEM_ATOMIC = 1
 FEM_ACCUMULATE = 2
 
+FEM_OP_MASS = 1
+FEM_OP_WMASS = 2
+FEM_OP_STIFF = 4
+FEM_OP_ELAS = 8
+
 STATUS_NAMES = {0: "FEM_OK", -1: "FEM_EINVAL", -2: "FEM_ERANGE", -3: "FEM_EDEGEN",
                 -4: "FEM_ENOSPC", -5: "FEM_EOVERFLOW", -6: "FEM_EHIP", -8: "FEM_EUNSUPPORTED"}
 
@@ -31,7 +36,7 @@ class FemError(RuntimeError):
 
 
 class fem_tune(C.Structure):
-    _fields_ = [("lds_entries", C.c_int32), ("grid_blocks", C.c_int32)]
+    _fields_ = [("lds_entries", C.c_int32), ("grid_blocks", C.c_int32), ("variant", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -53,6 +58,10 @@ SIGNATURES = {
                            C.POINTER(_i64), _vp]),
     "fem_transpose_map": (_int, [_i32, _i64, _vp, _vp, _vp, _vp]),
     "fem_elas_pattern": (_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "fem_assemble_workspace": (_int, [_i32, _int, _szp]),
+    "fem_assemble": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl,
+                            _dbl, _vp, _vp, _vp, _vp, _vp, C.c_size_t, C.POINTER(fem_tune), _int,
+                            _vp]),
     "fem_assemble_mass": (_int, _NUM_HEAD + _PAT + [_vp, _int, _vp]),
     "fem_assemble_wmass": (_int, _NUM_HEAD + _PAT + [_vp, _vp, _int, _vp]),
     "fem_assemble_stiff": (_int, _NUM_HEAD + _PAT + [_vp, _int, _vp]),
@@ -66,7 +75,7 @@ SIGNATURES = {
     "fem_graph_end": (_int, [_vp, C.POINTER(_vp)]),
     "fem_graph_launch": (_int, [_vp, _vp]),
     "fem_graph_destroy": (_int, [_vp]),
-    "fem_adjoint_workspace": (_int, [_i64, _szp]),
+    "fem_adjoint_workspace": (_int, [_i32, _i64, _szp]),
     "fem_adjoint_stiff_wmass": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                        _vp, _vp, _vp, _vp, C.c_size_t, _int, _vp]),
 }

@@ -18,6 +18,10 @@ HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep packed-FP32 instructions out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no FMA contraction: every kernel instantiation (operator set, tile size)
+    # rounds the element formulas identically, so fused and single-operator
+    # calls agree bit for bit
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-result",
 ]
 

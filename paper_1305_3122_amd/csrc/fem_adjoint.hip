@@ -79,29 +79,39 @@ __device__ __forceinline__ void adj_tau(double x0, double y0, double x1, double 
     }
 }
 
-// Pass 1.  LDS tile per 64 rows: H accumulators (x, y, w) | qx | qy | w | GS | GM | col.
-template <bool HS, bool HM>
-__global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double *__restrict__ q,
-                                                   const double *__restrict__ w,
+// (x, y, w, 0) records: one random access per column in pass 1.
+__global__ __launch_bounds__(256) void k_adj_pack(int32_t nq, const double2 *__restrict__ q,
+                                                  const double *__restrict__ w,
+                                                  double4 *__restrict__ qw) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= nq) return;
+    const double2 a = q[v];
+    qw[v] = make_double4(a.x, a.y, w ? w[v] : 0.0, 0.0);
+}
+
+// Pass 1: tile of 64 rows (one per lane), staged like the forward kernel.
+// LDS: H accumulators (x, y, w) | q | w | GS | GM | ipos.  H is written as
+// (hx, hy, hw, 0) records so that pass 2 reads one record per entry.
+template <bool HS, bool HM, int U>
+__global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__restrict__ qw,
                                                    const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col_idx,
                                                    const int32_t *__restrict__ inc_ptr,
                                                    const uint32_t *__restrict__ inc_pos,
                                                    const double *__restrict__ GS,
                                                    const double *__restrict__ GM,
-                                                   double *__restrict__ H, int64_t nnz, int eb,
-                                                   int64_t ntiles) {
+                                                   double4 *__restrict__ H, int64_t ntiles) {
+    constexpr int EB = U * WAVE;
     extern __shared__ double smem[];
     double *s_hx = smem;
-    double *s_hy = s_hx + eb;
-    double *s_hw = s_hy + eb;
-    double *s_qx = s_hw + eb;
-    double *s_qy = s_qx + eb;
-    double *s_w = s_qy + eb;
-    double *s_gs = s_w + eb;
-    double *s_gm = s_gs + eb;
-    int32_t *s_col = reinterpret_cast<int32_t *>(s_gm + eb);
-    double *Hx = H, *Hy = H + nnz, *Hw = H + 2 * nnz;
+    double *s_hy = s_hx + EB;
+    double *s_hw = s_hy + EB;
+    double *s_qx = s_hw + EB;
+    double *s_qy = s_qx + EB;
+    double *s_w = s_qy + EB;
+    double *s_gs = s_w + EB;
+    double *s_gm = s_gs + EB;
+    uint32_t *s_ip = reinterpret_cast<uint32_t *>(s_gm + EB);
     const int lane = threadIdx.x;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = tile * WAVE;
@@ -109,34 +119,72 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double *__r
         const int64_t i = r0 + lane;
         const bool active = i < nq;
         const int32_t E0 = row_ptr[r0], E1 = row_ptr[r1], Ew = E1 - E0;
+        const int32_t I0 = inc_ptr[r0], I1 = inc_ptr[r1], Iw = I1 - I0;
         const int32_t rs = active ? row_ptr[i] : 0;
         const int32_t len = active ? row_ptr[i + 1] - rs : 0;
-        if (Ew <= eb) {
-            for (int e = lane; e < Ew; e += WAVE) {
-                const int32_t c = col_idx[E0 + e];
-                s_col[e] = c;
-                const double2 qc = reinterpret_cast<const double2 *>(q)[c];
-                s_qx[e] = qc.x;
-                s_qy[e] = qc.y;
-                s_w[e] = HM ? w[c] : 0.0;
-                s_gs[e] = HS ? GS[E0 + e] : 0.0;
-                s_gm[e] = HM ? GM[E0 + e] : 0.0;
-                s_hx[e] = 0.0;
-                s_hy[e] = 0.0;
-                s_hw[e] = 0.0;
+        const int32_t is = active ? inc_ptr[i] : 0;
+        const int32_t ie = active ? inc_ptr[i + 1] : 0;
+        if (Ew <= EB && Iw <= EB) {
+            int32_t cidx[U];
+            double gsv[U], gmv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                cidx[u] = e < Ew ? __builtin_nontemporal_load(col_idx + E0 + e) : 0;
+                gsv[u] = (HS && e < Ew) ? __builtin_nontemporal_load(GS + E0 + e) : 0.0;
+                gmv[u] = (HM && e < Ew) ? __builtin_nontemporal_load(GM + E0 + e) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = lane + u * WAVE;
+                if (t < Iw) s_ip[t] = __builtin_nontemporal_load(inc_pos + I0 + t);
+            }
+            double4 qv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                qv[u] = e < Ew ? qw[cidx[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                if (e < Ew) {
+                    s_qx[e] = qv[u].x;
+                    s_qy[e] = qv[u].y;
+                    s_w[e] = qv[u].z;
+                    s_gs[e] = gsv[u];
+                    s_gm[e] = gmv[u];
+                    s_hx[e] = 0.0;
+                    s_hy[e] = 0.0;
+                    s_hw[e] = 0.0;
+                }
             }
             __syncthreads();
             if (active && len > 0) {
                 const int32_t off = rs - E0;
-                int32_t pd = 0;
-                while (pd < len - 1 && s_col[off + pd] != (int32_t)i) ++pd;
+                int32_t pd;
+                if (len <= 64) {
+                    uint64_t seen = 0;
+                    for (int32_t t = is - I0; t < ie - I0; ++t) {
+                        const uint32_t pp = s_ip[t];
+                        seen |= (1ull << (pp & 0xffffu)) | (1ull << (pp >> 16));
+                    }
+                    pd = __builtin_ctzll(~seen);
+                } else {
+                    int32_t lo = 0, hi = len;
+                    while (lo < hi) {
+                        const int32_t mid = (lo + hi) >> 1;
+                        if (col_idx[rs + mid] < (int32_t)i) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    pd = lo;
+                }
                 const int32_t d0 = off + pd;
                 const double x0 = s_qx[d0], y0 = s_qy[d0], w0 = s_w[d0];
                 const double g0 = s_gs[d0], h0 = s_gm[d0];
                 double ox = 0.0, oy = 0.0, ow = 0.0;
-                const int32_t t1 = inc_ptr[i + 1];
-                for (int32_t t = inc_ptr[i]; t < t1; ++t) {
-                    const uint32_t pp = inc_pos[t];
+                for (int32_t t = is - I0; t < ie - I0; ++t) {
+                    const uint32_t pp = s_ip[t];
                     const int32_t p1 = off + (int32_t)(pp & 0xffffu);
                     const int32_t p2 = off + (int32_t)(pp >> 16);
                     AdjGrad o;
@@ -157,48 +205,47 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double *__r
                 s_hw[d0] += ow;
             }
             __syncthreads();
-            for (int e = lane; e < Ew; e += WAVE) {
-                Hx[E0 + e] = s_hx[e];
-                Hy[E0 + e] = s_hy[e];
-                Hw[E0 + e] = s_hw[e];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                if (e < Ew) H[E0 + e] = make_double4(s_hx[e], s_hy[e], s_hw[e], 0.0);
             }
             __syncthreads();
         } else if (active && len > 0) {
             // tile too large for LDS: own row in global memory, same order
-            for (int e = 0; e < len; ++e) {
-                Hx[rs + e] = 0.0;
-                Hy[rs + e] = 0.0;
-                Hw[rs + e] = 0.0;
-            }
+            for (int e = 0; e < len; ++e) H[rs + e] = make_double4(0.0, 0.0, 0.0, 0.0);
             const int32_t *cr = col_idx + rs;
             int32_t pd = 0;
             while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
-            const double x0 = q[2 * i], y0 = q[2 * i + 1], w0 = HM ? w[i] : 0.0;
+            const double4 xi = qw[i];
             const double g0 = HS ? GS[rs + pd] : 0.0, h0 = HM ? GM[rs + pd] : 0.0;
             double ox = 0.0, oy = 0.0, ow = 0.0;
-            const int32_t t1 = inc_ptr[i + 1];
-            for (int32_t t = inc_ptr[i]; t < t1; ++t) {
+            for (int32_t t = is; t < ie; ++t) {
                 const uint32_t pp = inc_pos[t];
                 const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
-                const int64_t j1 = cr[p1], j2 = cr[p2];
+                const double4 x1 = qw[cr[p1]], x2 = qw[cr[p2]];
                 AdjGrad o;
-                adj_tau<HS, HM>(x0, y0, q[2 * j1], q[2 * j1 + 1], q[2 * j2], q[2 * j2 + 1], w0,
-                                HM ? w[j1] : 0.0, HM ? w[j2] : 0.0, g0, HS ? GS[rs + p1] : 0.0,
-                                HS ? GS[rs + p2] : 0.0, h0, HM ? GM[rs + p1] : 0.0,
-                                HM ? GM[rs + p2] : 0.0, o);
+                adj_tau<HS, HM>(xi.x, xi.y, x1.x, x1.y, x2.x, x2.y, xi.z, x1.z, x2.z, g0,
+                                HS ? GS[rs + p1] : 0.0, HS ? GS[rs + p2] : 0.0, h0,
+                                HM ? GM[rs + p1] : 0.0, HM ? GM[rs + p2] : 0.0, o);
                 ox += o.gx[0];
                 oy += o.gy[0];
                 ow += o.gw[0];
-                Hx[rs + p1] += o.gx[1];
-                Hy[rs + p1] += o.gy[1];
-                Hw[rs + p1] += o.gw[1];
-                Hx[rs + p2] += o.gx[2];
-                Hy[rs + p2] += o.gy[2];
-                Hw[rs + p2] += o.gw[2];
+                double4 h1 = H[rs + p1], h2 = H[rs + p2];
+                h1.x += o.gx[1];
+                h1.y += o.gy[1];
+                h1.z += o.gw[1];
+                H[rs + p1] = h1;
+                h2.x += o.gx[2];
+                h2.y += o.gy[2];
+                h2.z += o.gw[2];
+                H[rs + p2] = h2;
             }
-            Hx[rs + pd] += ox;
-            Hy[rs + pd] += oy;
-            Hw[rs + pd] += ow;
+            double4 hd = H[rs + pd];
+            hd.x += ox;
+            hd.y += oy;
+            hd.z += ow;
+            H[rs + pd] = hd;
         }
     }
 }
@@ -218,12 +265,11 @@ __device__ inline int32_t find_in_row(const int32_t *__restrict__ col_idx, int32
 __global__ __launch_bounds__(256) void k_adj_cols(int32_t nq, const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col_idx,
                                                   const int32_t *__restrict__ tpos,
-                                                  const double *__restrict__ H, int64_t nnz,
+                                                  const double4 *__restrict__ H,
                                                   double *__restrict__ dq, double *__restrict__ dw,
                                                   int accumulate) {
     const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (u >= nq) return;
-    const double *Hx = H, *Hy = H + nnz, *Hw = H + 2 * nnz;
     double gx = 0.0, gy = 0.0, gw = 0.0;
     const int32_t rs = row_ptr[u], re = row_ptr[u + 1];
     for (int32_t p = rs; p < re; ++p) {
@@ -237,9 +283,10 @@ __global__ __launch_bounds__(256) void k_adj_cols(int32_t nq, const int32_t *__r
             if (t >= re_v || col_idx[t] != (int32_t)u) t = -1;
         }
         if (t < 0) continue;   // no transposed entry (never for a P1 pattern)
-        gx += Hx[t];
-        gy += Hy[t];
-        gw += Hw[t];
+        const double4 h = H[t];
+        gx += h.x;
+        gy += h.y;
+        gw += h.z;
     }
     if (accumulate) {
         dq[2 * u] += gx;
@@ -253,29 +300,31 @@ __global__ __launch_bounds__(256) void k_adj_cols(int32_t nq, const int32_t *__r
 }
 
 namespace {
-constexpr int ADJ_EB = 512;
+constexpr int ADJ_U = 8;
 
 template <bool HS, bool HM>
-int launch_adj(int32_t nq, const double *q, const double *w, const int32_t *row_ptr,
-               const int32_t *col_idx, const int32_t *inc_ptr, const uint32_t *inc_pos,
-               const double *GS, const double *GM, double *H, int64_t nnz, hipStream_t s) {
+int launch_adj(int32_t nq, const double4 *qw, const int32_t *row_ptr, const int32_t *col_idx,
+               const int32_t *inc_ptr, const uint32_t *inc_pos, const double *GS, const double *GM,
+               double4 *H, hipStream_t s) {
     const int64_t ntiles = (nq + WAVE - 1) / WAVE;
-    const size_t lds = (size_t)ADJ_EB * (8 * 8 + 4);
-    hipLaunchKernelGGL((k_adj_rows<HS, HM>), dim3((unsigned)ntiles), dim3(WAVE), lds, s, nq, q, w,
-                       row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, nnz, ADJ_EB, ntiles);
+    const size_t lds = (size_t)ADJ_U * WAVE * (8 * 8 + 4);
+    hipLaunchKernelGGL((k_adj_rows<HS, HM, ADJ_U>), dim3((unsigned)ntiles), dim3(WAVE), lds, s, nq,
+                       qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, ntiles);
     FEM_LAUNCH_CHECK();
     return FEM_OK;
 }
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 }  // namespace
 
 }  // namespace fem
 
 using namespace fem;
 
-extern "C" int fem_adjoint_workspace(int64_t nnz, size_t *bytes) {
+extern "C" int fem_adjoint_workspace(int32_t nq, int64_t nnz, size_t *bytes) {
     clear_error();
-    FEM_REQUIRE(bytes && nnz >= 0, FEM_EINVAL, "fem_adjoint_workspace: bad arguments");
-    *bytes = (size_t)(3 * nnz > 0 ? 3 * nnz : 1) * sizeof(double);
+    FEM_REQUIRE(bytes && nq >= 1 && nnz >= 0, FEM_EINVAL, "fem_adjoint_workspace: bad arguments");
+    *bytes = align256(sizeof(double4) * (size_t)nq) + sizeof(double4) * (size_t)(nnz > 0 ? nnz : 1);
     return FEM_OK;
 }
 
@@ -295,19 +344,23 @@ extern "C" int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, con
                 "fem_adjoint_stiff_wmass: NULL pattern array");
     FEM_REQUIRE(!GM || (w && dw), FEM_EINVAL, "fem_adjoint_stiff_wmass: the GM term needs w and dw");
     size_t need = 0;
-    fem_adjoint_workspace(nnz, &need);
+    fem_adjoint_workspace(nq, nnz, &need);
     FEM_REQUIRE(work_bytes >= need, FEM_ENOSPC, "fem_adjoint_stiff_wmass: workspace %zu < %zu",
                 work_bytes, need);
     hipStream_t s = as_stream(stream);
-    double *H = static_cast<double *>(work);
+    double4 *qw = static_cast<double4 *>(work);
+    double4 *H = reinterpret_cast<double4 *>(static_cast<char *>(work) + align256(sizeof(double4) * (size_t)nq));
+    hipLaunchKernelGGL(k_adj_pack, dim3(grid_for(nq, 256)), dim3(256), 0, s, nq,
+                       reinterpret_cast<const double2 *>(q), GM ? w : nullptr, qw);
+    FEM_LAUNCH_CHECK();
     int st;
-    if (GS && GM) st = launch_adj<true, true>(nq, q, w, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, nnz, s);
-    else if (GS) st = launch_adj<true, false>(nq, q, w, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, nnz, s);
-    else if (GM) st = launch_adj<false, true>(nq, q, w, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, nnz, s);
-    else st = fill_f64(H, 3 * nnz, 0.0, s);
+    if (GS && GM) st = launch_adj<true, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, s);
+    else if (GS) st = launch_adj<true, false>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, s);
+    else if (GM) st = launch_adj<false, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, s);
+    else st = fill_f64(reinterpret_cast<double *>(H), 4 * nnz, 0.0, s);
     if (st) return st;
     hipLaunchKernelGGL(k_adj_cols, dim3(grid_for(nq, 256)), dim3(256), 0, s, nq, row_ptr, col_idx,
-                       tpos, H, nnz, dq, dw, (flags & FEM_ACCUMULATE) ? 1 : 0);
+                       tpos, H, dq, dw, (flags & FEM_ACCUMULATE) ? 1 : 0);
     FEM_LAUNCH_CHECK();
     return FEM_OK;
 }

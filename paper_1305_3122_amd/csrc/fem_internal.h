@@ -57,6 +57,8 @@ struct PatternCounters {
     int wide_count;       // vertices routed to the workgroup-per-row path
     int max_row_len;      // longest CSR row
     int max_inc;          // most triangles around one vertex
+    int mid_count;        // vertices routed to the per-lane LDS path
+    int pad_;
     long long total[4];   // totals written by the scans
 };
 

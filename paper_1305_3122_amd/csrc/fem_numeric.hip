@@ -1,14 +1,17 @@
 // fem_numeric.hip -- numeric phase: element matrices and their summation
 // into the CSR values.
 //
-// Element formulas (FP64, no MFMA: the work is a gather/scatter bound by HBM,
-// not a dense contraction):
+// Element formulas (FP64, no MFMA: the work is a gather/scatter bound by
+// memory, not a dense contraction):
 //   |T| = |det| / 2, det = (q2-q1) x (q3-q1)
 //   mass (eq. MassElem)            |T|/12 [2 1 1; 1 2 1; 1 1 2]
 //   weighted mass (eq. MassWElem)  |T|/30 (3w_a + w_b + w_c) on the diagonal,
 //                                  |T|/30 (w_a + w_b + w_c/2) off it (c third)
 //   stiffness (eq. StiffMatElem)   <r_a, r_b> / (4|T|), r = (q2-q3, q3-q1, q1-q2)
-//   elasticity                     |T| B^T C B, gradients r_a^perp / det
+//   elasticity                     |T| B^T C B, gradients perp(r_a) / det
+// Any subset of the four operators is assembled in one pass (`ops` mask), so
+// that the gathers of q and w -- the dominant cost on a relabelled mesh,
+// where every gather is a random access -- are shared.
 //
 // Two summation schemes:
 //
@@ -16,76 +19,72 @@
 //   and walks the triangles around i (inc_ptr / inc_pos), computing the row of
 //   each element matrix that belongs to i and adding it into the row's
 //   entries.  A wave owns 64 consecutive rows, whose entries are contiguous in
-//   col_idx/values: it stages that slice in LDS (columns, gathered vertex
-//   coordinates, accumulators), so every read of the pattern and every write
-//   of values is coalesced and written exactly once; the only random
-//   accesses are the gathers of q (and w) by column.  Each element is
-//   evaluated once per vertex (three times), which costs flops, not bytes.
-//   Every value is summed by one lane in ascending triangle order, so results
-//   are bitwise reproducible.
-// FEM_ATOMIC -- one lane per triangle computes the full element matrix and
-//   adds it through the slot map with FP64 atomics (global_atomic_add_f64).
+//   col_idx/values: it stages that slice in LDS (gathered vertex coordinates,
+//   accumulators), so every read of the pattern and every write of values is
+//   coalesced and written exactly once; the only random accesses are the
+//   gathers of q (and w) by column.  Each element is evaluated once per
+//   vertex (three times), which costs flops, not bytes.  Every value is summed
+//   by one lane in ascending triangle order: bitwise reproducible.
+// FEM_ATOMIC -- one lane per triangle computes the full element matrices and
+//   adds them through the slot map with FP64 atomics (global_atomic_add_f64).
 #include "fem_internal.h"
 
 namespace fem {
 
-enum Op : int { OP_MASS = 0, OP_WMASS, OP_STIFF, OP_STIFF_MASS, OP_STIFF_WMASS, OP_ELAS };
+// operator bits (same values as FEM_OP_* of the C ABI)
+enum : int { M_BIT = 1, W_BIT = 2, S_BIT = 4, K_BIT = 8 };
 
-template <int OP> struct OpInfo;
-template <> struct OpInfo<OP_MASS> { static constexpr int NACC = 1, NOUT = 1; static constexpr bool W = false; };
-template <> struct OpInfo<OP_WMASS> { static constexpr int NACC = 1, NOUT = 1; static constexpr bool W = true; };
-template <> struct OpInfo<OP_STIFF> { static constexpr int NACC = 1, NOUT = 1; static constexpr bool W = false; };
-template <> struct OpInfo<OP_STIFF_MASS> { static constexpr int NACC = 2, NOUT = 2; static constexpr bool W = false; };
-template <> struct OpInfo<OP_STIFF_WMASS> { static constexpr int NACC = 2, NOUT = 2; static constexpr bool W = true; };
-template <> struct OpInfo<OP_ELAS> { static constexpr int NACC = 4, NOUT = 1; static constexpr bool W = false; };
+template <int MASK> struct Ops {
+    static constexpr bool M = (MASK & M_BIT) != 0, W = (MASK & W_BIT) != 0;
+    static constexpr bool S = (MASK & S_BIT) != 0, K = (MASK & K_BIT) != 0;
+    static constexpr int NS = (M ? 1 : 0) + (W ? 1 : 0) + (S ? 1 : 0);   // scalar accumulators
+    static constexpr int IM = 0, IW = M ? 1 : 0, IS = (M ? 1 : 0) + (W ? 1 : 0);
+};
 
 struct Lame {
     double lam, mu;
 };
 
 // Row of the element matrices that belongs to vertex 0 of the triangle
-// (x0, x1, x2), where (0, 1, 2) is a cyclic rotation of the triangle's own
-// vertex order (so orientation and the edge vectors r are those of the
-// paper's formulas).  c[0] is the diagonal term, c[1] / c[2] the terms of
-// columns x1 / x2.  For elasticity c holds the three 2x2 blocks, row-major.
-template <int OP>
+// (x0, x1, x2), a cyclic rotation of the triangle's own vertex order (so the
+// orientation and the edge vectors r are those of the paper's formulas).
+// c[m][0] diagonal term of scalar operator m, c[m][1] / c[m][2] the terms of
+// columns x1 / x2; ce[b] the 2x2 elasticity block (row-major) of column b.
+template <int MASK>
 __device__ __forceinline__ void elem_row(double x0, double y0, double x1, double y1, double x2,
                                          double y2, double w0, double w1, double w2, Lame L,
-                                         double (&c)[OpInfo<OP>::NACC][3],
+                                         double (&c)[Ops<MASK>::NS > 0 ? Ops<MASK>::NS : 1][3],
                                          double (&ce)[3][4]) {
+    using O = Ops<MASK>;
     const double e1x = x1 - x0, e1y = y1 - y0;
     const double e2x = x2 - x0, e2y = y2 - y0;
     const double det = e1x * e2y - e2x * e1y;
     const double ad = fabs(det);
     const double area = 0.5 * ad;
-    if constexpr (OP == OP_STIFF || OP == OP_STIFF_MASS || OP == OP_STIFF_WMASS) {
+    if constexpr (O::S) {
         // r0 = x1 - x2, r1 = x2 - x0, r2 = x0 - x1;  S_0b = <r0, rb> / (2 |det|)
         const double r0x = x1 - x2, r0y = y1 - y2;
         const double inv = 1.0 / (2.0 * ad);
-        c[0][0] = (r0x * r0x + r0y * r0y) * inv;
-        c[0][1] = (r0x * e2x + r0y * e2y) * inv;
-        c[0][2] = -(r0x * e1x + r0y * e1y) * inv;
+        c[O::IS][0] = (r0x * r0x + r0y * r0y) * inv;
+        c[O::IS][1] = (r0x * e2x + r0y * e2y) * inv;
+        c[O::IS][2] = -(r0x * e1x + r0y * e1y) * inv;
     }
-    if constexpr (OP == OP_MASS || OP == OP_STIFF_MASS) {
-        constexpr int m = (OP == OP_MASS) ? 0 : 1;
-        c[m][0] = area / 6.0;
-        c[m][1] = area / 12.0;
-        c[m][2] = area / 12.0;
+    if constexpr (O::M) {
+        c[O::IM][0] = area / 6.0;
+        c[O::IM][1] = area / 12.0;
+        c[O::IM][2] = area / 12.0;
     }
-    if constexpr (OP == OP_WMASS || OP == OP_STIFF_WMASS) {
-        constexpr int m = (OP == OP_WMASS) ? 0 : 1;
+    if constexpr (O::W) {
         const double a30 = area / 30.0;
-        c[m][0] = a30 * (3.0 * w0 + w1 + w2);
-        c[m][1] = a30 * (w0 + w1 + 0.5 * w2);
-        c[m][2] = a30 * (w0 + 0.5 * w1 + w2);
+        c[O::IW][0] = a30 * (3.0 * w0 + w1 + w2);
+        c[O::IW][1] = a30 * (w0 + w1 + 0.5 * w2);
+        c[O::IW][2] = a30 * (w0 + 0.5 * w1 + w2);
     }
-    if constexpr (OP == OP_ELAS) {
-        // gradients of the barycentric functions: perp(r_a) / det
+    if constexpr (O::K) {
         const double id = 1.0 / det;
         const double g0x = (y1 - y2) * id, g0y = -(x1 - x2) * id;
-        const double g1x = e2y * id, g1y = -e2x * id;
-        const double g2x = -e1y * id, g2y = e1x * id;
-        const double gx[3] = {g0x, g1x, g2x}, gy[3] = {g0y, g1y, g2y};
+        const double gx[3] = {g0x, e2y * id, -e1y * id};
+        const double gy[3] = {g0y, -e2x * id, e1x * id};
         const double l2m = L.lam + 2.0 * L.mu;
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
@@ -97,187 +96,533 @@ __device__ __forceinline__ void elem_row(double x0, double y0, double x1, double
     }
 }
 
-// ------------------------------------------------------------------ row owner
+struct Outs {
+    double *o[4];   // M, Mw, S, K (K in the 2x2 block layout of fem_elas_pattern)
+};
 
-template <int OP>
+// (x, y, w, 0) records, so that a vertex costs one random access.
+__global__ __launch_bounds__(256) void k_pack_qw(int32_t nq, const double2 *__restrict__ q,
+                                                 const double *__restrict__ w,
+                                                 double4 *__restrict__ qw) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= nq) return;
+    const double2 a = q[v];
+    qw[v] = make_double4(a.x, a.y, w ? w[v] : 0.0, 0.0);
+}
+
+// ------------------------------------------------------------------ row owner
+//
+// Tile = 64 consecutive rows (one per lane) = a contiguous slice of col_idx /
+// values and of inc_pos.  Staged in three rounds of independent loads, each
+// issued in full before anything waits on it:
+//   A  row_ptr / inc_ptr bounds of the lane's row and of the tile
+//   B  the tile's columns (registers) and triangle positions (LDS), streaming
+//   C  the gathers of q (and w) by column
+// then every lane sums its row from LDS and the tile is written back
+// coalesced.  U = LDS entries per tile / 64.  The diagonal position of a row
+// is the one position no triangle refers to (p1, p2 are always neighbours).
+
+template <int MASK, int U>
 __global__ __launch_bounds__(WAVE) void k_rows_numeric(
     int32_t nq, const double *__restrict__ q, const double *__restrict__ w,
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
-    const int32_t *__restrict__ inc_ptr, const uint32_t *__restrict__ inc_pos,
-    double *__restrict__ out0, double *__restrict__ out1, Lame L, int eb, int accumulate,
-    int64_t ntiles) {
-    using I = OpInfo<OP>;
-    constexpr int NACC = I::NACC;
+    const double4 *__restrict__ qw, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ col_idx, const int32_t *__restrict__ inc_ptr,
+    const uint32_t *__restrict__ inc_pos, Outs out, Lame L, int accumulate, int64_t ntiles) {
+    using O = Ops<MASK>;
+    constexpr int NS = O::NS;
+    constexpr int NSA = NS > 0 ? NS : 1;
+    constexpr int EB = U * WAVE;
+    // LDS tile: scalar acc [NS EB] | K acc [4 EB] | q [EB] (double2) | w [EB] | ipos [EB]
     extern __shared__ double smem[];
-    // LDS tile: acc[NACC * eb] | qx[eb] | qy[eb] | (w[eb]) | col[eb] (int32)
     double *s_acc = smem;
-    double *s_qx = s_acc + (size_t)NACC * eb;
-    double *s_qy = s_qx + eb;
-    double *s_w = s_qy + eb;
-    int32_t *s_col = reinterpret_cast<int32_t *>(s_w + (I::W ? eb : 0));
+    double *s_k = s_acc + (size_t)NS * EB;
+    double2 *s_q = reinterpret_cast<double2 *>(s_k + (O::K ? 4 * EB : 0));
+    double *s_w = reinterpret_cast<double *>(s_q + EB);
+    uint32_t *s_ip = reinterpret_cast<uint32_t *>(s_w + (O::W ? EB : 0));
     const int lane = threadIdx.x;
+    const double2 *q2 = reinterpret_cast<const double2 *>(q);
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        // ---- round A
         const int64_t r0 = tile * WAVE;
         const int64_t r1 = (r0 + WAVE < nq) ? r0 + WAVE : nq;
         const int64_t i = r0 + lane;
         const bool active = i < nq;
-        const int32_t E0 = row_ptr[r0];
-        const int32_t E1 = row_ptr[r1];
-        const int32_t Ew = E1 - E0;
+        const int32_t E0 = row_ptr[r0], E1 = row_ptr[r1];
+        const int32_t I0 = inc_ptr[r0], I1 = inc_ptr[r1];
         const int32_t rs = active ? row_ptr[i] : 0;
         const int32_t re = active ? row_ptr[i + 1] : 0;
-        const int32_t len = re - rs;
+        const int32_t is = active ? inc_ptr[i] : 0;
+        const int32_t ie = active ? inc_ptr[i + 1] : 0;
+        const int32_t Ew = E1 - E0, Iw = I1 - I0, len = re - rs;
 
-        if (Ew <= eb) {
-            // ---- stage the tile: columns, gathered coordinates, zeroed accumulators
-            for (int e = lane; e < Ew; e += WAVE) {
-                const int32_t cidx = col_idx[E0 + e];
-                s_col[e] = cidx;
-                const double2 qc = reinterpret_cast<const double2 *>(q)[cidx];
-                s_qx[e] = qc.x;
-                s_qy[e] = qc.y;
-                if constexpr (I::W) s_w[e] = w[cidx];
-            }
-            if constexpr (OP == OP_ELAS) {
-                for (int e = lane; e < 4 * Ew; e += WAVE) s_acc[e] = 0.0;
-            } else {
+        if (Ew <= EB && Iw <= EB) {
+            // ---- round B
+            int32_t cidx[U];
 #pragma unroll
-                for (int m = 0; m < NACC; ++m)
-                    for (int e = lane; e < Ew; e += WAVE) s_acc[m * eb + e] = 0.0;
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                cidx[u] = e < Ew ? __builtin_nontemporal_load(col_idx + E0 + e) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = lane + u * WAVE;
+                if (t < Iw) s_ip[t] = __builtin_nontemporal_load(inc_pos + I0 + t);
+            }
+            // ---- round C: one random access per column (packed records if given)
+            double2 qv[U];
+            double wv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                wv[u] = 0.0;
+                if (e < Ew) {
+                    if (O::W && qw) {
+                        const double4 r = qw[cidx[u]];
+                        qv[u] = make_double2(r.x, r.y);
+                        wv[u] = r.z;
+                    } else {
+                        qv[u] = q2[cidx[u]];
+                        if constexpr (O::W) wv[u] = w[cidx[u]];
+                    }
+                } else {
+                    qv[u] = make_double2(0.0, 0.0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                if (e < Ew) {
+                    s_q[e] = qv[u];
+                    if constexpr (O::W) s_w[e] = wv[u];
+#pragma unroll
+                    for (int m = 0; m < NS; ++m) s_acc[m * EB + e] = 0.0;
+                }
+            }
+            if constexpr (O::K) {
+#pragma unroll
+                for (int u = 0; u < 4 * U; ++u) {
+                    const int e = lane + u * WAVE;
+                    if (e < 4 * Ew) s_k[e] = 0.0;
+                }
             }
             __syncthreads();
             // ---- each lane: the triangles around its vertex, ascending id
             if (active && len > 0) {
                 const int32_t off = rs - E0;
-                int32_t pd = 0;
-                while (pd < len - 1 && s_col[off + pd] != (int32_t)i) ++pd;
-                const double x0 = s_qx[off + pd], y0 = s_qy[off + pd];
-                const double w0 = I::W ? s_w[off + pd] : 0.0;
-                double dg[NACC];
+                int32_t pd;
+                if (len <= 64) {
+                    uint64_t seen = 0;
+                    for (int32_t t = is - I0; t < ie - I0; ++t) {
+                        const uint32_t pp = s_ip[t];
+                        seen |= (1ull << (pp & 0xffffu)) | (1ull << (pp >> 16));
+                    }
+                    pd = __builtin_ctzll(~seen);
+                } else {
+                    int32_t lo = 0, hi = len;
+                    while (lo < hi) {
+                        const int32_t mid = (lo + hi) >> 1;
+                        if (col_idx[rs + mid] < (int32_t)i) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    pd = lo;
+                }
+                const double2 x0 = s_q[off + pd];
+                const double w0 = O::W ? s_w[off + pd] : 0.0;
+                double dg[NSA], dk[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int m = 0; m < NACC; ++m) dg[m] = 0.0;
-                const int32_t t1 = inc_ptr[i + 1];
-                for (int32_t t = inc_ptr[i]; t < t1; ++t) {
-                    const uint32_t pp = inc_pos[t];
-                    const int32_t p1 = off + (int32_t)(pp & 0xffffu);
-                    const int32_t p2 = off + (int32_t)(pp >> 16);
-                    double c[NACC][3];
+                for (int m = 0; m < NSA; ++m) dg[m] = 0.0;
+                for (int32_t t = is - I0; t < ie - I0; ++t) {
+                    const uint32_t pp = s_ip[t];
+                    const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
+                    const double2 x1 = s_q[off + p1], x2 = s_q[off + p2];
+                    double c[NSA][3];
                     double ce[3][4];
-                    elem_row<OP>(x0, y0, s_qx[p1], s_qy[p1], s_qx[p2], s_qy[p2], w0,
-                                 I::W ? s_w[p1] : 0.0, I::W ? s_w[p2] : 0.0, L, c, ce);
-                    if constexpr (OP == OP_ELAS) {
-                        // row 2i: [off*4 + 2p + beta], row 2i+1: [+ 2 len]
-                        const int32_t b0 = 4 * off;
-                        const int32_t q1 = p1 - off, q2 = p2 - off;
-                        dg[0] += ce[0][0];
-                        dg[1] += ce[0][1];
-                        dg[2] += ce[0][2];
-                        dg[3] += ce[0][3];
-                        s_acc[b0 + 2 * q1] += ce[1][0];
-                        s_acc[b0 + 2 * q1 + 1] += ce[1][1];
-                        s_acc[b0 + 2 * len + 2 * q1] += ce[1][2];
-                        s_acc[b0 + 2 * len + 2 * q1 + 1] += ce[1][3];
-                        s_acc[b0 + 2 * q2] += ce[2][0];
-                        s_acc[b0 + 2 * q2 + 1] += ce[2][1];
-                        s_acc[b0 + 2 * len + 2 * q2] += ce[2][2];
-                        s_acc[b0 + 2 * len + 2 * q2 + 1] += ce[2][3];
-                    } else {
+                    elem_row<MASK>(x0.x, x0.y, x1.x, x1.y, x2.x, x2.y, w0,
+                                   O::W ? s_w[off + p1] : 0.0, O::W ? s_w[off + p2] : 0.0, L, c, ce);
 #pragma unroll
-                        for (int m = 0; m < NACC; ++m) {
-                            dg[m] += c[m][0];
-                            s_acc[m * eb + p1] += c[m][1];
-                            s_acc[m * eb + p2] += c[m][2];
-                        }
+                    for (int m = 0; m < NS; ++m) {
+                        dg[m] += c[m][0];
+                        s_acc[m * EB + off + p1] += c[m][1];
+                        s_acc[m * EB + off + p2] += c[m][2];
+                    }
+                    if constexpr (O::K) {
+                        // row 2i: [4 off + 2p + beta], row 2i+1: [+ 2 len]
+                        const int32_t b0 = 4 * off;
+#pragma unroll
+                        for (int z = 0; z < 4; ++z) dk[z] += ce[0][z];
+                        s_k[b0 + 2 * p1] += ce[1][0];
+                        s_k[b0 + 2 * p1 + 1] += ce[1][1];
+                        s_k[b0 + 2 * len + 2 * p1] += ce[1][2];
+                        s_k[b0 + 2 * len + 2 * p1 + 1] += ce[1][3];
+                        s_k[b0 + 2 * p2] += ce[2][0];
+                        s_k[b0 + 2 * p2 + 1] += ce[2][1];
+                        s_k[b0 + 2 * len + 2 * p2] += ce[2][2];
+                        s_k[b0 + 2 * len + 2 * p2 + 1] += ce[2][3];
                     }
                 }
-                if constexpr (OP == OP_ELAS) {
-                    const int32_t b0 = 4 * off;
-                    s_acc[b0 + 2 * pd] += dg[0];
-                    s_acc[b0 + 2 * pd + 1] += dg[1];
-                    s_acc[b0 + 2 * len + 2 * pd] += dg[2];
-                    s_acc[b0 + 2 * len + 2 * pd + 1] += dg[3];
-                } else {
 #pragma unroll
-                    for (int m = 0; m < NACC; ++m) s_acc[m * eb + off + pd] += dg[m];
+                for (int m = 0; m < NS; ++m) s_acc[m * EB + off + pd] += dg[m];
+                if constexpr (O::K) {
+                    const int32_t b0 = 4 * off;
+                    s_k[b0 + 2 * pd] += dk[0];
+                    s_k[b0 + 2 * pd + 1] += dk[1];
+                    s_k[b0 + 2 * len + 2 * pd] += dk[2];
+                    s_k[b0 + 2 * len + 2 * pd + 1] += dk[3];
                 }
             }
             __syncthreads();
-            // ---- write the tile back, coalesced
-            if constexpr (OP == OP_ELAS) {
-                for (int e = lane; e < 4 * Ew; e += WAVE) {
-                    const int64_t g = 4 * (int64_t)E0 + e;
-                    out0[g] = accumulate ? out0[g] + s_acc[e] : s_acc[e];
+            // ---- write the tile back, coalesced (no read unless accumulating)
+            if (!accumulate) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = lane + u * WAVE;
+                    if (e < Ew) {
+#pragma unroll
+                        for (int m = 0; m < NS; ++m)
+                            __builtin_nontemporal_store(s_acc[m * EB + e], out.o[m] + E0 + e);
+                    }
+                }
+                if constexpr (O::K) {
+                    double *ok = out.o[3] + 4 * (int64_t)E0;
+#pragma unroll
+                    for (int u = 0; u < 4 * U; ++u) {
+                        const int e = lane + u * WAVE;
+                        if (e < 4 * Ew) __builtin_nontemporal_store(s_k[e], ok + e);
+                    }
                 }
             } else {
                 for (int e = lane; e < Ew; e += WAVE) {
-                    out0[E0 + e] = accumulate ? out0[E0 + e] + s_acc[e] : s_acc[e];
-                    if constexpr (I::NOUT == 2)
-                        out1[E0 + e] = accumulate ? out1[E0 + e] + s_acc[eb + e] : s_acc[eb + e];
+#pragma unroll
+                    for (int m = 0; m < NS; ++m) out.o[m][E0 + e] += s_acc[m * EB + e];
+                }
+                if constexpr (O::K) {
+                    double *ok = out.o[3] + 4 * (int64_t)E0;
+                    for (int e = lane; e < 4 * Ew; e += WAVE) ok[e] += s_k[e];
                 }
             }
             __syncthreads();
         } else if (active && len > 0) {
             // ---- tile too large for LDS: the lane works on its own row in
             // global memory (same order of additions, so same results)
-            const int32_t nrow = (OP == OP_ELAS) ? 4 * len : len;
-            double *o0 = out0 + ((OP == OP_ELAS) ? 4 * (int64_t)rs : (int64_t)rs);
-            double *o1 = (I::NOUT == 2) ? out1 + rs : nullptr;
+            double *os[NSA];
+#pragma unroll
+            for (int m = 0; m < NSA; ++m) os[m] = m < NS ? out.o[m] + rs : nullptr;
+            double *ok = O::K ? out.o[3] + 4 * (int64_t)rs : nullptr;
             if (!accumulate) {
-                for (int e = 0; e < nrow; ++e) o0[e] = 0.0;
-                if constexpr (I::NOUT == 2)
-                    for (int e = 0; e < len; ++e) o1[e] = 0.0;
+                for (int e = 0; e < len; ++e) {
+#pragma unroll
+                    for (int m = 0; m < NS; ++m) os[m][e] = 0.0;
+                }
+                if constexpr (O::K)
+                    for (int e = 0; e < 4 * len; ++e) ok[e] = 0.0;
             }
             const int32_t *cr = col_idx + rs;
             int32_t pd = 0;
             while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
             const double x0 = q[2 * i], y0 = q[2 * i + 1];
-            const double w0 = I::W ? w[i] : 0.0;
-            double dg[NACC];
+            const double w0 = O::W ? w[i] : 0.0;
+            double dg[NSA], dk[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int m = 0; m < NACC; ++m) dg[m] = 0.0;
-            const int32_t t1 = inc_ptr[i + 1];
-            for (int32_t t = inc_ptr[i]; t < t1; ++t) {
+            for (int m = 0; m < NSA; ++m) dg[m] = 0.0;
+            for (int32_t t = is; t < ie; ++t) {
                 const uint32_t pp = inc_pos[t];
                 const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
-                const int32_t j1 = cr[p1], j2 = cr[p2];
-                double c[NACC][3];
+                const int64_t j1 = cr[p1], j2 = cr[p2];
+                double c[NSA][3];
                 double ce[3][4];
-                elem_row<OP>(x0, y0, q[2 * (int64_t)j1], q[2 * (int64_t)j1 + 1], q[2 * (int64_t)j2],
-                             q[2 * (int64_t)j2 + 1], w0, I::W ? w[j1] : 0.0, I::W ? w[j2] : 0.0, L,
-                             c, ce);
-                if constexpr (OP == OP_ELAS) {
-                    dg[0] += ce[0][0];
-                    dg[1] += ce[0][1];
-                    dg[2] += ce[0][2];
-                    dg[3] += ce[0][3];
-                    o0[2 * p1] += ce[1][0];
-                    o0[2 * p1 + 1] += ce[1][1];
-                    o0[2 * len + 2 * p1] += ce[1][2];
-                    o0[2 * len + 2 * p1 + 1] += ce[1][3];
-                    o0[2 * p2] += ce[2][0];
-                    o0[2 * p2 + 1] += ce[2][1];
-                    o0[2 * len + 2 * p2] += ce[2][2];
-                    o0[2 * len + 2 * p2 + 1] += ce[2][3];
+                elem_row<MASK>(x0, y0, q[2 * j1], q[2 * j1 + 1], q[2 * j2], q[2 * j2 + 1], w0,
+                               O::W ? w[j1] : 0.0, O::W ? w[j2] : 0.0, L, c, ce);
+#pragma unroll
+                for (int m = 0; m < NS; ++m) {
+                    dg[m] += c[m][0];
+                    os[m][p1] += c[m][1];
+                    os[m][p2] += c[m][2];
+                }
+                if constexpr (O::K) {
+#pragma unroll
+                    for (int z = 0; z < 4; ++z) dk[z] += ce[0][z];
+                    ok[2 * p1] += ce[1][0];
+                    ok[2 * p1 + 1] += ce[1][1];
+                    ok[2 * len + 2 * p1] += ce[1][2];
+                    ok[2 * len + 2 * p1 + 1] += ce[1][3];
+                    ok[2 * p2] += ce[2][0];
+                    ok[2 * p2 + 1] += ce[2][1];
+                    ok[2 * len + 2 * p2] += ce[2][2];
+                    ok[2 * len + 2 * p2 + 1] += ce[2][3];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < NS; ++m) os[m][pd] += dg[m];
+            if constexpr (O::K) {
+                ok[2 * pd] += dk[0];
+                ok[2 * pd + 1] += dk[1];
+                ok[2 * len + 2 * pd] += dk[2];
+                ok[2 * len + 2 * pd + 1] += dk[3];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ row owner, registers
+//
+// Same tiling and load rounds as above, but each lane keeps the accumulators
+// of its row in registers (rows of at most LMAX entries: a static slot loop
+// adds each triangle's terms into slots p1 / p2), so LDS only stages the
+// gathered coordinates and the triangle positions, and is then reused to
+// transpose the accumulators for coalesced stores.  Far more waves fit per CU
+// than with LDS accumulators.  Lanes whose row is longer than LMAX take the
+// per-lane global-memory path; the order of additions is the same everywhere.
+
+template <int MASK, int U, int LMAX>
+__global__ __launch_bounds__(WAVE) void k_rows_reg(
+    int32_t nq, const double *__restrict__ q, const double *__restrict__ w,
+    const double4 *__restrict__ qw, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ col_idx, const int32_t *__restrict__ inc_ptr,
+    const uint32_t *__restrict__ inc_pos, Outs out, Lame L, int accumulate, int64_t ntiles) {
+    using O = Ops<MASK>;
+    constexpr int NS = O::NS;
+    constexpr int NSA = NS > 0 ? NS : 1;
+    constexpr int NV = NS + (O::K ? 4 : 0);      // accumulators per entry
+    constexpr int EB = U * WAVE;
+    // LDS: stage [EB] (24 or 32 B per entry: q (16) + w (8), reused to
+    // transpose the outputs, 4 doubles per entry when K is requested) | ipos
+    constexpr int SD = O::K ? 4 : (O::W ? 3 : 2); // doubles per entry in the stage
+    extern __shared__ double smem[];
+    double *s_stage = smem;
+    double2 *s_q = reinterpret_cast<double2 *>(smem);
+    double *s_w = smem + 2 * EB;
+    uint32_t *s_ip = reinterpret_cast<uint32_t *>(smem + SD * EB);
+    const int lane = threadIdx.x;
+    const double2 *q2 = reinterpret_cast<const double2 *>(q);
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * WAVE;
+        const int64_t r1 = (r0 + WAVE < nq) ? r0 + WAVE : nq;
+        const int64_t i = r0 + lane;
+        const bool active = i < nq;
+        const int32_t E0 = row_ptr[r0], E1 = row_ptr[r1];
+        const int32_t I0 = inc_ptr[r0], I1 = inc_ptr[r1];
+        const int32_t rs = active ? row_ptr[i] : 0;
+        const int32_t re = active ? row_ptr[i + 1] : 0;
+        const int32_t is = active ? inc_ptr[i] : 0;
+        const int32_t ie = active ? inc_ptr[i + 1] : 0;
+        const int32_t Ew = E1 - E0, Iw = I1 - I0, len = re - rs;
+        const bool tile_fits = Ew <= EB && Iw <= EB;
+
+        if (tile_fits) {
+            int32_t cidx[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                cidx[u] = e < Ew ? __builtin_nontemporal_load(col_idx + E0 + e) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = lane + u * WAVE;
+                if (t < Iw) s_ip[t] = __builtin_nontemporal_load(inc_pos + I0 + t);
+            }
+            double2 qv[U];
+            double wv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                wv[u] = 0.0;
+                if (e < Ew) {
+                    if (O::W && qw) {
+                        const double4 r = qw[cidx[u]];
+                        qv[u] = make_double2(r.x, r.y);
+                        wv[u] = r.z;
+                    } else {
+                        qv[u] = q2[cidx[u]];
+                        if constexpr (O::W) wv[u] = w[cidx[u]];
+                    }
                 } else {
-                    o0[p1] += c[0][1];
-                    o0[p2] += c[0][2];
-                    dg[0] += c[0][0];
-                    if constexpr (I::NOUT == 2) {
-                        o1[p1] += c[1][1];
-                        o1[p2] += c[1][2];
-                        dg[1] += c[1][0];
+                    qv[u] = make_double2(0.0, 0.0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                if (e < Ew) {
+                    s_q[e] = qv[u];
+                    if constexpr (O::W) s_w[e] = wv[u];
+                }
+            }
+            __syncthreads();
+        }
+        // ---- each lane sums its row (registers when it fits)
+        const bool in_regs = tile_fits && active && len > 0 && len <= LMAX;
+        double acc[NV][LMAX];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int k = 0; k < LMAX; ++k) acc[v][k] = 0.0;
+        if (in_regs) {
+            const int32_t off = rs - E0;
+            uint64_t seen = 0;
+            for (int32_t t = is - I0; t < ie - I0; ++t) {
+                const uint32_t pp = s_ip[t];
+                seen |= (1ull << (pp & 0xffffu)) | (1ull << (pp >> 16));
+            }
+            const int32_t pd = __builtin_ctzll(~seen);
+            const double2 x0 = s_q[off + pd];
+            const double w0 = O::W ? s_w[off + pd] : 0.0;
+            double dg[NSA], dk[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int m = 0; m < NSA; ++m) dg[m] = 0.0;
+            for (int32_t t = is - I0; t < ie - I0; ++t) {
+                const uint32_t pp = s_ip[t];
+                const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
+                const double2 x1 = s_q[off + p1], x2 = s_q[off + p2];
+                double c[NSA][3];
+                double ce[3][4];
+                elem_row<MASK>(x0.x, x0.y, x1.x, x1.y, x2.x, x2.y, w0,
+                               O::W ? s_w[off + p1] : 0.0, O::W ? s_w[off + p2] : 0.0, L, c, ce);
+#pragma unroll
+                for (int m = 0; m < NS; ++m) dg[m] += c[m][0];
+                if constexpr (O::K) {
+#pragma unroll
+                    for (int z = 0; z < 4; ++z) dk[z] += ce[0][z];
+                }
+#pragma unroll
+                for (int k = 0; k < LMAX; ++k) {
+                    const bool h1 = k == p1, h2 = k == p2;
+#pragma unroll
+                    for (int m = 0; m < NS; ++m) {
+                        const double a = h1 ? c[m][1] : (h2 ? c[m][2] : 0.0);
+                        acc[m][k] += a;
+                    }
+                    if constexpr (O::K) {
+#pragma unroll
+                        for (int z = 0; z < 4; ++z) {
+                            const double a = h1 ? ce[1][z] : (h2 ? ce[2][z] : 0.0);
+                            acc[NS + z][k] += a;
+                        }
                     }
                 }
             }
-            if constexpr (OP == OP_ELAS) {
-                o0[2 * pd] += dg[0];
-                o0[2 * pd + 1] += dg[1];
-                o0[2 * len + 2 * pd] += dg[2];
-                o0[2 * len + 2 * pd + 1] += dg[3];
-            } else {
-                o0[pd] += dg[0];
-                if constexpr (I::NOUT == 2) o1[pd] += dg[1];
+#pragma unroll
+            for (int k = 0; k < LMAX; ++k) {
+                if (k == pd) {
+#pragma unroll
+                    for (int m = 0; m < NS; ++m) acc[m][k] += dg[m];
+                    if constexpr (O::K) {
+#pragma unroll
+                        for (int z = 0; z < 4; ++z) acc[NS + z][k] += dk[z];
+                    }
+                }
+            }
+        }
+        if (tile_fits) {
+            // ---- transpose through LDS, coalesced stores (rows in registers);
+            // rows in the fallback write their own entries below
+            __syncthreads();   // everyone is done reading the staged coordinates
+            const int32_t off = rs - E0;
+            // rows not in registers stage zeros here (their lane writes them
+            // after the tile, below)
+            const bool zero_row = !in_regs && active && len > 0;
+#pragma unroll
+            for (int m = 0; m < NS; ++m) {
+                if (in_regs) {
+#pragma unroll
+                    for (int k = 0; k < LMAX; ++k)
+                        if (k < len) s_stage[off + k] = acc[m][k];
+                } else if (zero_row) {
+                    for (int k = 0; k < len; ++k) s_stage[off + k] = 0.0;
+                }
+                __syncthreads();
+                double *o = out.o[m] + E0;
+                for (int e = lane; e < Ew; e += WAVE) {
+                    const double v = s_stage[e];
+                    if (accumulate) o[e] += v;
+                    else __builtin_nontemporal_store(v, o + e);
+                }
+                __syncthreads();
+            }
+            if constexpr (O::K) {
+                if (in_regs) {
+                    // row 2i: [4 off + 2k + beta], row 2i+1: [4 off + 2 len + 2k + beta]
+#pragma unroll
+                    for (int k = 0; k < LMAX; ++k)
+                        if (k < len) {
+                            s_stage[4 * off + 2 * k] = acc[NS + 0][k];
+                            s_stage[4 * off + 2 * k + 1] = acc[NS + 1][k];
+                            s_stage[4 * off + 2 * len + 2 * k] = acc[NS + 2][k];
+                            s_stage[4 * off + 2 * len + 2 * k + 1] = acc[NS + 3][k];
+                        }
+                } else if (zero_row) {
+                    for (int k = 0; k < 4 * len; ++k) s_stage[4 * off + k] = 0.0;
+                }
+                __syncthreads();
+                double *o = out.o[3] + 4 * (int64_t)E0;
+                for (int e = lane; e < 4 * Ew; e += WAVE) {
+                    const double v = s_stage[e];
+                    if (accumulate) o[e] += v;
+                    else __builtin_nontemporal_store(v, o + e);
+                }
+                __syncthreads();
+            }
+        }
+        if (!in_regs && active && len > 0) {
+            // ---- long row or tile too large: the lane's own row in global
+            // memory, same order of additions.  The tile stores above wrote 0
+            // (or added 0) at this row, and the workgroup barrier after them
+            // made those stores complete before these.
+            double *os[NSA];
+#pragma unroll
+            for (int m = 0; m < NSA; ++m) os[m] = m < NS ? out.o[m] + rs : nullptr;
+            double *ok = O::K ? out.o[3] + 4 * (int64_t)rs : nullptr;
+            if (!accumulate) {
+                for (int e = 0; e < len; ++e) {
+#pragma unroll
+                    for (int m = 0; m < NS; ++m) os[m][e] = 0.0;
+                }
+                if constexpr (O::K)
+                    for (int e = 0; e < 4 * len; ++e) ok[e] = 0.0;
+            }
+            const int32_t *cr = col_idx + rs;
+            int32_t pd = 0;
+            while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
+            const double x0 = q[2 * i], y0 = q[2 * i + 1];
+            const double w0 = O::W ? w[i] : 0.0;
+            double dg[NSA], dk[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int m = 0; m < NSA; ++m) dg[m] = 0.0;
+            for (int32_t t = is; t < ie; ++t) {
+                const uint32_t pp = inc_pos[t];
+                const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
+                const int64_t j1 = cr[p1], j2 = cr[p2];
+                double c[NSA][3];
+                double ce[3][4];
+                elem_row<MASK>(x0, y0, q[2 * j1], q[2 * j1 + 1], q[2 * j2], q[2 * j2 + 1], w0,
+                               O::W ? w[j1] : 0.0, O::W ? w[j2] : 0.0, L, c, ce);
+#pragma unroll
+                for (int m = 0; m < NS; ++m) {
+                    dg[m] += c[m][0];
+                    os[m][p1] += c[m][1];
+                    os[m][p2] += c[m][2];
+                }
+                if constexpr (O::K) {
+#pragma unroll
+                    for (int z = 0; z < 4; ++z) dk[z] += ce[0][z];
+                    ok[2 * p1] += ce[1][0];
+                    ok[2 * p1 + 1] += ce[1][1];
+                    ok[2 * len + 2 * p1] += ce[1][2];
+                    ok[2 * len + 2 * p1 + 1] += ce[1][3];
+                    ok[2 * p2] += ce[2][0];
+                    ok[2 * p2 + 1] += ce[2][1];
+                    ok[2 * len + 2 * p2] += ce[2][2];
+                    ok[2 * len + 2 * p2 + 1] += ce[2][3];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < NS; ++m) os[m][pd] += dg[m];
+            if constexpr (O::K) {
+                ok[2 * pd] += dk[0];
+                ok[2 * pd + 1] += dk[1];
+                ok[2 * len + 2 * pd] += dk[2];
+                ok[2 * len + 2 * pd + 1] += dk[3];
             }
         }
     }
@@ -285,15 +630,16 @@ __global__ __launch_bounds__(WAVE) void k_rows_numeric(
 
 // ------------------------------------------------------------------ triangle + atomics
 
-template <int OP>
+template <int MASK>
 __global__ __launch_bounds__(256) void k_elem_atomic(int32_t nme, const double *__restrict__ q,
                                                      const double *__restrict__ w,
                                                      const int32_t *__restrict__ me,
                                                      const int32_t *__restrict__ slot,
-                                                     const int32_t *__restrict__ row_ptr,
-                                                     double *__restrict__ out0,
-                                                     double *__restrict__ out1, Lame L) {
-    using I = OpInfo<OP>;
+                                                     const int32_t *__restrict__ row_ptr, Outs out,
+                                                     Lame L) {
+    using O = Ops<MASK>;
+    constexpr int NS = O::NS;
+    constexpr int NSA = NS > 0 ? NS : 1;
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= nme) return;
     const int32_t v[3] = {me[3 * k], me[3 * k + 1], me[3 * k + 2]};
@@ -303,7 +649,7 @@ __global__ __launch_bounds__(256) void k_elem_atomic(int32_t nme, const double *
         const double2 qc = reinterpret_cast<const double2 *>(q)[v[a]];
         x[a] = qc.x;
         y[a] = qc.y;
-        wl[a] = I::W ? w[v[a]] : 0.0;
+        wl[a] = O::W ? w[v[a]] : 0.0;
     }
     int32_t sl[9];
 #pragma unroll
@@ -312,28 +658,27 @@ __global__ __launch_bounds__(256) void k_elem_atomic(int32_t nme, const double *
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
-        double c[I::NACC][3];
+        double c[NSA][3];
         double ce[3][4];
-        elem_row<OP>(x[a], y[a], x[a1], y[a1], x[a2], y[a2], wl[a], wl[a1], wl[a2], L, c, ce);
+        elem_row<MASK>(x[a], y[a], x[a1], y[a1], x[a2], y[a2], wl[a], wl[a1], wl[a2], L, c, ce);
         const int bcol[3] = {a, a1, a2};
-        if constexpr (OP == OP_ELAS) {
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+            const int32_t p = sl[3 * bcol[bb] + a];
+#pragma unroll
+            for (int m = 0; m < NS; ++m) unsafeAtomicAdd(out.o[m] + p, c[m][bb]);
+        }
+        if constexpr (O::K) {
             const int32_t rs = row_ptr[v[a]];
             const int32_t len = row_ptr[v[a] + 1] - rs;
 #pragma unroll
             for (int bb = 0; bb < 3; ++bb) {
                 const int32_t p = sl[3 * bcol[bb] + a] - rs;
                 const int64_t base = 4 * (int64_t)rs + 2 * p;
-                unsafeAtomicAdd(out0 + base, ce[bb][0]);
-                unsafeAtomicAdd(out0 + base + 1, ce[bb][1]);
-                unsafeAtomicAdd(out0 + base + 2 * len, ce[bb][2]);
-                unsafeAtomicAdd(out0 + base + 2 * len + 1, ce[bb][3]);
-            }
-        } else {
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb) {
-                const int32_t p = sl[3 * bcol[bb] + a];
-                unsafeAtomicAdd(out0 + p, c[0][bb]);
-                if constexpr (I::NOUT == 2) unsafeAtomicAdd(out1 + p, c[1][bb]);
+                unsafeAtomicAdd(out.o[3] + base, ce[bb][0]);
+                unsafeAtomicAdd(out.o[3] + base + 1, ce[bb][1]);
+                unsafeAtomicAdd(out.o[3] + base + 2 * len, ce[bb][2]);
+                unsafeAtomicAdd(out.o[3] + base + 2 * len + 1, ce[bb][3]);
             }
         }
     }
@@ -345,83 +690,201 @@ namespace {
 
 constexpr int DEFAULT_EB = 512;
 
-template <int OP> size_t lds_bytes(int eb) {
-    using I = OpInfo<OP>;
-    return (size_t)eb * (8 * I::NACC + 16 + (I::W ? 8 : 0) + 4);
-}
-
 struct Args {
+    int ops;
     int32_t nq, nme;
     int64_t nnz;
     const double *q, *w;
     const int32_t *me, *row_ptr, *col_idx, *inc_ptr, *slot;
     const uint32_t *inc_pos;
-    double *out0, *out1;
+    double *vals[4];   // M, Mw, S, K
     Lame L;
+    void *work;
+    size_t work_bytes;
     int flags;
     hipStream_t s;
 };
 
-int check_common(const char *fn, const Args &a, bool need_w, int nout) {
+template <int MASK>
+size_t lds_bytes(int eb) {
+    using O = Ops<MASK>;
+    return (size_t)eb * (8 * O::NS + (O::K ? 32 : 0) + 16 + (O::W ? 8 : 0) + 4);
+}
+
+// scalar outputs are compacted in M, Mw, S order; K stays in slot 3
+Outs outs_for(const Args &a) {
+    Outs o{{nullptr, nullptr, nullptr, a.vals[3]}};
+    int m = 0;
+    for (int b = 0; b < 3; ++b)
+        if (a.ops & (1 << b)) o.o[m++] = a.vals[b];
+    return o;
+}
+
+constexpr int LMAX_REG = 8;   // row entries kept in registers by k_rows_reg
+
+template <int MASK>
+size_t lds_bytes_reg(int eb) {
+    using O = Ops<MASK>;
+    const int sd = O::K ? 4 : (O::W ? 3 : 2);
+    return (size_t)eb * (8 * sd + 4);
+}
+
+template <int MASK, int U>
+int launch_reg_u(const Args &a, const double4 *qw, int grid_blocks) {
+    const int64_t ntiles = (a.nq + WAVE - 1) / WAVE;
+    const int64_t grid = grid_blocks > 0 ? (grid_blocks < ntiles ? grid_blocks : ntiles) : ntiles;
+    FEM_REQUIRE(grid <= INT32_MAX, FEM_EOVERFLOW, "too many tiles");
+    const size_t lds = lds_bytes_reg<MASK>(U * WAVE);
+    hipLaunchKernelGGL((k_rows_reg<MASK, U, LMAX_REG>), dim3((unsigned)grid), dim3(WAVE), lds, a.s,
+                       a.nq, a.q, a.w, qw, a.row_ptr, a.col_idx, a.inc_ptr, a.inc_pos, outs_for(a),
+                       a.L, (a.flags & FEM_ACCUMULATE) ? 1 : 0, ntiles);
+    FEM_LAUNCH_CHECK();
+    return FEM_OK;
+}
+
+template <int MASK>
+int launch_reg(const Args &a, const double4 *qw, int eb, int grid_blocks) {
+    if (eb <= 0) eb = DEFAULT_EB;
+    const int u = (eb + WAVE - 1) / WAVE;
+    if (u <= 4) return launch_reg_u<MASK, 4>(a, qw, grid_blocks);
+    if (u <= 7) return launch_reg_u<MASK, 7>(a, qw, grid_blocks);
+    if (u <= 8) return launch_reg_u<MASK, 8>(a, qw, grid_blocks);
+    if (u <= 10) return launch_reg_u<MASK, 10>(a, qw, grid_blocks);
+    if (u <= 12) return launch_reg_u<MASK, 12>(a, qw, grid_blocks);
+    return launch_reg_u<MASK, 16>(a, qw, grid_blocks);
+}
+
+template <int MASK, int U>
+int launch_rows_u(const Args &a, const double4 *qw, int grid_blocks) {
+    const int64_t ntiles = (a.nq + WAVE - 1) / WAVE;
+    const int64_t grid = grid_blocks > 0 ? (grid_blocks < ntiles ? grid_blocks : ntiles) : ntiles;
+    FEM_REQUIRE(grid <= INT32_MAX, FEM_EOVERFLOW, "too many tiles");
+    const size_t lds = lds_bytes<MASK>(U * WAVE);
+    FEM_REQUIRE(lds <= 64 * 1024, FEM_EINVAL, "lds_entries %d needs %zu bytes of LDS (limit 65536)",
+                U * WAVE, lds);
+    hipLaunchKernelGGL((k_rows_numeric<MASK, U>), dim3((unsigned)grid), dim3(WAVE), lds, a.s, a.nq,
+                       a.q, a.w, qw, a.row_ptr, a.col_idx, a.inc_ptr, a.inc_pos, outs_for(a), a.L,
+                       (a.flags & FEM_ACCUMULATE) ? 1 : 0, ntiles);
+    FEM_LAUNCH_CHECK();
+    return FEM_OK;
+}
+
+template <int MASK>
+int launch_rows(const Args &a, const double4 *qw, int eb, int grid_blocks) {
+    if (eb <= 0) eb = DEFAULT_EB;
+    int u = (eb + WAVE - 1) / WAVE;
+    // keep the LDS tile within 64 KiB for the wide operator sets
+    while (u > 4 && lds_bytes<MASK>(u * WAVE) > 64 * 1024) --u;
+    if (u <= 4) return launch_rows_u<MASK, 4>(a, qw, grid_blocks);
+    if (u <= 7) return launch_rows_u<MASK, 7>(a, qw, grid_blocks);
+    if (u <= 8) return launch_rows_u<MASK, 8>(a, qw, grid_blocks);
+    if (u <= 10) return launch_rows_u<MASK, 10>(a, qw, grid_blocks);
+    if (u <= 12) return launch_rows_u<MASK, 12>(a, qw, grid_blocks);
+    return launch_rows_u<MASK, 16>(a, qw, grid_blocks);
+}
+
+template <int MASK>
+int launch_atomic(const Args &a) {
+    using O = Ops<MASK>;
+    if (!(a.flags & FEM_ACCUMULATE)) {
+        int st;
+        for (int b = 0; b < 3; ++b)
+            if ((MASK & (1 << b)) && (st = fill_f64(a.vals[b], a.nnz, 0.0, a.s))) return st;
+        if (O::K && (st = fill_f64(a.vals[3], 4 * a.nnz, 0.0, a.s))) return st;
+    }
+    if (a.nme == 0) return FEM_OK;
+    hipLaunchKernelGGL(k_elem_atomic<MASK>, dim3(grid_for(a.nme, 256)), dim3(256), 0, a.s, a.nme,
+                       a.q, a.w, a.me, a.slot, a.row_ptr, outs_for(a), a.L);
+    FEM_LAUNCH_CHECK();
+    return FEM_OK;
+}
+
+template <int MASK>
+int run_mask(const Args &a, const double4 *qw, const fem_tune *tune) {
+    if (a.flags & FEM_ATOMIC) return launch_atomic<MASK>(a);
+    const int eb = tune ? tune->lds_entries : 0, grid = tune ? tune->grid_blocks : 0;
+    if (tune && tune->variant == 1) return launch_rows<MASK>(a, qw, eb, grid);
+    return launch_reg<MASK>(a, qw, eb, grid);
+}
+
+int run(const char *fn, const Args &a, const fem_tune *tune) {
+    FEM_REQUIRE(a.ops >= 1 && a.ops <= 15, FEM_EINVAL, "%s: ops must be a nonzero subset of FEM_OP_*", fn);
     FEM_REQUIRE(a.nq >= 1 && a.nme >= 0 && a.nnz >= 0, FEM_EINVAL, "%s: bad sizes nq=%d nme=%d nnz=%lld",
                 fn, a.nq, a.nme, (long long)a.nnz);
-    FEM_REQUIRE(a.nnz <= INT32_MAX, FEM_EOVERFLOW, "%s: nnz exceeds int32", fn);
+    FEM_REQUIRE(a.nnz <= INT32_MAX && (!(a.ops & K_BIT) || 4 * a.nnz <= INT32_MAX), FEM_EOVERFLOW,
+                "%s: nnz exceeds int32 indexing", fn);
     FEM_REQUIRE((a.flags & ~(FEM_ATOMIC | FEM_ACCUMULATE)) == 0, FEM_EINVAL, "%s: unknown flags 0x%x", fn,
                 a.flags);
     FEM_REQUIRE(a.q && a.row_ptr, FEM_EINVAL, "%s: NULL q or row_ptr", fn);
-    FEM_REQUIRE(a.nnz == 0 || (a.out0 && (nout < 2 || a.out1)), FEM_EINVAL, "%s: NULL output", fn);
-    FEM_REQUIRE(!need_w || a.w, FEM_EINVAL, "%s: NULL w", fn);
+    for (int b = 0; b < 4; ++b)
+        FEM_REQUIRE(!(a.ops & (1 << b)) || a.nnz == 0 || a.vals[b], FEM_EINVAL, "%s: NULL output", fn);
+    FEM_REQUIRE(!(a.ops & W_BIT) || a.w, FEM_EINVAL, "%s: NULL w", fn);
+    FEM_REQUIRE(!(a.ops & K_BIT) || a.L.lam + a.L.mu > 0.0, FEM_EINVAL,
+                "%s: need lambda + mu > 0 (got %g)", fn, a.L.lam + a.L.mu);
     if (a.flags & FEM_ATOMIC) {
         FEM_REQUIRE(a.nme == 0 || (a.me && a.slot), FEM_EINVAL, "%s: FEM_ATOMIC needs me and slot", fn);
     } else {
         FEM_REQUIRE(a.nnz == 0 || (a.col_idx && a.inc_ptr && a.inc_pos), FEM_EINVAL,
                     "%s: NULL col_idx, inc_ptr or inc_pos", fn);
     }
-    return FEM_OK;
-}
-
-template <int OP>
-int launch_rows(const Args &a, int eb, int grid_blocks) {
-    using I = OpInfo<OP>;
-    if (a.nq == 0) return FEM_OK;
-    if (eb <= 0) eb = DEFAULT_EB;
-    eb = (eb + WAVE - 1) / WAVE * WAVE;
-    const int64_t ntiles = (a.nq + WAVE - 1) / WAVE;
-    const int64_t grid = grid_blocks > 0 ? (grid_blocks < ntiles ? grid_blocks : ntiles) : ntiles;
-    FEM_REQUIRE(grid <= INT32_MAX, FEM_EOVERFLOW, "too many tiles");
-    const size_t lds = lds_bytes<OP>(eb);
-    FEM_REQUIRE(lds <= 64 * 1024, FEM_EINVAL, "lds_entries %d needs %zu bytes of LDS (limit 65536)", eb, lds);
-    hipLaunchKernelGGL(k_rows_numeric<OP>, dim3((unsigned)grid), dim3(WAVE), lds, a.s, a.nq, a.q, a.w,
-                       a.row_ptr, a.col_idx, a.inc_ptr, a.inc_pos, a.out0, a.out1, a.L, eb,
-                       (a.flags & FEM_ACCUMULATE) ? 1 : 0, ntiles);
-    FEM_LAUNCH_CHECK();
-    (void)I::NOUT;
-    return FEM_OK;
-}
-
-template <int OP>
-int launch_atomic(const Args &a) {
-    using I = OpInfo<OP>;
-    const int64_t nvals = (OP == OP_ELAS) ? 4 * a.nnz : a.nnz;
-    if (!(a.flags & FEM_ACCUMULATE)) {
-        int st = fill_f64(a.out0, nvals, 0.0, a.s);
-        if (st) return st;
-        if (I::NOUT == 2 && (st = fill_f64(a.out1, a.nnz, 0.0, a.s))) return st;
+    // packed (x, y, w) records when the weighted mass is requested and a
+    // workspace is given: one random access per column instead of two
+    const double4 *qw = nullptr;
+    if ((a.ops & W_BIT) && !(a.flags & FEM_ATOMIC) && a.work &&
+        a.work_bytes >= sizeof(double4) * (size_t)a.nq) {
+        double4 *p = static_cast<double4 *>(a.work);
+        hipLaunchKernelGGL(k_pack_qw, dim3(grid_for(a.nq, 256)), dim3(256), 0, a.s, a.nq,
+                           reinterpret_cast<const double2 *>(a.q), a.w, p);
+        FEM_LAUNCH_CHECK();
+        qw = p;
     }
-    if (a.nme == 0) return FEM_OK;
-    hipLaunchKernelGGL(k_elem_atomic<OP>, dim3(grid_for(a.nme, 256)), dim3(256), 0, a.s, a.nme, a.q,
-                       a.w, a.me, a.slot, a.row_ptr, a.out0, a.out1, a.L);
-    FEM_LAUNCH_CHECK();
-    return FEM_OK;
+    switch (a.ops) {
+    case 1: return run_mask<1>(a, qw, tune);
+    case 2: return run_mask<2>(a, qw, tune);
+    case 3: return run_mask<3>(a, qw, tune);
+    case 4: return run_mask<4>(a, qw, tune);
+    case 5: return run_mask<5>(a, qw, tune);
+    case 6: return run_mask<6>(a, qw, tune);
+    case 7: return run_mask<7>(a, qw, tune);
+    case 8: return run_mask<8>(a, qw, tune);
+    case 9: return run_mask<9>(a, qw, tune);
+    case 10: return run_mask<10>(a, qw, tune);
+    case 11: return run_mask<11>(a, qw, tune);
+    case 12: return run_mask<12>(a, qw, tune);
+    case 13: return run_mask<13>(a, qw, tune);
+    case 14: return run_mask<14>(a, qw, tune);
+    default: return run_mask<15>(a, qw, tune);
+    }
 }
 
-template <int OP>
-int run(const char *fn, const Args &a, const fem_tune *tune = nullptr) {
-    using I = OpInfo<OP>;
-    int st = check_common(fn, a, I::W, I::NOUT);
-    if (st) return st;
-    if (a.flags & FEM_ATOMIC) return launch_atomic<OP>(a);
-    return launch_rows<OP>(a, tune ? tune->lds_entries : 0, tune ? tune->grid_blocks : 0);
+Args make_args(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q, const double *w,
+               const int32_t *me, const int32_t *row_ptr, const int32_t *col_idx,
+               const int32_t *inc_ptr, const uint32_t *inc_pos, const int32_t *slot, double lam,
+               double mu, double *vM, double *vW, double *vS, double *vK, void *work,
+               size_t work_bytes, int flags, void *stream) {
+    Args a{};
+    a.ops = ops;
+    a.nq = nq;
+    a.nme = nme;
+    a.nnz = nnz;
+    a.q = q;
+    a.w = w;
+    a.me = me;
+    a.row_ptr = row_ptr;
+    a.col_idx = col_idx;
+    a.inc_ptr = inc_ptr;
+    a.inc_pos = inc_pos;
+    a.slot = slot;
+    a.L = {lam, mu};
+    a.vals[0] = vM;
+    a.vals[1] = vW;
+    a.vals[2] = vS;
+    a.vals[3] = vK;
+    a.work = work;
+    a.work_bytes = work_bytes;
+    a.flags = flags;
+    a.s = as_stream(stream);
+    return a;
 }
 
 }  // namespace
@@ -429,14 +892,33 @@ int run(const char *fn, const Args &a, const fem_tune *tune = nullptr) {
 
 using namespace fem;
 
+extern "C" int fem_assemble_workspace(int32_t nq, int ops, size_t *bytes) {
+    clear_error();
+    FEM_REQUIRE(bytes && nq >= 1, FEM_EINVAL, "fem_assemble_workspace: bad arguments");
+    *bytes = (ops & FEM_OP_WMASS) ? sizeof(double4) * (size_t)nq : 0;
+    return FEM_OK;
+}
+
+extern "C" int fem_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q,
+                            const double *w, const int32_t *me, const int32_t *row_ptr,
+                            const int32_t *col_idx, const int32_t *inc_ptr, const uint32_t *inc_pos,
+                            const int32_t *slot, double lambda, double mu, double *vals_M,
+                            double *vals_Mw, double *vals_S, double *vals_K, void *work,
+                            size_t work_bytes, const fem_tune *tune, int flags, void *stream) {
+    clear_error();
+    Args a = make_args(ops, nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, inc_pos, slot, lambda,
+                       mu, vals_M, vals_Mw, vals_S, vals_K, work, work_bytes, flags, stream);
+    return run("fem_assemble", a, tune);
+}
+
 extern "C" int fem_assemble_mass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                                  const int32_t *me, const int32_t *row_ptr, const int32_t *col_idx,
                                  const int32_t *inc_ptr, const uint32_t *inc_pos,
                                  const int32_t *slot, double *values, int flags, void *stream) {
     clear_error();
-    Args a{nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, slot, inc_pos, values, nullptr,
-           {0, 0}, flags, as_stream(stream)};
-    return run<OP_MASS>("fem_assemble_mass", a);
+    Args a = make_args(M_BIT, nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, inc_pos, slot,
+                       0, 0, values, nullptr, nullptr, nullptr, nullptr, 0, flags, stream);
+    return run("fem_assemble_mass", a, nullptr);
 }
 
 extern "C" int fem_assemble_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
@@ -445,9 +927,9 @@ extern "C" int fem_assemble_wmass(int32_t nq, int32_t nme, int64_t nnz, const do
                                   const int32_t *slot, const double *w, double *values, int flags,
                                   void *stream) {
     clear_error();
-    Args a{nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, slot, inc_pos, values, nullptr,
-           {0, 0}, flags, as_stream(stream)};
-    return run<OP_WMASS>("fem_assemble_wmass", a);
+    Args a = make_args(W_BIT, nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, inc_pos, slot, 0, 0,
+                       nullptr, values, nullptr, nullptr, nullptr, 0, flags, stream);
+    return run("fem_assemble_wmass", a, nullptr);
 }
 
 extern "C" int fem_assemble_stiff(int32_t nq, int32_t nme, int64_t nnz, const double *q,
@@ -455,9 +937,9 @@ extern "C" int fem_assemble_stiff(int32_t nq, int32_t nme, int64_t nnz, const do
                                   const int32_t *inc_ptr, const uint32_t *inc_pos,
                                   const int32_t *slot, double *values, int flags, void *stream) {
     clear_error();
-    Args a{nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, slot, inc_pos, values, nullptr,
-           {0, 0}, flags, as_stream(stream)};
-    return run<OP_STIFF>("fem_assemble_stiff", a);
+    Args a = make_args(S_BIT, nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, inc_pos, slot,
+                       0, 0, nullptr, nullptr, values, nullptr, nullptr, 0, flags, stream);
+    return run("fem_assemble_stiff", a, nullptr);
 }
 
 extern "C" int fem_assemble_stiff_mass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
@@ -466,9 +948,9 @@ extern "C" int fem_assemble_stiff_mass(int32_t nq, int32_t nme, int64_t nnz, con
                                        const uint32_t *inc_pos, const int32_t *slot,
                                        double *vals_S, double *vals_M, int flags, void *stream) {
     clear_error();
-    Args a{nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, slot, inc_pos, vals_S, vals_M,
-           {0, 0}, flags, as_stream(stream)};
-    return run<OP_STIFF_MASS>("fem_assemble_stiff_mass", a);
+    Args a = make_args(S_BIT | M_BIT, nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr,
+                       inc_pos, slot, 0, 0, vals_M, nullptr, vals_S, nullptr, nullptr, 0, flags, stream);
+    return run("fem_assemble_stiff_mass", a, nullptr);
 }
 
 extern "C" int fem_assemble_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
@@ -478,9 +960,9 @@ extern "C" int fem_assemble_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, co
                                         const double *w, double *vals_S, double *vals_Mw, int flags,
                                         void *stream) {
     clear_error();
-    Args a{nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, slot, inc_pos, vals_S, vals_Mw,
-           {0, 0}, flags, as_stream(stream)};
-    return run<OP_STIFF_WMASS>("fem_assemble_stiff_wmass", a);
+    Args a = make_args(S_BIT | W_BIT, nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, inc_pos,
+                       slot, 0, 0, nullptr, vals_Mw, vals_S, nullptr, nullptr, 0, flags, stream);
+    return run("fem_assemble_stiff_wmass", a, nullptr);
 }
 
 extern "C" int fem_assemble_elas(int32_t nq, int32_t nme, int64_t nnz, const double *q,
@@ -489,12 +971,9 @@ extern "C" int fem_assemble_elas(int32_t nq, int32_t nme, int64_t nnz, const dou
                                  const int32_t *slot, double lambda, double mu, double *values_e,
                                  int flags, void *stream) {
     clear_error();
-    FEM_REQUIRE(lambda + mu > 0.0, FEM_EINVAL, "fem_assemble_elas: need lambda + mu > 0 (got %g)",
-                lambda + mu);
-    FEM_REQUIRE(4 * nnz <= INT32_MAX, FEM_EOVERFLOW, "fem_assemble_elas: 4 nnz exceeds int32");
-    Args a{nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, slot, inc_pos, values_e, nullptr,
-           {lambda, mu}, flags, as_stream(stream)};
-    return run<OP_ELAS>("fem_assemble_elas", a);
+    Args a = make_args(K_BIT, nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, inc_pos, slot,
+                       lambda, mu, nullptr, nullptr, nullptr, values_e, nullptr, 0, flags, stream);
+    return run("fem_assemble_elas", a, nullptr);
 }
 
 extern "C" int fem_assemble_stiff_mass_batched(int32_t nb, int32_t nq, int64_t nnz, const double *q,
@@ -506,9 +985,10 @@ extern "C" int fem_assemble_stiff_mass_batched(int32_t nb, int32_t nq, int64_t n
     FEM_REQUIRE(nb >= 1, FEM_EINVAL, "fem_assemble_stiff_mass_batched: nb must be >= 1");
     FEM_REQUIRE((flags & FEM_ATOMIC) == 0, FEM_EINVAL,
                 "fem_assemble_stiff_mass_batched: only the row-owner scheme is batched");
-    Args a{nq, 0, nnz, q, nullptr, nullptr, row_ptr, col_idx, inc_ptr, nullptr, inc_pos, vals_S,
-           vals_M, {0, 0}, flags, as_stream(stream)};
-    return run<OP_STIFF_MASS>("fem_assemble_stiff_mass_batched", a, tune);
+    Args a = make_args(S_BIT | M_BIT, nq, 0, nnz, q, nullptr, nullptr, row_ptr, col_idx, inc_ptr,
+                       inc_pos, nullptr, 0, 0, vals_M, nullptr, vals_S, nullptr, nullptr, 0, flags,
+                       stream);
+    return run("fem_assemble_stiff_mass_batched", a, tune);
 }
 
 // -------------------------------------------------------------------- batch helper

@@ -3,20 +3,27 @@
 //
 // Replaces the global index arrays Ig, Jg of the vectorised assembly
 // (Section 5, Remark on Ig/Jg) and the sort/compress that sparse(Ig,Jg,Kg)
-// performs.  Instead of sorting 9 nme triplets, every vertex gathers the
-// triangles around it and sorts/uniques its own neighbour list in LDS: a P1
-// row holds the vertex itself and its mesh neighbours, so rows are short.
+// performs.  Instead of sorting 9 nme triplets, the 3 nme (vertex, triangle)
+// incidences are grouped by vertex, and every vertex sorts/uniques its own
+// short neighbour list in LDS (a P1 row holds the vertex and its neighbours).
 //
-//   1 count      one lane per triangle: mesh checks, triangles per vertex
-//   2 scan       -> inc_ptr
-//   3 fill       one lane per triangle: inc[] (unordered inside a vertex)
-//   4 rows       one lane per vertex: sort its triangles by id, gather the
-//                two other vertices of each, sort+unique in LDS -> row length,
-//                row-relative positions (inc_pos), sorted columns (staged)
-//   4w rows_wide one workgroup per vertex with more than LANE_MAX triangles
-//   5 scan       -> row_ptr, nnz            (host waits here once)
-//   6 copy       staged columns -> col_idx
-//   7 slot       one lane per triangle: binary search of its 9 entries
+// Grouping by vertex (the transpose of me) without global atomics: a
+// two-level counting sort.
+//   1 bucket count    one workgroup per 4096 triangles: mesh checks, LDS
+//                     histogram of the buckets (4096 consecutive vertex ids)
+//   2 scan            bucket-major offsets of every (bucket, workgroup) run
+//   3 bucket scatter  the same workgroups write each incidence
+//                     (v, 3k + a, other two vertices) into its bucket run
+//   4 bucket sort     one workgroup per bucket: LDS counting sort by vertex
+//                     -> inc_ptr, triangle lists and neighbour pairs
+// (meshes with more than 2^26 vertices use a global-atomic count/fill instead)
+//   5 rows       one lane per vertex: sort its triangles by id, sort+unique
+//                its neighbours in LDS -> row length, row-relative positions
+//                (inc_pos), sorted columns (staged)
+//   5w rows_wide one workgroup per vertex with more than LANE_MAX triangles
+//   6 scan       -> row_ptr, nnz            (host waits here once)
+//   7 copy       staged columns -> col_idx
+//   8 slot       one lane per triangle: binary search of its 9 entries
 #include "fem_internal.h"
 
 namespace fem {
@@ -47,7 +54,7 @@ __global__ __launch_bounds__(256) void k_count(int32_t nme, const int32_t *__res
 __global__ __launch_bounds__(256) void k_fill(int32_t nme, const int32_t *__restrict__ me,
                                               int32_t nq, const int32_t *__restrict__ inc_ptr,
                                               int32_t *__restrict__ cursor,
-                                              int32_t *__restrict__ inc) {
+                                              int32_t *__restrict__ inc, int2 *__restrict__ nbr) {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= nme) return;
     int32_t v[3] = {me[3 * k], me[3 * k + 1], me[3 * k + 2]};
@@ -58,6 +65,180 @@ __global__ __launch_bounds__(256) void k_fill(int32_t nme, const int32_t *__rest
     for (int a = 0; a < 3; ++a) {
         const int32_t pos = atomicSub(&cursor[v[a]], 1) - 1;
         inc[(int64_t)inc_ptr[v[a]] + pos] = static_cast<int32_t>(3 * k + a);
+        nbr[(int64_t)inc_ptr[v[a]] + pos] = make_int2(v[(a + 1) % 3], v[(a + 2) % 3]);
+    }
+}
+
+// Maximum into a counter shared by every wave: read first, so that the
+// atomic (serialised on one address) is issued only while the value grows.
+__device__ inline void max_into(int *dst, int v) {
+    if (v > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dst, v);
+}
+
+// ---------------------------------------------------------------- bucket sort
+
+constexpr int BKT_SHIFT = 12;                 // 4096 vertices per bucket
+constexpr int BKT_V = 1 << BKT_SHIFT;
+constexpr int BKT_THREADS = 256;
+constexpr int BKT_TRI_PER_THREAD = 16;
+constexpr int BKT_TRI = BKT_THREADS * BKT_TRI_PER_THREAD;   // triangles per workgroup
+constexpr int BKT_MAX = 16384;                // buckets the LDS histogram holds
+
+__device__ inline bool tri_ok(int32_t a, int32_t b, int32_t c, int32_t nq, int *err) {
+    if ((uint32_t)a >= (uint32_t)nq || (uint32_t)b >= (uint32_t)nq || (uint32_t)c >= (uint32_t)nq) {
+        if (err) atomicOr(err, ERR_RANGE);
+        return false;
+    }
+    if (a == b || b == c || a == c) {
+        if (err) atomicOr(err, ERR_DEGEN);
+        return false;
+    }
+    return true;
+}
+
+// counts[b * nblk + blk] = incidences of workgroup blk falling in bucket b
+__global__ __launch_bounds__(BKT_THREADS) void k_bkt_count(int32_t nme, const int32_t *__restrict__ me,
+                                                          int32_t nq, int32_t nbkt,
+                                                          int32_t *__restrict__ counts,
+                                                          PatternCounters *cnt) {
+    extern __shared__ int32_t s_hist[];
+    const int32_t nblk = gridDim.x;
+    for (int b = threadIdx.x; b < nbkt; b += BKT_THREADS) s_hist[b] = 0;
+    __syncthreads();
+    int bad = 0;
+#pragma unroll 8
+    for (int j = 0; j < BKT_TRI_PER_THREAD; ++j) {
+        const int64_t k = (int64_t)blockIdx.x * BKT_TRI + j * BKT_THREADS + threadIdx.x;
+        if (k >= nme) break;
+        const int32_t a = me[3 * k], b = me[3 * k + 1], c = me[3 * k + 2];
+        if ((uint32_t)a >= (uint32_t)nq || (uint32_t)b >= (uint32_t)nq || (uint32_t)c >= (uint32_t)nq) {
+            bad |= ERR_RANGE;
+            continue;
+        }
+        if (a == b || b == c || a == c) {
+            bad |= ERR_DEGEN;
+            continue;
+        }
+        atomicAdd(&s_hist[a >> BKT_SHIFT], 1);
+        atomicAdd(&s_hist[b >> BKT_SHIFT], 1);
+        atomicAdd(&s_hist[c >> BKT_SHIFT], 1);
+    }
+    if (bad) atomicOr(&cnt->err, bad);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbkt; b += BKT_THREADS)
+        counts[(int64_t)b * nblk + blockIdx.x] = s_hist[b];
+}
+
+// Same triangles per workgroup as k_bkt_count: each incidence goes to the run
+// of its (bucket, workgroup) pair.  Entry = (v, 3k + a, next, previous).
+__global__ __launch_bounds__(BKT_THREADS) void k_bkt_scatter(int32_t nme, const int32_t *__restrict__ me,
+                                                            int32_t nq, int32_t nbkt,
+                                                            const int32_t *__restrict__ offs,
+                                                            int4 *__restrict__ ent) {
+    extern __shared__ int32_t s_cur[];
+    const int32_t nblk = gridDim.x;
+    for (int b = threadIdx.x; b < nbkt; b += BKT_THREADS)
+        s_cur[b] = offs[(int64_t)b * nblk + blockIdx.x];
+    __syncthreads();
+    constexpr int H = BKT_TRI_PER_THREAD / 2;   // two halves of independent loads
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        int32_t v[H][3];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int64_t k = (int64_t)blockIdx.x * BKT_TRI + (h * H + j) * BKT_THREADS + threadIdx.x;
+            v[j][0] = v[j][1] = v[j][2] = -1;
+            if (k < nme) {
+                v[j][0] = me[3 * k];
+                v[j][1] = me[3 * k + 1];
+                v[j][2] = me[3 * k + 2];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int64_t k = (int64_t)blockIdx.x * BKT_TRI + (h * H + j) * BKT_THREADS + threadIdx.x;
+            if (k >= nme || !tri_ok(v[j][0], v[j][1], v[j][2], nq, nullptr)) continue;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int32_t pos = atomicAdd(&s_cur[v[j][a] >> BKT_SHIFT], 1);
+                ent[pos] = make_int4(v[j][a], static_cast<int32_t>(3 * k + a), v[j][(a + 1) % 3],
+                                     v[j][(a + 2) % 3]);
+            }
+        }
+    }
+}
+
+// One workgroup per bucket: counting sort of its incidences by vertex in LDS.
+// Writes inc_ptr for the bucket's vertices and the (unordered within a vertex)
+// triangle lists and neighbour pairs.
+__global__ __launch_bounds__(BKT_THREADS) void k_bkt_sort(int32_t nq, int32_t nblk,
+                                                         const int32_t *__restrict__ offs,
+                                                         const int32_t *__restrict__ total_ptr,
+                                                         const int4 *__restrict__ ent,
+                                                         int32_t *__restrict__ inc_ptr,
+                                                         int32_t *__restrict__ inc,
+                                                         int2 *__restrict__ nbr) {
+    __shared__ int32_t s_cnt[BKT_V];
+    __shared__ long long s_wsum[BKT_THREADS / WAVE];
+    const int32_t b = blockIdx.x;
+    const int64_t total = *total_ptr;
+    const int64_t e0 = offs[(int64_t)b * nblk];
+    const int64_t e1 = (b + 1 < (int32_t)gridDim.x) ? offs[(int64_t)(b + 1) * nblk] : total;
+    const int32_t v0 = b << BKT_SHIFT;
+    for (int i = threadIdx.x; i < BKT_V; i += BKT_THREADS) s_cnt[i] = 0;
+    __syncthreads();
+    // batches of 8 independent loads per thread
+    constexpr int B8 = 8;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += B8 * BKT_THREADS) {
+        int32_t lv[B8];
+#pragma unroll
+        for (int u = 0; u < B8; ++u) {
+            const int64_t x = e + u * BKT_THREADS;
+            lv[u] = x < e1 ? ent[x].x - v0 : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < B8; ++u)
+            if (lv[u] >= 0) atomicAdd(&s_cnt[lv[u]], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the 4096 counts: 16 consecutive per thread
+    constexpr int PER = BKT_V / BKT_THREADS;
+    int32_t loc[PER];
+    int32_t sum = 0;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        loc[t] = s_cnt[threadIdx.x * PER + t];
+        sum += loc[t];
+    }
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    int32_t incl = wave_inclusive_scan(sum);
+    if (lane == WAVE - 1) s_wsum[wid] = incl;
+    __syncthreads();
+    int32_t run = incl - sum;
+    for (int w = 0; w < wid; ++w) run += (int32_t)s_wsum[w];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int32_t lv = threadIdx.x * PER + t;
+        s_cnt[lv] = run;   // becomes the cursor
+        if (v0 + lv < nq) inc_ptr[v0 + lv] = static_cast<int32_t>(e0) + run;
+        run += loc[t];
+    }
+    if (b == (int32_t)gridDim.x - 1 && threadIdx.x == 0) inc_ptr[nq] = static_cast<int32_t>(total);
+    __syncthreads();
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += B8 * BKT_THREADS) {
+        int4 x[B8];
+#pragma unroll
+        for (int u = 0; u < B8; ++u) {
+            const int64_t y = e + u * BKT_THREADS;
+            x[u] = y < e1 ? ent[y] : make_int4(-1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < B8; ++u) {
+            if (x[u].x < 0) continue;
+            const int64_t pos = e0 + atomicAdd(&s_cnt[x[u].x - v0], 1);
+            inc[pos] = x[u].y;
+            nbr[pos] = make_int2(x[u].z, x[u].w);
+        }
     }
 }
 
@@ -71,55 +252,194 @@ __device__ inline int32_t lower_bound(const int32_t *a, int32_t n, int32_t x) {
     return lo;
 }
 
+// Bitonic sorting networks on register arrays (all indices static after
+// unrolling, so the arrays stay in VGPRs).  sort_kv: key + two payloads.
+template <int N>
+__device__ __forceinline__ void bitonic_sort_kv(int32_t (&k)[N], int32_t (&p)[N], int32_t (&r)[N]) {
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ stride;
+                if (l > i) {
+                    const bool up = (i & size) == 0;
+                    const bool sw = (k[i] > k[l]) == up;
+                    const int32_t k0 = k[i], p0 = p[i], r0 = r[i];
+                    k[i] = sw ? k[l] : k0;
+                    p[i] = sw ? p[l] : p0;
+                    r[i] = sw ? r[l] : r0;
+                    k[l] = sw ? k0 : k[l];
+                    p[l] = sw ? p0 : p[l];
+                    r[l] = sw ? r0 : r[l];
+                }
+            }
+}
+
+template <int N>
+__device__ __forceinline__ void bitonic_sort(int32_t (&k)[N]) {
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ stride;
+                if (l > i) {
+                    const bool up = (i & size) == 0;
+                    const int32_t a = k[i], b = k[l];
+                    k[i] = up ? min(a, b) : max(a, b);
+                    k[l] = up ? max(a, b) : min(a, b);
+                }
+            }
+}
+
+// Triangles per vertex handled entirely in registers by k_rows.
+constexpr int REG_MAX = 8;
+
 // Per-lane LDS arrays are stored [slot][lane] so that the 64 lanes of a wave
 // touch 64 consecutive words (no bank conflicts).
 #define LANE_AT(arr, t) arr[(t) * WAVE + lane]
 
 __global__ __launch_bounds__(WAVE) void k_rows(int32_t nq, const int32_t *__restrict__ inc_ptr,
                                                int32_t *__restrict__ inc,
-                                               const int32_t *__restrict__ me,
+                                               const int2 *__restrict__ nbr,
                                                int32_t *__restrict__ rowlen,
                                                int32_t *__restrict__ stage,
                                                uint32_t *__restrict__ inc_pos,
+                                               int32_t *__restrict__ mid_list,
                                                int32_t *__restrict__ wide_list,
                                                PatternCounters *cnt) {
-    __shared__ int32_t s_inc[LANE_MAX * WAVE];
-    __shared__ int32_t s_nb[2 * LANE_MAX * WAVE];
-    __shared__ int32_t s_col[CAND_MAX * WAVE];
     const int lane = threadIdx.x;
     const int64_t v = blockIdx.x * (int64_t)WAVE + lane;
     const bool in = v < nq;
     const int32_t is = in ? inc_ptr[v] : 0;
     const int32_t d0 = in ? inc_ptr[v + 1] - is : 0;
-    const bool wide = d0 > LANE_MAX;
-    const int32_t d = wide ? 0 : d0;
-    if (wide) {
-        wide_list[atomicAdd(&cnt->wide_count, 1)] = static_cast<int32_t>(v);
-        rowlen[v] = 0;
+    // more than REG_MAX triangles: the LDS path (<= LANE_MAX) or the
+    // workgroup-per-vertex path
+    if (d0 > LANE_MAX) wide_list[atomicAdd(&cnt->wide_count, 1)] = static_cast<int32_t>(v);
+    else if (d0 > REG_MAX) mid_list[atomicAdd(&cnt->mid_count, 1)] = static_cast<int32_t>(v);
+    const int32_t d = d0 > REG_MAX ? 0 : d0;
+    int n = 0;
+    if (d <= REG_MAX) {
+        // ---- common case, all in registers: sort the (at most 8) triangles
+        // by id with their neighbour pairs, sort the 2d neighbours, and rank
+        // columns by counting distinct smaller values
+        int32_t key[REG_MAX], n1[REG_MAX], n2[REG_MAX];
+#pragma unroll
+        for (int t = 0; t < REG_MAX; ++t) {
+            key[t] = n1[t] = n2[t] = INT32_MAX;
+            if (t < d) {
+                key[t] = inc[is + t];
+                const int2 nb = nbr[is + t];
+                n1[t] = nb.x;
+                n2[t] = nb.y;
+            }
+        }
+        bitonic_sort_kv<REG_MAX>(key, n1, n2);
+        int32_t c[2 * REG_MAX];
+#pragma unroll
+        for (int t = 0; t < REG_MAX; ++t) {
+            if (t < d) inc[is + t] = key[t];
+            c[2 * t] = n1[t];
+            c[2 * t + 1] = n2[t];
+        }
+        bitonic_sort<2 * REG_MAX>(c);
+        // first occurrence flags; v itself is never its own neighbour
+        bool f[2 * REG_MAX];
+#pragma unroll
+        for (int k = 0; k < 2 * REG_MAX; ++k)
+            f[k] = c[k] != INT32_MAX && (k == 0 || c[k] != c[k - 1]);
+        auto rank = [&](int32_t x) {
+            int32_t r = (int32_t)v < x ? 1 : 0;
+#pragma unroll
+            for (int k = 0; k < 2 * REG_MAX; ++k) r += (f[k] && c[k] < x) ? 1 : 0;
+            return r;
+        };
+#pragma unroll
+        for (int t = 0; t < REG_MAX; ++t)
+            if (t < d)
+                inc_pos[is + t] = static_cast<uint32_t>(rank(n1[t])) |
+                                  (static_cast<uint32_t>(rank(n2[t])) << 16);
+        if (d > 0) {
+            const int64_t base = 2 * (int64_t)is + v;
+            int32_t below = 0;   // distinct neighbours written so far
+            bool vdone = false;
+#pragma unroll
+            for (int k = 0; k < 2 * REG_MAX; ++k) {
+                if (f[k]) {
+                    if (!vdone && c[k] > (int32_t)v) {
+                        stage[base + below] = (int32_t)v;
+                        vdone = true;
+                    }
+                    stage[base + below + (vdone ? 1 : 0)] = c[k];
+                    ++below;
+                }
+            }
+            if (!vdone) stage[base + below] = (int32_t)v;
+            n = below + 1;
+        }
     }
-    // triangles of v in ascending id (insertion sort)
+    if (in && d0 <= REG_MAX) rowlen[v] = n;
+    // one atomic per wave for the maxima
+    int mr = n, mi = d0;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        mr = max(mr, __shfl_xor(mr, o, WAVE));
+        mi = max(mi, __shfl_xor(mi, o, WAVE));
+    }
+    if (lane == 0) {
+        max_into(&cnt->max_row_len, mr);
+        max_into(&cnt->max_inc, mi);
+    }
+}
+
+// Vertices with REG_MAX < d <= LANE_MAX triangles: one lane per vertex with
+// per-lane LDS lists (insertion sorts), looping over the list built by k_rows.
+__global__ __launch_bounds__(WAVE) void k_rows_mid(const int32_t *__restrict__ inc_ptr,
+                                                   int32_t *__restrict__ inc,
+                                                   const int2 *__restrict__ nbr,
+                                                   int32_t *__restrict__ rowlen,
+                                                   int32_t *__restrict__ stage,
+                                                   uint32_t *__restrict__ inc_pos,
+                                                   const int32_t *__restrict__ mid_list,
+                                                   PatternCounters *cnt) {
+    __shared__ int32_t s_inc[LANE_MAX * WAVE];
+    __shared__ int32_t s_nb[2 * LANE_MAX * WAVE];
+    __shared__ int32_t s_col[CAND_MAX * WAVE];
+    const int lane = threadIdx.x;
+    const int nmid = cnt->mid_count;
+    for (int64_t idx = blockIdx.x * (int64_t)WAVE + lane; idx - lane < nmid; idx += (int64_t)gridDim.x * WAVE) {
+    const bool in = idx < nmid;
+    const int64_t v = in ? mid_list[idx] : 0;
+    const int32_t is = in ? inc_ptr[v] : 0;
+    const int32_t d = in ? inc_ptr[v + 1] - is : 0;
+    int n = 0;
+    // load the triangle ids and neighbour pairs (independent loads), then
+    // sort them by triangle id (insertion sort in LDS)
     for (int t = 0; t < d; ++t) {
-        const int32_t x = inc[is + t];
+        LANE_AT(s_inc, t) = inc[is + t];
+        const int2 nb = nbr[is + t];
+        LANE_AT(s_nb, 2 * t) = nb.x;
+        LANE_AT(s_nb, 2 * t + 1) = nb.y;
+    }
+    for (int t = 1; t < d; ++t) {
+        const int32_t x = LANE_AT(s_inc, t);
+        const int32_t n1 = LANE_AT(s_nb, 2 * t), n2 = LANE_AT(s_nb, 2 * t + 1);
         int j = t;
         while (j > 0 && LANE_AT(s_inc, j - 1) > x) {
             LANE_AT(s_inc, j) = LANE_AT(s_inc, j - 1);
+            LANE_AT(s_nb, 2 * j) = LANE_AT(s_nb, 2 * j - 2);
+            LANE_AT(s_nb, 2 * j + 1) = LANE_AT(s_nb, 2 * j - 1);
             --j;
         }
         LANE_AT(s_inc, j) = x;
+        LANE_AT(s_nb, 2 * j) = n1;
+        LANE_AT(s_nb, 2 * j + 1) = n2;
     }
-    // the other two vertices of each triangle, in cyclic order after v
-    for (int t = 0; t < d; ++t) {
-        const int32_t x = LANE_AT(s_inc, t);
-        inc[is + t] = x;
-        const int64_t k = x / 3;
-        const int a = x - 3 * static_cast<int32_t>(k);
-        const int a1 = a == 2 ? 0 : a + 1;
-        const int a2 = a == 0 ? 2 : a - 1;
-        LANE_AT(s_nb, 2 * t) = me[3 * k + a1];
-        LANE_AT(s_nb, 2 * t + 1) = me[3 * k + a2];
-    }
-    // sorted unique columns: v itself and every neighbour (none if v is unused)
-    int n = 0;
+    for (int t = 0; t < d; ++t) inc[is + t] = LANE_AT(s_inc, t);
+    // sorted unique columns: v itself and every neighbour
     for (int t = -1; t < 2 * d; ++t) {
         const int32_t x = t < 0 ? static_cast<int32_t>(v) : LANE_AT(s_nb, t);
         int j = n;
@@ -129,7 +449,6 @@ __global__ __launch_bounds__(WAVE) void k_rows(int32_t nq, const int32_t *__rest
         LANE_AT(s_col, j) = x;
         ++n;
     }
-    if (d == 0) n = 0;
     // row-relative positions of the two neighbours of each triangle
     for (int t = 0; t < d; ++t) {
         int32_t lo1 = 0, hi1 = n, lo2 = 0, hi2 = n;
@@ -146,21 +465,15 @@ __global__ __launch_bounds__(WAVE) void k_rows(int32_t nq, const int32_t *__rest
         }
         inc_pos[is + t] = static_cast<uint32_t>(lo1) | (static_cast<uint32_t>(lo2) << 16);
     }
-    if (in && !wide) {
-        rowlen[v] = n;
+    {
         const int64_t base = 2 * (int64_t)is + v;
         for (int u = 0; u < n; ++u) stage[base + u] = LANE_AT(s_col, u);
     }
-    // one atomic per wave for the maxima
-    int mr = n, mi = d0;
+    if (in) rowlen[v] = n;
+    int mr = n;
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
-        mr = max(mr, __shfl_xor(mr, o, WAVE));
-        mi = max(mi, __shfl_xor(mi, o, WAVE));
-    }
-    if (lane == 0) {
-        atomicMax(&cnt->max_row_len, mr);
-        atomicMax(&cnt->max_inc, mi);
+    for (int o = WAVE / 2; o > 0; o >>= 1) mr = max(mr, __shfl_xor(mr, o, WAVE));
+    if (lane == 0) max_into(&cnt->max_row_len, mr);
     }
 }
 #undef LANE_AT
@@ -170,7 +483,7 @@ __global__ __launch_bounds__(WAVE) void k_rows(int32_t nq, const int32_t *__rest
 // the same layout as `stage` (2 d + 1 slots at 2 inc_ptr[v] + v).
 __global__ __launch_bounds__(256) void k_rows_wide(const int32_t *__restrict__ inc_ptr,
                                                    int32_t *__restrict__ inc,
-                                                   const int32_t *__restrict__ me,
+                                                   const int2 *__restrict__ nbr,
                                                    int32_t *__restrict__ rowlen,
                                                    int32_t *__restrict__ stage,
                                                    int32_t *__restrict__ scratch,
@@ -186,24 +499,20 @@ __global__ __launch_bounds__(256) void k_rows_wide(const int32_t *__restrict__ i
         const int64_t base = 2 * (int64_t)is + v;
         int32_t *cand = scratch + base;   // 2d + 1 slots
         int32_t *cols = stage + base;     // 2d + 1 slots
-        // 1. sort the triangle ids (distinct): rank sort through `cols`
+        // 1. sort the triangle ids (distinct) with their neighbour pairs: rank
+        // sort, ids through `cols`, pairs through `cand`
         for (int t = threadIdx.x; t < d; t += blockDim.x) {
             const int32_t x = inc[is + t];
             int32_t r = 0;
             for (int s = 0; s < d; ++s) r += inc[is + s] < x;
             cols[r] = x;
+            const int2 nb = nbr[is + t];
+            cand[1 + 2 * r] = nb.x;
+            cand[2 + 2 * r] = nb.y;
         }
         __syncthreads();
         for (int t = threadIdx.x; t < d; t += blockDim.x) inc[is + t] = cols[t];
-        __syncthreads();
         // 2. candidates: v, then the two other vertices of each triangle
-        for (int t = threadIdx.x; t < d; t += blockDim.x) {
-            const int32_t x = inc[is + t];
-            const int64_t k = x / 3;
-            const int a = x - 3 * static_cast<int32_t>(k);
-            cand[1 + 2 * t] = me[3 * k + (a == 2 ? 0 : a + 1)];
-            cand[2 + 2 * t] = me[3 * k + (a == 0 ? 2 : a - 1)];
-        }
         if (threadIdx.x == 0) cand[0] = v;
         __syncthreads();
         // 3. stable rank sort of the 2d+1 candidates into `cols`
@@ -222,7 +531,7 @@ __global__ __launch_bounds__(256) void k_rows_wide(const int32_t *__restrict__ i
                 if (m == 0 || cols[t] != cols[m - 1]) cols[m++] = cols[t];
             s_len = m;
             rowlen[v] = m;
-            atomicMax(&cnt->max_row_len, m);
+            max_into(&cnt->max_row_len, m);
             if (m > 65535) atomicOr(&cnt->err, ERR_ROWLEN);
         }
         __syncthreads();
@@ -237,15 +546,36 @@ __global__ __launch_bounds__(256) void k_rows_wide(const int32_t *__restrict__ i
     }
 }
 
-__global__ __launch_bounds__(256) void k_copy_cols(int32_t nq, const int32_t *__restrict__ row_ptr,
-                                                   const int32_t *__restrict__ inc_ptr,
-                                                   const int32_t *__restrict__ stage,
-                                                   int32_t *__restrict__ col_idx) {
-    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (v >= nq) return;
-    const int32_t rs = row_ptr[v], L = row_ptr[v + 1] - rs;
-    const int64_t base = 2 * (int64_t)inc_ptr[v] + v;
-    for (int u = 0; u < L; ++u) col_idx[(int64_t)rs + u] = stage[base + u];
+// Tile of 64 rows: the staged columns of each row (2 inc_ptr[v] + v) are
+// copied into the contiguous col_idx slice of the tile, one output entry per
+// lane (coalesced writes).
+__global__ __launch_bounds__(WAVE) void k_copy_cols(int32_t nq, const int32_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ inc_ptr,
+                                                    const int32_t *__restrict__ stage,
+                                                    int32_t *__restrict__ col_idx) {
+    __shared__ int32_t s_rs[WAVE + 1];
+    __shared__ int64_t s_base[WAVE];
+    const int lane = threadIdx.x;
+    const int64_t r0 = blockIdx.x * (int64_t)WAVE;
+    const int64_t i = r0 + lane;
+    const int nr = (int)((r0 + WAVE < nq ? r0 + WAVE : nq) - r0);
+    if (lane < nr) {
+        s_rs[lane] = row_ptr[i];
+        s_base[lane] = 2 * (int64_t)inc_ptr[i] + i;
+    }
+    if (lane == 0) s_rs[nr] = row_ptr[r0 + nr];
+    __syncthreads();
+    const int32_t E0 = s_rs[0], Ew = s_rs[nr] - E0;
+    for (int e = lane; e < Ew; e += WAVE) {
+        const int32_t g = E0 + e;
+        int lo = 0, hi = nr - 1;   // last row with s_rs[row] <= g
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_rs[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        col_idx[g] = stage[s_base[lo] + (g - s_rs[lo])];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_slot(int32_t nme, const int32_t *__restrict__ me,
@@ -277,27 +607,42 @@ __global__ __launch_bounds__(256) void k_transpose(int32_t nq, const int32_t *__
     }
 }
 
-__global__ __launch_bounds__(256) void k_elas_pattern(int32_t nq, const int32_t *__restrict__ row_ptr,
-                                                      const int32_t *__restrict__ col_idx,
-                                                      int32_t *__restrict__ row_ptr_e,
-                                                      int32_t *__restrict__ col_idx_e) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i > nq) return;
-    const int32_t rs = row_ptr[i];
-    if (i == nq) {
+// Tile of 64 scalar rows = a contiguous slice of 4 Ew elasticity entries:
+// one output entry per lane (coalesced), its row found by a search over the
+// tile's 64 row offsets in LDS.
+__global__ __launch_bounds__(WAVE) void k_elas_pattern(int32_t nq, const int32_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col_idx,
+                                                       int32_t *__restrict__ row_ptr_e,
+                                                       int32_t *__restrict__ col_idx_e) {
+    __shared__ int32_t s_rs[WAVE + 1];
+    const int lane = threadIdx.x;
+    const int64_t r0 = blockIdx.x * (int64_t)WAVE;
+    const int64_t i = r0 + lane;
+    const int nr = (int)((r0 + WAVE < nq ? r0 + WAVE : nq) - r0);
+    if (lane < nr) s_rs[lane] = row_ptr[i];
+    if (lane == 0) s_rs[nr] = row_ptr[r0 + nr];
+    __syncthreads();
+    if (lane < nr) {
+        const int32_t rs = s_rs[lane], L = s_rs[lane + 1] - rs;
         row_ptr_e[2 * i] = 4 * rs;
-        return;
+        row_ptr_e[2 * i + 1] = 4 * rs + 2 * L;
     }
-    const int32_t L = row_ptr[i + 1] - rs;
-    row_ptr_e[2 * i] = 4 * rs;
-    row_ptr_e[2 * i + 1] = 4 * rs + 2 * L;
-    for (int32_t p = 0; p < L; ++p) {
-        const int32_t j = col_idx[rs + p];
-        const int64_t e = 4 * (int64_t)rs + 2 * p;
-        col_idx_e[e] = 2 * j;
-        col_idx_e[e + 1] = 2 * j + 1;
-        col_idx_e[e + 2 * L] = 2 * j;
-        col_idx_e[e + 2 * L + 1] = 2 * j + 1;
+    if (r0 + nr == nq && lane == 0) row_ptr_e[2 * (int64_t)nq] = 4 * s_rs[nr];
+    const int32_t E0 = s_rs[0], Ew = s_rs[nr] - E0;
+    for (int32_t o = lane; o < 4 * Ew; o += WAVE) {
+        const int32_t g = E0 + (o >> 2);
+        int lo = 0, hi = nr - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_rs[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        // rs <= g < re  <=>  4 rs <= 4 E0 + o < 4 re: the row's 4 L slots
+        // [row 2i | row 2i+1]
+        const int32_t rs = s_rs[lo], L = s_rs[lo + 1] - rs;
+        const int32_t rem = 4 * E0 + o - 4 * rs;
+        const int32_t r2 = rem % (2 * L);
+        col_idx_e[4 * (int64_t)E0 + o] = 2 * col_idx[rs + (r2 >> 1)] + (r2 & 1);
     }
 }
 
@@ -306,9 +651,12 @@ __global__ __launch_bounds__(256) void k_elas_pattern(int32_t nq, const int32_t 
 namespace {
 struct PatternWork {
     PatternCounters *cnt;
-    int32_t *deg, *rowlen, *wide;
+    int32_t *deg, *rowlen, *wide, *mid, *counts;
     long long *part;
+    int2 *nbr;
+    int4 *ent;                 // bucket entries; reused for `stage` and `scratch`
     int32_t *stage, *scratch;
+    int32_t nbkt, nblk;        // bucket path: buckets, triangle workgroups (0: atomic path)
     size_t bytes;
 };
 
@@ -322,14 +670,28 @@ PatternWork carve(int32_t nq, int32_t nme, char *base) {
         off += align_up(bytes);
         return p;
     };
+    const int64_t nbkt = ((int64_t)nq + BKT_V - 1) >> BKT_SHIFT;
+    const int64_t nblk = ((int64_t)nme + BKT_TRI - 1) / BKT_TRI;
+    const bool bucket = nbkt <= BKT_MAX && nme > 0;
+    w.nbkt = bucket ? (int32_t)nbkt : 0;
+    w.nblk = bucket ? (int32_t)(nblk > 0 ? nblk : 1) : 0;
     const size_t stage_n = 6 * (size_t)nme + (size_t)nq + 1;
+    const int64_t ncounts = bucket ? (int64_t)w.nbkt * w.nblk : 0;
+    const int64_t nscan = ncounts > nq ? ncounts : nq;
     w.cnt = reinterpret_cast<PatternCounters *>(take(sizeof(PatternCounters)));
     w.deg = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nq));
     w.rowlen = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nq));
     w.wide = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nq));
-    w.part = reinterpret_cast<long long *>(take(sizeof(long long) * (size_t)scan_partials(nq)));
-    w.stage = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * stage_n));
-    w.scratch = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * stage_n));
+    w.mid = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nq));
+    w.counts = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(ncounts + 1)));
+    w.part = reinterpret_cast<long long *>(take(sizeof(long long) * (size_t)scan_partials(nscan)));
+    w.nbr = reinterpret_cast<int2 *>(take(sizeof(int2) * (3 * (size_t)nme + 1)));
+    const size_t ent_bytes = bucket ? sizeof(int4) * 3 * (size_t)nme : 0;
+    const size_t stage_bytes = align_up(sizeof(int32_t) * stage_n);
+    char *big = take(ent_bytes > 2 * stage_bytes ? ent_bytes : 2 * stage_bytes);
+    w.ent = reinterpret_cast<int4 *>(big);
+    w.stage = reinterpret_cast<int32_t *>(big);
+    w.scratch = reinterpret_cast<int32_t *>(big ? big + stage_bytes : nullptr);
     w.bytes = off;
     return w;
 }
@@ -374,23 +736,47 @@ extern "C" int fem_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *
 
     int st;
     if ((st = fill_i32(reinterpret_cast<int32_t *>(W.cnt), sizeof(PatternCounters) / 4, 0, s))) return st;
-    if ((st = fill_i32(W.deg, nq, 0, s))) return st;
-    if (nme > 0) {
-        hipLaunchKernelGGL(k_count, dim3(grid_for(nme, 256)), dim3(256), 0, s, nme, me, nq, W.deg,
-                           W.cnt);
+    if (W.nbkt > 0) {
+        // group the incidences by vertex: two-level counting sort, no global atomics
+        const size_t hist_lds = sizeof(int32_t) * (size_t)W.nbkt;
+        hipLaunchKernelGGL(k_bkt_count, dim3(W.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me, nq,
+                           W.nbkt, W.counts, W.cnt);
         FEM_LAUNCH_CHECK();
-    }
-    if ((st = exclusive_scan_i32(W.deg, inc_ptr, nq, W.part, &W.cnt->total[0], &W.cnt->err, s)))
-        return st;
-    if (nme > 0) {
-        hipLaunchKernelGGL(k_fill, dim3(grid_for(nme, 256)), dim3(256), 0, s, nme, me, nq, inc_ptr,
-                           W.deg, inc);
+        const int64_t ncounts = (int64_t)W.nbkt * W.nblk;
+        if ((st = exclusive_scan_i32(W.counts, W.counts, ncounts, W.part, &W.cnt->total[2],
+                                     &W.cnt->err, s)))
+            return st;
+        hipLaunchKernelGGL(k_bkt_scatter, dim3(W.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me, nq,
+                           W.nbkt, W.counts, W.ent);
         FEM_LAUNCH_CHECK();
+        // the total is only known on the device; every incidence passed the
+        // checks iff total == 3 nme (else the error bits are set and the host
+        // returns before the outputs are used)
+        hipLaunchKernelGGL(k_bkt_sort, dim3(W.nbkt), dim3(BKT_THREADS), 0, s, nq, W.nblk, W.counts,
+                           W.counts + ncounts, W.ent, inc_ptr, inc, W.nbr);
+        FEM_LAUNCH_CHECK();
+    } else {
+        if ((st = fill_i32(W.deg, nq, 0, s))) return st;
+        if (nme > 0) {
+            hipLaunchKernelGGL(k_count, dim3(grid_for(nme, 256)), dim3(256), 0, s, nme, me, nq, W.deg,
+                               W.cnt);
+            FEM_LAUNCH_CHECK();
+        }
+        if ((st = exclusive_scan_i32(W.deg, inc_ptr, nq, W.part, &W.cnt->total[0], &W.cnt->err, s)))
+            return st;
+        if (nme > 0) {
+            hipLaunchKernelGGL(k_fill, dim3(grid_for(nme, 256)), dim3(256), 0, s, nme, me, nq,
+                               inc_ptr, W.deg, inc, W.nbr);
+            FEM_LAUNCH_CHECK();
+        }
     }
-    hipLaunchKernelGGL(k_rows, dim3(grid_for(nq, WAVE)), dim3(WAVE), 0, s, nq, inc_ptr, inc, me,
-                       W.rowlen, W.stage, inc_pos, W.wide, W.cnt);
+    hipLaunchKernelGGL(k_rows, dim3(grid_for(nq, WAVE)), dim3(WAVE), 0, s, nq, inc_ptr, inc, W.nbr,
+                       W.rowlen, W.stage, inc_pos, W.mid, W.wide, W.cnt);
     FEM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_rows_wide, dim3(256), dim3(256), 0, s, inc_ptr, inc, me, W.rowlen, W.stage,
+    hipLaunchKernelGGL(k_rows_mid, dim3(1024), dim3(WAVE), 0, s, inc_ptr, inc, W.nbr, W.rowlen,
+                       W.stage, inc_pos, W.mid, W.cnt);
+    FEM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_rows_wide, dim3(256), dim3(256), 0, s, inc_ptr, inc, W.nbr, W.rowlen, W.stage,
                        W.scratch, inc_pos, W.wide, W.cnt);
     FEM_LAUNCH_CHECK();
     if ((st = exclusive_scan_i32(W.rowlen, row_ptr, nq, W.part, &W.cnt->total[1], &W.cnt->err, s)))
@@ -407,7 +793,7 @@ extern "C" int fem_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *
     const int64_t nnz = h.total[1];
     FEM_REQUIRE(nnz <= col_cap, FEM_ENOSPC, "fem_pattern: nnz = %lld exceeds col_cap = %lld",
                 (long long)nnz, (long long)col_cap);
-    hipLaunchKernelGGL(k_copy_cols, dim3(grid_for(nq, 256)), dim3(256), 0, s, nq, row_ptr, inc_ptr,
+    hipLaunchKernelGGL(k_copy_cols, dim3(grid_for(nq, WAVE)), dim3(WAVE), 0, s, nq, row_ptr, inc_ptr,
                        W.stage, col_idx);
     FEM_LAUNCH_CHECK();
     if (slot && nme > 0) {
@@ -439,7 +825,7 @@ extern "C" int fem_elas_pattern(int32_t nq, int64_t nnz, const int32_t *row_ptr,
                 "fem_elas_pattern: 4 nnz = %lld exceeds int32", (long long)(4 * nnz));
     FEM_REQUIRE(row_ptr && row_ptr_e && (nnz == 0 || (col_idx && col_idx_e)), FEM_EINVAL,
                 "fem_elas_pattern: NULL array");
-    hipLaunchKernelGGL(k_elas_pattern, dim3(grid_for((int64_t)nq + 1, 256)), dim3(256), 0,
+    hipLaunchKernelGGL(k_elas_pattern, dim3(grid_for(nq, WAVE)), dim3(WAVE), 0,
                        as_stream(stream), nq, row_ptr, col_idx, row_ptr_e, col_idx_e);
     FEM_LAUNCH_CHECK();
     return FEM_OK;

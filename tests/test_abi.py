@@ -43,7 +43,7 @@ def test_version_and_bounds(lib):
     assert lib.fem_pattern_workspace(1089, 2048, C.byref(sz)) == 0
     assert sz.value > 4 * (6 * 2048 + 1089)
     assert lib.fem_pattern_workspace(0, 5, C.byref(sz)) == _lib.FEM_EINVAL
-    assert lib.fem_adjoint_workspace(100, C.byref(sz)) == 0 and sz.value == 2400
+    assert lib.fem_adjoint_workspace(10, 100, C.byref(sz)) == 0 and sz.value == 512 + 3200
 
 
 def test_host_validation_before_any_launch(lib):

@@ -92,7 +92,7 @@ def _meshes():
            ("disk24", mg.unit_disk(24, seed=5))]
     for s in range(3):
         out.append((f"tiny{s}", mg.random_tiny_mesh(np.random.default_rng(rng.integers(1 << 30)), 40)))
-    for n_fan, extra in ((17, 0), (40, 3), (300, 5)):
+    for n_fan, extra in ((9, 1), (12, 0), (16, 2), (17, 0), (40, 3), (300, 5)):
         q, me = fan_mesh(n_fan, extra, seed=n_fan)
         out.append((f"fan{n_fan}", mg.Mesh(q, me, "fan")))
     q = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
@@ -266,3 +266,32 @@ def test_full_size_atomic_sampled_rows():
         for a in range(3):
             np.testing.assert_array_equal(ci[sl[3 * b + a]], m.me[:, b])
             np.testing.assert_array_equal(rows_of[sl[3 * b + a]], m.me[:, a])
+
+
+# ------------------------------------------------------------ fused operator sets
+
+@pytest.mark.parametrize("ops", list(range(1, 16)))
+def test_fused_operator_sets(ops):
+    m = mg.unit_disk(20, seed=ops)
+    print(f"[case] fused ops={ops} nq={m.nq}", flush=True)
+    w = np.random.default_rng(ops).uniform(0.5, 2.0, size=m.nq)
+    qd, wd = _up(m.q), _up(w)
+    pat = fem.fem_pattern(_up(m.me), m.nq, slot=True)
+    lam, mu = 1.5, 0.75
+    single = {"M": fem.fem_assemble_mass(pat, qd), "Mw": fem.fem_assemble_wmass(pat, qd, wd),
+              "S": fem.fem_assemble_stiff(pat, qd), "K": fem.fem_assemble_elas(pat, qd, lam, mu)}
+    packed = fem.fem_assemble(pat, qd, ops, w=wd, lam=lam, mu=mu)
+    unpacked = fem.fem_assemble(pat, qd, ops, w=wd, lam=lam, mu=mu,
+                                work=torch.empty(0, dtype=torch.uint8, device=DEV))
+    atomic = fem.fem_assemble(pat, qd, ops, w=wd, lam=lam, mu=mu, flags=fem.FEM_ATOMIC)
+    torch.cuda.synchronize()
+    bits = {"M": 1, "Mw": 2, "S": 4, "K": 8}
+    assert set(packed) == {k for k, b in bits.items() if ops & b}
+    rp = _np(pat.row_ptr)
+    rpe = np.concatenate([[0], np.cumsum(np.repeat(2 * np.diff(rp), 2))])
+    for k in packed:
+        # same kernel order of additions: bitwise equal to the single-operator call
+        assert torch.equal(packed[k], single[k]), k
+        assert torch.equal(unpacked[k], single[k]), k
+        err = row_rel_err(rpe if k == "K" else rp, _np(atomic[k]), _np(single[k]))
+        assert err <= 2 * RTOL_ROW, (k, err)
