@@ -121,14 +121,34 @@ int64_t fem_nnz_bound(int32_t nq, int32_t nme);
  * Requires nq >= 1, nme >= 0, 3 nme and nq + 6 nme within int32.  Returns
  * FEM_ERANGE / FEM_EDEGEN for an invalid me, FEM_ENOSPC if col_cap < nnz,
  * FEM_EUNSUPPORTED if a row would exceed 65535 entries.  Synchronises
- * `stream` once (after the row lengths are known); the remaining work is
- * enqueued asynchronously.  Integer results are identical on every run. */
+ * `stream` once (twice when a mesh falls back from the fine to the coarse
+ * bucket path); what follows the synchronisation is enqueued asynchronously.
+ * Integer results are identical on every run and on every path. */
 int fem_pattern(int32_t nq, int32_t nme, const int32_t *me,
                 int32_t *row_ptr, int32_t *col_idx, int64_t col_cap,
                 int32_t *inc_ptr, int32_t *inc, uint32_t *inc_pos,
                 int32_t *slot,
                 void *work, size_t work_bytes,
                 int64_t *nnz_out /* HOST */, void *stream);
+
+/* HOST ONLY.  Which algorithm fem_pattern uses to group the incidences by
+ * vertex (all give identical outputs):
+ *   FEM_PATTERN_AUTO    fine buckets of 512 vertices sorted and turned into
+ *                       rows in one kernel; coarse buckets of 4096 vertices
+ *                       when a fine bucket does not fit (a vertex with more
+ *                       than 64 triangles, or more than 4096 incidences in a
+ *                       bucket); atomic counting beyond 151M vertices
+ *   FEM_PATTERN_COARSE  coarse buckets, then per-vertex row kernels
+ *   FEM_PATTERN_ATOMIC  per-vertex atomic counters, then per-vertex row kernels
+ * A process-wide setting, meant for tests and tuning; returns FEM_EINVAL for
+ * an unknown value and FEM_EUNSUPPORTED for FEM_PATTERN_COARSE on a mesh the
+ * coarse histogram cannot hold (checked by fem_pattern). */
+enum {
+    FEM_PATTERN_AUTO = 0,
+    FEM_PATTERN_COARSE = 1,
+    FEM_PATTERN_ATOMIC = 2
+};
+int fem_pattern_set_path(int path);
 
 /* Transpose map: tpos[p] is the position of entry (j, i) for the entry
  * p = (i, j), or -1 if the pattern has no entry (j, i) (every P1 mesh

@@ -21,11 +21,13 @@ from typing import Optional
 
 from . import _lib
 from ._lib import (FEM_ACCUMULATE, FEM_ATOMIC, FEM_DETERMINISTIC, FEM_OP_ELAS,  # noqa: F401
-                   FEM_OP_MASS, FEM_OP_STIFF, FEM_OP_WMASS, FemError, fem_tune)
+                   FEM_OP_MASS, FEM_OP_STIFF, FEM_OP_WMASS, FEM_PATTERN_ATOMIC, FEM_PATTERN_AUTO,
+                   FEM_PATTERN_COARSE, FemError, fem_tune)
 
 __all__ = [
     "Pattern", "FemError", "FEM_ATOMIC", "FEM_DETERMINISTIC", "FEM_ACCUMULATE", "fem_tune",
     "FEM_OP_MASS", "FEM_OP_WMASS", "FEM_OP_STIFF", "FEM_OP_ELAS",
+    "FEM_PATTERN_AUTO", "FEM_PATTERN_COARSE", "FEM_PATTERN_ATOMIC", "fem_pattern_set_path",
     "fem_pattern", "fem_transpose_map", "fem_elas_pattern", "fem_assemble", "fem_assemble_mass",
     "fem_assemble_wmass", "fem_assemble_stiff", "fem_assemble_stiff_mass",
     "fem_assemble_stiff_wmass", "fem_assemble_elas", "fem_batch_globalize",
@@ -120,6 +122,11 @@ def fem_pattern(me, nq: int, *, slot: bool = False, stream=None) -> Pattern:
     n = int(nnz.value)
     return Pattern(int(nq), nme, n, me, row_ptr, col_buf[:n], inc_ptr, inc[:3 * nme],
                    inc_pos[:3 * nme], None if sl is None else sl[:9 * nme].view(9, nme))
+
+
+def fem_pattern_set_path(path: int) -> None:
+    """Process-wide choice of the symbolic algorithm (C: fem_pattern_set_path)."""
+    _lib.check(_lib.load().fem_pattern_set_path(int(path)))
 
 
 def fem_transpose_map(pat: Pattern, *, stream=None):

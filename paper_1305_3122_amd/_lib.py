@@ -20,6 +20,10 @@ FEM_DETERMINISTIC = 0
 FEM_ATOMIC = 1
 FEM_ACCUMULATE = 2
 
+FEM_PATTERN_AUTO = 0
+FEM_PATTERN_COARSE = 1
+FEM_PATTERN_ATOMIC = 2
+
 FEM_OP_MASS = 1
 FEM_OP_WMASS = 2
 FEM_OP_STIFF = 4
@@ -56,6 +60,7 @@ SIGNATURES = {
     "fem_nnz_bound": (_i64, [_i32, _i32]),
     "fem_pattern": (_int, [_i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, C.c_size_t,
                            C.POINTER(_i64), _vp]),
+    "fem_pattern_set_path": (_int, [_int]),
     "fem_transpose_map": (_int, [_i32, _i64, _vp, _vp, _vp, _vp]),
     "fem_elas_pattern": (_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp]),
     "fem_assemble_workspace": (_int, [_i32, _int, _szp]),

@@ -76,29 +76,40 @@ __device__ inline void max_into(int *dst, int v) {
 }
 
 // ---------------------------------------------------------------- bucket sort
+//
+// Buckets are ranges of 2^bs consecutive vertex ids.  A first pass
+// partitions the incidences by bucket (k_bkt_count / scan / k_bkt_scatter:
+// each workgroup of triangles writes one contiguous run per bucket).  Then
+// either
+//   fine buckets (512 vertices): k_bkt_rows does everything for a bucket in
+//     LDS -- counting sort by vertex, per-vertex rows -- and a decoupled
+//     look-back over the buckets gives its offset in col_idx, so row_ptr and
+//     col_idx are written directly;
+//   coarse buckets (4096 vertices, very large meshes or a bucket too large for
+//     LDS): k_bkt_sort writes the triangle lists, then the per-vertex kernels.
 
-constexpr int BKT_SHIFT = 12;                 // 4096 vertices per bucket
-constexpr int BKT_V = 1 << BKT_SHIFT;
-constexpr int BKT_THREADS = 256;
-constexpr int BKT_TRI_PER_THREAD = 16;
-constexpr int BKT_TRI = BKT_THREADS * BKT_TRI_PER_THREAD;   // triangles per workgroup
-constexpr int BKT_MAX = 16384;                // buckets the LDS histogram holds
+constexpr int BKT_THREADS = 512;
+constexpr int FINE_SHIFT = 9;                 // 512 vertices per fine bucket
+constexpr int FINE_V = 1 << FINE_SHIFT;
+constexpr int FINE_CAP = 4096;                // incidences a fine bucket may hold in LDS
+constexpr int COARSE_SHIFT = 12;              // 4096 vertices per coarse bucket
+constexpr int COARSE_V = 1 << COARSE_SHIFT;
+constexpr int FINE_DMAX = 64;                // triangles per vertex on the fine path
+constexpr int HIST_MAX = 36864;               // buckets an LDS histogram holds (144 KiB)
+constexpr int NBLK_TARGET = 256;              // triangle workgroups of the partition pass
 
-__device__ inline bool tri_ok(int32_t a, int32_t b, int32_t c, int32_t nq, int *err) {
-    if ((uint32_t)a >= (uint32_t)nq || (uint32_t)b >= (uint32_t)nq || (uint32_t)c >= (uint32_t)nq) {
-        if (err) atomicOr(err, ERR_RANGE);
-        return false;
-    }
-    if (a == b || b == c || a == c) {
-        if (err) atomicOr(err, ERR_DEGEN);
-        return false;
-    }
-    return true;
+// device-side error bits of the fine path
+enum : int { ERR_BUCKET = 16, ERR_NOSPC = 32 };
+
+__device__ inline bool tri_ok(int32_t a, int32_t b, int32_t c, int32_t nq) {
+    return (uint32_t)a < (uint32_t)nq && (uint32_t)b < (uint32_t)nq && (uint32_t)c < (uint32_t)nq &&
+           a != b && b != c && a != c;
 }
 
-// counts[b * nblk + blk] = incidences of workgroup blk falling in bucket b
+// counts[b * nblk + blk] = incidences of workgroup blk (tpb triangles)
+// falling in bucket b; mesh checks.
 __global__ __launch_bounds__(BKT_THREADS) void k_bkt_count(int32_t nme, const int32_t *__restrict__ me,
-                                                          int32_t nq, int32_t nbkt,
+                                                          int32_t nq, int bs, int32_t nbkt, int32_t tpb,
                                                           int32_t *__restrict__ counts,
                                                           PatternCounters *cnt) {
     extern __shared__ int32_t s_hist[];
@@ -106,10 +117,10 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_count(int32_t nme, const in
     for (int b = threadIdx.x; b < nbkt; b += BKT_THREADS) s_hist[b] = 0;
     __syncthreads();
     int bad = 0;
-#pragma unroll 8
-    for (int j = 0; j < BKT_TRI_PER_THREAD; ++j) {
-        const int64_t k = (int64_t)blockIdx.x * BKT_TRI + j * BKT_THREADS + threadIdx.x;
-        if (k >= nme) break;
+    const int64_t k0 = (int64_t)blockIdx.x * tpb;
+    const int64_t k1 = (k0 + tpb < nme) ? k0 + tpb : nme;
+#pragma unroll 4
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += BKT_THREADS) {
         const int32_t a = me[3 * k], b = me[3 * k + 1], c = me[3 * k + 2];
         if ((uint32_t)a >= (uint32_t)nq || (uint32_t)b >= (uint32_t)nq || (uint32_t)c >= (uint32_t)nq) {
             bad |= ERR_RANGE;
@@ -119,9 +130,9 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_count(int32_t nme, const in
             bad |= ERR_DEGEN;
             continue;
         }
-        atomicAdd(&s_hist[a >> BKT_SHIFT], 1);
-        atomicAdd(&s_hist[b >> BKT_SHIFT], 1);
-        atomicAdd(&s_hist[c >> BKT_SHIFT], 1);
+        atomicAdd(&s_hist[a >> bs], 1);
+        atomicAdd(&s_hist[b >> bs], 1);
+        atomicAdd(&s_hist[c >> bs], 1);
     }
     if (bad) atomicOr(&cnt->err, bad);
     __syncthreads();
@@ -130,9 +141,11 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_count(int32_t nme, const in
 }
 
 // Same triangles per workgroup as k_bkt_count: each incidence goes to the run
-// of its (bucket, workgroup) pair.  Entry = (v, 3k + a, next, previous).
+// of its (bucket, workgroup) pair as one record (vertex, 3k + a, next,
+// previous).
 __global__ __launch_bounds__(BKT_THREADS) void k_bkt_scatter(int32_t nme, const int32_t *__restrict__ me,
-                                                            int32_t nq, int32_t nbkt,
+                                                            int32_t nq, int bs, int32_t nbkt,
+                                                            int32_t tpb,
                                                             const int32_t *__restrict__ offs,
                                                             int4 *__restrict__ ent) {
     extern __shared__ int32_t s_cur[];
@@ -140,15 +153,16 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_scatter(int32_t nme, const 
     for (int b = threadIdx.x; b < nbkt; b += BKT_THREADS)
         s_cur[b] = offs[(int64_t)b * nblk + blockIdx.x];
     __syncthreads();
-    constexpr int H = BKT_TRI_PER_THREAD / 2;   // two halves of independent loads
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    const int64_t k0 = (int64_t)blockIdx.x * tpb;
+    const int64_t k1 = (k0 + tpb < nme) ? k0 + tpb : nme;
+    constexpr int H = 4;   // triangles with independent loads in flight per thread
+    for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += H * BKT_THREADS) {
         int32_t v[H][3];
 #pragma unroll
         for (int j = 0; j < H; ++j) {
-            const int64_t k = (int64_t)blockIdx.x * BKT_TRI + (h * H + j) * BKT_THREADS + threadIdx.x;
+            const int64_t k = kb + j * BKT_THREADS;
             v[j][0] = v[j][1] = v[j][2] = -1;
-            if (k < nme) {
+            if (k < k1) {
                 v[j][0] = me[3 * k];
                 v[j][1] = me[3 * k + 1];
                 v[j][2] = me[3 * k + 2];
@@ -156,11 +170,11 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_scatter(int32_t nme, const 
         }
 #pragma unroll
         for (int j = 0; j < H; ++j) {
-            const int64_t k = (int64_t)blockIdx.x * BKT_TRI + (h * H + j) * BKT_THREADS + threadIdx.x;
-            if (k >= nme || !tri_ok(v[j][0], v[j][1], v[j][2], nq, nullptr)) continue;
+            const int64_t k = kb + j * BKT_THREADS;
+            if (k >= k1 || !tri_ok(v[j][0], v[j][1], v[j][2], nq)) continue;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const int32_t pos = atomicAdd(&s_cur[v[j][a] >> BKT_SHIFT], 1);
+                const int32_t pos = atomicAdd(&s_cur[v[j][a] >> bs], 1);
                 ent[pos] = make_int4(v[j][a], static_cast<int32_t>(3 * k + a), v[j][(a + 1) % 3],
                                      v[j][(a + 2) % 3]);
             }
@@ -168,9 +182,9 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_scatter(int32_t nme, const 
     }
 }
 
-// One workgroup per bucket: counting sort of its incidences by vertex in LDS.
-// Writes inc_ptr for the bucket's vertices and the (unordered within a vertex)
-// triangle lists and neighbour pairs.
+// Coarse path: one workgroup per bucket of COARSE_V vertices: counting sort of
+// its incidences by vertex in LDS.  Writes inc_ptr for the bucket's vertices
+// and the (unordered within a vertex) triangle lists and neighbour pairs.
 __global__ __launch_bounds__(BKT_THREADS) void k_bkt_sort(int32_t nq, int32_t nblk,
                                                          const int32_t *__restrict__ offs,
                                                          const int32_t *__restrict__ total_ptr,
@@ -178,17 +192,16 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_sort(int32_t nq, int32_t nb
                                                          int32_t *__restrict__ inc_ptr,
                                                          int32_t *__restrict__ inc,
                                                          int2 *__restrict__ nbr) {
-    __shared__ int32_t s_cnt[BKT_V];
-    __shared__ long long s_wsum[BKT_THREADS / WAVE];
+    __shared__ int32_t s_cnt[COARSE_V];
+    __shared__ int32_t s_wsum[BKT_THREADS / WAVE];
     const int32_t b = blockIdx.x;
     const int64_t total = *total_ptr;
     const int64_t e0 = offs[(int64_t)b * nblk];
     const int64_t e1 = (b + 1 < (int32_t)gridDim.x) ? offs[(int64_t)(b + 1) * nblk] : total;
-    const int32_t v0 = b << BKT_SHIFT;
-    for (int i = threadIdx.x; i < BKT_V; i += BKT_THREADS) s_cnt[i] = 0;
+    const int32_t v0 = b << COARSE_SHIFT;
+    for (int i = threadIdx.x; i < COARSE_V; i += BKT_THREADS) s_cnt[i] = 0;
     __syncthreads();
-    // batches of 8 independent loads per thread
-    constexpr int B8 = 8;
+    constexpr int B8 = 8;   // batches of independent loads per thread
     for (int64_t e = e0 + threadIdx.x; e < e1; e += B8 * BKT_THREADS) {
         int32_t lv[B8];
 #pragma unroll
@@ -201,8 +214,7 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_sort(int32_t nq, int32_t nb
             if (lv[u] >= 0) atomicAdd(&s_cnt[lv[u]], 1);
     }
     __syncthreads();
-    // exclusive scan of the 4096 counts: 16 consecutive per thread
-    constexpr int PER = BKT_V / BKT_THREADS;
+    constexpr int PER = COARSE_V / BKT_THREADS;
     int32_t loc[PER];
     int32_t sum = 0;
 #pragma unroll
@@ -215,7 +227,7 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_sort(int32_t nq, int32_t nb
     if (lane == WAVE - 1) s_wsum[wid] = incl;
     __syncthreads();
     int32_t run = incl - sum;
-    for (int w = 0; w < wid; ++w) run += (int32_t)s_wsum[w];
+    for (int w = 0; w < wid; ++w) run += s_wsum[w];
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
         const int32_t lv = threadIdx.x * PER + t;
@@ -297,6 +309,250 @@ __device__ __forceinline__ void bitonic_sort(int32_t (&k)[N]) {
 
 // Triangles per vertex handled entirely in registers by k_rows.
 constexpr int REG_MAX = 8;
+
+// Exclusive scan of one int per thread over a workgroup of BKT_THREADS.
+__device__ inline int32_t block_exclusive_scan_i32(int32_t v, int32_t *s_wsum, int32_t *total) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int32_t incl = wave_inclusive_scan(v);
+    if (lane == WAVE - 1) s_wsum[wid] = incl;
+    __syncthreads();
+    int32_t off = incl - v, tot = 0;
+#pragma unroll
+    for (int w = 0; w < BKT_THREADS / WAVE; ++w) {
+        if (w < wid) off += s_wsum[w];
+        tot += s_wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off;
+}
+
+// Fine path: one workgroup (one thread per vertex) per bucket of FINE_V
+// vertices, everything in LDS:
+//   1 count the bucket's incidences per vertex, scan -> inc_ptr
+//   2 counting sort of (3k + a, next, previous) by vertex into LDS
+//   3 per vertex: triangles by id, distinct neighbours, row length
+//   4 offsets of the rows inside the bucket (rowoff) and the bucket's total
+//   5 inc (triangles by id) and inc_pos (their neighbours' places in the row)
+//   6 the bucket's rows, one after the other, into its own part of `stage`
+//     (at 2 e0 + v0: at most 2 n + FINE_V entries for n incidences)
+// k_bkt_copy then moves each bucket's rows to col_idx once the bucket totals
+// are scanned.  A bucket with more than FINE_CAP incidences, or a vertex with
+// more than FINE_DMAX triangles, sets ERR_BUCKET: the host then rebuilds with
+// the coarse path.
+__global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
+    int32_t nq, int32_t nbkt, int32_t nblk, const int32_t *__restrict__ offs,
+    const int32_t *__restrict__ total_ptr, const int4 *__restrict__ ent, int32_t *__restrict__ inc_ptr,
+    int32_t *__restrict__ inc, uint32_t *__restrict__ inc_pos, int32_t *__restrict__ rowoff,
+    int32_t *__restrict__ btot, int32_t *__restrict__ stage, PatternCounters *cnt) {
+    __shared__ int32_t s_cur[FINE_V];
+    __shared__ int32_t s_key[FINE_CAP], s_n1[FINE_CAP], s_n2[FINE_CAP];
+    __shared__ int32_t s_wsum[BKT_THREADS / WAVE];
+    const int tid = threadIdx.x;
+    const int32_t b = blockIdx.x;
+    const int64_t total = *total_ptr;
+    const int64_t e0 = offs[(int64_t)b * nblk];
+    const int64_t e1 = (b + 1 < nbkt) ? offs[(int64_t)(b + 1) * nblk] : total;
+    const bool fits = e1 - e0 <= FINE_CAP;
+    const int32_t v0 = b << FINE_SHIFT;
+    const int64_t v = (int64_t)v0 + tid;
+    int32_t d = 0, is = 0;
+    // ---- 1 count, scan (the bucket's records stay in registers)
+    constexpr int EPT = FINE_CAP / BKT_THREADS;
+    int4 x[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int64_t y = e0 + tid + u * BKT_THREADS;
+        x[u] = (fits && y < e1) ? ent[y] : make_int4(-1, 0, 0, 0);
+    }
+    s_cur[tid] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < EPT; ++u)
+        if (x[u].x >= 0) atomicAdd(&s_cur[x[u].x - v0], 1);
+    __syncthreads();
+    d = s_cur[tid];
+    int32_t unused;
+    is = block_exclusive_scan_i32(d, s_wsum, &unused);
+    s_cur[tid] = is;
+    if (v < nq) inc_ptr[v] = static_cast<int32_t>(e0) + is;
+    if (b == nbkt - 1 && tid == 0) inc_ptr[nq] = static_cast<int32_t>(total);
+    __syncthreads();
+    // ---- 2 counting sort into LDS
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        if (x[u].x < 0) continue;
+        const int32_t p = atomicAdd(&s_cur[x[u].x - v0], 1);
+        s_key[p] = x[u].y;
+        s_n1[p] = x[u].z;
+        s_n2[p] = x[u].w;
+    }
+    __syncthreads();
+    // ---- 3 per vertex: triangles by id, distinct neighbours, row length
+    bool bad = !fits;
+    int32_t L = 0;
+    int32_t key[REG_MAX], n1[REG_MAX], n2[REG_MAX], c[2 * REG_MAX];
+    bool f[2 * REG_MAX];
+    // LDS path (REG_MAX < d <= FINE_DMAX): candidate u is entry u % 2 of the
+    // neighbour pair of triangle u / 2; m0, m1 flag the first occurrences
+    uint64_t m0 = 0, m1 = 0;
+    auto cand = [&](int u) { return (u & 1) ? s_n2[is + (u >> 1)] : s_n1[is + (u >> 1)]; };
+    auto first = [&](int u) { return ((u < 64 ? m0 >> u : m1 >> (u - 64)) & 1) != 0; };
+    auto lds_rank = [&](int32_t y) {
+        int32_t r = (int32_t)v < y ? 1 : 0;
+        for (int u = 0; u < 2 * d; ++u) r += (first(u) && cand(u) < y) ? 1 : 0;
+        return r;
+    };
+    auto reg_rank = [&](int32_t y) {
+        int32_t r = (int32_t)v < y ? 1 : 0;
+#pragma unroll
+        for (int k = 0; k < 2 * REG_MAX; ++k) r += (f[k] && c[k] < y) ? 1 : 0;
+        return r;
+    };
+    if (!fits || v >= nq) {
+        d = 0;
+    }
+    const bool in_regs = d <= REG_MAX;
+    if (in_regs) {
+#pragma unroll
+        for (int t = 0; t < REG_MAX; ++t) {
+            key[t] = n1[t] = n2[t] = INT32_MAX;
+            if (t < d) {
+                key[t] = s_key[is + t];
+                n1[t] = s_n1[is + t];
+                n2[t] = s_n2[is + t];
+            }
+        }
+        bitonic_sort_kv<REG_MAX>(key, n1, n2);
+#pragma unroll
+        for (int t = 0; t < REG_MAX; ++t) {
+            c[2 * t] = n1[t];
+            c[2 * t + 1] = n2[t];
+        }
+        bitonic_sort<2 * REG_MAX>(c);
+        int32_t nd = 0;
+#pragma unroll
+        for (int k = 0; k < 2 * REG_MAX; ++k) {
+            f[k] = c[k] != INT32_MAX && (k == 0 || c[k] != c[k - 1]);
+            nd += f[k] ? 1 : 0;
+        }
+        L = d > 0 ? nd + 1 : 0;
+    } else if (d <= FINE_DMAX) {
+        // insertion sort of the vertex's LDS slice by triangle
+        for (int t = 1; t < d; ++t) {
+            const int32_t y = s_key[is + t], a1 = s_n1[is + t], a2 = s_n2[is + t];
+            int j = t;
+            while (j > 0 && s_key[is + j - 1] > y) {
+                s_key[is + j] = s_key[is + j - 1];
+                s_n1[is + j] = s_n1[is + j - 1];
+                s_n2[is + j] = s_n2[is + j - 1];
+                --j;
+            }
+            s_key[is + j] = y;
+            s_n1[is + j] = a1;
+            s_n2[is + j] = a2;
+        }
+        int32_t nd = 0;
+        for (int u = 0; u < 2 * d; ++u) {
+            const int32_t y = cand(u);
+            bool fu = true;
+            for (int w = 0; w < u && fu; ++w) fu = cand(w) != y;
+            if (fu) {
+                if (u < 64) m0 |= 1ull << u;
+                else m1 |= 1ull << (u - 64);
+                ++nd;
+            }
+        }
+        L = nd + 1;
+    } else {
+        bad = true;
+    }
+    if (bad) atomicOr(&cnt->err, ERR_BUCKET);
+    // ---- 4 row offsets inside the bucket
+    int32_t Tb;
+    const int32_t lro = block_exclusive_scan_i32(L, s_wsum, &Tb);
+    if (v < nq) rowoff[v] = lro;
+    if (tid == 0) btot[b] = Tb;
+    // ---- 5 the vertex's slice of inc / inc_pos
+    const int64_t ib = e0 + is;
+    if (!bad && d > 0) {
+        if (in_regs) {
+#pragma unroll
+            for (int t = 0; t < REG_MAX; ++t)
+                if (t < d) {
+                    inc[ib + t] = key[t];
+                    inc_pos[ib + t] = static_cast<uint32_t>(reg_rank(n1[t])) |
+                                      (static_cast<uint32_t>(reg_rank(n2[t])) << 16);
+                }
+        } else {
+            for (int t = 0; t < d; ++t) {
+                inc[ib + t] = s_key[is + t];
+                inc_pos[ib + t] = static_cast<uint32_t>(lds_rank(s_n1[is + t])) |
+                                  (static_cast<uint32_t>(lds_rank(s_n2[is + t])) << 16);
+            }
+        }
+    }
+    // ---- 6 the rows, into the bucket's part of stage
+    if (L > 0 && !bad) {
+        int32_t *out = stage + 2 * e0 + v0 + lro;
+        if (in_regs) {
+            int32_t below = 0;
+            bool vdone = false;
+#pragma unroll
+            for (int k = 0; k < 2 * REG_MAX; ++k) {
+                if (f[k]) {
+                    if (!vdone && c[k] > (int32_t)v) {
+                        out[below] = (int32_t)v;
+                        vdone = true;
+                    }
+                    out[below + (vdone ? 1 : 0)] = c[k];
+                    ++below;
+                }
+            }
+            if (!vdone) out[below] = (int32_t)v;
+        } else {
+            for (int u = 0; u < 2 * d; ++u)
+                if (first(u)) out[lds_rank(cand(u))] = cand(u);
+            out[lds_rank((int32_t)v)] = (int32_t)v;
+        }
+    }
+    // ---- maxima
+    int mr = L, mi = d;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        mr = max(mr, __shfl_xor(mr, o, WAVE));
+        mi = max(mi, __shfl_xor(mi, o, WAVE));
+    }
+    if ((tid & (WAVE - 1)) == 0) {
+        max_into(&cnt->max_row_len, mr);
+        max_into(&cnt->max_inc, mi);
+    }
+}
+
+// Bucket b's rows, staged by k_bkt_rows, to col_idx at bptr[b] (the scan of
+// the bucket totals), and row_ptr of its vertices.
+__global__ __launch_bounds__(256) void k_bkt_copy(int32_t nq, int32_t nbkt, int32_t nblk,
+                                                 const int32_t *__restrict__ offs,
+                                                 const int32_t *__restrict__ bptr,
+                                                 const int32_t *__restrict__ rowoff,
+                                                 const int32_t *__restrict__ stage,
+                                                 int32_t *__restrict__ row_ptr,
+                                                 int32_t *__restrict__ col_idx, int64_t col_cap,
+                                                 PatternCounters *cnt) {
+    const int32_t b = blockIdx.x;
+    const int64_t e0 = offs[(int64_t)b * nblk];
+    const int32_t v0 = b << FINE_SHIFT;
+    const int32_t P = bptr[b], T = bptr[b + 1] - P;
+    for (int t = threadIdx.x; t < FINE_V; t += 256)
+        if (v0 + t < nq) row_ptr[v0 + t] = P + rowoff[v0 + t];
+    if (b == nbkt - 1 && threadIdx.x == 0) row_ptr[nq] = bptr[nbkt];
+    if (P + (int64_t)T > col_cap) {
+        if (threadIdx.x == 0) atomicOr(&cnt->err, ERR_NOSPC);
+        return;
+    }
+    const int32_t *src = stage + 2 * e0 + v0;
+    for (int i = threadIdx.x; i < T; i += 256) col_idx[P + i] = src[i];
+}
 
 // Per-lane LDS arrays are stored [slot][lane] so that the 64 lanes of a wave
 // touch 64 consecutive words (no bank conflicts).
@@ -649,14 +905,35 @@ __global__ __launch_bounds__(WAVE) void k_elas_pattern(int32_t nq, const int32_t
 // ---------------------------------------------------------------- workspace layout
 
 namespace {
+// One level of the bucket partition: `nbkt` buckets of 2^shift vertices,
+// `nblk` triangle workgroups of `tpb` triangles each.
+struct BucketPlan {
+    int32_t shift, nbkt, nblk, tpb;
+    int64_t ncounts() const { return (int64_t)nbkt * nblk; }
+};
+
+BucketPlan plan_buckets(int32_t nq, int32_t nme, int shift) {
+    BucketPlan p{shift, 0, 0, 0};
+    const int64_t nbkt = ((int64_t)nq + (1ll << shift) - 1) >> shift;
+    if (nme <= 0 || nbkt > HIST_MAX) return p;
+    int64_t tpb = ((int64_t)nme + NBLK_TARGET - 1) / NBLK_TARGET;
+    tpb = (tpb + BKT_THREADS - 1) / BKT_THREADS * BKT_THREADS;
+    p.nbkt = (int32_t)nbkt;
+    p.tpb = (int32_t)tpb;
+    p.nblk = (int32_t)(((int64_t)nme + tpb - 1) / tpb);
+    return p;
+}
+
 struct PatternWork {
     PatternCounters *cnt;
+    int32_t *btot, *bptr;                  // fine path: bucket totals and their scan
     int32_t *deg, *rowlen, *wide, *mid, *counts;
     long long *part;
     int2 *nbr;
-    int4 *ent;                 // bucket entries; reused for `stage` and `scratch`
+    int4 *ent;                             // bucket records; the region is reused
+                                           //   for `stage` and `scratch`
     int32_t *stage, *scratch;
-    int32_t nbkt, nblk;        // bucket path: buckets, triangle workgroups (0: atomic path)
+    BucketPlan fine, coarse;               // nbkt == 0: level not usable
     size_t bytes;
 };
 
@@ -670,22 +947,26 @@ PatternWork carve(int32_t nq, int32_t nme, char *base) {
         off += align_up(bytes);
         return p;
     };
-    const int64_t nbkt = ((int64_t)nq + BKT_V - 1) >> BKT_SHIFT;
-    const int64_t nblk = ((int64_t)nme + BKT_TRI - 1) / BKT_TRI;
-    const bool bucket = nbkt <= BKT_MAX && nme > 0;
-    w.nbkt = bucket ? (int32_t)nbkt : 0;
-    w.nblk = bucket ? (int32_t)(nblk > 0 ? nblk : 1) : 0;
+    w.fine = plan_buckets(nq, nme, FINE_SHIFT);
+    w.coarse = plan_buckets(nq, nme, COARSE_SHIFT);
+    const bool bucket = w.coarse.nbkt > 0;
     const size_t stage_n = 6 * (size_t)nme + (size_t)nq + 1;
-    const int64_t ncounts = bucket ? (int64_t)w.nbkt * w.nblk : 0;
+    int64_t ncounts = w.fine.ncounts() > w.coarse.ncounts() ? w.fine.ncounts() : w.coarse.ncounts();
     const int64_t nscan = ncounts > nq ? ncounts : nq;
     w.cnt = reinterpret_cast<PatternCounters *>(take(sizeof(PatternCounters)));
+    w.btot = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(w.fine.nbkt + 1)));
+    w.bptr = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(w.fine.nbkt + 1)));
     w.deg = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nq));
     w.rowlen = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nq));
     w.wide = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nq));
     w.mid = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nq));
     w.counts = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(ncounts + 1)));
     w.part = reinterpret_cast<long long *>(take(sizeof(long long) * (size_t)scan_partials(nscan)));
-    w.nbr = reinterpret_cast<int2 *>(take(sizeof(int2) * (3 * (size_t)nme + 1)));
+    // nbr (coarse and atomic paths) doubles as the fine path's row staging
+    // area, which must not alias the bucket records it is built from
+    const size_t nbr_bytes = sizeof(int2) * (3 * (size_t)nme + 1);
+    const size_t fstage_bytes = sizeof(int32_t) * (6 * (size_t)nme + (size_t)nq + FINE_V);
+    w.nbr = reinterpret_cast<int2 *>(take(nbr_bytes > fstage_bytes ? nbr_bytes : fstage_bytes));
     const size_t ent_bytes = bucket ? sizeof(int4) * 3 * (size_t)nme : 0;
     const size_t stage_bytes = align_up(sizeof(int32_t) * stage_n);
     char *big = take(ent_bytes > 2 * stage_bytes ? ent_bytes : 2 * stage_bytes);
@@ -695,11 +976,49 @@ PatternWork carve(int32_t nq, int32_t nme, char *base) {
     w.bytes = off;
     return w;
 }
+
+// Partition the incidences into the buckets of plan P: counts per
+// (bucket, workgroup), their scan, and the scatter into ent_*.  The total
+// number of incidences stays on the device at counts[P.ncounts()].
+int partition(const PatternWork &W, const BucketPlan &P, int32_t nq, int32_t nme, const int32_t *me,
+              hipStream_t s) {
+    const size_t hist_lds = sizeof(int32_t) * (size_t)P.nbkt;
+    hipLaunchKernelGGL(k_bkt_count, dim3(P.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me, nq,
+                       P.shift, P.nbkt, P.tpb, W.counts, W.cnt);
+    FEM_LAUNCH_CHECK();
+    int st;
+    if ((st = exclusive_scan_i32(W.counts, W.counts, P.ncounts(), W.part, &W.cnt->total[2],
+                                 &W.cnt->err, s)))
+        return st;
+    hipLaunchKernelGGL(k_bkt_scatter, dim3(P.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me, nq,
+                       P.shift, P.nbkt, P.tpb, W.counts, W.ent);
+    FEM_LAUNCH_CHECK();
+    return FEM_OK;
+}
+
+int check_mesh_errors(const PatternCounters &h, int32_t nq) {
+    FEM_REQUIRE(!(h.err & ERR_RANGE), FEM_ERANGE, "fem_pattern: a vertex index of me is outside [0, %d)", nq);
+    FEM_REQUIRE(!(h.err & ERR_DEGEN), FEM_EDEGEN, "fem_pattern: a triangle repeats a vertex");
+    FEM_REQUIRE(!(h.err & ERR_OVERFLOW), FEM_EOVERFLOW, "fem_pattern: count overflow");
+    return FEM_OK;
+}
 }  // namespace
 
 }  // namespace fem
 
 using namespace fem;
+
+namespace {
+int g_pattern_path = FEM_PATTERN_AUTO;
+}
+
+extern "C" int fem_pattern_set_path(int path) {
+    clear_error();
+    FEM_REQUIRE(path == FEM_PATTERN_AUTO || path == FEM_PATTERN_COARSE || path == FEM_PATTERN_ATOMIC,
+                FEM_EINVAL, "fem_pattern_set_path: unknown path %d", path);
+    g_pattern_path = path;
+    return FEM_OK;
+}
 
 extern "C" int64_t fem_nnz_bound(int32_t nq, int32_t nme) {
     return (int64_t)(nq > 0 ? nq : 0) + 6 * (int64_t)(nme > 0 ? nme : 0);
@@ -735,67 +1054,89 @@ extern "C" int fem_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *
     hipStream_t s = as_stream(stream);
 
     int st;
-    if ((st = fill_i32(reinterpret_cast<int32_t *>(W.cnt), sizeof(PatternCounters) / 4, 0, s))) return st;
-    if (W.nbkt > 0) {
-        // group the incidences by vertex: two-level counting sort, no global atomics
-        const size_t hist_lds = sizeof(int32_t) * (size_t)W.nbkt;
-        hipLaunchKernelGGL(k_bkt_count, dim3(W.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me, nq,
-                           W.nbkt, W.counts, W.cnt);
+    PatternCounters h{};
+    auto read_counters = [&]() -> int {
+        FEM_HIP_CHECK(hipMemcpyAsync(&h, W.cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+        FEM_HIP_CHECK(hipStreamSynchronize(s));
+        return FEM_OK;
+    };
+    const int32_t n_cnt_words = sizeof(PatternCounters) / 4;
+    if ((st = fill_i32(reinterpret_cast<int32_t *>(W.cnt), n_cnt_words, 0, s))) return st;
+    const int path = g_pattern_path;
+    FEM_REQUIRE(path != FEM_PATTERN_COARSE || W.coarse.nbkt > 0 || nme == 0, FEM_EUNSUPPORTED,
+                "fem_pattern: the coarse path cannot hold nq = %d", nq);
+    bool done = false;
+    if (W.fine.nbkt > 0 && path == FEM_PATTERN_AUTO) {
+        // fine path: partition into 512-vertex buckets; one kernel sorts each
+        // bucket and writes inc_ptr, inc, inc_pos and the staged rows; the
+        // scan of the bucket totals places the rows in col_idx
+        if ((st = partition(W, W.fine, nq, nme, me, s))) return st;
+        int32_t *fstage = reinterpret_cast<int32_t *>(W.nbr);
+        hipLaunchKernelGGL(k_bkt_rows, dim3(W.fine.nbkt), dim3(BKT_THREADS), 0, s, nq, W.fine.nbkt,
+                           W.fine.nblk, W.counts, W.counts + W.fine.ncounts(), W.ent, inc_ptr, inc,
+                           inc_pos, W.rowlen, W.btot, fstage, W.cnt);
         FEM_LAUNCH_CHECK();
-        const int64_t ncounts = (int64_t)W.nbkt * W.nblk;
-        if ((st = exclusive_scan_i32(W.counts, W.counts, ncounts, W.part, &W.cnt->total[2],
+        if ((st = exclusive_scan_i32(W.btot, W.bptr, W.fine.nbkt, W.part, &W.cnt->total[1],
                                      &W.cnt->err, s)))
             return st;
-        hipLaunchKernelGGL(k_bkt_scatter, dim3(W.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me, nq,
-                           W.nbkt, W.counts, W.ent);
+        hipLaunchKernelGGL(k_bkt_copy, dim3(W.fine.nbkt), dim3(256), 0, s, nq, W.fine.nbkt,
+                           W.fine.nblk, W.counts, W.bptr, W.rowlen, fstage, row_ptr, col_idx, col_cap,
+                           W.cnt);
         FEM_LAUNCH_CHECK();
-        // the total is only known on the device; every incidence passed the
-        // checks iff total == 3 nme (else the error bits are set and the host
-        // returns before the outputs are used)
-        hipLaunchKernelGGL(k_bkt_sort, dim3(W.nbkt), dim3(BKT_THREADS), 0, s, nq, W.nblk, W.counts,
-                           W.counts + ncounts, W.ent, inc_ptr, inc, W.nbr);
-        FEM_LAUNCH_CHECK();
-    } else {
-        if ((st = fill_i32(W.deg, nq, 0, s))) return st;
-        if (nme > 0) {
-            hipLaunchKernelGGL(k_count, dim3(grid_for(nme, 256)), dim3(256), 0, s, nme, me, nq, W.deg,
-                               W.cnt);
-            FEM_LAUNCH_CHECK();
-        }
-        if ((st = exclusive_scan_i32(W.deg, inc_ptr, nq, W.part, &W.cnt->total[0], &W.cnt->err, s)))
-            return st;
-        if (nme > 0) {
-            hipLaunchKernelGGL(k_fill, dim3(grid_for(nme, 256)), dim3(256), 0, s, nme, me, nq,
-                               inc_ptr, W.deg, inc, W.nbr);
-            FEM_LAUNCH_CHECK();
-        }
+        if ((st = read_counters())) return st;
+        if ((st = check_mesh_errors(h, nq))) return st;
+        // a bucket too large for LDS (or a vertex with very many triangles):
+        // start again on the coarse path
+        done = !(h.err & ERR_BUCKET);
+        if (!done && (st = fill_i32(reinterpret_cast<int32_t *>(W.cnt), n_cnt_words, 0, s))) return st;
     }
-    hipLaunchKernelGGL(k_rows, dim3(grid_for(nq, WAVE)), dim3(WAVE), 0, s, nq, inc_ptr, inc, W.nbr,
-                       W.rowlen, W.stage, inc_pos, W.mid, W.wide, W.cnt);
-    FEM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_rows_mid, dim3(1024), dim3(WAVE), 0, s, inc_ptr, inc, W.nbr, W.rowlen,
-                       W.stage, inc_pos, W.mid, W.cnt);
-    FEM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_rows_wide, dim3(256), dim3(256), 0, s, inc_ptr, inc, W.nbr, W.rowlen, W.stage,
-                       W.scratch, inc_pos, W.wide, W.cnt);
-    FEM_LAUNCH_CHECK();
-    if ((st = exclusive_scan_i32(W.rowlen, row_ptr, nq, W.part, &W.cnt->total[1], &W.cnt->err, s)))
-        return st;
-
-    PatternCounters h{};
-    FEM_HIP_CHECK(hipMemcpyAsync(&h, W.cnt, sizeof(h), hipMemcpyDeviceToHost, s));
-    FEM_HIP_CHECK(hipStreamSynchronize(s));
-    FEM_REQUIRE(!(h.err & ERR_RANGE), FEM_ERANGE, "fem_pattern: a vertex index of me is outside [0, %d)", nq);
-    FEM_REQUIRE(!(h.err & ERR_DEGEN), FEM_EDEGEN, "fem_pattern: a triangle repeats a vertex");
-    FEM_REQUIRE(!(h.err & ERR_OVERFLOW), FEM_EOVERFLOW, "fem_pattern: count overflow");
-    FEM_REQUIRE(!(h.err & ERR_ROWLEN) && h.max_row_len <= 65535, FEM_EUNSUPPORTED,
-                "fem_pattern: a row has %d entries (limit 65535)", h.max_row_len);
+    if (!done) {
+        if (W.coarse.nbkt > 0 && path != FEM_PATTERN_ATOMIC) {
+            // group the incidences by vertex: two-level counting sort, no global atomics
+            if ((st = partition(W, W.coarse, nq, nme, me, s))) return st;
+            hipLaunchKernelGGL(k_bkt_sort, dim3(W.coarse.nbkt), dim3(BKT_THREADS), 0, s, nq,
+                               W.coarse.nblk, W.counts, W.counts + W.coarse.ncounts(), W.ent,
+                               inc_ptr, inc, W.nbr);
+            FEM_LAUNCH_CHECK();
+        } else {
+            if ((st = fill_i32(W.deg, nq, 0, s))) return st;
+            if (nme > 0) {
+                hipLaunchKernelGGL(k_count, dim3(grid_for(nme, 256)), dim3(256), 0, s, nme, me, nq,
+                                   W.deg, W.cnt);
+                FEM_LAUNCH_CHECK();
+            }
+            if ((st = exclusive_scan_i32(W.deg, inc_ptr, nq, W.part, &W.cnt->total[0], &W.cnt->err, s)))
+                return st;
+            if (nme > 0) {
+                hipLaunchKernelGGL(k_fill, dim3(grid_for(nme, 256)), dim3(256), 0, s, nme, me, nq,
+                                   inc_ptr, W.deg, inc, W.nbr);
+                FEM_LAUNCH_CHECK();
+            }
+        }
+        hipLaunchKernelGGL(k_rows, dim3(grid_for(nq, WAVE)), dim3(WAVE), 0, s, nq, inc_ptr, inc,
+                           W.nbr, W.rowlen, W.stage, inc_pos, W.mid, W.wide, W.cnt);
+        FEM_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_rows_mid, dim3(1024), dim3(WAVE), 0, s, inc_ptr, inc, W.nbr, W.rowlen,
+                           W.stage, inc_pos, W.mid, W.cnt);
+        FEM_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_rows_wide, dim3(256), dim3(256), 0, s, inc_ptr, inc, W.nbr, W.rowlen,
+                           W.stage, W.scratch, inc_pos, W.wide, W.cnt);
+        FEM_LAUNCH_CHECK();
+        if ((st = exclusive_scan_i32(W.rowlen, row_ptr, nq, W.part, &W.cnt->total[1], &W.cnt->err, s)))
+            return st;
+        if ((st = read_counters())) return st;
+        if ((st = check_mesh_errors(h, nq))) return st;
+        FEM_REQUIRE(!(h.err & ERR_ROWLEN) && h.max_row_len <= 65535, FEM_EUNSUPPORTED,
+                    "fem_pattern: a row has %d entries (limit 65535)", h.max_row_len);
+        FEM_REQUIRE(h.total[1] <= col_cap, FEM_ENOSPC, "fem_pattern: nnz = %lld exceeds col_cap = %lld",
+                    (long long)h.total[1], (long long)col_cap);
+        hipLaunchKernelGGL(k_copy_cols, dim3(grid_for(nq, WAVE)), dim3(WAVE), 0, s, nq, row_ptr,
+                           inc_ptr, W.stage, col_idx);
+        FEM_LAUNCH_CHECK();
+    }
     const int64_t nnz = h.total[1];
-    FEM_REQUIRE(nnz <= col_cap, FEM_ENOSPC, "fem_pattern: nnz = %lld exceeds col_cap = %lld",
-                (long long)nnz, (long long)col_cap);
-    hipLaunchKernelGGL(k_copy_cols, dim3(grid_for(nq, WAVE)), dim3(WAVE), 0, s, nq, row_ptr, inc_ptr,
-                       W.stage, col_idx);
-    FEM_LAUNCH_CHECK();
+    FEM_REQUIRE(!(h.err & ERR_NOSPC) && nnz <= col_cap, FEM_ENOSPC,
+                "fem_pattern: nnz = %lld exceeds col_cap = %lld", (long long)nnz, (long long)col_cap);
     if (slot && nme > 0) {
         hipLaunchKernelGGL(k_slot, dim3(grid_for(nme, 256)), dim3(256), 0, s, nme, me, row_ptr,
                            col_idx, slot);

@@ -1,0 +1,142 @@
+"""The three algorithms of the symbolic phase (fine buckets with the fused row
+kernel, coarse buckets, atomic counting) give bit-identical patterns, equal to
+the oracle's; a fine bucket that does not fit falls back to the coarse path;
+a too small col_idx capacity is reported on every path."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1305_3122_amd import meshgen as mg
+from tests.helpers import fan_mesh
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1305_3122_amd as fem  # noqa: E402
+from paper_1305_3122_amd import _lib  # noqa: E402
+
+DEV = torch.device("cuda:0")
+PATHS = {"auto": fem.FEM_PATTERN_AUTO, "coarse": fem.FEM_PATTERN_COARSE,
+         "atomic": fem.FEM_PATTERN_ATOMIC}
+
+
+def _up(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture
+def path_reset():
+    yield
+    fem.fem_pattern_set_path(fem.FEM_PATTERN_AUTO)
+
+
+def _crowded_bucket(seed=7):
+    # 2400 random triangles over 600 vertices: about 10 per vertex, so the
+    # first 512 vertices hold ~5100 incidences, more than one fine bucket holds
+    rng = np.random.default_rng(seed)
+    nq, nme = 600, 2400
+    me = np.stack([rng.choice(nq, 3, replace=False) for _ in range(nme)]).astype(np.int32)
+    return mg.Mesh(rng.uniform(-1, 1, (nq, 2)), me, "crowded")
+
+
+def _cases():
+    out = [("cfg1", mg.config_mesh(1)), ("disk40", mg.unit_disk(40, seed=9)),
+           ("square64_perm", mg.unit_square(64, seed=11)), ("crowded", _crowded_bucket())]
+    for n_fan, extra in ((10, 0), (40, 3), (64, 0), (65, 0), (300, 5)):
+        q, me = fan_mesh(n_fan, extra, seed=n_fan)
+        out.append((f"fan{n_fan}", mg.Mesh(q, me, "fan")))
+    rng = np.random.default_rng(99)
+    for s in range(4):
+        out.append((f"tiny{s}", mg.random_tiny_mesh(np.random.default_rng(rng.integers(1 << 30)), 50)))
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+@pytest.mark.parametrize("name,m", CASES, ids=[n for n, _ in CASES])
+def test_paths_bit_exact(name, m, path, path_reset):
+    print(f"[case] pattern path={path} {name} nq={m.nq} nme={m.nme}", flush=True)
+    fem.fem_pattern_set_path(PATHS[path])
+    P = oracle.pattern(m.nq, m.me)
+    pat = fem.fem_pattern(_up(m.me), m.nq, slot=True)
+    torch.cuda.synchronize()
+    assert pat.nnz == P.nnz
+    np.testing.assert_array_equal(_np(pat.row_ptr), P.row_ptr)
+    np.testing.assert_array_equal(_np(pat.col_idx), P.col_idx)
+    np.testing.assert_array_equal(_np(pat.inc_ptr), P.inc_ptr)
+    np.testing.assert_array_equal(_np(pat.inc), P.inc)
+    np.testing.assert_array_equal(_np(pat.slot), P.slot)
+    pos = _np(pat.inc_pos).view(np.uint32)
+    v = np.repeat(np.arange(P.nq), np.diff(P.inc_ptr))
+    k, a = P.inc // 3, P.inc % 3
+    rs = P.row_ptr[v]
+    np.testing.assert_array_equal(P.col_idx[rs + (pos & 0xFFFF)], m.me[k, (a + 1) % 3])
+    np.testing.assert_array_equal(P.col_idx[rs + (pos >> 16)], m.me[k, (a + 2) % 3])
+
+
+def test_paths_agree_on_full_size_mesh(path_reset):
+    m = mg.config_mesh(2)
+    print(f"[case] pattern paths cfg2 nq={m.nq} nme={m.nme}", flush=True)
+    me = _up(m.me)
+    res = {}
+    for name, p in PATHS.items():
+        fem.fem_pattern_set_path(p)
+        pat = fem.fem_pattern(me, m.nq)
+        torch.cuda.synchronize()
+        res[name] = pat
+    ref = res["auto"]
+    # Euler: nnz = nq + 2 E with E = nq + nme - 1 edges on a simply connected mesh
+    assert ref.nnz == m.nq + 2 * (m.nq + m.nme - 1)
+    for name in ("coarse", "atomic"):
+        for f in ("row_ptr", "col_idx", "inc_ptr", "inc", "inc_pos"):
+            assert torch.equal(getattr(res[name], f), getattr(ref, f)), (name, f)
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+def test_col_cap_too_small(path, path_reset):
+    fem.fem_pattern_set_path(PATHS[path])
+    m = mg.unit_square(20, seed=5)
+    P = oracle.pattern(m.nq, m.me)
+    lib = _lib.load()
+    me = _up(m.me)
+    nq, nme = m.nq, m.nme
+    ws = C.c_size_t(0)
+    _lib.check(lib.fem_pattern_workspace(nq, nme, C.byref(ws)))
+    i32 = dict(dtype=torch.int32, device=DEV)
+    row_ptr = torch.empty(nq + 1, **i32)
+    inc_ptr = torch.empty(nq + 1, **i32)
+    inc = torch.empty(3 * nme, **i32)
+    inc_pos = torch.empty(3 * nme, **i32)
+    work = torch.empty(int(ws.value), dtype=torch.uint8, device=DEV)
+    stream = torch.cuda.current_stream().cuda_stream
+    nnz = C.c_int64(0)
+    for cap, ok in ((P.nnz - 1, False), (P.nnz, True)):
+        col = torch.full((cap + 64,), -7, **i32)
+        st = lib.fem_pattern(nq, nme, me.data_ptr(), row_ptr.data_ptr(), col.data_ptr(), cap,
+                             inc_ptr.data_ptr(), inc.data_ptr(), inc_pos.data_ptr(), None,
+                             work.data_ptr(), int(ws.value), C.byref(nnz), stream)
+        torch.cuda.synchronize()
+        assert (st == 0) == ok, (cap, st)
+        if ok:
+            np.testing.assert_array_equal(_np(col[:cap]), P.col_idx)
+        else:
+            assert st == _lib.FEM_ENOSPC
+        # nothing is written beyond the capacity
+        assert bool((col[cap:] == -7).all())
+
+
+def test_set_path_rejects_unknown():
+    with pytest.raises(fem.FemError) as e:
+        fem.fem_pattern_set_path(7)
+    assert e.value.status == _lib.FEM_EINVAL
