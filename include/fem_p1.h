@@ -67,7 +67,12 @@ enum {
                               order; bitwise reproducible from run to run (default) */
     FEM_ATOMIC = 1,        /* one lane per triangle, FP64 atomic adds through the slot map
                               (needs me and slot); order of additions unspecified */
-    FEM_ACCUMULATE = 2     /* add into values instead of overwriting them */
+    FEM_ACCUMULATE = 2,    /* add into values instead of overwriting them */
+    FEM_PACKED_QW = 4      /* fem_adjoint_stiff_wmass only: the first 32 nq bytes of its
+                              workspace already hold the (x, y, w, 0) record of every vertex
+                              for these q and w, as fem_assemble leaves them in its own
+                              workspace when it assembles Mw (pass the same buffer to both);
+                              the packing pass is skipped */
 };
 
 /* Tunable launch shape of the row-owner kernels. */
@@ -293,8 +298,9 @@ int fem_adjoint_workspace(int32_t nq, int64_t nnz, size_t *bytes /* HOST */);
  * respect to q and w (GS, GM [nnz] on the scalar pattern; either may be NULL
  * to drop its term; w may be NULL only if GM is).  dq [nq][2] and dw [nq]
  * are overwritten (FEM_ACCUMULATE adds into them).  tpos from
- * fem_transpose_map, or NULL (then found by search).  Deterministic: two
- * passes over the rows, no atomics. */
+ * fem_transpose_map, or NULL (then found by search).  flags: FEM_ACCUMULATE,
+ * FEM_PACKED_QW.  Deterministic: two passes over the rows, no atomics; the
+ * result does not depend on tpos, FEM_PACKED_QW or the launch shape. */
 int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                             const double *w, const int32_t *row_ptr, const int32_t *col_idx,
                             const int32_t *inc_ptr, const uint32_t *inc_pos, const int32_t *tpos,

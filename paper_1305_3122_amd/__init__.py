@@ -31,7 +31,8 @@ __all__ = [
     "fem_pattern", "fem_transpose_map", "fem_elas_pattern", "fem_assemble", "fem_assemble_mass",
     "fem_assemble_wmass", "fem_assemble_stiff", "fem_assemble_stiff_mass",
     "fem_assemble_stiff_wmass", "fem_assemble_elas", "fem_batch_globalize",
-    "fem_assemble_stiff_mass_batched", "Graph", "fem_adjoint_stiff_wmass", "AssembleStiffWMass",
+    "fem_assemble_stiff_mass_batched", "Graph", "fem_adjoint_workspace", "fem_adjoint_stiff_wmass",
+    "AssembleStiffWMass",
     "library_path",
 ]
 
@@ -313,9 +314,21 @@ class Graph:
             self.handle = None
 
 
+def fem_adjoint_workspace(pat: Pattern):
+    """A device workspace for fem_adjoint_stiff_wmass (also usable as the
+    packing workspace of fem_assemble, see FEM_PACKED_QW)."""
+    torch = _torch()
+    ws = C.c_size_t(0)
+    _lib.check(_lib.load().fem_adjoint_workspace(pat.nq, pat.nnz, C.byref(ws)))
+    return torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=pat.row_ptr.device)
+
+
 def fem_adjoint_stiff_wmass(pat: Pattern, q, w, GS, GM, *, dq=None, dw=None, flags: int = 0,
-                            stream=None):
-    """(dq [nq][2], dw [nq]) of L = <GS, S(q)> + <GM, Mw(q, w)>."""
+                            work=None, packed: bool = False, stream=None):
+    """(dq [nq][2], dw [nq]) of L = <GS, S(q)> + <GM, Mw(q, w)>.
+
+    packed=True: `work` is the workspace fem_assemble packed the (x, y, w)
+    records of these q and w into (C flag FEM_PACKED_QW)."""
     torch = _torch()
     lib = _lib.load()
     dev = pat.row_ptr.device
@@ -327,13 +340,17 @@ def fem_adjoint_stiff_wmass(pat: Pattern, q, w, GS, GM, *, dq=None, dw=None, fla
         _dev(w, torch.float64, "w", (pat.nq,))
     dq = torch.empty((pat.nq, 2), dtype=torch.float64, device=dev) if dq is None else dq
     dw = torch.empty(pat.nq, dtype=torch.float64, device=dev) if dw is None else dw
-    ws = C.c_size_t(0)
-    _lib.check(lib.fem_adjoint_workspace(pat.nq, pat.nnz, C.byref(ws)))
-    work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
+    if packed and work is None:
+        raise ValueError("packed=True needs the workspace fem_assemble packed into")
+    if work is None:
+        work = fem_adjoint_workspace(pat)
+    if packed:
+        flags |= _lib.FEM_PACKED_QW
     _lib.check(lib.fem_adjoint_stiff_wmass(pat.nq, pat.nme, pat.nnz, _ptr(q), _ptr(w),
                                            _ptr(pat.row_ptr), _ptr(pat.col_idx), _ptr(pat.inc_ptr),
                                            _ptr(pat.inc_pos), _ptr(pat.tpos), _ptr(GS), _ptr(GM),
-                                           _ptr(dq), _ptr(dw), _ptr(work), int(ws.value), flags,
+                                           _ptr(dq), _ptr(dw), _ptr(work),
+                                           work.numel() * work.element_size(), flags,
                                            _stream(stream)))
     return dq, dw
 
@@ -347,18 +364,26 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, q, w, pat):
-            r = fem_assemble(pat, q.contiguous(), FEM_OP_STIFF | FEM_OP_WMASS, w=w.contiguous())
+            # the adjoint's workspace doubles as the forward's packing
+            # workspace, so the backward reuses the packed (x, y, w) records
+            work = fem_adjoint_workspace(pat)
+            r = fem_assemble(pat, q.contiguous(), FEM_OP_STIFF | FEM_OP_WMASS, w=w.contiguous(),
+                             work=work)
             S, M = r["S"], r["Mw"]
             ctx.pat = pat
+            ctx.work = work
             ctx.save_for_backward(q, w)
             return S, M
 
         @staticmethod
         def backward(ctx, gS, gM):
-            q, w = ctx.saved_tensors
+            q, w = ctx.saved_tensors   # version-checked: q, w unchanged since forward
             gS = None if gS is None else gS.contiguous()
             gM = None if gM is None else gM.contiguous()
-            dq, dw = fem_adjoint_stiff_wmass(ctx.pat, q.contiguous(), w.contiguous(), gS, gM)
+            dq, dw = fem_adjoint_stiff_wmass(ctx.pat, q.contiguous(), w.contiguous(), gS, gM,
+                                             work=ctx.work, packed=q.is_contiguous() and
+                                             w.is_contiguous())
+            ctx.work = None
             return dq, (dw if gM is not None else None), None
 
     return AssembleStiffWMass

@@ -19,6 +19,7 @@ FEM_EUNSUPPORTED = -8
 FEM_DETERMINISTIC = 0
 FEM_ATOMIC = 1
 FEM_ACCUMULATE = 2
+FEM_PACKED_QW = 4
 
 FEM_PATTERN_AUTO = 0
 FEM_PATTERN_COARSE = 1

@@ -90,9 +90,13 @@ __global__ __launch_bounds__(256) void k_adj_pack(int32_t nq, const double2 *__r
 }
 
 // Pass 1: tile of 64 rows (one per lane), staged like the forward kernel.
-// LDS: H accumulators (x, y, w) | q | w | GS | GM | ipos.  H is written as
-// (hx, hy, hw, 0) records so that pass 2 reads one record per entry.
-template <bool HS, bool HM, int U>
+// LDS: q (x, y) | w | GS | GM | ipos per entry; each lane keeps the H
+// accumulators (x, y, w) of its row in registers (rows of at most LMAX
+// entries), then LDS is reused to transpose them, and H is written coalesced
+// as (hx, hy, hw, 0) records so that pass 2 reads one record per entry.  Rows
+// longer than LMAX (or tiles too large for LDS) take the per-lane
+// global-memory path; the order of additions is the same everywhere.
+template <bool HS, bool HM, int U, int LMAX>
 __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__restrict__ qw,
                                                    const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col_idx,
@@ -103,15 +107,12 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__
                                                    double4 *__restrict__ H, int64_t ntiles) {
     constexpr int EB = U * WAVE;
     extern __shared__ double smem[];
-    double *s_hx = smem;
-    double *s_hy = s_hx + EB;
-    double *s_hw = s_hy + EB;
-    double *s_qx = s_hw + EB;
-    double *s_qy = s_qx + EB;
-    double *s_w = s_qy + EB;
-    double *s_gs = s_w + EB;
-    double *s_gm = s_gs + EB;
-    uint32_t *s_ip = reinterpret_cast<uint32_t *>(s_gm + EB);
+    double2 *s_q = reinterpret_cast<double2 *>(smem);
+    double *s_w = smem + 2 * EB;
+    double *s_gs = smem + 3 * EB;
+    double *s_gm = smem + 4 * EB;
+    uint32_t *s_ip = reinterpret_cast<uint32_t *>(smem + 5 * EB);
+    double *s_stage = smem;   // 3 doubles per entry, after the sums
     const int lane = threadIdx.x;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = tile * WAVE;
@@ -124,7 +125,8 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__
         const int32_t len = active ? row_ptr[i + 1] - rs : 0;
         const int32_t is = active ? inc_ptr[i] : 0;
         const int32_t ie = active ? inc_ptr[i + 1] : 0;
-        if (Ew <= EB && Iw <= EB) {
+        const bool tile_fits = Ew <= EB && Iw <= EB;
+        if (tile_fits) {
             int32_t cidx[U];
             double gsv[U], gmv[U];
 #pragma unroll
@@ -149,70 +151,79 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__
             for (int u = 0; u < U; ++u) {
                 const int e = lane + u * WAVE;
                 if (e < Ew) {
-                    s_qx[e] = qv[u].x;
-                    s_qy[e] = qv[u].y;
+                    s_q[e] = make_double2(qv[u].x, qv[u].y);
                     s_w[e] = qv[u].z;
-                    s_gs[e] = gsv[u];
-                    s_gm[e] = gmv[u];
-                    s_hx[e] = 0.0;
-                    s_hy[e] = 0.0;
-                    s_hw[e] = 0.0;
+                    if constexpr (HS) s_gs[e] = gsv[u];
+                    if constexpr (HM) s_gm[e] = gmv[u];
                 }
             }
             __syncthreads();
-            if (active && len > 0) {
-                const int32_t off = rs - E0;
-                int32_t pd;
-                if (len <= 64) {
-                    uint64_t seen = 0;
-                    for (int32_t t = is - I0; t < ie - I0; ++t) {
-                        const uint32_t pp = s_ip[t];
-                        seen |= (1ull << (pp & 0xffffu)) | (1ull << (pp >> 16));
-                    }
-                    pd = __builtin_ctzll(~seen);
-                } else {
-                    int32_t lo = 0, hi = len;
-                    while (lo < hi) {
-                        const int32_t mid = (lo + hi) >> 1;
-                        if (col_idx[rs + mid] < (int32_t)i) lo = mid + 1;
-                        else hi = mid;
-                    }
-                    pd = lo;
-                }
-                const int32_t d0 = off + pd;
-                const double x0 = s_qx[d0], y0 = s_qy[d0], w0 = s_w[d0];
-                const double g0 = s_gs[d0], h0 = s_gm[d0];
-                double ox = 0.0, oy = 0.0, ow = 0.0;
-                for (int32_t t = is - I0; t < ie - I0; ++t) {
-                    const uint32_t pp = s_ip[t];
-                    const int32_t p1 = off + (int32_t)(pp & 0xffffu);
-                    const int32_t p2 = off + (int32_t)(pp >> 16);
-                    AdjGrad o;
-                    adj_tau<HS, HM>(x0, y0, s_qx[p1], s_qy[p1], s_qx[p2], s_qy[p2], w0, s_w[p1],
-                                    s_w[p2], g0, s_gs[p1], s_gs[p2], h0, s_gm[p1], s_gm[p2], o);
-                    ox += o.gx[0];
-                    oy += o.gy[0];
-                    ow += o.gw[0];
-                    s_hx[p1] += o.gx[1];
-                    s_hy[p1] += o.gy[1];
-                    s_hw[p1] += o.gw[1];
-                    s_hx[p2] += o.gx[2];
-                    s_hy[p2] += o.gy[2];
-                    s_hw[p2] += o.gw[2];
-                }
-                s_hx[d0] += ox;
-                s_hy[d0] += oy;
-                s_hw[d0] += ow;
-            }
-            __syncthreads();
+        }
+        const bool in_regs = tile_fits && active && len > 0 && len <= LMAX;
+        double hx[LMAX], hy[LMAX], hw[LMAX];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = lane + u * WAVE;
-                if (e < Ew) H[E0 + e] = make_double4(s_hx[e], s_hy[e], s_hw[e], 0.0);
+        for (int k = 0; k < LMAX; ++k) hx[k] = hy[k] = hw[k] = 0.0;
+        if (in_regs) {
+            const int32_t off = rs - E0;
+            uint64_t seen = 0;
+            for (int32_t t = is - I0; t < ie - I0; ++t) {
+                const uint32_t pp = s_ip[t];
+                seen |= (1ull << (pp & 0xffffu)) | (1ull << (pp >> 16));
+            }
+            const int32_t pd = __builtin_ctzll(~seen);
+            const double2 x0 = s_q[off + pd];
+            const double w0 = s_w[off + pd];
+            const double g0 = HS ? s_gs[off + pd] : 0.0, h0 = HM ? s_gm[off + pd] : 0.0;
+            double ox = 0.0, oy = 0.0, ow = 0.0;
+            for (int32_t t = is - I0; t < ie - I0; ++t) {
+                const uint32_t pp = s_ip[t];
+                const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
+                const double2 x1 = s_q[off + p1], x2 = s_q[off + p2];
+                AdjGrad o;
+                adj_tau<HS, HM>(x0.x, x0.y, x1.x, x1.y, x2.x, x2.y, w0, s_w[off + p1],
+                                s_w[off + p2], g0, HS ? s_gs[off + p1] : 0.0,
+                                HS ? s_gs[off + p2] : 0.0, h0, HM ? s_gm[off + p1] : 0.0,
+                                HM ? s_gm[off + p2] : 0.0, o);
+                ox += o.gx[0];
+                oy += o.gy[0];
+                ow += o.gw[0];
+#pragma unroll
+                for (int k = 0; k < LMAX; ++k) {
+                    const bool a1 = k == p1, a2 = k == p2;
+                    hx[k] += a1 ? o.gx[1] : (a2 ? o.gx[2] : 0.0);
+                    hy[k] += a1 ? o.gy[1] : (a2 ? o.gy[2] : 0.0);
+                    if constexpr (HM) hw[k] += a1 ? o.gw[1] : (a2 ? o.gw[2] : 0.0);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < LMAX; ++k)
+                if (k == pd) {
+                    hx[k] += ox;
+                    hy[k] += oy;
+                    hw[k] += ow;
+                }
+        }
+        if (tile_fits) {
+            __syncthreads();   // everyone is done reading the staged inputs
+            const int32_t off = rs - E0;
+            if (in_regs) {
+#pragma unroll
+                for (int k = 0; k < LMAX; ++k)
+                    if (k < len) {
+                        s_stage[3 * (off + k)] = hx[k];
+                        s_stage[3 * (off + k) + 1] = hy[k];
+                        s_stage[3 * (off + k) + 2] = hw[k];
+                    }
+            } else if (active && len > 0) {
+                for (int k = 0; k < 3 * len; ++k) s_stage[3 * off + k] = 0.0;
             }
             __syncthreads();
-        } else if (active && len > 0) {
-            // tile too large for LDS: own row in global memory, same order
+            for (int e = lane; e < Ew; e += WAVE)
+                H[E0 + e] = make_double4(s_stage[3 * e], s_stage[3 * e + 1], s_stage[3 * e + 2], 0.0);
+            __syncthreads();
+        }
+        if (!in_regs && active && len > 0) {
+            // long row or tile too large: own row in global memory, same order
             for (int e = 0; e < len; ++e) H[rs + e] = make_double4(0.0, 0.0, 0.0, 0.0);
             const int32_t *cr = col_idx + rs;
             int32_t pd = 0;
@@ -299,17 +310,91 @@ __global__ __launch_bounds__(256) void k_adj_cols(int32_t nq, const int32_t *__r
     }
 }
 
+// Pass 2 with the transpose map: tile of 64 vertices u (one per lane); the
+// tile's entries are contiguous, so tpos is read coalesced and every lane has
+// U gathers of H in flight before anything waits; each lane then sums its
+// row from LDS in ascending position (the same order as k_adj_cols).
+template <int U>
+__global__ __launch_bounds__(WAVE) void k_adj_cols_tpos(int32_t nq, const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ tpos,
+                                                        const double4 *__restrict__ H,
+                                                        double *__restrict__ dq, double *__restrict__ dw,
+                                                        int accumulate, int64_t ntiles) {
+    constexpr int EB = U * WAVE;
+    __shared__ double s_h[3 * EB];
+    const int lane = threadIdx.x;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * WAVE;
+        const int64_t r1 = (r0 + WAVE < nq) ? r0 + WAVE : nq;
+        const int64_t u = r0 + lane;
+        const bool active = u < nq;
+        const int32_t E0 = row_ptr[r0], E1 = row_ptr[r1], Ew = E1 - E0;
+        const int32_t rs = active ? row_ptr[u] : 0;
+        const int32_t re = active ? row_ptr[u + 1] : 0;
+        double gx = 0.0, gy = 0.0, gw = 0.0;
+        if (Ew <= EB) {
+            int32_t t[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int e = lane + k * WAVE;
+                t[k] = e < Ew ? __builtin_nontemporal_load(tpos + E0 + e) : 0;
+            }
+            double4 h[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int e = lane + k * WAVE;
+                h[k] = e < Ew ? H[t[k]] : make_double4(0.0, 0.0, 0.0, 0.0);
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int e = lane + k * WAVE;
+                if (e < Ew) {
+                    s_h[3 * e] = h[k].x;
+                    s_h[3 * e + 1] = h[k].y;
+                    s_h[3 * e + 2] = h[k].z;
+                }
+            }
+            __syncthreads();
+            for (int32_t e = rs - E0; e < re - E0; ++e) {
+                gx += s_h[3 * e];
+                gy += s_h[3 * e + 1];
+                gw += s_h[3 * e + 2];
+            }
+            __syncthreads();
+        } else {
+            for (int32_t p = rs; p < re; ++p) {
+                const double4 hv = H[tpos[p]];
+                gx += hv.x;
+                gy += hv.y;
+                gw += hv.z;
+            }
+        }
+        if (!active) continue;
+        if (accumulate) {
+            dq[2 * u] += gx;
+            dq[2 * u + 1] += gy;
+            if (dw) dw[u] += gw;
+        } else {
+            dq[2 * u] = gx;
+            dq[2 * u + 1] = gy;
+            if (dw) dw[u] = gw;
+        }
+    }
+}
+
 namespace {
 constexpr int ADJ_U = 8;
+
+constexpr int ADJ_LMAX = 8;
 
 template <bool HS, bool HM>
 int launch_adj(int32_t nq, const double4 *qw, const int32_t *row_ptr, const int32_t *col_idx,
                const int32_t *inc_ptr, const uint32_t *inc_pos, const double *GS, const double *GM,
                double4 *H, hipStream_t s) {
     const int64_t ntiles = (nq + WAVE - 1) / WAVE;
-    const size_t lds = (size_t)ADJ_U * WAVE * (8 * 8 + 4);
-    hipLaunchKernelGGL((k_adj_rows<HS, HM, ADJ_U>), dim3((unsigned)ntiles), dim3(WAVE), lds, s, nq,
-                       qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, ntiles);
+    const size_t lds = (size_t)ADJ_U * WAVE * (5 * 8 + 4);
+    hipLaunchKernelGGL((k_adj_rows<HS, HM, ADJ_U, ADJ_LMAX>), dim3((unsigned)ntiles), dim3(WAVE), lds,
+                       s, nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, ntiles);
     FEM_LAUNCH_CHECK();
     return FEM_OK;
 }
@@ -337,8 +422,8 @@ extern "C" int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, con
     clear_error();
     FEM_REQUIRE(nq >= 1 && nme >= 0 && nnz >= 0 && nnz <= INT32_MAX, FEM_EINVAL,
                 "fem_adjoint_stiff_wmass: bad sizes");
-    FEM_REQUIRE((flags & ~FEM_ACCUMULATE) == 0, FEM_EINVAL,
-                "fem_adjoint_stiff_wmass: only FEM_ACCUMULATE is supported");
+    FEM_REQUIRE((flags & ~(FEM_ACCUMULATE | FEM_PACKED_QW)) == 0, FEM_EINVAL,
+                "fem_adjoint_stiff_wmass: only FEM_ACCUMULATE and FEM_PACKED_QW are supported");
     FEM_REQUIRE(q && row_ptr && dq && work, FEM_EINVAL, "fem_adjoint_stiff_wmass: NULL q, row_ptr, dq or work");
     FEM_REQUIRE(nnz == 0 || (col_idx && inc_ptr && inc_pos), FEM_EINVAL,
                 "fem_adjoint_stiff_wmass: NULL pattern array");
@@ -350,17 +435,26 @@ extern "C" int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, con
     hipStream_t s = as_stream(stream);
     double4 *qw = static_cast<double4 *>(work);
     double4 *H = reinterpret_cast<double4 *>(static_cast<char *>(work) + align256(sizeof(double4) * (size_t)nq));
-    hipLaunchKernelGGL(k_adj_pack, dim3(grid_for(nq, 256)), dim3(256), 0, s, nq,
-                       reinterpret_cast<const double2 *>(q), GM ? w : nullptr, qw);
-    FEM_LAUNCH_CHECK();
+    if (!(flags & FEM_PACKED_QW)) {
+        hipLaunchKernelGGL(k_adj_pack, dim3(grid_for(nq, 256)), dim3(256), 0, s, nq,
+                           reinterpret_cast<const double2 *>(q), GM ? w : nullptr, qw);
+        FEM_LAUNCH_CHECK();
+    }
     int st;
     if (GS && GM) st = launch_adj<true, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, s);
     else if (GS) st = launch_adj<true, false>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, s);
     else if (GM) st = launch_adj<false, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, s);
     else st = fill_f64(reinterpret_cast<double *>(H), 4 * nnz, 0.0, s);
     if (st) return st;
-    hipLaunchKernelGGL(k_adj_cols, dim3(grid_for(nq, 256)), dim3(256), 0, s, nq, row_ptr, col_idx,
-                       tpos, H, dq, dw, (flags & FEM_ACCUMULATE) ? 1 : 0);
+    const int acc = (flags & FEM_ACCUMULATE) ? 1 : 0;
+    if (tpos) {
+        const int64_t ntiles = (nq + WAVE - 1) / WAVE;
+        hipLaunchKernelGGL(k_adj_cols_tpos<ADJ_U>, dim3((unsigned)ntiles), dim3(WAVE), 0, s, nq,
+                           row_ptr, tpos, H, dq, dw, acc, ntiles);
+    } else {
+        hipLaunchKernelGGL(k_adj_cols, dim3(grid_for(nq, 256)), dim3(256), 0, s, nq, row_ptr,
+                           col_idx, tpos, H, dq, dw, acc);
+    }
     FEM_LAUNCH_CHECK();
     return FEM_OK;
 }

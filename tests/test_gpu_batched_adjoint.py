@@ -148,6 +148,27 @@ def test_adjoint_matches_oracle(cfg5):
     pat.tpos = None
 
 
+def test_adjoint_variants_bitwise_equal(cfg5):
+    # tpos or search, packed records from the forward or packed here, fresh or
+    # reused workspace: the same sums in the same order
+    m, w, P, G, pat = cfg5
+    q, wd, Gd = _up(m.q), _up(w), _up(G)
+    pat.tpos = None
+    ref = fem.fem_adjoint_stiff_wmass(pat, q, wd, Gd, Gd)
+    fem.fem_transpose_map(pat)
+    work = fem.fem_adjoint_workspace(pat)
+    fem.fem_assemble(pat, q, fem.FEM_OP_STIFF | fem.FEM_OP_WMASS, w=wd, work=work)
+    for packed in (True, False, True):
+        got = fem.fem_adjoint_stiff_wmass(pat, q, wd, Gd, Gd, work=work, packed=packed)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), packed
+    # accumulate adds into the outputs
+    dq, dw = ref[0].clone(), ref[1].clone()
+    fem.fem_adjoint_stiff_wmass(pat, q, wd, Gd, Gd, dq=dq, dw=dw, flags=fem.FEM_ACCUMULATE)
+    assert torch.equal(dq, 2 * ref[0]) and torch.equal(dw, 2 * ref[1])
+    pat.tpos = None
+
+
 def test_adjoint_central_differences(cfg5):
     # central differences of L on 64 random coordinates (h = 1e-6 for q); L restricted
     # to the rows the perturbed vertex touches (the other values are computed
