@@ -166,7 +166,7 @@ int fem_transpose_map(int32_t nq, int64_t nnz, const int32_t *row_ptr, const int
  * 2i + alpha holds columns 2j, 2j + 1 for every column j of scalar row i.
  *   row_ptr_e [2nq+1]: row_ptr_e[2i] = 4 row_ptr[i],
  *                      row_ptr_e[2i+1] = 4 row_ptr[i] + 2 len_i
- *   col_idx_e [4 nnz]
+ *   col_idx_e [4 nnz], 8-byte aligned (FEM_EINVAL otherwise)
  * Entry (2i+alpha, 2j+beta), j the p-th column of row i, sits at
  * 4 row_ptr[i] + 2 alpha len_i + 2 (p - row_ptr[i]) + beta. */
 int fem_elas_pattern(int32_t nq, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,

@@ -437,6 +437,15 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
             nd += f[k] ? 1 : 0;
         }
         L = d > 0 ? nd + 1 : 0;
+        // sorted triangles and the positions of their two neighbours in the
+        // row, back into the vertex's own LDS slice (copied out in step 5)
+#pragma unroll
+        for (int t = 0; t < REG_MAX; ++t)
+            if (t < d) {
+                s_key[is + t] = key[t];
+                s_n1[is + t] = static_cast<int32_t>(static_cast<uint32_t>(reg_rank(n1[t])) |
+                                                    (static_cast<uint32_t>(reg_rank(n2[t])) << 16));
+            }
     } else if (d <= FINE_DMAX) {
         // insertion sort of the vertex's LDS slice by triangle
         for (int t = 1; t < d; ++t) {
@@ -473,24 +482,17 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
     const int32_t lro = block_exclusive_scan_i32(L, s_wsum, &Tb);
     if (v < nq) rowoff[v] = lro;
     if (tid == 0) btot[b] = Tb;
-    // ---- 5 the vertex's slice of inc / inc_pos
+    // ---- 5 inc / inc_pos.  The register path has put its sorted triangles
+    // and positions into its own LDS slices (s_key, s_n1) in step 3; the LDS
+    // path (whose s_n1 / s_n2 are still read in step 6) writes its positions
+    // directly and marks its slice afterwards; the whole bucket is then
+    // copied out coalesced.
+    constexpr uint32_t POS_DIRECT = 0xffffffffu;   // never a position pair here
     const int64_t ib = e0 + is;
-    if (!bad && d > 0) {
-        if (in_regs) {
-#pragma unroll
-            for (int t = 0; t < REG_MAX; ++t)
-                if (t < d) {
-                    inc[ib + t] = key[t];
-                    inc_pos[ib + t] = static_cast<uint32_t>(reg_rank(n1[t])) |
-                                      (static_cast<uint32_t>(reg_rank(n2[t])) << 16);
-                }
-        } else {
-            for (int t = 0; t < d; ++t) {
-                inc[ib + t] = s_key[is + t];
-                inc_pos[ib + t] = static_cast<uint32_t>(lds_rank(s_n1[is + t])) |
-                                  (static_cast<uint32_t>(lds_rank(s_n2[is + t])) << 16);
-            }
-        }
+    if (!bad && d > 0 && !in_regs) {
+        for (int t = 0; t < d; ++t)
+            inc_pos[ib + t] = static_cast<uint32_t>(lds_rank(s_n1[is + t])) |
+                              (static_cast<uint32_t>(lds_rank(s_n2[is + t])) << 16);
     }
     // ---- 6 the rows, into the bucket's part of stage
     if (L > 0 && !bad) {
@@ -514,6 +516,16 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
             for (int u = 0; u < 2 * d; ++u)
                 if (first(u)) out[lds_rank(cand(u))] = cand(u);
             out[lds_rank((int32_t)v)] = (int32_t)v;
+            for (int t = 0; t < d; ++t) s_n1[is + t] = static_cast<int32_t>(POS_DIRECT);
+        }
+    }
+    __syncthreads();
+    if (fits) {
+        const int32_t n = static_cast<int32_t>(e1 - e0);
+        for (int32_t p = tid; p < n; p += BKT_THREADS) {
+            inc[e0 + p] = s_key[p];
+            const uint32_t pp = static_cast<uint32_t>(s_n1[p]);
+            if (pp != POS_DIRECT) inc_pos[e0 + p] = pp;
         }
     }
     // ---- maxima
@@ -863,14 +875,20 @@ __global__ __launch_bounds__(256) void k_transpose(int32_t nq, const int32_t *__
     }
 }
 
-// Tile of 64 scalar rows = a contiguous slice of 4 Ew elasticity entries:
-// one output entry per lane (coalesced), its row found by a search over the
-// tile's 64 row offsets in LDS.
+constexpr int ELAS_STAGE = 8 * WAVE;   // scalar entries of a tile staged in LDS (8 KiB)
+
+// Tile of 64 scalar rows = a contiguous slice of Ew scalar entries and of
+// 4 Ew elasticity entries.  One lane per scalar entry (coalesced read of
+// col_idx): its row is found by a search over the tile's 64 row offsets in
+// LDS, and it writes the pair (2c, 2c+1) into both elasticity rows 2i and
+// 2i+1 (8-byte aligned: 4 rs + 2k and 4 rs + 2L + 2k are even).
 __global__ __launch_bounds__(WAVE) void k_elas_pattern(int32_t nq, const int32_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ col_idx,
                                                        int32_t *__restrict__ row_ptr_e,
-                                                       int32_t *__restrict__ col_idx_e) {
+                                                       int32_t *__restrict__ col_idx_e,
+                                                       int aligned16) {
     __shared__ int32_t s_rs[WAVE + 1];
+    __shared__ __align__(16) int32_t s_out[4 * ELAS_STAGE];
     const int lane = threadIdx.x;
     const int64_t r0 = blockIdx.x * (int64_t)WAVE;
     const int64_t i = r0 + lane;
@@ -885,20 +903,31 @@ __global__ __launch_bounds__(WAVE) void k_elas_pattern(int32_t nq, const int32_t
     }
     if (r0 + nr == nq && lane == 0) row_ptr_e[2 * (int64_t)nq] = 4 * s_rs[nr];
     const int32_t E0 = s_rs[0], Ew = s_rs[nr] - E0;
-    for (int32_t o = lane; o < 4 * Ew; o += WAVE) {
-        const int32_t g = E0 + (o >> 2);
+    // tiles of at most ELAS_STAGE entries are assembled in LDS and written
+    // as int4 (the tile's output starts at 4 E0 ints: 16-byte aligned when
+    // col_idx_e is)
+    const bool staged = aligned16 && Ew <= ELAS_STAGE;
+    for (int32_t e = lane; e < Ew; e += WAVE) {
+        const int32_t g = E0 + e;
+        const int32_t c = col_idx[g];
+        // the row holding g: the last row start <= g (empty rows share a start)
         int lo = 0, hi = nr - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (s_rs[mid] <= g) lo = mid;
             else hi = mid - 1;
         }
-        // rs <= g < re  <=>  4 rs <= 4 E0 + o < 4 re: the row's 4 L slots
-        // [row 2i | row 2i+1]
-        const int32_t rs = s_rs[lo], L = s_rs[lo + 1] - rs;
-        const int32_t rem = 4 * E0 + o - 4 * rs;
-        const int32_t r2 = rem % (2 * L);
-        col_idx_e[4 * (int64_t)E0 + o] = 2 * col_idx[rs + (r2 >> 1)] + (r2 & 1);
+        const int32_t rs = s_rs[lo], L = s_rs[lo + 1] - rs, k = g - rs;
+        const int2 v = make_int2(2 * c, 2 * c + 1);
+        int32_t *base = staged ? s_out + 4 * (rs - E0) + 2 * k : col_idx_e + 4 * (int64_t)rs + 2 * k;
+        *reinterpret_cast<int2 *>(base) = v;
+        *reinterpret_cast<int2 *>(base + 2 * L) = v;
+    }
+    if (staged) {
+        __syncthreads();
+        int4 *dst = reinterpret_cast<int4 *>(col_idx_e + 4 * (int64_t)E0);
+        const int4 *src = reinterpret_cast<const int4 *>(s_out);
+        for (int32_t t = lane; t < Ew; t += WAVE) dst[t] = src[t];
     }
 }
 
@@ -1166,8 +1195,11 @@ extern "C" int fem_elas_pattern(int32_t nq, int64_t nnz, const int32_t *row_ptr,
                 "fem_elas_pattern: 4 nnz = %lld exceeds int32", (long long)(4 * nnz));
     FEM_REQUIRE(row_ptr && row_ptr_e && (nnz == 0 || (col_idx && col_idx_e)), FEM_EINVAL,
                 "fem_elas_pattern: NULL array");
+    FEM_REQUIRE((reinterpret_cast<uintptr_t>(col_idx_e) & 7) == 0, FEM_EINVAL,
+                "fem_elas_pattern: col_idx_e must be 8-byte aligned");
     hipLaunchKernelGGL(k_elas_pattern, dim3(grid_for(nq, WAVE)), dim3(WAVE), 0,
-                       as_stream(stream), nq, row_ptr, col_idx, row_ptr_e, col_idx_e);
+                       as_stream(stream), nq, row_ptr, col_idx, row_ptr_e, col_idx_e,
+                       (reinterpret_cast<uintptr_t>(col_idx_e) & 15) == 0 ? 1 : 0);
     FEM_LAUNCH_CHECK();
     return FEM_OK;
 }

@@ -140,3 +140,29 @@ def test_set_path_rejects_unknown():
     with pytest.raises(fem.FemError) as e:
         fem.fem_pattern_set_path(7)
     assert e.value.status == _lib.FEM_EINVAL
+
+
+def test_elas_pattern_alignments():
+    # 16-byte aligned output: LDS-staged int4 stores; 8-byte aligned: direct
+    # int2 stores; 4-byte aligned: refused
+    m = mg.unit_square(20, seed=6)
+    pat = fem.fem_pattern(_up(m.me), m.nq)
+    rpe, cie, _ = oracle.pattern_elas(m.nq, m.me)
+    lib = _lib.load()
+    stream = torch.cuda.current_stream().cuda_stream
+    n4 = 4 * pat.nnz
+    rp = torch.empty(2 * m.nq + 1, dtype=torch.int32, device=DEV)
+    buf = torch.full((n4 + 8,), -1, dtype=torch.int32, device=DEV)
+    for shift, ok in ((0, True), (2, True), (1, False)):
+        buf.fill_(-1)
+        view = buf[shift:shift + n4]
+        st = lib.fem_elas_pattern(m.nq, pat.nnz, pat.row_ptr.data_ptr(), pat.col_idx.data_ptr(),
+                                  rp.data_ptr(), view.data_ptr(), stream)
+        torch.cuda.synchronize()
+        assert (st == 0) == ok, (shift, st)
+        if ok:
+            np.testing.assert_array_equal(_np(rp), rpe)
+            np.testing.assert_array_equal(_np(view), cie)
+            assert bool((buf[:shift] == -1).all()) and bool((buf[shift + n4:] == -1).all())
+        else:
+            assert st == _lib.FEM_EINVAL
