@@ -101,6 +101,43 @@ constexpr int NBLK_TARGET = 256;              // triangle workgroups of the part
 // device-side error bits of the fine path
 enum : int { ERR_BUCKET = 16, ERR_NOSPC = 32 };
 
+// Bucket records.  Wide (16 B): (v, 3k + a, next, previous).  Packed (12 B,
+// fine buckets of meshes with nq <= 2^23 vertices): (3k + a, next | (v mod
+// FINE_V) << 23, previous).  rec_* give the vertex relative to its bucket,
+// the key and the two neighbours, whichever the layout; a vertex of -1 marks
+// an empty slot.
+constexpr int PACK_SHIFT = 23;
+constexpr int32_t PACK_MASK = (1 << PACK_SHIFT) - 1;
+
+struct Rec {
+    int32_t lv, key, n1, n2;
+};
+
+template <bool PK>
+__device__ __forceinline__ Rec load_rec(const int32_t *__restrict__ ent, int64_t e, int32_t v0) {
+    if constexpr (PK) {
+        const int32_t *p = ent + 3 * e;
+        const int32_t k = p[0], a = p[1], c = p[2];
+        return Rec{static_cast<int32_t>(static_cast<uint32_t>(a) >> PACK_SHIFT), k, a & PACK_MASK, c};
+    } else {
+        const int4 r = reinterpret_cast<const int4 *>(ent)[e];
+        return Rec{r.x - v0, r.y, r.z, r.w};
+    }
+}
+
+template <bool PK>
+__device__ __forceinline__ void store_rec(int32_t *__restrict__ ent, int64_t e, int32_t v, int32_t key,
+                                          int32_t n1, int32_t n2) {
+    if constexpr (PK) {
+        int32_t *p = ent + 3 * e;
+        p[0] = key;
+        p[1] = n1 | ((v & (FINE_V - 1)) << PACK_SHIFT);
+        p[2] = n2;
+    } else {
+        reinterpret_cast<int4 *>(ent)[e] = make_int4(v, key, n1, n2);
+    }
+}
+
 __device__ inline bool tri_ok(int32_t a, int32_t b, int32_t c, int32_t nq) {
     return (uint32_t)a < (uint32_t)nq && (uint32_t)b < (uint32_t)nq && (uint32_t)c < (uint32_t)nq &&
            a != b && b != c && a != c;
@@ -141,13 +178,13 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_count(int32_t nme, const in
 }
 
 // Same triangles per workgroup as k_bkt_count: each incidence goes to the run
-// of its (bucket, workgroup) pair as one record (vertex, 3k + a, next,
-// previous).
+// of its (bucket, workgroup) pair as one record.
+template <bool PK>
 __global__ __launch_bounds__(BKT_THREADS) void k_bkt_scatter(int32_t nme, const int32_t *__restrict__ me,
                                                             int32_t nq, int bs, int32_t nbkt,
                                                             int32_t tpb,
                                                             const int32_t *__restrict__ offs,
-                                                            int4 *__restrict__ ent) {
+                                                            int32_t *__restrict__ ent) {
     extern __shared__ int32_t s_cur[];
     const int32_t nblk = gridDim.x;
     for (int b = threadIdx.x; b < nbkt; b += BKT_THREADS)
@@ -175,8 +212,8 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_scatter(int32_t nme, const 
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int32_t pos = atomicAdd(&s_cur[v[j][a] >> bs], 1);
-                ent[pos] = make_int4(v[j][a], static_cast<int32_t>(3 * k + a), v[j][(a + 1) % 3],
-                                     v[j][(a + 2) % 3]);
+                store_rec<PK>(ent, pos, v[j][a], static_cast<int32_t>(3 * k + a), v[j][(a + 1) % 3],
+                              v[j][(a + 2) % 3]);
             }
         }
     }
@@ -188,12 +225,13 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_scatter(int32_t nme, const 
 __global__ __launch_bounds__(BKT_THREADS) void k_bkt_sort(int32_t nq, int32_t nblk,
                                                          const int32_t *__restrict__ offs,
                                                          const int32_t *__restrict__ total_ptr,
-                                                         const int4 *__restrict__ ent,
+                                                         const int32_t *__restrict__ ent_w,
                                                          int32_t *__restrict__ inc_ptr,
                                                          int32_t *__restrict__ inc,
                                                          int2 *__restrict__ nbr) {
     __shared__ int32_t s_cnt[COARSE_V];
     __shared__ int32_t s_wsum[BKT_THREADS / WAVE];
+    const int4 *ent = reinterpret_cast<const int4 *>(ent_w);
     const int32_t b = blockIdx.x;
     const int64_t total = *total_ptr;
     const int64_t e0 = offs[(int64_t)b * nblk];
@@ -340,9 +378,10 @@ __device__ inline int32_t block_exclusive_scan_i32(int32_t v, int32_t *s_wsum, i
 // are scanned.  A bucket with more than FINE_CAP incidences, or a vertex with
 // more than FINE_DMAX triangles, sets ERR_BUCKET: the host then rebuilds with
 // the coarse path.
+template <bool PK>
 __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
     int32_t nq, int32_t nbkt, int32_t nblk, const int32_t *__restrict__ offs,
-    const int32_t *__restrict__ total_ptr, const int4 *__restrict__ ent, int32_t *__restrict__ inc_ptr,
+    const int32_t *__restrict__ total_ptr, const int32_t *__restrict__ ent, int32_t *__restrict__ inc_ptr,
     int32_t *__restrict__ inc, uint32_t *__restrict__ inc_pos, int32_t *__restrict__ rowoff,
     int32_t *__restrict__ btot, int32_t *__restrict__ stage, PatternCounters *cnt) {
     __shared__ int32_t s_cur[FINE_V];
@@ -359,17 +398,17 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
     int32_t d = 0, is = 0;
     // ---- 1 count, scan (the bucket's records stay in registers)
     constexpr int EPT = FINE_CAP / BKT_THREADS;
-    int4 x[EPT];
+    Rec x[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
         const int64_t y = e0 + tid + u * BKT_THREADS;
-        x[u] = (fits && y < e1) ? ent[y] : make_int4(-1, 0, 0, 0);
+        x[u] = (fits && y < e1) ? load_rec<PK>(ent, y, v0) : Rec{-1, 0, 0, 0};
     }
     s_cur[tid] = 0;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < EPT; ++u)
-        if (x[u].x >= 0) atomicAdd(&s_cur[x[u].x - v0], 1);
+        if (x[u].lv >= 0) atomicAdd(&s_cur[x[u].lv], 1);
     __syncthreads();
     d = s_cur[tid];
     int32_t unused;
@@ -381,11 +420,11 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
     // ---- 2 counting sort into LDS
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-        if (x[u].x < 0) continue;
-        const int32_t p = atomicAdd(&s_cur[x[u].x - v0], 1);
-        s_key[p] = x[u].y;
-        s_n1[p] = x[u].z;
-        s_n2[p] = x[u].w;
+        if (x[u].lv < 0) continue;
+        const int32_t p = atomicAdd(&s_cur[x[u].lv], 1);
+        s_key[p] = x[u].key;
+        s_n1[p] = x[u].n1;
+        s_n2[p] = x[u].n2;
     }
     __syncthreads();
     // ---- 3 per vertex: triangles by id, distinct neighbours, row length
@@ -959,8 +998,8 @@ struct PatternWork {
     int32_t *deg, *rowlen, *wide, *mid, *counts;
     long long *part;
     int2 *nbr;
-    int4 *ent;                             // bucket records; the region is reused
-                                           //   for `stage` and `scratch`
+    int32_t *ent;                          // bucket records (12 or 16 B); the region
+                                           //   is reused for `stage` and `scratch`
     int32_t *stage, *scratch;
     BucketPlan fine, coarse;               // nbkt == 0: level not usable
     size_t bytes;
@@ -999,7 +1038,7 @@ PatternWork carve(int32_t nq, int32_t nme, char *base) {
     const size_t ent_bytes = bucket ? sizeof(int4) * 3 * (size_t)nme : 0;
     const size_t stage_bytes = align_up(sizeof(int32_t) * stage_n);
     char *big = take(ent_bytes > 2 * stage_bytes ? ent_bytes : 2 * stage_bytes);
-    w.ent = reinterpret_cast<int4 *>(big);
+    w.ent = reinterpret_cast<int32_t *>(big);
     w.stage = reinterpret_cast<int32_t *>(big);
     w.scratch = reinterpret_cast<int32_t *>(big ? big + stage_bytes : nullptr);
     w.bytes = off;
@@ -1009,8 +1048,8 @@ PatternWork carve(int32_t nq, int32_t nme, char *base) {
 // Partition the incidences into the buckets of plan P: counts per
 // (bucket, workgroup), their scan, and the scatter into ent_*.  The total
 // number of incidences stays on the device at counts[P.ncounts()].
-int partition(const PatternWork &W, const BucketPlan &P, int32_t nq, int32_t nme, const int32_t *me,
-              hipStream_t s) {
+int partition(const PatternWork &W, const BucketPlan &P, bool packed, int32_t nq, int32_t nme,
+              const int32_t *me, hipStream_t s) {
     const size_t hist_lds = sizeof(int32_t) * (size_t)P.nbkt;
     hipLaunchKernelGGL(k_bkt_count, dim3(P.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me, nq,
                        P.shift, P.nbkt, P.tpb, W.counts, W.cnt);
@@ -1019,8 +1058,12 @@ int partition(const PatternWork &W, const BucketPlan &P, int32_t nq, int32_t nme
     if ((st = exclusive_scan_i32(W.counts, W.counts, P.ncounts(), W.part, &W.cnt->total[2],
                                  &W.cnt->err, s)))
         return st;
-    hipLaunchKernelGGL(k_bkt_scatter, dim3(P.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me, nq,
-                       P.shift, P.nbkt, P.tpb, W.counts, W.ent);
+    if (packed)
+        hipLaunchKernelGGL(k_bkt_scatter<true>, dim3(P.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me,
+                           nq, P.shift, P.nbkt, P.tpb, W.counts, W.ent);
+    else
+        hipLaunchKernelGGL(k_bkt_scatter<false>, dim3(P.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me,
+                           nq, P.shift, P.nbkt, P.tpb, W.counts, W.ent);
     FEM_LAUNCH_CHECK();
     return FEM_OK;
 }
@@ -1099,11 +1142,18 @@ extern "C" int fem_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *
         // fine path: partition into 512-vertex buckets; one kernel sorts each
         // bucket and writes inc_ptr, inc, inc_pos and the staged rows; the
         // scan of the bucket totals places the rows in col_idx
-        if ((st = partition(W, W.fine, nq, nme, me, s))) return st;
+        // 12-byte records when a vertex index leaves 9 spare bits
+        const bool packed = nq <= (1 << PACK_SHIFT);
+        if ((st = partition(W, W.fine, packed, nq, nme, me, s))) return st;
         int32_t *fstage = reinterpret_cast<int32_t *>(W.nbr);
-        hipLaunchKernelGGL(k_bkt_rows, dim3(W.fine.nbkt), dim3(BKT_THREADS), 0, s, nq, W.fine.nbkt,
-                           W.fine.nblk, W.counts, W.counts + W.fine.ncounts(), W.ent, inc_ptr, inc,
-                           inc_pos, W.rowlen, W.btot, fstage, W.cnt);
+        if (packed)
+            hipLaunchKernelGGL(k_bkt_rows<true>, dim3(W.fine.nbkt), dim3(BKT_THREADS), 0, s, nq,
+                               W.fine.nbkt, W.fine.nblk, W.counts, W.counts + W.fine.ncounts(), W.ent,
+                               inc_ptr, inc, inc_pos, W.rowlen, W.btot, fstage, W.cnt);
+        else
+            hipLaunchKernelGGL(k_bkt_rows<false>, dim3(W.fine.nbkt), dim3(BKT_THREADS), 0, s, nq,
+                               W.fine.nbkt, W.fine.nblk, W.counts, W.counts + W.fine.ncounts(), W.ent,
+                               inc_ptr, inc, inc_pos, W.rowlen, W.btot, fstage, W.cnt);
         FEM_LAUNCH_CHECK();
         if ((st = exclusive_scan_i32(W.btot, W.bptr, W.fine.nbkt, W.part, &W.cnt->total[1],
                                      &W.cnt->err, s)))
@@ -1122,7 +1172,7 @@ extern "C" int fem_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *
     if (!done) {
         if (W.coarse.nbkt > 0 && path != FEM_PATTERN_ATOMIC) {
             // group the incidences by vertex: two-level counting sort, no global atomics
-            if ((st = partition(W, W.coarse, nq, nme, me, s))) return st;
+            if ((st = partition(W, W.coarse, false, nq, nme, me, s))) return st;
             hipLaunchKernelGGL(k_bkt_sort, dim3(W.coarse.nbkt), dim3(BKT_THREADS), 0, s, nq,
                                W.coarse.nblk, W.counts, W.counts + W.coarse.ncounts(), W.ent,
                                inc_ptr, inc, W.nbr);

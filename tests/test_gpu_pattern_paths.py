@@ -166,3 +166,29 @@ def test_elas_pattern_alignments():
             assert bool((buf[:shift] == -1).all()) and bool((buf[shift + n4:] == -1).all())
         else:
             assert st == _lib.FEM_EINVAL
+
+
+def test_wide_records_above_packing_limit(path_reset):
+    # nq = 2898^2 = 8,398,404 > 2^23: the fine path stores 16-byte records
+    # (the vertex no longer fits beside a neighbour index); it must agree bit
+    # for bit with the coarse path, and nnz must follow Euler's formula
+    m = mg.unit_square(2897, seed=mg.BASE_SEED + 77)
+    assert m.nq > (1 << 23)
+    print(f"[case] wide records nq={m.nq} nme={m.nme}", flush=True)
+    me = _up(m.me)
+    fem.fem_pattern_set_path(fem.FEM_PATTERN_AUTO)
+    a = fem.fem_pattern(me, m.nq)
+    fem.fem_pattern_set_path(fem.FEM_PATTERN_COARSE)
+    b = fem.fem_pattern(me, m.nq)
+    torch.cuda.synchronize()
+    assert a.nnz == m.nq + 2 * (m.nq + m.nme - 1)
+    for f in ("row_ptr", "col_idx", "inc_ptr", "inc", "inc_pos"):
+        assert torch.equal(getattr(a, f), getattr(b, f)), f
+    # sampled rows: the vertex and its neighbours, from the triangles around it
+    rng = np.random.default_rng(5)
+    rows = np.unique(rng.choice(m.nq, 200, replace=False)).astype(np.int32)
+    rp, ci = _np(a.row_ptr), _np(a.col_idx)
+    near = m.me[np.isin(m.me, rows).any(axis=1)]
+    for r in rows:
+        want = np.unique(near[(near == r).any(axis=1)].ravel())
+        np.testing.assert_array_equal(ci[rp[r]:rp[r + 1]], want)
