@@ -286,6 +286,44 @@ int fem_graph_launch(void *graph, void *stream);
 int fem_graph_destroy(void *graph);
 
 /* ------------------------------------------------------------------------ */
+/* General sparse(I, J, V, m, n)                                             */
+/* ------------------------------------------------------------------------ */
+
+/* HOST ONLY.  Bytes of device workspace fem_sparse needs for nt triplets. */
+int fem_sparse_workspace(int32_t m, int32_t n, int64_t nt, size_t *bytes /* HOST */);
+
+/* Matlab's A = sparse(I, J, V, m, n) (the compression that ends every OptV2
+ * assembly, Section 6; storage as in Section 4), 0-based and in CSR:
+ *   I, J [nt] int32   row and column of each triplet, in [0, m) and [0, n)
+ *   V    [nt] f64     values (may be NULL when vals is NULL)
+ *   row_ptr [m+1], col_idx [col_cap]   rows ascending, columns ascending, one
+ *                     entry per distinct (i, j); entries whose values sum to
+ *                     zero are kept (structural)
+ *   vals [col_cap] or NULL: vals[p] = sum of V[t] over the triplets of entry p,
+ *                     added in ascending t (a left-to-right sum: bitwise
+ *                     reproducible, equal to a sequential loop over t)
+ *   contrib_ptr [col_cap+1], contrib [nt], both or neither: the triplets of
+ *                     entry p are contrib[contrib_ptr[p] .. contrib_ptr[p+1]),
+ *                     ascending (fem_sparse_values re-sums new values)
+ *   work [work_bytes] >= fem_sparse_workspace(m, n, nt); nnz_out HOST
+ * Requires m, n >= 1, 0 <= nt <= 2^31 - 1 and m <= 36864 * 512.  Returns
+ * FEM_ERANGE for an index outside its range, FEM_ENOSPC if col_cap < nnz.
+ * Synchronises `stream` once (to return nnz).  Rows whose triplets do not fit
+ * the on-chip sort (more than 3072 in a bucket of rows) take a slower path
+ * through global memory; results are identical. */
+int fem_sparse(int32_t m, int32_t n, int64_t nt, const int32_t *I, const int32_t *J,
+               const double *V, int32_t *row_ptr, int32_t *col_idx, double *vals,
+               int64_t col_cap, int32_t *contrib_ptr, int32_t *contrib, void *work,
+               size_t work_bytes, int64_t *nnz_out /* HOST */, void *stream);
+
+/* vals[p] = sum of V[contrib[k]], k from contrib_ptr[p] to contrib_ptr[p+1] - 1,
+ * in that order (the numeric phase of fem_sparse for new values on the same
+ * I, J; bitwise equal to what fem_sparse returns for them).  flags: 0 or
+ * FEM_ACCUMULATE. */
+int fem_sparse_values(int64_t nnz, const int32_t *contrib_ptr, const int32_t *contrib,
+                      const double *V, double *vals, int flags, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Adjoint                                                                   */
 /* ------------------------------------------------------------------------ */
 

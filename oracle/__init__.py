@@ -150,6 +150,18 @@ def sparse(I, J, V, nrows: int, ncols: int):
     return row_ptr, col_idx[:nnz].copy(), vals[:nnz].copy()
 
 
+def sparse_positions(I, J, nrows: int, ncols: int):
+    """(row_ptr, col_idx, pos) of sparse(I, J, ., nrows, ncols): pos[t] is the
+    CSR position triplet t is summed into."""
+    I, J = _i32(I), _i32(J)
+    n = I.shape[0]
+    row_ptr = np.zeros(nrows + 1, np.int32)
+    col_idx = np.zeros(max(n, 1), np.int32)
+    pos = np.zeros(max(n, 1), np.int64)
+    nnz = _check(_load().oracle_csr_pattern(nrows, ncols, n, I, J, row_ptr, col_idx, pos))
+    return row_ptr, col_idx[:nnz].copy(), pos[:n].copy()
+
+
 # ---- mesh-level entry points ----------------------------------------------------
 
 class Pattern:

@@ -31,7 +31,8 @@ __all__ = [
     "fem_pattern", "fem_transpose_map", "fem_elas_pattern", "fem_assemble", "fem_assemble_mass",
     "fem_assemble_wmass", "fem_assemble_stiff", "fem_assemble_stiff_mass",
     "fem_assemble_stiff_wmass", "fem_assemble_elas", "fem_batch_globalize",
-    "fem_assemble_stiff_mass_batched", "Graph", "fem_adjoint_workspace", "fem_adjoint_stiff_wmass",
+    "fem_assemble_stiff_mass_batched", "Graph", "SparseCSR", "fem_sparse", "fem_sparse_values",
+    "fem_adjoint_workspace", "fem_adjoint_stiff_wmass",
     "AssembleStiffWMass",
     "library_path",
 ]
@@ -312,6 +313,66 @@ class Graph:
         if self.handle is not None and _lib._lib is not None:
             _lib._lib.fem_graph_destroy(self.handle)
             self.handle = None
+
+
+@dataclasses.dataclass
+class SparseCSR:
+    """Result of fem_sparse (device tensors)."""
+    m: int
+    n: int
+    nnz: int
+    row_ptr: object          # [m+1] int32
+    col_idx: object          # [nnz] int32
+    vals: object = None      # [nnz] float64 or None
+    contrib_ptr: object = None   # [nnz+1] int32 or None
+    contrib: object = None       # [nt] int32 or None
+
+    def csr(self):
+        torch = _torch()
+        return torch.sparse_csr_tensor(self.row_ptr, self.col_idx, self.vals, (self.m, self.n))
+
+
+def fem_sparse(I, J, V, m: int, n: int, *, contrib: bool = False, stream=None) -> SparseCSR:
+    """sparse(I, J, V, m, n) into CSR (C: fem_sparse).  I, J: [nt] int32 and V:
+    [nt] float64 (or None for the pattern only) on the GPU."""
+    torch = _torch()
+    lib = _lib.load()
+    _dev(I, torch.int32, "I")
+    nt = int(I.shape[0])
+    _dev(J, torch.int32, "J", (nt,))
+    if V is not None:
+        _dev(V, torch.float64, "V", (nt,))
+    dev = I.device
+    ws = C.c_size_t(0)
+    _lib.check(lib.fem_sparse_workspace(int(m), int(n), nt, C.byref(ws)))
+    work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
+    cap = nt
+    i32 = dict(dtype=torch.int32, device=dev)
+    row_ptr = torch.empty(int(m) + 1, **i32)
+    col = torch.empty(max(cap, 1), **i32)
+    vals = torch.empty(max(cap, 1), dtype=torch.float64, device=dev) if V is not None else None
+    cptr = torch.empty(cap + 1, **i32) if contrib else None
+    ctb = torch.empty(max(nt, 1), **i32) if contrib else None
+    nnz = C.c_int64(0)
+    _lib.check(lib.fem_sparse(int(m), int(n), nt, _ptr(I), _ptr(J), _ptr(V), _ptr(row_ptr),
+                              _ptr(col), _ptr(vals), cap, _ptr(cptr), _ptr(ctb), _ptr(work),
+                              int(ws.value), C.byref(nnz), _stream(stream)))
+    k = int(nnz.value)
+    return SparseCSR(int(m), int(n), k, row_ptr, col[:k], None if vals is None else vals[:k],
+                     None if cptr is None else cptr[:k + 1], None if ctb is None else ctb[:nt])
+
+
+def fem_sparse_values(A: SparseCSR, V, *, out=None, flags: int = 0, stream=None):
+    """New values on the triplets of a fem_sparse result built with contrib=True
+    (C: fem_sparse_values)."""
+    torch = _torch()
+    if A.contrib is None:
+        raise ValueError("fem_sparse_values needs a fem_sparse result with contrib=True")
+    _dev(V, torch.float64, "V", (int(A.contrib.shape[0]),))
+    out = torch.empty(max(A.nnz, 1), dtype=torch.float64, device=V.device)[:A.nnz] if out is None else out
+    _lib.check(_lib.load().fem_sparse_values(A.nnz, _ptr(A.contrib_ptr), _ptr(A.contrib), _ptr(V),
+                                             _ptr(out), flags, _stream(stream)))
+    return out
 
 
 def fem_adjoint_workspace(pat: Pattern):

@@ -81,6 +81,10 @@ SIGNATURES = {
     "fem_graph_end": (_int, [_vp, C.POINTER(_vp)]),
     "fem_graph_launch": (_int, [_vp, _vp]),
     "fem_graph_destroy": (_int, [_vp]),
+    "fem_sparse_workspace": (_int, [_i32, _i32, _i64, _szp]),
+    "fem_sparse": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
+                          C.c_size_t, C.POINTER(_i64), _vp]),
+    "fem_sparse_values": (_int, [_i64, _vp, _vp, _vp, _vp, _int, _vp]),
     "fem_adjoint_workspace": (_int, [_i32, _i64, _szp]),
     "fem_adjoint_stiff_wmass": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                        _vp, _vp, _vp, _vp, C.c_size_t, _int, _vp]),

@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfem_p1.so")
-SOURCES = ["fem_common.hip", "fem_pattern.hip", "fem_numeric.hip", "fem_adjoint.hip"]
+SOURCES = ["fem_common.hip", "fem_pattern.hip", "fem_numeric.hip", "fem_adjoint.hip",
+           "fem_sparse.hip"]
 ARCH = os.environ.get("FEM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
