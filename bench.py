@@ -14,7 +14,8 @@ Also reported: per-call HIP-event times and the roofline of each numeric
 kernel (algorithmic bytes), the stiffness + mass pair alone, the batched
 block-diagonal assembly of 512 meshes (one graph-captured launch) against a
 per-mesh launch loop, the forward + backward / forward ratio of the
-differentiable assembly, and the CPU oracle timed on a bounded sample.
+differentiable assembly, the general sparse(I, J, V) compression of the
+OptV2 triplet arrays, and the CPU oracle timed on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
 
@@ -529,6 +530,74 @@ def run_adjoint(torch, fem, args):
     return out
 
 
+def run_sparse(torch, fem, args):
+    """General sparse(I, J, V, m, n) on the OptV2 triplet arrays of the
+    2048 x 2048 square (Ig, Jg of all 9 local entries of every triangle, 75.5M
+    triplets, random values): the compression the OptV2 assembly ends in."""
+    from paper_1305_3122_amd import meshgen as mg
+    lib = fem._lib.load()
+    dev = torch.device("cuda:0")
+    m = mg.config_mesh(2)
+    a = np.tile(np.arange(3), 3)
+    b = np.repeat(np.arange(3), 3)
+    I = torch.from_numpy(np.ascontiguousarray(m.me[:, a].T.reshape(-1))).to(dev)
+    J = torch.from_numpy(np.ascontiguousarray(m.me[:, b].T.reshape(-1))).to(dev)
+    nt = int(I.shape[0])
+    V = torch.from_numpy(mg.normal_seed(nt, seed=mg.BASE_SEED + 202)).to(dev)
+    ws = C.c_size_t(0)
+    fem._lib.check(lib.fem_sparse_workspace(m.nq, m.nq, nt, C.byref(ws)))
+    work = torch.empty(int(ws.value), dtype=torch.uint8, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    row_ptr = torch.empty(m.nq + 1, **i32)
+    col = torch.empty(nt, **i32)
+    vals = torch.empty(nt, dtype=torch.float64, device=dev)
+    cptr = torch.empty(nt + 1, **i32)
+    ctb = torch.empty(nt, **i32)
+    s = torch.cuda.current_stream().cuda_stream
+    nnz = C.c_int64(0)
+
+    def call(with_contrib):
+        fem._lib.check(lib.fem_sparse(
+            m.nq, m.nq, nt, I.data_ptr(), J.data_ptr(), V.data_ptr(), row_ptr.data_ptr(),
+            col.data_ptr(), vals.data_ptr(), nt, cptr.data_ptr() if with_contrib else None,
+            ctb.data_ptr() if with_contrib else None, work.data_ptr(), int(ws.value),
+            C.byref(nnz), s))
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            ea = torch.cuda.Event(enable_timing=True)
+            eb = torch.cuda.Event(enable_timing=True)
+            ea.record()
+            fn()
+            eb.record()
+            torch.cuda.synchronize()
+            out.append(ea.elapsed_time(eb) * 1e3)
+        return float(np.median(out))
+
+    t_plain = timed(lambda: call(False))
+    t_contrib = timed(lambda: call(True))
+    k = int(nnz.value)
+
+    def values():
+        fem._lib.check(lib.fem_sparse_values(k, cptr.data_ptr(), ctb.data_ptr(), V.data_ptr(),
+                                             vals.data_ptr(), 0, s))
+
+    t_values = timed(values, reps=10)
+    alg = 16 * nt + 4 * (m.nq + 1) + 12 * k
+    out = {"workload": "OptV2 triplets (Ig, Jg) of the 2048x2048 square, 75.5M triplets, FP64 values",
+           "nt": nt, "nnz": k, "us": round(t_plain, 1), "us_with_contrib": round(t_contrib, 1),
+           "Mtriplets_per_s": round(nt / t_plain, 1),
+           "alg_bytes": alg, "alg_GBps": round(alg / (t_plain * 1e-6) / 1e9, 1),
+           "resum_us": round(t_values, 1)}
+    log(f"[bench] sparse nt={nt}: {t_plain:.0f}us ({nt / t_plain:.0f} Mtriplets/s), with "
+        f"contributor lists {t_contrib:.0f}us, re-summation {t_values:.0f}us")
+    del work
+    return out
+
+
 def run_cpu_baseline(args):
     """The oracle, as it stands, on a bounded sample: the same recipe at
     1448 x 1448 cells (half of the workload), one full step."""
@@ -590,6 +659,7 @@ def main():
     if not args.no_extras:
         extras["batched"] = run_batched(torch, fem, args)
         extras["adjoint"] = run_adjoint(torch, fem, args)
+        extras["sparse"] = run_sparse(torch, fem, args)
     traffic = read_traffic()
 
     def roof(p):

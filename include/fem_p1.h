@@ -306,10 +306,10 @@ int fem_sparse_workspace(int32_t m, int32_t n, int64_t nt, size_t *bytes /* HOST
  *                     entry p are contrib[contrib_ptr[p] .. contrib_ptr[p+1]),
  *                     ascending (fem_sparse_values re-sums new values)
  *   work [work_bytes] >= fem_sparse_workspace(m, n, nt); nnz_out HOST
- * Requires m, n >= 1, 0 <= nt <= 2^31 - 1 and m <= 36864 * 512.  Returns
+ * Requires m, n >= 1 and 0 <= nt <= 2^31 - 1.  Returns
  * FEM_ERANGE for an index outside its range, FEM_ENOSPC if col_cap < nnz.
  * Synchronises `stream` once (to return nnz).  Rows whose triplets do not fit
- * the on-chip sort (more than 3072 in a bucket of rows) take a slower path
+ * the on-chip sort (more than 2688 in a bucket of rows) take a slower path
  * through global memory; results are identical. */
 int fem_sparse(int32_t m, int32_t n, int64_t nt, const int32_t *I, const int32_t *J,
                const double *V, int32_t *row_ptr, int32_t *col_idx, double *vals,

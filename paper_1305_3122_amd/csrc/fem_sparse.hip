@@ -3,15 +3,20 @@
 // the compression every OptV2 assembly ends in (Section 4 for the storage,
 // Section 6 for the triplet arrays Ig, Jg, Kg).
 //
-// Bucketed by row, no global atomics:
-//   k_sp_count / scan / k_sp_scatter   triplets -> runs of (bucket, workgroup):
-//                                      (row mod R, column, t) + value
-//   k_sp_rows (LDS) / k_sp_rows_big    one workgroup per bucket of R rows:
-//                                      counting sort by row, then each row
-//                                      sorted by (column, t), duplicates
-//                                      summed in ascending t; rows staged per
-//                                      bucket, sorted triplet order written as
-//                                      the contributor list
+// Bucketed by row in two levels, no global atomics:
+//   k_sp_count / scan / k_sp_scatter   triplets -> runs of (coarse bucket,
+//                                      workgroup): row mod Rc, (column, t),
+//                                      value; 256 to 512 coarse buckets, so the
+//                                      runs are long and the count matrix small
+//   k_sp_split                         one workgroup per coarse bucket splits
+//                                      it into fine buckets of Rf rows (about
+//                                      SP_CAP / 2 triplets each) -> fine_off
+//   k_sp_rows (LDS) / k_sp_rows_big    one workgroup per fine bucket: counting
+//                                      sort by row, then each row sorted by
+//                                      (column, t), duplicates summed in
+//                                      ascending t; rows staged per bucket,
+//                                      sorted triplet order written as the
+//                                      contributor list
 //   scan of bucket totals / k_sp_copy  rows -> col_idx / values, row_ptr
 // Every value is the sum of its triplets' values in ascending t, so the result
 // is bitwise reproducible and equal to a sequential left-to-right sum.
@@ -22,11 +27,15 @@ namespace fem {
 
 namespace {
 
-constexpr int SP_THREADS = 256;
-constexpr int SP_CAP = 3072;          // triplets of a bucket held in LDS (3 workgroups / CU)
-constexpr int SP_RMAX_SHIFT = 9;      // at most 512 rows per bucket
-constexpr int SP_HIST_MAX = 36864;    // buckets an LDS histogram holds
-constexpr int SP_NBLK_TARGET = 256;   // triplet workgroups of the partition pass
+constexpr int SP_THREADS = 256;       // fine-bucket kernels
+constexpr int SPP_THREADS = 1024;     // partition and split kernels
+constexpr int SP_CAP = 2688;          // triplets of a bucket held in LDS (3 workgroups / CU)
+constexpr int SP_RMAX_SHIFT = 9;      // at most 512 rows per fine bucket
+constexpr int SP_COARSE_TARGET = 512; // coarse buckets: long runs in the first scatter, and
+                                      // one split workgroup per CU or more
+constexpr int SP_COARSE_MAX = 4096;   // coarse buckets the partition's LDS holds
+constexpr int SP_SPLIT_MAX_SHIFT = 12;  // at most 4096 fine buckets per coarse one
+constexpr int SP_NBLK_TARGET = 512;   // triplet workgroups of the partition pass (2 per CU)
 
 enum : int { SP_ERR_RANGE = 1, SP_ERR_OVERFLOW = 4, SP_ERR_NOSPC = 32 };
 
@@ -42,60 +51,255 @@ __device__ inline void max_into_sp(int *dst, int v) {
     if (v > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dst, v);
 }
 
-// counts[b * nblk + blk]: triplets of workgroup blk (tpb triplets) in bucket b
-__global__ __launch_bounds__(SP_THREADS) void k_sp_count(int64_t nt, const int32_t *__restrict__ I,
-                                                        const int32_t *__restrict__ J, int32_t m,
-                                                        int32_t n, int rs, int32_t nbkt, int64_t tpb,
-                                                        int32_t *__restrict__ counts,
-                                                        SparseCounters *cnt) {
+// counts[b * nblk + blk]: triplets of workgroup blk (tpb triplets) in coarse
+// bucket b; range checks.
+__global__ __launch_bounds__(SPP_THREADS) void k_sp_count(int64_t nt, const int32_t *__restrict__ I,
+                                                         const int32_t *__restrict__ J, int32_t m,
+                                                         int32_t n, int rs, int32_t nbkt, int64_t tpb,
+                                                         int32_t *__restrict__ counts,
+                                                         SparseCounters *cnt) {
     extern __shared__ int32_t s_hist[];
     const int32_t nblk = gridDim.x;
-    for (int b = threadIdx.x; b < nbkt; b += SP_THREADS) s_hist[b] = 0;
+    for (int b = threadIdx.x; b < nbkt; b += SPP_THREADS) s_hist[b] = 0;
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * tpb;
     const int64_t t1 = (t0 + tpb < nt) ? t0 + tpb : nt;
     int bad = 0;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += SP_THREADS) {
-        const int32_t i = I[t], j = J[t];
-        if ((uint32_t)i >= (uint32_t)m || (uint32_t)j >= (uint32_t)n) {
-            bad = 1;
-            continue;
+    constexpr int H = 4;
+    for (int64_t tb = t0 + threadIdx.x; tb < t1; tb += H * SPP_THREADS) {
+        int32_t i[H], j[H];
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+            const int64_t t = tb + u * SPP_THREADS;
+            i[u] = t < t1 ? I[t] : 0;
+            j[u] = t < t1 ? J[t] : 0;
         }
-        atomicAdd(&s_hist[i >> rs], 1);
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+            if (tb + u * SPP_THREADS >= t1) continue;
+            if ((uint32_t)i[u] >= (uint32_t)m || (uint32_t)j[u] >= (uint32_t)n) {
+                bad = 1;
+                continue;
+            }
+            atomicAdd(&s_hist[i[u] >> rs], 1);
+        }
     }
     if (bad) atomicOr(&cnt->err, SP_ERR_RANGE);
     __syncthreads();
-    for (int b = threadIdx.x; b < nbkt; b += SP_THREADS)
+    for (int b = threadIdx.x; b < nbkt; b += SPP_THREADS)
         counts[(int64_t)b * nblk + blockIdx.x] = s_hist[b];
 }
 
+// Tile multisplit: a workgroup's TILE elements (IPT per thread: bucket key
+// in [0, nk), or -1 for none, and the payload rl / ct / val) are sorted by
+// bucket in LDS, then each bucket's elements of the tile are written as one
+// contiguous segment at the workgroup's cursor for that bucket, g_cur[key]
+// (advanced by the segment).  Consecutive tiles extend the same runs, so the
+// runs' lines fill while they are still in L2.  LDS (dynamic): cnt [nk+1] |
+// gcur [nk] | key [TILE] | rl [TILE] | ct [TILE] | val [TILE].
+constexpr int TILE = 2048;
+constexpr int IPT = TILE / SPP_THREADS;
+
+struct TileLds {
+    int32_t *cnt, *gcur, *rl;
+    uint16_t *key;
+    int2 *ct;
+    double *val;
+};
+
+__device__ inline TileLds tile_lds(int32_t nk) {
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    TileLds L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = s_dyn + off;
+        off += (bytes + 15) & ~size_t(15);
+        return p;
+    };
+    L.cnt = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (nk + 1)));
+    L.gcur = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * nk));
+    L.key = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * TILE));
+    L.rl = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * TILE));
+    L.ct = reinterpret_cast<int2 *>(take(sizeof(int2) * TILE));
+    L.val = reinterpret_cast<double *>(take(sizeof(double) * TILE));
+    return L;
+}
+
+inline size_t tile_lds_bytes(int32_t nk) {
+    auto up = [](size_t b) { return (b + 15) & ~size_t(15); };
+    return up(4 * (size_t)(nk + 1)) + up(4 * (size_t)nk) + up(2 * TILE) + up(4 * TILE) + up(8 * TILE) +
+           up(8 * TILE);
+}
+
+// Exclusive scan of cnt[0, nk) in place over the workgroup; cnt[nk] = total.
+__device__ inline void block_scan_counts(int32_t *cnt, int32_t nk, int32_t *s_wsum) {
+    const int tid = threadIdx.x;
+    const int per = (nk + SPP_THREADS - 1) / SPP_THREADS;
+    int32_t mine = 0;
+    for (int k = 0; k < per; ++k) {
+        const int32_t j = tid * per + k;
+        if (j < nk) mine += cnt[j];
+    }
+    const int lane = tid & (WAVE - 1), wid = tid / WAVE;
+    const int32_t incl = wave_inclusive_scan(mine);
+    if (lane == WAVE - 1) s_wsum[wid] = incl;
+    __syncthreads();
+    int32_t run = incl - mine, tot = 0;
+    for (int w = 0; w < SPP_THREADS / WAVE; ++w) {
+        if (w < wid) run += s_wsum[w];
+        tot += s_wsum[w];
+    }
+    for (int k = 0; k < per; ++k) {
+        const int32_t j = tid * per + k;
+        if (j < nk) {
+            const int32_t c = cnt[j];
+            cnt[j] = run;
+            run += c;
+        }
+    }
+    if (tid == 0) cnt[nk] = tot;
+    __syncthreads();
+}
+
+__device__ inline void tile_multisplit(const TileLds &L, int32_t nk, const int32_t (&key)[IPT],
+                                       const int32_t (&prl)[IPT], const int2 (&pct)[IPT],
+                                       const double (&pval)[IPT], bool has_val, int32_t *s_wsum,
+                                       int32_t *__restrict__ out_rl, int2 *__restrict__ out_ct,
+                                       double *__restrict__ out_val) {
+    const int tid = threadIdx.x;
+    for (int32_t k = tid; k < nk; k += SPP_THREADS) L.cnt[k] = 0;
+    __syncthreads();
+    int32_t rank[IPT];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) rank[u] = key[u] >= 0 ? atomicAdd(&L.cnt[key[u]], 1) : 0;
+    __syncthreads();
+    block_scan_counts(L.cnt, nk, s_wsum);
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+        if (key[u] < 0) continue;
+        const int32_t p = L.cnt[key[u]] + rank[u];
+        L.key[p] = static_cast<uint16_t>(key[u]);
+        L.rl[p] = prl[u];
+        L.ct[p] = pct[u];
+        if (has_val) L.val[p] = pval[u];
+    }
+    __syncthreads();
+    const int32_t ntile = L.cnt[nk];
+    for (int32_t p = tid; p < ntile; p += SPP_THREADS) {
+        const int32_t k = L.key[p];
+        const int64_t g = (int64_t)L.gcur[k] + (p - L.cnt[k]);
+        out_rl[g] = L.rl[p];
+        out_ct[g] = L.ct[p];
+        if (has_val) out_val[g] = L.val[p];
+    }
+    __syncthreads();
+    for (int32_t k = tid; k < nk; k += SPP_THREADS) L.gcur[k] += L.cnt[k + 1] - L.cnt[k];
+    __syncthreads();
+}
+
 // Same triplets per workgroup as k_sp_count: each goes to the run of its
-// (bucket, workgroup) pair: rec = (row mod R, column, t), val = V[t].
-__global__ __launch_bounds__(SP_THREADS) void k_sp_scatter(int64_t nt, const int32_t *__restrict__ I,
-                                                          const int32_t *__restrict__ J,
-                                                          const double *__restrict__ V, int32_t m,
-                                                          int32_t n, int rs, int32_t nbkt, int64_t tpb,
-                                                          const int32_t *__restrict__ offs,
-                                                          int32_t *__restrict__ rec,
-                                                          double *__restrict__ rval) {
-    extern __shared__ int32_t s_cur[];
+// (coarse bucket, workgroup) pair, as rl = row mod Rc, ct = (column, t) and
+// rval = V[t] (three arrays, so that the split's count reads rl alone).
+__global__ __launch_bounds__(SPP_THREADS) void k_sp_scatter(int64_t nt, const int32_t *__restrict__ I,
+                                                           const int32_t *__restrict__ J,
+                                                           const double *__restrict__ V, int32_t m,
+                                                           int32_t n, int rs, int32_t nbkt, int64_t tpb,
+                                                           const int32_t *__restrict__ offs,
+                                                           int32_t *__restrict__ rl, int2 *__restrict__ ct,
+                                                           double *__restrict__ rval) {
+    __shared__ int32_t s_wsum[SPP_THREADS / WAVE];
+    const TileLds L = tile_lds(nbkt);
     const int32_t nblk = gridDim.x;
-    for (int b = threadIdx.x; b < nbkt; b += SP_THREADS)
-        s_cur[b] = offs[(int64_t)b * nblk + blockIdx.x];
+    for (int b = threadIdx.x; b < nbkt; b += SPP_THREADS)
+        L.gcur[b] = offs[(int64_t)b * nblk + blockIdx.x];
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * tpb;
     const int64_t t1 = (t0 + tpb < nt) ? t0 + tpb : nt;
     const int32_t rmask = (1 << rs) - 1;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += SP_THREADS) {
-        const int32_t i = I[t], j = J[t];
-        if ((uint32_t)i >= (uint32_t)m || (uint32_t)j >= (uint32_t)n) continue;
-        const int32_t pos = atomicAdd(&s_cur[i >> rs], 1);
-        int32_t *r = rec + 3 * (int64_t)pos;
-        r[0] = i & rmask;
-        r[1] = j;
-        r[2] = static_cast<int32_t>(t);
-        if (V) rval[pos] = V[t];
+    for (int64_t tb = t0; tb < t1; tb += TILE) {
+        int32_t key[IPT], prl[IPT];
+        int2 pct[IPT];
+        double pval[IPT];
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+            const int64_t t = tb + threadIdx.x + u * SPP_THREADS;
+            const int32_t i = t < t1 ? I[t] : -1;
+            const int32_t j = t < t1 ? J[t] : -1;
+            pval[u] = (V && t < t1) ? V[t] : 0.0;
+            const bool ok = (uint32_t)i < (uint32_t)m && (uint32_t)j < (uint32_t)n;
+            key[u] = ok ? (i >> rs) : -1;
+            prl[u] = i & rmask;
+            pct[u] = make_int2(j, static_cast<int32_t>(t));
+        }
+        tile_multisplit(L, nbkt, key, prl, pct, pval, V != nullptr, s_wsum, rl, ct, rval);
     }
+}
+
+// One workgroup per coarse bucket: its triplets, sorted into nf = Rc / Rf
+// fine buckets (counting sort, tiles multisplit in order), and the fine
+// buckets' starts fine_off[cb * nf + j].
+__global__ __launch_bounds__(SPP_THREADS) void k_sp_split(
+    int32_t nbkt_c, int32_t nblk, int32_t nbkt_f, int rf, int nf_shift,
+    const int32_t *__restrict__ offs, const int32_t *__restrict__ total_ptr,
+    const int32_t *__restrict__ rl, const int2 *__restrict__ ct, const double *__restrict__ rval,
+    int has_val, int32_t *__restrict__ rl2, int2 *__restrict__ ct2, double *__restrict__ rval2,
+    int32_t *__restrict__ fine_off) {
+    __shared__ int32_t s_wsum[SPP_THREADS / WAVE];
+    const int tid = threadIdx.x;
+    const int32_t cb = blockIdx.x;
+    const int32_t nf = 1 << nf_shift;
+    const TileLds L = tile_lds(nf);
+    const int64_t total = *total_ptr;
+    const int64_t e0 = offs[(int64_t)cb * nblk];
+    const int64_t e1 = (cb + 1 < nbkt_c) ? offs[(int64_t)(cb + 1) * nblk] : total;
+    for (int j = tid; j < nf; j += SPP_THREADS) L.cnt[j] = 0;
+    __syncthreads();
+    for (int64_t xb = e0 + tid; xb < e1; xb += 8 * SPP_THREADS) {
+        int32_t r0[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t x = xb + u * SPP_THREADS;
+            r0[u] = x < e1 ? rl[x] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (r0[u] >= 0) atomicAdd(&L.cnt[r0[u] >> rf], 1);
+    }
+    __syncthreads();
+    block_scan_counts(L.cnt, nf, s_wsum);
+    for (int j = tid; j < nf; j += SPP_THREADS) {
+        const int64_t fb = ((int64_t)cb << nf_shift) + j;
+        const int32_t st = static_cast<int32_t>(e0 + L.cnt[j]);
+        if (fb < nbkt_f) fine_off[fb] = st;
+        L.gcur[j] = st;
+    }
+    if (cb == nbkt_c - 1 && tid == 0) fine_off[nbkt_f] = static_cast<int32_t>(total);
+    __syncthreads();
+    const int32_t fmask = (1 << rf) - 1;
+    for (int64_t xb = e0; xb < e1; xb += TILE) {
+        int32_t key[IPT], prl[IPT];
+        int2 pct[IPT];
+        double pval[IPT];
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+            const int64_t x = xb + tid + u * SPP_THREADS;
+            const int32_t r0 = x < e1 ? rl[x] : -1;
+            key[u] = r0 >= 0 ? (r0 >> rf) : -1;
+            prl[u] = r0 & fmask;
+            pct[u] = x < e1 ? ct[x] : make_int2(0, 0);
+            pval[u] = (has_val && x < e1) ? rval[x] : 0.0;
+        }
+        tile_multisplit(L, nf, key, prl, pct, pval, has_val != 0, s_wsum, rl2, ct2, rval2);
+    }
+}
+
+// Without a split (one fine bucket per coarse bucket): the fine starts are
+// the coarse ones.
+__global__ void k_sp_fine_off(int32_t nbkt, int32_t nblk, const int32_t *__restrict__ offs,
+                              const int32_t *__restrict__ total_ptr, int32_t *__restrict__ fine_off) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b < nbkt) fine_off[b] = offs[b * nblk];
+    if (b == nbkt) fine_off[b] = *total_ptr;
 }
 
 __device__ inline int32_t block_scan_sp(int32_t v, int32_t *s_wsum, int32_t *total) {
@@ -114,39 +318,66 @@ __device__ inline int32_t block_scan_sp(int32_t v, int32_t *s_wsum, int32_t *tot
     return off;
 }
 
-// The rows of one bucket, with the bucket's triplets (sorted by row) in
+// Rows of at most RANK_MAX triplets are sorted by ranking (each element's
+// place = the number of smaller keys), longer ones by insertion.
+constexpr int RANK_MAX = 64;
+
+// The rows of one bucket, with the bucket's triplets (grouped by row) in
 // arrays `col`, `tt`, `val` (LDS or global scratch) at [0, nb):
-//   1 each row sorted by (column, t) (insertion sort; t breaks ties, so the
-//     order is the stable one)
-//   2 unique columns -> row lengths; scan -> offsets inside the bucket
+//   1 each row ordered by (column, t) -- t breaks ties, so the order is the
+//     stable one.  Rows of at most RANK_MAX triplets: perm[s + rank] = k,
+//     the arrays stay in place; longer rows: insertion sort of col / tt / val
+//     in place, perm the identity.  Unique columns -> row lengths.
+//   2 scan of the row lengths -> offsets of the rows inside the bucket
 //   3 each row's unique columns, the sums of their runs (ascending t) and the
-//     start of each run in the sorted triplet order, staged at e0 + offset
+//     start of each run in the sorted triplet order, staged at e0 + offset,
+//     and the sorted t as the bucket's part of the contributor list
 // Rows are taken by the threads in turn (thread r: rows r, r + 256, ...).
-template <typename ColT, typename ValT>
+template <typename ColT, typename ValT, typename PermT>
 __device__ void sp_bucket_rows(int32_t R, int32_t v0, int32_t m, int64_t e0, const int32_t *s_rs,
-                               ColT *col, ColT *tt, ValT *val, bool has_val, int32_t *s_len,
-                               int32_t *s_wsum, int32_t *__restrict__ stage_col,
+                               ColT *col, ColT *tt, ValT *val, PermT *perm, bool has_val,
+                               int32_t *s_len, int32_t *s_wsum, int32_t *__restrict__ stage_col,
                                double *__restrict__ stage_val, int32_t *__restrict__ stage_cptr,
-                               int32_t *__restrict__ rowoff, int32_t *__restrict__ btot, int32_t b) {
+                               int32_t *__restrict__ contrib, int32_t *__restrict__ rowoff,
+                               int32_t *__restrict__ btot, int32_t b) {
     const int tid = threadIdx.x;
     for (int32_t r = tid; r < R; r += SP_THREADS) {
-        const int32_t s = s_rs[r], e = s_rs[r + 1];
-        for (int32_t x = s + 1; x < e; ++x) {
-            const int32_t c = col[x], t = tt[x];
-            double vx = has_val ? static_cast<double>(val[x]) : 0.0;
-            int32_t y = x;
-            while (y > s && (col[y - 1] > c || (col[y - 1] == c && tt[y - 1] > t))) {
-                col[y] = col[y - 1];
-                tt[y] = tt[y - 1];
-                if (has_val) val[y] = val[y - 1];
-                --y;
-            }
-            col[y] = c;
-            tt[y] = t;
-            if (has_val) val[y] = vx;
-        }
+        const int32_t s = s_rs[r], e = s_rs[r + 1], d = e - s;
         int32_t L = 0;
-        for (int32_t x = s; x < e; ++x) L += (x == s || col[x] != col[x - 1]) ? 1 : 0;
+        if (d <= RANK_MAX) {
+            for (int32_t k = 0; k < d; ++k) {
+                const int32_t ck = col[s + k], tk = tt[s + k];
+                int32_t rank = 0;
+                bool first = true;
+                for (int32_t j = 0; j < d; ++j) {
+                    const int32_t cj = col[s + j], tj = tt[s + j];
+                    const bool same_before = cj == ck && tj < tk;
+                    rank += (cj < ck || same_before) ? 1 : 0;
+                    first = first && !same_before;
+                }
+                perm[s + rank] = static_cast<PermT>(k);
+                L += first ? 1 : 0;
+            }
+        } else {
+            for (int32_t x = s + 1; x < e; ++x) {
+                const int32_t c = col[x], t = tt[x];
+                const double vx = has_val ? static_cast<double>(val[x]) : 0.0;
+                int32_t y = x;
+                while (y > s && (col[y - 1] > c || (col[y - 1] == c && tt[y - 1] > t))) {
+                    col[y] = col[y - 1];
+                    tt[y] = tt[y - 1];
+                    if (has_val) val[y] = val[y - 1];
+                    --y;
+                }
+                col[y] = c;
+                tt[y] = t;
+                if (has_val) val[y] = vx;
+            }
+            for (int32_t x = s; x < e; ++x) {
+                L += (x == s || col[x] != col[x - 1]) ? 1 : 0;
+                perm[x] = static_cast<PermT>(x - s);
+            }
+        }
         s_len[r] = L;
     }
     __syncthreads();
@@ -174,11 +405,15 @@ __device__ void sp_bucket_rows(int32_t R, int32_t v0, int32_t m, int64_t e0, con
         const int32_t s = s_rs[r], e = s_rs[r + 1];
         int64_t o = e0 + s_len[r];
         for (int32_t x = s; x < e;) {
-            const int32_t c = col[x];
+            const int32_t c = col[s + static_cast<int32_t>(perm[x])];
             double acc = 0.0;
             int32_t y = x;
-            for (; y < e && col[y] == c; ++y)
-                if (has_val) acc += static_cast<double>(val[y]);
+            for (; y < e; ++y) {
+                const int32_t p = s + static_cast<int32_t>(perm[y]);
+                if (col[p] != c) break;
+                if (has_val) acc += static_cast<double>(val[p]);
+                if (contrib) contrib[e0 + y] = tt[p];
+            }
             stage_col[o] = c;
             if (has_val) stage_val[o] = acc;
             if (stage_cptr) stage_cptr[o] = static_cast<int32_t>(e0 + x);
@@ -191,33 +426,46 @@ __device__ void sp_bucket_rows(int32_t R, int32_t v0, int32_t m, int64_t e0, con
 // One workgroup per bucket whose triplets fit in LDS; larger buckets are
 // listed for k_sp_rows_big.
 __global__ __launch_bounds__(SP_THREADS) void k_sp_rows(
-    int32_t m, int32_t nbkt, int32_t nblk, int rs, const int32_t *__restrict__ offs,
-    const int32_t *__restrict__ total_ptr, const int32_t *__restrict__ rec,
-    const double *__restrict__ rval, int has_val, int32_t *__restrict__ stage_col,
+    int32_t m, int rs, const int32_t *__restrict__ fine_off, const int32_t *__restrict__ rl,
+    const int2 *__restrict__ ct, const double *__restrict__ rval, int has_val,
+    int32_t *__restrict__ stage_col,
     double *__restrict__ stage_val, int32_t *__restrict__ stage_cptr, int32_t *__restrict__ contrib,
     int32_t *__restrict__ rowoff, int32_t *__restrict__ btot, int32_t *__restrict__ big,
     SparseCounters *cnt) {
     __shared__ int32_t s_col[SP_CAP], s_t[SP_CAP];
     __shared__ double s_val[SP_CAP];
+    __shared__ uint16_t s_perm[SP_CAP];
     __shared__ int32_t s_rs[(1 << SP_RMAX_SHIFT) + 1];
     __shared__ int32_t s_len[1 << SP_RMAX_SHIFT];
     __shared__ int32_t s_wsum[SP_THREADS / WAVE];
     const int tid = threadIdx.x;
     const int32_t b = blockIdx.x;
     const int32_t R = 1 << rs;
-    const int64_t total = *total_ptr;
-    const int64_t e0 = offs[(int64_t)b * nblk];
-    const int64_t e1 = (b + 1 < nbkt) ? offs[(int64_t)(b + 1) * nblk] : total;
+    const int64_t e0 = fine_off[b], e1 = fine_off[b + 1];
     const int32_t nb = static_cast<int32_t>(e1 - e0);
     if (e1 - e0 > SP_CAP) {
         if (tid == 0) big[atomicAdd(&cnt->big_count, 1)] = b;
         return;
     }
     const int32_t v0 = b << rs;
-    // 1 triplets per row, scan -> row starts
+    // 1 the bucket's triplets into registers (all loads in flight), triplets
+    // per row, scan -> row starts
+    constexpr int EPT = (SP_CAP + SP_THREADS - 1) / SP_THREADS;
+    int32_t xr[EPT];
+    int2 xc[EPT];
+    double xv[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int32_t x = tid + u * SP_THREADS;
+        xr[u] = x < nb ? rl[e0 + x] : -1;
+        xc[u] = x < nb ? ct[e0 + x] : make_int2(0, 0);
+        xv[u] = (has_val && x < nb) ? rval[e0 + x] : 0.0;
+    }
     for (int32_t r = tid; r < R; r += SP_THREADS) s_len[r] = 0;
     __syncthreads();
-    for (int32_t x = tid; x < nb; x += SP_THREADS) atomicAdd(&s_len[rec[3 * (e0 + x)]], 1);
+#pragma unroll
+    for (int u = 0; u < EPT; ++u)
+        if (xr[u] >= 0) atomicAdd(&s_len[xr[u]], 1);
     __syncthreads();
     const int per = (R + SP_THREADS - 1) / SP_THREADS;
     int32_t mine = 0, mx = 0;
@@ -245,31 +493,28 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_rows(
     if ((tid & (WAVE - 1)) == 0) max_into_sp(&cnt->max_row, mx);
     __syncthreads();
     // 2 counting sort by row into LDS
-    for (int32_t x = tid; x < nb; x += SP_THREADS) {
-        const int32_t *rr = rec + 3 * (e0 + x);
-        const int32_t p = atomicAdd(&s_len[rr[0]], 1);
-        s_col[p] = rr[1];
-        s_t[p] = rr[2];
-        if (has_val) s_val[p] = rval[e0 + x];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        if (xr[u] < 0) continue;
+        const int32_t p = atomicAdd(&s_len[xr[u]], 1);
+        s_col[p] = xc[u].x;
+        s_t[p] = xc[u].y;
+        if (has_val) s_val[p] = xv[u];
     }
     __syncthreads();
-    sp_bucket_rows(R, v0, m, e0, s_rs, s_col, s_t, s_val, has_val != 0, s_len, s_wsum, stage_col,
-                   stage_val, stage_cptr, rowoff, btot, b);
-    // the sorted triplet order of the bucket = its part of the contributor list
-    if (contrib) {
-        __syncthreads();
-        for (int32_t x = tid; x < nb; x += SP_THREADS) contrib[e0 + x] = s_t[x];
-    }
+    sp_bucket_rows(R, v0, m, e0, s_rs, s_col, s_t, s_val, s_perm, has_val != 0, s_len, s_wsum,
+                   stage_col, stage_val, stage_cptr, contrib, rowoff, btot, b);
 }
 
 // Buckets listed by k_sp_rows (more than SP_CAP triplets): the same steps
 // with the triplets in global scratch (gcol, gt, gval at the bucket's own
 // range [e0, e1)).  Slower, for skewed inputs only.
 __global__ __launch_bounds__(SP_THREADS) void k_sp_rows_big(
-    int32_t m, int32_t nbkt, int32_t nblk, int rs, const int32_t *__restrict__ offs,
-    const int32_t *__restrict__ total_ptr, const int32_t *__restrict__ rec,
-    const double *__restrict__ rval, int has_val, int32_t *__restrict__ gcol,
-    int32_t *__restrict__ gt, double *__restrict__ gval, int32_t *__restrict__ stage_col,
+    int32_t m, int rs, const int32_t *__restrict__ fine_off, const int32_t *__restrict__ rl,
+    const int2 *__restrict__ ct, const double *__restrict__ rval, int has_val,
+    int32_t *__restrict__ gcol,
+    int32_t *__restrict__ gt, double *__restrict__ gval, int32_t *__restrict__ gperm,
+    int32_t *__restrict__ stage_col,
     double *__restrict__ stage_val, int32_t *__restrict__ stage_cptr, int32_t *__restrict__ contrib,
     int32_t *__restrict__ rowoff, int32_t *__restrict__ btot, const int32_t *__restrict__ big,
     SparseCounters *cnt) {
@@ -279,16 +524,14 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_rows_big(
     const int tid = threadIdx.x;
     const int32_t nbig = cnt->big_count;
     const int32_t R = 1 << rs;
-    const int64_t total = *total_ptr;
     for (int32_t q = blockIdx.x; q < nbig; q += gridDim.x) {
         const int32_t b = big[q];
-        const int64_t e0 = offs[(int64_t)b * nblk];
-        const int64_t e1 = (b + 1 < nbkt) ? offs[(int64_t)(b + 1) * nblk] : total;
+        const int64_t e0 = fine_off[b], e1 = fine_off[b + 1];
         const int32_t nb = static_cast<int32_t>(e1 - e0);
         const int32_t v0 = b << rs;
         for (int32_t r = tid; r < R; r += SP_THREADS) s_len[r] = 0;
         __syncthreads();
-        for (int32_t x = tid; x < nb; x += SP_THREADS) atomicAdd(&s_len[rec[3 * (e0 + x)]], 1);
+        for (int32_t x = tid; x < nb; x += SP_THREADS) atomicAdd(&s_len[rl[e0 + x]], 1);
         __syncthreads();
         const int per = (R + SP_THREADS - 1) / SP_THREADS;
         int32_t mine = 0, mx = 0;
@@ -319,18 +562,15 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_rows_big(
         int32_t *bt = gt + e0;
         double *bv = gval + e0;
         for (int32_t x = tid; x < nb; x += SP_THREADS) {
-            const int32_t *rr = rec + 3 * (e0 + x);
-            const int32_t p = atomicAdd(&s_len[rr[0]], 1);
-            bc[p] = rr[1];
-            bt[p] = rr[2];
+            const int2 c = ct[e0 + x];
+            const int32_t p = atomicAdd(&s_len[rl[e0 + x]], 1);
+            bc[p] = c.x;
+            bt[p] = c.y;
             if (has_val) bv[p] = rval[e0 + x];
         }
         __syncthreads();
-        sp_bucket_rows(R, v0, m, e0, s_rs, bc, bt, bv, has_val != 0, s_len, s_wsum, stage_col,
-                       stage_val, stage_cptr, rowoff, btot, b);
-        __syncthreads();
-        if (contrib)
-            for (int32_t x = tid; x < nb; x += SP_THREADS) contrib[e0 + x] = bt[x];
+        sp_bucket_rows(R, v0, m, e0, s_rs, bc, bt, bv, gperm + e0, has_val != 0, s_len, s_wsum,
+                       stage_col, stage_val, stage_cptr, contrib, rowoff, btot, b);
         __syncthreads();
     }
 }
@@ -338,14 +578,14 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_rows_big(
 // Bucket b's staged rows to col_idx / values / contrib_ptr at bptr[b], and
 // row_ptr of its rows.
 __global__ __launch_bounds__(SP_THREADS) void k_sp_copy(
-    int32_t m, int32_t nbkt, int32_t nblk, int rs, const int32_t *__restrict__ offs,
+    int32_t m, int32_t nbkt, int rs, const int32_t *__restrict__ fine_off,
     const int32_t *__restrict__ bptr, const int32_t *__restrict__ rowoff,
     const int32_t *__restrict__ stage_col, const double *__restrict__ stage_val,
     const int32_t *__restrict__ stage_cptr, int32_t *__restrict__ row_ptr,
     int32_t *__restrict__ col_idx, double *__restrict__ vals, int32_t *__restrict__ contrib_ptr,
     int64_t col_cap, int64_t nt, SparseCounters *cnt) {
     const int32_t b = blockIdx.x;
-    const int64_t e0 = offs[(int64_t)b * nblk];
+    const int64_t e0 = fine_off[b];
     const int32_t v0 = b << rs, R = 1 << rs;
     const int32_t P = bptr[b], T = bptr[b + 1] - P;
     for (int32_t r = threadIdx.x; r < R; r += SP_THREADS)
@@ -380,27 +620,35 @@ __global__ __launch_bounds__(256) void k_sp_values(int64_t nnz, const int32_t *_
 }
 
 struct SparsePlan {
-    int rs;                // log2 rows per bucket
-    int32_t nbkt, nblk;
+    int rf, rc;            // log2 rows per fine / coarse bucket
+    int32_t nbkt_f, nbkt_c, nblk;
     int64_t tpb;
-    int64_t ncounts() const { return (int64_t)nbkt * nblk; }
+    int nf_shift() const { return rc - rf; }
+    int64_t ncounts() const { return (int64_t)nbkt_c * nblk; }
 };
 
-// Rows per bucket: a power of two with about SP_CAP / 2 triplets per bucket
-// on average, at least enough that the buckets fit an LDS histogram.
+// Fine buckets: a power of two of rows with about SP_CAP / 2 triplets on
+// average; coarse buckets: the fewest powers of two of fine buckets that keep
+// at most SP_COARSE_MAX of them.
 bool plan_sparse(int32_t m, int64_t nt, SparsePlan *p) {
-    int rs = 0;
-    while (rs < SP_RMAX_SHIFT && ((int64_t)m + (1ll << rs) - 1) >> rs > SP_HIST_MAX) ++rs;
-    if (((int64_t)m + (1ll << rs) - 1) >> rs > SP_HIST_MAX) return false;
     const double avg = m > 0 ? (double)nt / (double)m : 0.0;
-    int rs_fit = 0;
-    while (rs_fit < SP_RMAX_SHIFT && avg * (double)(1 << (rs_fit + 1)) <= SP_CAP / 2) ++rs_fit;
-    if (rs_fit > SP_RMAX_SHIFT) rs_fit = SP_RMAX_SHIFT;
-    p->rs = rs > rs_fit ? rs : rs_fit;
-    p->nbkt = (int32_t)(((int64_t)m + (1ll << p->rs) - 1) >> p->rs);
+    int rf = 0;
+    while (rf < SP_RMAX_SHIFT && avg * (double)(1 << (rf + 1)) <= 0.875 * SP_CAP) ++rf;
+    int rc = rf;
+    while (rc < 31 && (((int64_t)m + (1ll << rc) - 1) >> rc) > SP_COARSE_TARGET) ++rc;
+    // no more than 2^SP_SPLIT_MAX_SHIFT fine buckets per coarse one: fewer,
+    // larger coarse buckets beat larger fine ones while the histogram fits
+    while (rc - rf > SP_SPLIT_MAX_SHIFT && (((int64_t)m + (1ll << (rc - 1)) - 1) >> (rc - 1)) <= SP_COARSE_MAX)
+        --rc;
+    if (rc - rf > SP_SPLIT_MAX_SHIFT) rf = rc - SP_SPLIT_MAX_SHIFT;
+    if (rf > SP_RMAX_SHIFT) return false;
+    p->rf = rf;
+    p->rc = rc;
+    p->nbkt_f = (int32_t)(((int64_t)m + (1ll << rf) - 1) >> rf);
+    p->nbkt_c = (int32_t)(((int64_t)m + (1ll << rc) - 1) >> rc);
     int64_t tpb = (nt + SP_NBLK_TARGET - 1) / SP_NBLK_TARGET;
-    tpb = (tpb + SP_THREADS - 1) / SP_THREADS * SP_THREADS;
-    if (tpb < SP_THREADS) tpb = SP_THREADS;
+    tpb = (tpb + SPP_THREADS - 1) / SPP_THREADS * SPP_THREADS;
+    if (tpb < SPP_THREADS) tpb = SPP_THREADS;
     p->tpb = tpb;
     p->nblk = (int32_t)((nt + tpb - 1) / tpb);
     if (p->nblk < 1) p->nblk = 1;
@@ -409,8 +657,10 @@ bool plan_sparse(int32_t m, int64_t nt, SparsePlan *p) {
 
 struct SparseWork {
     SparseCounters *cnt;
-    int32_t *counts, *rec, *gcol, *gt, *stage_col, *stage_cptr, *rowoff, *btot, *bptr, *big;
-    double *rval, *gval, *stage_val;
+    int32_t *counts, *rl, *rl2, *gcol, *gt, *gperm, *stage_col, *stage_cptr, *rowoff, *btot, *bptr,
+        *big, *fine_off;
+    int2 *ct, *ct2;
+    double *rval, *rval2, *gval, *stage_val;
     long long *part;
     size_t bytes;
 };
@@ -426,18 +676,25 @@ SparseWork carve_sparse(int32_t m, int64_t nt, const SparsePlan &P, char *base) 
         return p;
     };
     const size_t ntc = (size_t)(nt > 0 ? nt : 1);
-    const int64_t nscan = P.ncounts() > P.nbkt ? P.ncounts() : P.nbkt;
+    const int64_t nscan = P.ncounts() > P.nbkt_f ? P.ncounts() : P.nbkt_f;
     w.cnt = reinterpret_cast<SparseCounters *>(take(sizeof(SparseCounters)));
     w.counts = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(P.ncounts() + 1)));
     w.part = reinterpret_cast<long long *>(take(sizeof(long long) * (size_t)scan_partials(nscan)));
-    w.btot = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(P.nbkt + 1)));
-    w.bptr = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(P.nbkt + 1)));
-    w.big = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)P.nbkt));
+    w.fine_off = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(P.nbkt_f + 1)));
+    w.btot = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(P.nbkt_f + 1)));
+    w.bptr = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(P.nbkt_f + 1)));
+    w.big = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)P.nbkt_f));
     w.rowoff = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
-    w.rec = reinterpret_cast<int32_t *>(take(3 * sizeof(int32_t) * ntc));
+    w.rl = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc));
+    w.ct = reinterpret_cast<int2 *>(take(sizeof(int2) * ntc));
     w.rval = reinterpret_cast<double *>(take(sizeof(double) * ntc));
+    const bool split = P.nf_shift() > 0;
+    w.rl2 = split ? reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc)) : w.rl;
+    w.ct2 = split ? reinterpret_cast<int2 *>(take(sizeof(int2) * ntc)) : w.ct;
+    w.rval2 = split ? reinterpret_cast<double *>(take(sizeof(double) * ntc)) : w.rval;
     w.gcol = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc));
     w.gt = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc));
+    w.gperm = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc));
     w.gval = reinterpret_cast<double *>(take(sizeof(double) * ntc));
     w.stage_col = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc));
     w.stage_cptr = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc));
@@ -485,10 +742,10 @@ extern "C" int fem_sparse(int32_t m, int32_t n, int64_t nt, const int32_t *I, co
     int st;
     if ((st = fill_i32(reinterpret_cast<int32_t *>(W.cnt), sizeof(SparseCounters) / 4, 0, s))) return st;
     const bool has_val = vals != nullptr;
-    const size_t hist_lds = sizeof(int32_t) * (size_t)P.nbkt;
+    const size_t hist_lds = sizeof(int32_t) * (size_t)P.nbkt_c;
     if (nt > 0) {
-        hipLaunchKernelGGL(k_sp_count, dim3(P.nblk), dim3(SP_THREADS), hist_lds, s, nt, I, J, m, n,
-                           P.rs, P.nbkt, P.tpb, W.counts, W.cnt);
+        hipLaunchKernelGGL(k_sp_count, dim3(P.nblk), dim3(SPP_THREADS), hist_lds, s, nt, I, J, m, n,
+                           P.rc, P.nbkt_c, P.tpb, W.counts, W.cnt);
         FEM_LAUNCH_CHECK();
     } else {
         if ((st = fill_i32(W.counts, P.ncounts(), 0, s))) return st;
@@ -497,24 +754,35 @@ extern "C" int fem_sparse(int32_t m, int32_t n, int64_t nt, const int32_t *I, co
                                  &W.cnt->err, s)))
         return st;
     if (nt > 0) {
-        hipLaunchKernelGGL(k_sp_scatter, dim3(P.nblk), dim3(SP_THREADS), hist_lds, s, nt, I, J,
-                           has_val ? V : nullptr, m, n, P.rs, P.nbkt, P.tpb, W.counts, W.rec, W.rval);
+        hipLaunchKernelGGL(k_sp_scatter, dim3(P.nblk), dim3(SPP_THREADS), tile_lds_bytes(P.nbkt_c), s,
+                           nt, I, J,
+                           has_val ? V : nullptr, m, n, P.rc, P.nbkt_c, P.tpb, W.counts, W.rl, W.ct,
+                           W.rval);
         FEM_LAUNCH_CHECK();
     }
     const int32_t *total_ptr = W.counts + P.ncounts();
-    hipLaunchKernelGGL(k_sp_rows, dim3(P.nbkt), dim3(SP_THREADS), 0, s, m, P.nbkt, P.nblk, P.rs,
-                       W.counts, total_ptr, W.rec, W.rval, has_val ? 1 : 0, W.stage_col, W.stage_val,
+    if (P.nf_shift() > 0) {
+        hipLaunchKernelGGL(k_sp_split, dim3(P.nbkt_c), dim3(SPP_THREADS),
+                           tile_lds_bytes(1 << P.nf_shift()), s, P.nbkt_c, P.nblk,
+                           P.nbkt_f, P.rf, P.nf_shift(), W.counts, total_ptr, W.rl, W.ct, W.rval,
+                           has_val ? 1 : 0, W.rl2, W.ct2, W.rval2, W.fine_off);
+    } else {
+        hipLaunchKernelGGL(k_sp_fine_off, dim3(grid_for((int64_t)P.nbkt_f + 1, 256)), dim3(256), 0, s,
+                           P.nbkt_f, P.nblk, W.counts, total_ptr, W.fine_off);
+    }
+    FEM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sp_rows, dim3(P.nbkt_f), dim3(SP_THREADS), 0, s, m, P.rf, W.fine_off,
+                       W.rl2, W.ct2, W.rval2, has_val ? 1 : 0, W.stage_col, W.stage_val,
                        contrib_ptr ? W.stage_cptr : nullptr, contrib, W.rowoff, W.btot, W.big, W.cnt);
     FEM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sp_rows_big, dim3(256), dim3(SP_THREADS), 0, s, m, P.nbkt, P.nblk, P.rs,
-                       W.counts, total_ptr, W.rec, W.rval, has_val ? 1 : 0, W.gcol, W.gt, W.gval,
-                       W.stage_col, W.stage_val, contrib_ptr ? W.stage_cptr : nullptr, contrib,
-                       W.rowoff, W.btot, W.big, W.cnt);
+    hipLaunchKernelGGL(k_sp_rows_big, dim3(256), dim3(SP_THREADS), 0, s, m, P.rf, W.fine_off, W.rl2,
+                       W.ct2, W.rval2, has_val ? 1 : 0, W.gcol, W.gt, W.gval, W.gperm, W.stage_col, W.stage_val,
+                       contrib_ptr ? W.stage_cptr : nullptr, contrib, W.rowoff, W.btot, W.big, W.cnt);
     FEM_LAUNCH_CHECK();
-    if ((st = exclusive_scan_i32(W.btot, W.bptr, P.nbkt, W.part, &W.cnt->total[1], &W.cnt->err, s)))
+    if ((st = exclusive_scan_i32(W.btot, W.bptr, P.nbkt_f, W.part, &W.cnt->total[1], &W.cnt->err, s)))
         return st;
-    hipLaunchKernelGGL(k_sp_copy, dim3(P.nbkt), dim3(SP_THREADS), 0, s, m, P.nbkt, P.nblk, P.rs,
-                       W.counts, W.bptr, W.rowoff, W.stage_col, has_val ? W.stage_val : nullptr,
+    hipLaunchKernelGGL(k_sp_copy, dim3(P.nbkt_f), dim3(SP_THREADS), 0, s, m, P.nbkt_f, P.rf,
+                       W.fine_off, W.bptr, W.rowoff, W.stage_col, has_val ? W.stage_val : nullptr,
                        W.stage_cptr, row_ptr, col_idx, vals, contrib_ptr, col_cap, nt, W.cnt);
     FEM_LAUNCH_CHECK();
     SparseCounters h{};
