@@ -54,7 +54,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-PROFILE_STATS = os.path.join(ROOT, "profiles", "step_square2048_kernel_stats.md")
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "step_square2048_hbm_traffic.md")
 # the single kernel each timed call launches (deterministic row-owner kernels:
 # operator mask, unroll, register row length)
@@ -79,7 +78,7 @@ def source_hash():
 
 def kernel_short_name(name):
     """'void fem::k_x<1, 2>(int, ...)' -> 'fem::k_x<1, 2>'."""
-    name = name.strip().strip('"')
+    name = name.strip().strip('"').replace("(anonymous namespace)::", "")
     if name.startswith("void "):
         name = name[5:]
     depth = 0
@@ -114,8 +113,25 @@ def read_traffic():
     return out if ok else {}
 
 
-def summarize_profiles(kt_dir, pf_dir, pw_dir, command):
+PROFILE_TITLES = {
+    "step_square2048": ("one assembly step on the 2048x2048-cell unit square",
+                        "Workload: 8,388,608 triangles, 4,198,401 vertices (jitter 0.2h, random vertex\n"
+                        "relabelling), nnz 29,372,417; FP64 values, int32 indices.  Per-call averages over\n"
+                        "the run (1 warm-up + 5 timed steps, plus the stiffness + mass pair timed alone and\n"
+                        "a 1 GiB fill and copy used to calibrate the counters)."),
+    "sparse_optv2_square2048": ("sparse(I, J, V) of the OptV2 triplets of the 2048x2048-cell square",
+                                "Workload: Ig, Jg of all 9 local entries of the 8,388,608 triangles (75,497,472\n"
+                                "triplets, random FP64 values) compressed to the 29,372,417-entry CSR; calls with\n"
+                                "and without contributor lists, and re-summations (fem_sparse_values).  The 1 GiB\n"
+                                "fill and copy calibrate the counters."),
+}
+
+
+def summarize_profiles(kt_dir, pf_dir, pw_dir, command, name="step_square2048"):
     """Write the two profiles/ summaries from rocprofv3 csv output."""
+    title, workload = PROFILE_TITLES[name]
+    stats_path = os.path.join(ROOT, "profiles", f"{name}_kernel_stats.md")
+    traffic_path = os.path.join(ROOT, "profiles", f"{name}_hbm_traffic.md")
     def one(d, pattern):
         f = glob.glob(os.path.join(d, "**", pattern), recursive=True)
         if not f:
@@ -125,12 +141,9 @@ def summarize_profiles(kt_dir, pf_dir, pw_dir, command):
     stats = one(kt_dir, "*kernel_stats.csv")
     total = sum(float(r["TotalDurationNs"]) for r in stats)
     sh = source_hash()
-    lines = ["# Kernel statistics: one assembly step on the 2048x2048-cell unit square",
+    lines = [f"# Kernel statistics: {title}",
              "",
-             "Workload: 8,388,608 triangles, 4,198,401 vertices (jitter 0.2h, random vertex",
-             "relabelling), nnz 29,372,417; FP64 values, int32 indices.  Per-call averages over",
-             "the run (1 warm-up + 5 timed steps, plus the stiffness + mass pair timed alone and",
-             "a 1 GiB fill and copy used to calibrate the counters).",
+             workload,
              "",
              f"source-sha256: {sh}",
              "",
@@ -142,7 +155,7 @@ def summarize_profiles(kt_dir, pf_dir, pw_dir, command):
         lines.append(f"| `{kernel_short_name(r['Name'])}` | {r['Calls']} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                      f"{float(r['MaxNs']) / 1e3:.1f} | {100 * float(r['TotalDurationNs']) / total:.1f} % |")
-    with open(PROFILE_STATS, "w") as f:
+    with open(stats_path, "w") as f:
         f.write("\n".join(lines) + "\n")
 
     def per_kernel(rows, counter):
@@ -161,7 +174,7 @@ def summarize_profiles(kt_dir, pf_dir, pw_dir, command):
     cw = max(write.get("__amd_rocclr_copyBuffer", [0.0]))
     sf = gib_kib / cf if cf > 0 else float("nan")
     sw = gib_kib / cw if cw > 0 else float("nan")
-    lines = ["# HBM traffic per dispatch: one assembly step on the 2048x2048-cell unit square",
+    lines = [f"# HBM traffic per dispatch: {title}",
              "",
              "FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the dispatches of the run),",
              "each scaled by what the same counter reads for a plain 1 GiB device-to-device copy",
@@ -180,10 +193,10 @@ def summarize_profiles(kt_dir, pf_dir, pw_dir, command):
         w_kib = float(np.mean(write[k])) if k in write else float("nan")
         lines.append(f"| `{k}` | {len(fetch.get(k, write.get(k, [])))} | {f_kib:.1f} | {w_kib:.1f} | "
                      f"{f_kib * 1024 * sf / 1e6:.3f} | {w_kib * 1024 * sw / 1e6:.3f} |")
-    with open(PROFILE_TRAFFIC, "w") as f:
+    with open(traffic_path, "w") as f:
         f.write("\n".join(lines) + "\n")
-    print(PROFILE_STATS)
-    print(PROFILE_TRAFFIC)
+    print(stats_path)
+    print(traffic_path)
 
 
 def algorithmic_bytes(nq, nme, nnz):
@@ -634,9 +647,13 @@ def main():
     ap.add_argument("--summarize", nargs=3, metavar=("KT", "PF", "PW"),
                     help="write the profiles/ summaries from rocprofv3 csv directories")
     ap.add_argument("--command", default="", help="command text recorded by --summarize")
+    ap.add_argument("--profile-name", default="step_square2048", choices=sorted(PROFILE_TITLES),
+                    help="which summary --summarize writes")
+    ap.add_argument("--only", choices=("sparse", "adjoint", "batched"),
+                    help="run one of the extra measurements alone and print its JSON (profiling)")
     args = ap.parse_args()
     if args.summarize:
-        summarize_profiles(*args.summarize, args.command)
+        summarize_profiles(*args.summarize, args.command, args.profile_name)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (the assembly of one mesh runs on one "
@@ -654,6 +671,10 @@ def main():
         torch.cuda.synchronize()
         log("[bench] calibration copy of 1 GiB done")
         del src, dst
+    if args.only:
+        fn = {"sparse": run_sparse, "adjoint": run_adjoint, "batched": run_batched}[args.only]
+        print(json.dumps({args.only: fn(torch, fem, args)}), flush=True)
+        return
     m, st, ms, kern = run_main(torch, fem, args)
     extras = {}
     if not args.no_extras:
