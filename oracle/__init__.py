@@ -66,6 +66,13 @@ def _load():
                                   _i32p, _i32p, _f64p]
     lib.oracle_validate.restype = C.c_int
     lib.oracle_validate.argtypes = [C.c_int32, C.c_int32, _i32p]
+    lib.oracle_tet_det.restype = C.c_double
+    lib.oracle_tet_det.argtypes = [_f64p, _f64p, _f64p, _f64p]
+    lib.oracle_elem_tet_mass.argtypes = [C.c_double, _f64p]
+    lib.oracle_elem_tet_stiff.argtypes = [_f64p, _f64p, _f64p, _f64p, _f64p]
+    lib.oracle_assemble_tet.restype = C.c_int64
+    lib.oracle_assemble_tet.argtypes = [C.c_int, C.c_int32, C.c_int32, _f64p, _i32p, _i32p, _i32p,
+                                        _f64p]
     lib.oracle_pattern.restype = C.c_int64
     lib.oracle_pattern.argtypes = [C.c_int32, C.c_int32, _i32p, _i32p, _i32p, vp, vp, vp]
     lib.oracle_pattern_elas.restype = C.c_int64
@@ -147,6 +154,36 @@ def sparse(I, J, V, nrows: int, ncols: int):
     col_idx = np.zeros(max(n, 1), np.int32)
     vals = np.zeros(max(n, 1), np.float64)
     nnz = _check(_load().oracle_sparse(nrows, ncols, n, I, J, V, row_ptr, col_idx, vals))
+    return row_ptr, col_idx[:nnz].copy(), vals[:nnz].copy()
+
+
+def tet_det(x0, x1, x2, x3) -> float:
+    """det [x1 - x0 | x2 - x0 | x3 - x0] (six times the signed volume)."""
+    return _load().oracle_tet_det(_f64(x0), _f64(x1), _f64(x2), _f64(x3))
+
+
+def elem_tet_mass(vol: float):
+    E = np.zeros(16)
+    _load().oracle_elem_tet_mass(float(vol), E)
+    return E.reshape(4, 4).T.copy()     # [a][b]
+
+
+def elem_tet_stiff(x0, x1, x2, x3):
+    E = np.zeros(16)
+    _load().oracle_elem_tet_stiff(_f64(x0), _f64(x1), _f64(x2), _f64(x3), E)
+    return E.reshape(4, 4).T.copy()
+
+
+def assemble_tet(op: str, q, me):
+    """Global P1 tetrahedron mass ("mass") or stiffness ("stiff") as CSR
+    (row_ptr, col_idx, values): OptV2 triplets t = r nme + k, then sparse()."""
+    q, me = _f64(q), _i32(me)
+    nq, nme = q.shape[0], me.shape[0]
+    row_ptr = np.zeros(nq + 1, np.int32)
+    col_idx = np.zeros(max(16 * nme, 1), np.int32)
+    vals = np.zeros(max(16 * nme, 1), np.float64)
+    nnz = _check(_load().oracle_assemble_tet({"mass": 0, "stiff": 1}[op], nq, nme, q.reshape(-1),
+                                             me.reshape(-1), row_ptr, col_idx, vals))
     return row_ptr, col_idx[:nnz].copy(), vals[:nnz].copy()
 
 

@@ -668,3 +668,124 @@ int oracle_adjoint_stiff_wmass(int32_t nq, int32_t nme, const double *q, const i
     }
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* P1 tetrahedra in 3D (the extension named in the Conclusion)        */
+/* ------------------------------------------------------------------ */
+/* q is [nq][3], me is [nme][4].  For the tetrahedron K = (x0, x1, x2, x3)
+ * with J = [x1 - x0 | x2 - x0 | x3 - x0] (columns), |K| = |det J| / 6, the
+ * barycentric coordinates are lambda_{1..3} = rows of J^{-1} applied to
+ * (x - x0) and lambda_0 = 1 - their sum, so grad lambda_i is row i of J^{-1}
+ * (i = 1..3) and grad lambda_0 = -(sum of those rows).                    */
+
+/* det J = (x1 - x0) . ((x2 - x0) x (x3 - x0)) */
+double oracle_tet_det(const double *x0, const double *x1, const double *x2, const double *x3)
+{
+    double a[3], b[3], c[3];
+    for (int i = 0; i < 3; ++i) {
+        a[i] = x1[i] - x0[i];
+        b[i] = x2[i] - x0[i];
+        c[i] = x3[i] - x0[i];
+    }
+    const double bxc0 = b[1] * c[2] - b[2] * c[1];
+    const double bxc1 = b[2] * c[0] - b[0] * c[2];
+    const double bxc2 = b[0] * c[1] - b[1] * c[0];
+    return a[0] * bxc0 + a[1] * bxc1 + a[2] * bxc2;
+}
+
+/* Mass: integral of lambda_a lambda_b = |K| (1 + delta_ab) / 20 (the 3D
+ * counterpart of eq. MassElem).  E column-major, E[4 b + a]. */
+void oracle_elem_tet_mass(double vol, double E[16])
+{
+    for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < 4; ++a)
+            E[4 * b + a] = vol * (a == b ? 2.0 : 1.0) / 20.0;
+}
+
+/* Stiffness: |K| grad lambda_a . grad lambda_b, with J^{-1} = adj(J) / det J. */
+void oracle_elem_tet_stiff(const double *x0, const double *x1, const double *x2,
+                           const double *x3, double E[16])
+{
+    double J[3][3];   /* J[r][c]: component r of column c */
+    for (int r = 0; r < 3; ++r) {
+        J[r][0] = x1[r] - x0[r];
+        J[r][1] = x2[r] - x0[r];
+        J[r][2] = x3[r] - x0[r];
+    }
+    const double det = oracle_tet_det(x0, x1, x2, x3);
+    /* inverse by the adjugate (cofactor transpose) */
+    double Ji[3][3];
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    double g[4][3];
+    for (int c = 0; c < 3; ++c) {
+        g[1][c] = Ji[0][c];
+        g[2][c] = Ji[1][c];
+        g[3][c] = Ji[2][c];
+        g[0][c] = -(g[1][c] + g[2][c] + g[3][c]);
+    }
+    const double vol = fabs(det) / 6.0;
+    for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < 4; ++a)
+            E[4 * b + a] = vol * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]);
+}
+
+/* Global P1 tetrahedron matrices the OptV2 way: Ig, Jg, Kg of all 16 local
+ * entries, triplet t = r nme + k for local entry r = 4 b + a of element k
+ * (row me[k][a], column me[k][b]), then sparse() (values summed in ascending
+ * t).  op: 0 mass, 1 stiffness.  col_idx / values hold 16 nme entries. */
+int64_t oracle_assemble_tet(int op, int32_t nq, int32_t nme, const double *q, const int32_t *me,
+                            int32_t *row_ptr, int32_t *col_idx, double *values)
+{
+    if (nq <= 0 || nme < 0 || (op != 0 && op != 1))
+        return ORACLE_EINVAL;
+    for (int64_t k = 0; k < nme; ++k) {
+        const int32_t *t = me + 4 * k;
+        for (int a = 0; a < 4; ++a) {
+            if (t[a] < 0 || t[a] >= nq)
+                return ORACLE_ERANGE;
+            for (int b = 0; b < a; ++b)
+                if (t[a] == t[b])
+                    return ORACLE_EDEGEN;
+        }
+    }
+    const int64_t nt = 16 * (int64_t)nme;
+    const size_t n = (size_t)(nt > 0 ? nt : 1);
+    int32_t *I = (int32_t *)malloc(sizeof(int32_t) * n);
+    int32_t *Jv = (int32_t *)malloc(sizeof(int32_t) * n);
+    double *V = (double *)malloc(sizeof(double) * n);
+    if (!I || !Jv || !V) {
+        free(I);
+        free(Jv);
+        free(V);
+        return ORACLE_ENOMEM;
+    }
+    for (int64_t k = 0; k < nme; ++k) {
+        const int32_t *t = me + 4 * k;
+        const double *x0 = q + 3 * (int64_t)t[0], *x1 = q + 3 * (int64_t)t[1];
+        const double *x2 = q + 3 * (int64_t)t[2], *x3 = q + 3 * (int64_t)t[3];
+        double E[16];
+        if (op == 0)
+            oracle_elem_tet_mass(fabs(oracle_tet_det(x0, x1, x2, x3)) / 6.0, E);
+        else
+            oracle_elem_tet_stiff(x0, x1, x2, x3, E);
+        for (int r = 0; r < 16; ++r) {
+            const int64_t s = (int64_t)r * nme + k;
+            I[s] = t[r % 4];
+            Jv[s] = t[r / 4];
+            V[s] = E[r];
+        }
+    }
+    const int64_t nnz = oracle_sparse(nq, nq, nt, I, Jv, V, row_ptr, col_idx, values);
+    free(I);
+    free(Jv);
+    free(V);
+    return nnz;
+}

@@ -23,6 +23,11 @@ Meshes
   relabelling.  nme = 6 K^2, nq = 1 + 3 K (K + 1).
 * ``batch_of_squares(...)``: many independent unit-square meshes with uneven
   sizes, concatenated with vertex offsets (block-diagonal global matrix).
+* ``unit_cube(n, ...)``: [0,1]^3 split into n^3 cells, each cut into the six
+  tetrahedra around its v000-v111 diagonal (Kuhn; conforming across cells),
+  all positively oriented before the jitter; interior vertices jittered by
+  U(-j h, j h) per coordinate; then a random relabelling.  q is [nq][3] and
+  me is [nme][4].
 
 The paper measures on FreeFEM++ unit-disk meshes that are not available; these
 seeded meshes stand in for them.
@@ -173,6 +178,52 @@ def batch_of_squares(nb: int = 512, n_min: int = 8, n_max: int = 512,
     me_glob = (me_local.astype(np.int64) + shift[:, None]).astype(np.int32)
     return Batch(np.ascontiguousarray(np.concatenate(qs, axis=0)), np.ascontiguousarray(me_glob),
                  np.ascontiguousarray(me_local), vtx_off, elem_off, sizes)
+
+
+def unit_cube(n: int, jitter: float = 0.1, seed: int | None = BASE_SEED,
+              permute: bool = True) -> Mesh:
+    """Unit cube, n^3 cells, 6 n^3 tetrahedra (q [nq][3], me [nme][4])."""
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = 1.0 / n
+    m = n + 1
+    kk, jj, ii = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    # vertex (i h, j h, k h) has index (k m + j) m + i before relabelling
+    q = np.stack([ii.ravel() * h, jj.ravel() * h, kk.ravel() * h], axis=1).astype(np.float64)
+    if jitter:
+        d = rng.uniform(-jitter * h, jitter * h, size=q.shape)
+        interior = ((ii.ravel() > 0) & (ii.ravel() < n) & (jj.ravel() > 0) & (jj.ravel() < n) &
+                    (kk.ravel() > 0) & (kk.ravel() < n))
+        q[interior] += d[interior]
+    ck, cj, ci = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    base = ((ck.ravel() * m + cj.ravel()) * m + ci.ravel()).astype(np.int64)
+    step = np.array([1, m, m * m], dtype=np.int64)     # +x, +y, +z
+    tets = []
+    # the six monotone paths v000 -> v111; odd permutations swap the last two
+    # vertices so that every tetrahedron is positively oriented
+    for perm, odd in (((0, 1, 2), False), ((1, 2, 0), False), ((2, 0, 1), False),
+                      ((0, 2, 1), True), ((2, 1, 0), True), ((1, 0, 2), True)):
+        a = base
+        b = a + step[perm[0]]
+        c = b + step[perm[1]]
+        d4 = c + step[perm[2]]
+        tets.append(np.stack([a, b, d4, c] if odd else [a, b, c, d4], axis=1))
+    me = np.stack(tets, axis=1).reshape(-1, 4)
+    if permute:
+        q, me = _relabel(rng, q, me)
+    return Mesh(np.ascontiguousarray(q), np.ascontiguousarray(me.astype(np.int32)), f"cube{n}")
+
+
+def random_tiny_tet_mesh(rng: np.random.Generator, max_q: int = 30):
+    """A small random tetrahedron soup over <= max_q vertices in [-1, 1]^3
+    (distinct vertices per element; elements may overlap, vertices may be
+    unused); for brute-force cross-checks."""
+    nq = int(rng.integers(4, max_q + 1))
+    q = rng.uniform(-1.0, 1.0, size=(nq, 3))
+    nme = int(rng.integers(1, 3 * nq))
+    me = np.stack([rng.choice(nq, 4, replace=False) for _ in range(nme)]).astype(np.int32)
+    return Mesh(q, me, "tiny_tets")
 
 
 def weight_quadratic(q: np.ndarray) -> np.ndarray:

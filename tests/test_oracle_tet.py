@@ -1,0 +1,167 @@
+"""Pins of the oracle's P1 tetrahedron assembly (no GPU).
+
+Each check ties the oracle to something other than its own formulas: the
+textbook element matrices of the reference tetrahedron, an exact quadrature
+rule, energy identities of linear fields, integrals over the unit cube, a
+closed form for the number of edges, and a dense brute-force assembly."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1305_3122_amd import meshgen as mg
+
+REF = [np.array(v, float) for v in ([0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1])]
+
+# degree-2 rule on a tetrahedron: four points (a, b, b, b) in barycentric
+# coordinates and permutations, equal weights vol / 4
+_QA, _QB = 0.5854101966249685, 0.1381966011250105
+
+
+def _quad_points(x):
+    X = np.stack(x)
+    pts = []
+    for i in range(4):
+        lam = np.full(4, _QB)
+        lam[i] = _QA
+        pts.append(lam @ X)
+    return pts
+
+
+def _random_tet(rng):
+    while True:
+        x = [rng.uniform(-1, 1, 3) for _ in range(4)]
+        if abs(oracle.tet_det(*x)) > 0.05:
+            return x
+
+
+def test_reference_tetrahedron_matrices():
+    assert oracle.tet_det(*REF) == pytest.approx(1.0)
+    S = oracle.elem_tet_stiff(*REF)
+    want = np.array([[3, -1, -1, -1], [-1, 1, 0, 0], [-1, 0, 1, 0], [-1, 0, 0, 1]]) / 6.0
+    np.testing.assert_allclose(S, want, atol=1e-15)
+    M = oracle.elem_tet_mass(1.0 / 6.0)
+    np.testing.assert_allclose(M, (np.ones((4, 4)) + np.eye(4)) / 120.0, atol=1e-16)
+
+
+def test_mass_quadratic_form_is_integral_by_quadrature():
+    rng = np.random.default_rng(31)
+    for _ in range(20):
+        x = _random_tet(rng)
+        vol = abs(oracle.tet_det(*x)) / 6.0
+        M = oracle.elem_tet_mass(vol)
+        c, g = rng.standard_normal(), rng.standard_normal(3)
+        u = np.array([c + g @ xi for xi in x])
+        integral = sum(vol / 4.0 * (c + g @ p) ** 2 for p in _quad_points(x))
+        assert u @ M @ u == pytest.approx(integral, rel=1e-13)
+
+
+def test_stiffness_energy_of_linear_fields():
+    rng = np.random.default_rng(32)
+    for _ in range(20):
+        x = _random_tet(rng)
+        vol = abs(oracle.tet_det(*x)) / 6.0
+        S = oracle.elem_tet_stiff(*x)
+        c, g = rng.standard_normal(), rng.standard_normal(3)
+        u = np.array([c + g @ xi for xi in x])
+        assert u @ S @ u == pytest.approx(vol * g @ g, rel=1e-12)
+        np.testing.assert_allclose(S.sum(axis=1), 0.0, atol=1e-12 * np.abs(S).max())
+        np.testing.assert_allclose(S, S.T, atol=1e-14 * np.abs(S).max())
+
+
+def test_orientation_and_vertex_order():
+    rng = np.random.default_rng(33)
+    x = _random_tet(rng)
+    S = oracle.elem_tet_stiff(*x)
+    for p in itertools.permutations(range(4)):
+        Sp = oracle.elem_tet_stiff(*[x[i] for i in p])
+        np.testing.assert_allclose(Sp, S[np.ix_(p, p)], rtol=1e-12, atol=1e-14)
+
+
+def test_unit_cube_integrals_and_null_space():
+    m = mg.unit_cube(4, seed=mg.BASE_SEED + 300)
+    rpM, ciM, M = oracle.assemble_tet("mass", m.q, m.me)
+    rpS, ciS, S = oracle.assemble_tet("stiff", m.q, m.me)
+    np.testing.assert_array_equal(rpM, rpS)
+    np.testing.assert_array_equal(ciM, ciS)
+    n = m.nq
+    rows = np.repeat(np.arange(n), np.diff(rpM))
+    Md = np.zeros((n, n))
+    Sd = np.zeros((n, n))
+    Md[rows, ciM] = M
+    Sd[rows, ciS] = S
+    x, y, z = m.q[:, 0], m.q[:, 1], m.q[:, 2]
+    one = np.ones(n)
+    assert one @ Md @ one == pytest.approx(1.0, rel=1e-13)            # volume
+    assert x @ Md @ x == pytest.approx(1.0 / 3.0, rel=1e-13)          # int x^2
+    assert one @ Md @ y == pytest.approx(0.5, rel=1e-13)              # int y
+    np.testing.assert_allclose(Sd @ one, 0.0, atol=1e-12)
+    g = np.array([0.3, -1.1, 0.7])
+    u = 2.0 + m.q @ g
+    assert u @ Sd @ u == pytest.approx(g @ g, rel=1e-12)               # |grad u|^2 vol
+    np.testing.assert_allclose(Sd, Sd.T, atol=1e-13)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5])
+def test_pattern_counts_edges(n):
+    # Kuhn triangulation of n^3 cells: axis edges 3 n (n+1)^2, one diagonal in
+    # each of the 3 n^2 (n+1) grid faces, one body diagonal per cell
+    m = mg.unit_cube(n, seed=5)
+    rp, _, _ = oracle.assemble_tet("mass", m.q, m.me)
+    edges = 3 * n * (n + 1) ** 2 + 3 * n * n * (n + 1) + n ** 3
+    assert rp[-1] == m.nq + 2 * edges
+
+
+def test_bruteforce_dense_assembly():
+    rng = np.random.default_rng(34)
+    for _ in range(5):
+        m = mg.random_tiny_tet_mesh(np.random.default_rng(rng.integers(1 << 30)), 20)
+        for op in ("mass", "stiff"):
+            rp, ci, v = oracle.assemble_tet(op, m.q, m.me)
+            A = np.zeros((m.nq, m.nq))
+            for t in m.me:
+                x = [m.q[i] for i in t]
+                E = (oracle.elem_tet_mass(abs(oracle.tet_det(*x)) / 6.0) if op == "mass"
+                     else oracle.elem_tet_stiff(*x))
+                for a in range(4):
+                    for b in range(4):
+                        A[t[a], t[b]] += E[a, b]
+            rows = np.repeat(np.arange(m.nq), np.diff(rp))
+            B = np.zeros_like(A)
+            B[rows, ci] = v
+            # every structural entry is one of A's nonzeros and vice versa
+            assert set(zip(rows.tolist(), ci.tolist())) == set(zip(*np.nonzero(A != 0)))
+            np.testing.assert_allclose(B, A, rtol=1e-13, atol=1e-14 * np.abs(A).max())
+
+
+def test_validation():
+    q = np.zeros((4, 3))
+    with pytest.raises(Exception):
+        oracle.assemble_tet("mass", q, np.array([[0, 1, 2, 4]], np.int32))
+    with pytest.raises(Exception):
+        oracle.assemble_tet("mass", q, np.array([[0, 1, 2, 2]], np.int32))
+
+
+def test_cube_generator_volumes_and_worst_case_jitter():
+    m = mg.unit_cube(5, seed=9)
+    dets = np.array([oracle.tet_det(*m.q[t]) for t in m.me])
+    assert dets.min() > 0
+    assert dets.sum() / 6.0 == pytest.approx(1.0, rel=1e-13)
+    # det is affine in each vertex coordinate, so its minimum over jitters of
+    # at most 0.1 h per coordinate is at a corner of the box: >= 0.4 h^3
+    E = np.eye(3)
+    paths = {(0, 1, 2): False, (1, 2, 0): False, (2, 0, 1): False,
+             (0, 2, 1): True, (2, 1, 0): True, (1, 0, 2): True}
+    signs = np.array(list(itertools.product([-1, 1], repeat=12))).reshape(-1, 4, 3)
+    worst = np.inf
+    for p, odd in paths.items():
+        a = np.zeros(3)
+        b = a + E[p[0]]
+        c = b + E[p[1]]
+        d = c + E[p[2]]
+        V = np.stack([a, b, d, c] if odd else [a, b, c, d])
+        W = V[None] + 0.1 * signs
+        worst = min(worst, np.linalg.det(np.stack([W[:, 1] - W[:, 0], W[:, 2] - W[:, 0],
+                                                    W[:, 3] - W[:, 0]], axis=1)).min())
+    assert worst >= 0.4 - 1e-12
