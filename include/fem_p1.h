@@ -324,6 +324,44 @@ int fem_sparse_values(int64_t nnz, const int32_t *contrib_ptr, const int32_t *co
                       const double *V, double *vals, int flags, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* P1 tetrahedra in 3D                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* HOST ONLY.  Bytes of device workspace fem_tet_pattern needs. */
+int fem_tet_pattern_workspace(int32_t nq, int32_t nme, size_t *bytes /* HOST */);
+
+/* Pattern of the P1 tetrahedron matrices (the 3D extension named in the
+ * Conclusion), built the OptV2 way: the index arrays of all 16 local entries,
+ * triplet t = r nme + k for entry r = 4 b + a of element k (row me[k][a],
+ * column me[k][b]), compressed by fem_sparse.
+ *   me [nme][4] int32, 16-byte aligned; row_ptr [nq+1], col_idx [col_cap]
+ *   contrib_ptr [col_cap+1], contrib [16 nme]: the triplets of each entry,
+ *                ascending (what fem_tet_assemble sums)
+ *   work [work_bytes] >= fem_tet_pattern_workspace(nq, nme); nnz_out HOST
+ * Requires 16 nme <= 2^31 - 1.  FEM_ERANGE / FEM_EDEGEN for an invalid me,
+ * FEM_ENOSPC if col_cap < nnz.  Synchronises `stream`. */
+int fem_tet_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *row_ptr,
+                    int32_t *col_idx, int64_t col_cap, int32_t *contrib_ptr, int32_t *contrib,
+                    void *work, size_t work_bytes, int64_t *nnz_out /* HOST */, void *stream);
+
+/* HOST ONLY.  Bytes of device workspace fem_tet_assemble needs (16 nme values
+ * per requested operator). */
+int fem_tet_assemble_workspace(int32_t nme, int ops, size_t *bytes /* HOST */);
+
+/* P1 tetrahedron mass (FEM_OP_MASS: |K| (1 + delta_ab) / 20) and / or
+ * stiffness (FEM_OP_STIFF: |K| grad lambda_a . grad lambda_b) on the pattern
+ * of fem_tet_pattern: the element matrices of every tetrahedron at their
+ * triplet positions (the paper's Kg), then for every entry the sum of its
+ * contributors in ascending t (bitwise reproducible).
+ *   q [nq][3] f64; me [nme][4] int32 (16-byte aligned); vals_M / vals_S [nnz]
+ *   work [work_bytes] >= fem_tet_assemble_workspace(nme, ops), 16-byte aligned
+ * flags: 0 or FEM_ACCUMULATE. */
+int fem_tet_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q,
+                     const int32_t *me, const int32_t *contrib_ptr, const int32_t *contrib,
+                     double *vals_M, double *vals_S, void *work, size_t work_bytes, int flags,
+                     void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Adjoint                                                                   */
 /* ------------------------------------------------------------------------ */
 

@@ -32,6 +32,7 @@ __all__ = [
     "fem_assemble_wmass", "fem_assemble_stiff", "fem_assemble_stiff_mass",
     "fem_assemble_stiff_wmass", "fem_assemble_elas", "fem_batch_globalize",
     "fem_assemble_stiff_mass_batched", "Graph", "SparseCSR", "fem_sparse", "fem_sparse_values",
+    "TetPattern", "fem_tet_pattern", "fem_tet_assemble",
     "fem_adjoint_workspace", "fem_adjoint_stiff_wmass",
     "AssembleStiffWMass",
     "library_path",
@@ -372,6 +373,74 @@ def fem_sparse_values(A: SparseCSR, V, *, out=None, flags: int = 0, stream=None)
     out = torch.empty(max(A.nnz, 1), dtype=torch.float64, device=V.device)[:A.nnz] if out is None else out
     _lib.check(_lib.load().fem_sparse_values(A.nnz, _ptr(A.contrib_ptr), _ptr(A.contrib), _ptr(V),
                                              _ptr(out), flags, _stream(stream)))
+    return out
+
+
+@dataclasses.dataclass
+class TetPattern:
+    """Result of fem_tet_pattern (device tensors)."""
+    nq: int
+    nme: int
+    nnz: int
+    me: object               # [nme][4] int32
+    row_ptr: object          # [nq+1] int32
+    col_idx: object          # [nnz] int32
+    contrib_ptr: object      # [nnz+1] int32
+    contrib: object          # [16 nme] int32
+
+    def csr(self, values):
+        torch = _torch()
+        return torch.sparse_csr_tensor(self.row_ptr, self.col_idx, values, (self.nq, self.nq))
+
+
+def fem_tet_pattern(me, nq: int, *, stream=None) -> TetPattern:
+    """P1 tetrahedron pattern (C: fem_tet_pattern).  me: [nme][4] int32 on the GPU."""
+    torch = _torch()
+    lib = _lib.load()
+    _dev(me, torch.int32, "me")
+    if me.dim() != 2 or me.shape[1] != 4:
+        raise ValueError("me must have shape [nme, 4]")
+    nme = int(me.shape[0])
+    dev = me.device
+    ws = C.c_size_t(0)
+    _lib.check(lib.fem_tet_pattern_workspace(int(nq), nme, C.byref(ws)))
+    work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
+    cap = 16 * nme
+    i32 = dict(dtype=torch.int32, device=dev)
+    row_ptr = torch.empty(int(nq) + 1, **i32)
+    col = torch.empty(max(cap, 1), **i32)
+    cptr = torch.empty(cap + 1, **i32)
+    ctb = torch.empty(max(cap, 1), **i32)
+    nnz = C.c_int64(0)
+    _lib.check(lib.fem_tet_pattern(int(nq), nme, _ptr(me), _ptr(row_ptr), _ptr(col), cap, _ptr(cptr),
+                                   _ptr(ctb), _ptr(work), int(ws.value), C.byref(nnz),
+                                   _stream(stream)))
+    k = int(nnz.value)
+    return TetPattern(int(nq), nme, k, me, row_ptr, col[:k], cptr[:k + 1], ctb[:cap])
+
+
+def fem_tet_assemble(pat: TetPattern, q, ops: int = FEM_OP_MASS | FEM_OP_STIFF, *, out=None,
+                     work=None, flags: int = 0, stream=None):
+    """P1 tetrahedron mass / stiffness values on `pat` (C: fem_tet_assemble).
+    q: [nq][3] float64 on the GPU.  Returns {"M": ..., "S": ...} for the
+    requested operators."""
+    torch = _torch()
+    lib = _lib.load()
+    _dev(q, torch.float64, "q", (pat.nq, 3))
+    dev = q.device
+    out = {} if out is None else dict(out)
+    f64 = dict(dtype=torch.float64, device=dev)
+    for key, bit in (("M", FEM_OP_MASS), ("S", FEM_OP_STIFF)):
+        if ops & bit and key not in out:
+            out[key] = torch.empty(max(pat.nnz, 1), **f64)[:pat.nnz]
+    if work is None:
+        ws = C.c_size_t(0)
+        _lib.check(lib.fem_tet_assemble_workspace(pat.nme, int(ops), C.byref(ws)))
+        work = torch.empty(max(int(ws.value), 16), dtype=torch.uint8, device=dev)
+    _lib.check(lib.fem_tet_assemble(int(ops), pat.nq, pat.nme, pat.nnz, _ptr(q), _ptr(pat.me),
+                                    _ptr(pat.contrib_ptr), _ptr(pat.contrib), _ptr(out.get("M")),
+                                    _ptr(out.get("S")), _ptr(work), work.numel() * work.element_size(),
+                                    flags, _stream(stream)))
     return out
 
 

@@ -85,6 +85,12 @@ SIGNATURES = {
     "fem_sparse": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
                           C.c_size_t, C.POINTER(_i64), _vp]),
     "fem_sparse_values": (_int, [_i64, _vp, _vp, _vp, _vp, _int, _vp]),
+    "fem_tet_pattern_workspace": (_int, [_i32, _i32, _szp]),
+    "fem_tet_pattern": (_int, [_i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t,
+                               C.POINTER(_i64), _vp]),
+    "fem_tet_assemble_workspace": (_int, [_i32, _int, _szp]),
+    "fem_tet_assemble": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                C.c_size_t, _int, _vp]),
     "fem_adjoint_workspace": (_int, [_i32, _i64, _szp]),
     "fem_adjoint_stiff_wmass": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                        _vp, _vp, _vp, _vp, C.c_size_t, _int, _vp]),

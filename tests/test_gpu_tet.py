@@ -1,0 +1,138 @@
+"""GPU P1 tetrahedra (mass, stiffness) against the oracle, through the C ABI.
+
+Pattern and contributor lists bit-exact; values within 1e-13 per row (max
+norm): both sides add the same triplets in the same order (ascending t) and
+differ only in the rounding of the element formulas."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1305_3122_amd import meshgen as mg
+from tests.helpers import RTOL_ROW, row_rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1305_3122_amd as fem  # noqa: E402
+from paper_1305_3122_amd import _lib  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _up(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def tet_triplets(me):
+    """Ig, Jg of the 16 local entries, t = r nme + k, r = 4 b + a."""
+    a = np.tile(np.arange(4), 4)
+    b = np.repeat(np.arange(4), 4)
+    return (me[:, a].T.reshape(-1).astype(np.int32), me[:, b].T.reshape(-1).astype(np.int32))
+
+
+def _check(m, contrib=True):
+    pat = fem.fem_tet_pattern(_up(m.me), m.nq)
+    q = _up(m.q)
+    both = fem.fem_tet_assemble(pat, q)
+    onlyM = fem.fem_tet_assemble(pat, q, fem.FEM_OP_MASS)["M"]
+    onlyS = fem.fem_tet_assemble(pat, q, fem.FEM_OP_STIFF)["S"]
+    torch.cuda.synchronize()
+    rp, ci, M = oracle.assemble_tet("mass", m.q, m.me)
+    _, _, S = oracle.assemble_tet("stiff", m.q, m.me)
+    assert pat.nnz == ci.shape[0]
+    np.testing.assert_array_equal(_np(pat.row_ptr), rp)
+    np.testing.assert_array_equal(_np(pat.col_idx), ci)
+    if contrib:
+        I, J = tet_triplets(m.me)
+        _, _, pos = oracle.sparse_positions(I, J, m.nq, m.nq)
+        np.testing.assert_array_equal(_np(pat.contrib), np.argsort(pos, kind="stable"))
+        np.testing.assert_array_equal(
+            _np(pat.contrib_ptr), np.concatenate([[0], np.cumsum(np.bincount(pos, minlength=pat.nnz))]))
+    assert row_rel_err(rp, _np(both["M"]), M) <= RTOL_ROW
+    assert row_rel_err(rp, _np(both["S"]), S) <= RTOL_ROW
+    # one pass for both operators adds the same terms as the single ones
+    assert torch.equal(both["M"], onlyM) and torch.equal(both["S"], onlyS)
+    return pat, both
+
+
+def _cases():
+    out = [("cube1", mg.unit_cube(1, seed=1)), ("cube3_flat", mg.unit_cube(3, jitter=0.0, seed=2)),
+           ("cube5", mg.unit_cube(5, seed=3)), ("cube12", mg.unit_cube(12, seed=4))]
+    rng = np.random.default_rng(77)
+    for s in range(3):
+        out.append((f"soup{s}", mg.random_tiny_tet_mesh(np.random.default_rng(rng.integers(1 << 30)), 30)))
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name,m", CASES, ids=[n for n, _ in CASES])
+def test_tet_matches_oracle(name, m):
+    print(f"[case] tet {name} nq={m.nq} nme={m.nme}", flush=True)
+    _check(m)
+
+
+def test_tet_cube48_full_parity():
+    m = mg.unit_cube(48, seed=mg.BASE_SEED + 48)
+    print(f"[case] tet cube48 nq={m.nq} nme={m.nme}", flush=True)
+    _check(m, contrib=False)
+
+
+def _row_ids(pat):
+    rp = pat.row_ptr.long()
+    return torch.repeat_interleave(torch.arange(pat.nq, device=DEV), rp[1:] - rp[:-1])
+
+
+def test_tet_full_size_properties():
+    # the 128^3 cube (12.6M tetrahedra, 201M triplets): Euler's count of the
+    # entries, the volume, the null space of S and the energy of a linear field
+    n = 128
+    m = mg.unit_cube(n, seed=mg.BASE_SEED + 128)
+    print(f"[case] tet cube128 nq={m.nq} nme={m.nme}", flush=True)
+    pat = fem.fem_tet_pattern(_up(m.me), m.nq)
+    vals = fem.fem_tet_assemble(pat, _up(m.q))
+    torch.cuda.synchronize()
+    edges = 3 * n * (n + 1) ** 2 + 3 * n * n * (n + 1) + n ** 3
+    assert pat.nnz == m.nq + 2 * edges
+    M, S = vals["M"], vals["S"]
+    assert float(M.sum()) == pytest.approx(1.0, rel=1e-11)
+    rows = _row_ids(pat)
+    cols = pat.col_idx.long()
+    assert int((rows == cols).sum()) == m.nq
+    rs = torch.zeros(m.nq, dtype=torch.float64, device=DEV).index_add_(0, rows, S)
+    diag = S[rows == cols]              # the largest entry of each row of S
+    assert float((rs.abs() / diag).max()) <= 1e-12
+    g = torch.tensor([0.3, -1.1, 0.7], dtype=torch.float64, device=DEV)
+    u = 2.0 + _up(m.q) @ g
+    Su = torch.zeros(m.nq, dtype=torch.float64, device=DEV).index_add_(0, rows, S * u[cols])
+    assert float(u @ Su) == pytest.approx(float(g @ g), rel=1e-10)
+    Mu = torch.zeros(m.nq, dtype=torch.float64, device=DEV).index_add_(0, rows, M * u[cols])
+    # int u^2 over the cube for u = 2 + g.x
+    gi = g.cpu().numpy()
+    exact = 4.0 + 2.0 * 2.0 * gi.sum() / 2.0 + (gi ** 2).sum() / 3.0 + 2 * (gi[0] * gi[1] + gi[0] * gi[2] + gi[1] * gi[2]) / 4.0
+    assert float(u @ Mu) == pytest.approx(exact, rel=1e-11)
+
+
+def test_tet_errors_and_empty():
+    q = np.zeros((5, 3))
+    with pytest.raises(fem.FemError) as e:
+        fem.fem_tet_pattern(_up(np.array([[0, 1, 2, 5]], np.int32)), 5)
+    assert e.value.status == _lib.FEM_ERANGE
+    with pytest.raises(fem.FemError) as e:
+        fem.fem_tet_pattern(_up(np.array([[0, 1, 2, 3], [0, 1, 1, 4]], np.int32)), 5)
+    assert e.value.status == _lib.FEM_EDEGEN
+    pat = fem.fem_tet_pattern(torch.zeros((0, 4), dtype=torch.int32, device=DEV), 5)
+    vals = fem.fem_tet_assemble(pat, _up(q))
+    torch.cuda.synchronize()
+    assert pat.nnz == 0 and vals["M"].numel() == 0
+    np.testing.assert_array_equal(_np(pat.row_ptr), np.zeros(6, np.int32))
+    # and the library keeps working
+    _check(mg.unit_cube(2, seed=8))
