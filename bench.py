@@ -15,7 +15,8 @@ kernel (algorithmic bytes), the stiffness + mass pair alone, the batched
 block-diagonal assembly of 512 meshes (one graph-captured launch) against a
 per-mesh launch loop, the forward + backward / forward ratio of the
 differentiable assembly, the general sparse(I, J, V) compression of the
-OptV2 triplet arrays, and the CPU oracle timed on a bounded sample.
+OptV2 triplet arrays, P1 tetrahedra on a 128^3 cube, and the CPU oracle timed
+on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
 
@@ -611,6 +612,75 @@ def run_sparse(torch, fem, args):
     return out
 
 
+def run_tet(torch, fem, args):
+    """P1 tetrahedra: the 128^3-cell unit cube (Kuhn, 12.6M tetrahedra, jitter
+    0.1h, random relabelling), pattern and fused mass + stiffness."""
+    from paper_1305_3122_amd import meshgen as mg
+    lib = fem._lib.load()
+    dev = torch.device("cuda:0")
+    n = 128
+    m = mg.unit_cube(n, seed=mg.BASE_SEED + 128)
+    me = torch.from_numpy(m.me).to(dev)
+    q = torch.from_numpy(m.q).to(dev)
+    ws = C.c_size_t(0)
+    fem._lib.check(lib.fem_tet_pattern_workspace(m.nq, m.nme, C.byref(ws)))
+    work = torch.empty(int(ws.value), dtype=torch.uint8, device=dev)
+    cap = 16 * m.nme
+    i32 = dict(dtype=torch.int32, device=dev)
+    row_ptr = torch.empty(m.nq + 1, **i32)
+    col = torch.empty(cap, **i32)
+    cptr = torch.empty(cap + 1, **i32)
+    ctb = torch.empty(cap, **i32)
+    s = torch.cuda.current_stream().cuda_stream
+    nnz = C.c_int64(0)
+
+    def pattern():
+        fem._lib.check(lib.fem_tet_pattern(m.nq, m.nme, me.data_ptr(), row_ptr.data_ptr(),
+                                           col.data_ptr(), cap, cptr.data_ptr(), ctb.data_ptr(),
+                                           work.data_ptr(), int(ws.value), C.byref(nnz), s))
+
+    pattern()
+    k = int(nnz.value)
+    ops = fem.FEM_OP_MASS | fem.FEM_OP_STIFF
+    aw = C.c_size_t(0)
+    fem._lib.check(lib.fem_tet_assemble_workspace(m.nme, ops, C.byref(aw)))
+    awork = torch.empty(int(aw.value), dtype=torch.uint8, device=dev)
+    M = torch.empty(k, dtype=torch.float64, device=dev)
+    S = torch.empty_like(M)
+
+    def assemble():
+        fem._lib.check(lib.fem_tet_assemble(ops, m.nq, m.nme, k, q.data_ptr(), me.data_ptr(),
+                                            cptr.data_ptr(), ctb.data_ptr(), M.data_ptr(),
+                                            S.data_ptr(), awork.data_ptr(), awork.numel(), 0, s))
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            ea = torch.cuda.Event(enable_timing=True)
+            eb = torch.cuda.Event(enable_timing=True)
+            ea.record()
+            fn()
+            eb.record()
+            torch.cuda.synchronize()
+            out.append(ea.elapsed_time(eb) * 1e3)
+        return float(np.median(out))
+
+    tp = timed(pattern, 3)
+    ta = timed(assemble, 10)
+    alg = 24 * m.nq + 16 * m.nme + 16 * k
+    out = {"workload": "unit cube 128^3 cells, 6 Kuhn tetrahedra per cell (12.6M), jitter 0.1h, "
+                       "random relabelling; P1 mass + stiffness FP64",
+           "nq": m.nq, "nme": m.nme, "nnz": k, "pattern_us": round(tp, 1),
+           "assemble_us": round(ta, 1), "Mtets_per_s_assemble": round(m.nme / ta, 1),
+           "Mtets_per_s_total": round(m.nme / (tp + ta), 1),
+           "assemble_alg_bytes": alg, "assemble_alg_GBps": round(alg / (ta * 1e-6) / 1e9, 1)}
+    log(f"[bench] tet cube128 nme={m.nme}: pattern {tp:.0f}us, mass+stiffness {ta:.0f}us "
+        f"({m.nme / ta:.0f} Mtets/s)")
+    return out
+
+
 def run_cpu_baseline(args):
     """The oracle, as it stands, on a bounded sample: the same recipe at
     1448 x 1448 cells (half of the workload), one full step."""
@@ -649,7 +719,7 @@ def main():
     ap.add_argument("--command", default="", help="command text recorded by --summarize")
     ap.add_argument("--profile-name", default="step_square2048", choices=sorted(PROFILE_TITLES),
                     help="which summary --summarize writes")
-    ap.add_argument("--only", choices=("sparse", "adjoint", "batched"),
+    ap.add_argument("--only", choices=("sparse", "adjoint", "batched", "tet"),
                     help="run one of the extra measurements alone and print its JSON (profiling)")
     args = ap.parse_args()
     if args.summarize:
@@ -672,7 +742,8 @@ def main():
         log("[bench] calibration copy of 1 GiB done")
         del src, dst
     if args.only:
-        fn = {"sparse": run_sparse, "adjoint": run_adjoint, "batched": run_batched}[args.only]
+        fn = {"sparse": run_sparse, "adjoint": run_adjoint, "batched": run_batched,
+              "tet": run_tet}[args.only]
         print(json.dumps({args.only: fn(torch, fem, args)}), flush=True)
         return
     m, st, ms, kern = run_main(torch, fem, args)
@@ -681,6 +752,7 @@ def main():
         extras["batched"] = run_batched(torch, fem, args)
         extras["adjoint"] = run_adjoint(torch, fem, args)
         extras["sparse"] = run_sparse(torch, fem, args)
+        extras["tet"] = run_tet(torch, fem, args)
     traffic = read_traffic()
 
     def roof(p):

@@ -16,7 +16,8 @@
 //                                      (column, t), duplicates summed in
 //                                      ascending t; rows staged per bucket,
 //                                      sorted triplet order written as the
-//                                      contributor list
+//                                      contributor list (every step parallel
+//                                      over the triplets)
 //   scan of bucket totals / k_sp_copy  rows -> col_idx / values, row_ptr
 // Every value is the sum of its triplets' values in ascending t, so the result
 // is bitwise reproducible and equal to a sequential left-to-right sum.
@@ -318,67 +319,54 @@ __device__ inline int32_t block_scan_sp(int32_t v, int32_t *s_wsum, int32_t *tot
     return off;
 }
 
-// Rows of at most RANK_MAX triplets are sorted by ranking (each element's
-// place = the number of smaller keys), longer ones by insertion.
-constexpr int RANK_MAX = 64;
+// The row (inside the bucket) holding bucket position x: the last row start
+// <= x (empty rows share their start with the next row).
+__device__ __forceinline__ int32_t row_of(const int32_t *s_rs, int32_t R, int32_t x) {
+    int32_t lo = 0, hi = R - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (s_rs[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 // The rows of one bucket, with the bucket's triplets (grouped by row) in
-// arrays `col`, `tt`, `val` (LDS or global scratch) at [0, nb):
-//   1 each row ordered by (column, t) -- t breaks ties, so the order is the
-//     stable one.  Rows of at most RANK_MAX triplets: perm[s + rank] = k,
-//     the arrays stay in place; longer rows: insertion sort of col / tt / val
-//     in place, perm the identity.  Unique columns -> row lengths.
+// arrays `col`, `tt`, `val` (LDS or global scratch) at [0, nb), every step
+// parallel over the triplets, whatever the row lengths:
+//   1 each triplet's place in its row in (column, t) order -- t breaks ties,
+//     so the order is the stable one -- is the number of smaller keys in the
+//     row: perm[s + rank] = its position; triplets with no equal column of
+//     smaller t start a run and count the row's unique columns (s_len)
 //   2 scan of the row lengths -> offsets of the rows inside the bucket
-//   3 each row's unique columns, the sums of their runs (ascending t) and the
-//     start of each run in the sorted triplet order, staged at e0 + offset,
-//     and the sorted t as the bucket's part of the contributor list
-// Rows are taken by the threads in turn (thread r: rows r, r + 256, ...).
+//   3 in sorted order: the contributor list (the triplets' t), and at each
+//     run start its slot in the row, the sum of the run (ascending t) and the
+//     run's first place, staged at e0 + offset
 template <typename ColT, typename ValT, typename PermT>
-__device__ void sp_bucket_rows(int32_t R, int32_t v0, int32_t m, int64_t e0, const int32_t *s_rs,
-                               ColT *col, ColT *tt, ValT *val, PermT *perm, bool has_val,
-                               int32_t *s_len, int32_t *s_wsum, int32_t *__restrict__ stage_col,
-                               double *__restrict__ stage_val, int32_t *__restrict__ stage_cptr,
-                               int32_t *__restrict__ contrib, int32_t *__restrict__ rowoff,
-                               int32_t *__restrict__ btot, int32_t b) {
+__device__ void sp_bucket_rows(int32_t R, int32_t nb, int32_t v0, int32_t m, int64_t e0,
+                               const int32_t *s_rs, ColT *col, ColT *tt, ValT *val, PermT *perm,
+                               bool has_val, int32_t *s_len, int32_t *s_wsum,
+                               int32_t *__restrict__ stage_col, double *__restrict__ stage_val,
+                               int32_t *__restrict__ stage_cptr, int32_t *__restrict__ contrib,
+                               int32_t *__restrict__ rowoff, int32_t *__restrict__ btot,
+                               int32_t b) {
     const int tid = threadIdx.x;
-    for (int32_t r = tid; r < R; r += SP_THREADS) {
-        const int32_t s = s_rs[r], e = s_rs[r + 1], d = e - s;
-        int32_t L = 0;
-        if (d <= RANK_MAX) {
-            for (int32_t k = 0; k < d; ++k) {
-                const int32_t ck = col[s + k], tk = tt[s + k];
-                int32_t rank = 0;
-                bool first = true;
-                for (int32_t j = 0; j < d; ++j) {
-                    const int32_t cj = col[s + j], tj = tt[s + j];
-                    const bool same_before = cj == ck && tj < tk;
-                    rank += (cj < ck || same_before) ? 1 : 0;
-                    first = first && !same_before;
-                }
-                perm[s + rank] = static_cast<PermT>(k);
-                L += first ? 1 : 0;
-            }
-        } else {
-            for (int32_t x = s + 1; x < e; ++x) {
-                const int32_t c = col[x], t = tt[x];
-                const double vx = has_val ? static_cast<double>(val[x]) : 0.0;
-                int32_t y = x;
-                while (y > s && (col[y - 1] > c || (col[y - 1] == c && tt[y - 1] > t))) {
-                    col[y] = col[y - 1];
-                    tt[y] = tt[y - 1];
-                    if (has_val) val[y] = val[y - 1];
-                    --y;
-                }
-                col[y] = c;
-                tt[y] = t;
-                if (has_val) val[y] = vx;
-            }
-            for (int32_t x = s; x < e; ++x) {
-                L += (x == s || col[x] != col[x - 1]) ? 1 : 0;
-                perm[x] = static_cast<PermT>(x - s);
-            }
+    for (int32_t r = tid; r < R; r += SP_THREADS) s_len[r] = 0;
+    __syncthreads();
+    for (int32_t x = tid; x < nb; x += SP_THREADS) {
+        const int32_t r = row_of(s_rs, R, x);
+        const int32_t s = s_rs[r], e = s_rs[r + 1];
+        const int32_t ck = col[x], tk = tt[x];
+        int32_t rank = 0;
+        bool first = true;
+        for (int32_t j = s; j < e; ++j) {
+            const int32_t cj = col[j], tj = tt[j];
+            const bool same_before = cj == ck && tj < tk;
+            rank += (cj < ck || same_before) ? 1 : 0;
+            first = first && !same_before;
         }
-        s_len[r] = L;
+        perm[s + rank] = static_cast<PermT>(x - s);
+        if (first) atomicAdd(&s_len[r], 1);
     }
     __syncthreads();
     // offsets of the rows inside the bucket (R / 256 rows per thread, in order)
@@ -401,25 +389,22 @@ __device__ void sp_bucket_rows(int32_t R, int32_t v0, int32_t m, int64_t e0, con
     }
     if (tid == 0) btot[b] = T;
     __syncthreads();
-    for (int32_t r = tid; r < R; r += SP_THREADS) {
+    for (int32_t y = tid; y < nb; y += SP_THREADS) {
+        const int32_t r = row_of(s_rs, R, y);
         const int32_t s = s_rs[r], e = s_rs[r + 1];
-        int64_t o = e0 + s_len[r];
-        for (int32_t x = s; x < e;) {
-            const int32_t c = col[s + static_cast<int32_t>(perm[x])];
-            double acc = 0.0;
-            int32_t y = x;
-            for (; y < e; ++y) {
-                const int32_t p = s + static_cast<int32_t>(perm[y]);
-                if (col[p] != c) break;
-                if (has_val) acc += static_cast<double>(val[p]);
-                if (contrib) contrib[e0 + y] = tt[p];
-            }
-            stage_col[o] = c;
-            if (has_val) stage_val[o] = acc;
-            if (stage_cptr) stage_cptr[o] = static_cast<int32_t>(e0 + x);
-            ++o;
-            x = y;
-        }
+        auto at = [&](int32_t z) { return s + static_cast<int32_t>(perm[z]); };
+        const int32_t p = at(y), c = col[p];
+        if (contrib) contrib[e0 + y] = tt[p];
+        if (y > s && col[at(y - 1)] == c) continue;   // not a run start
+        int32_t slot = 0;                              // run starts before y
+        for (int32_t z = s + 1; z <= y; ++z) slot += col[at(z)] != col[at(z - 1)] ? 1 : 0;
+        double acc = 0.0;
+        if (has_val)
+            for (int32_t z = y; z < e && col[at(z)] == c; ++z) acc += static_cast<double>(val[at(z)]);
+        const int64_t o = e0 + s_len[r] + slot;
+        stage_col[o] = c;
+        if (has_val) stage_val[o] = acc;
+        if (stage_cptr) stage_cptr[o] = static_cast<int32_t>(e0 + y);
     }
 }
 
@@ -502,7 +487,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_rows(
         if (has_val) s_val[p] = xv[u];
     }
     __syncthreads();
-    sp_bucket_rows(R, v0, m, e0, s_rs, s_col, s_t, s_val, s_perm, has_val != 0, s_len, s_wsum,
+    sp_bucket_rows(R, nb, v0, m, e0, s_rs, s_col, s_t, s_val, s_perm, has_val != 0, s_len, s_wsum,
                    stage_col, stage_val, stage_cptr, contrib, rowoff, btot, b);
 }
 
@@ -569,7 +554,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_rows_big(
             if (has_val) bv[p] = rval[e0 + x];
         }
         __syncthreads();
-        sp_bucket_rows(R, v0, m, e0, s_rs, bc, bt, bv, gperm + e0, has_val != 0, s_len, s_wsum,
+        sp_bucket_rows(R, nb, v0, m, e0, s_rs, bc, bt, bv, gperm + e0, has_val != 0, s_len, s_wsum,
                        stage_col, stage_val, stage_cptr, contrib, rowoff, btot, b);
         __syncthreads();
     }

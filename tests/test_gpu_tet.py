@@ -108,7 +108,7 @@ def test_tet_full_size_properties():
     cols = pat.col_idx.long()
     assert int((rows == cols).sum()) == m.nq
     rs = torch.zeros(m.nq, dtype=torch.float64, device=DEV).index_add_(0, rows, S)
-    diag = S[rows == cols]              # the largest entry of each row of S
+    diag = S[rows == cols]              # positive, the scale of its row
     assert float((rs.abs() / diag).max()) <= 1e-12
     g = torch.tensor([0.3, -1.1, 0.7], dtype=torch.float64, device=DEV)
     u = 2.0 + _up(m.q) @ g
