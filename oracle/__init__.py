@@ -66,6 +66,8 @@ def _load():
                                   _i32p, _i32p, _f64p]
     lib.oracle_validate.restype = C.c_int
     lib.oracle_validate.argtypes = [C.c_int32, C.c_int32, _i32p]
+    lib.oracle_adjoint_elas.argtypes = [C.c_int32, C.c_int32, _f64p, _i32p, _i32p, _f64p, C.c_double,
+                                        C.c_double, _f64p, _f64p]
     lib.oracle_tet_det.restype = C.c_double
     lib.oracle_tet_det.argtypes = [_f64p, _f64p, _f64p, _f64p]
     lib.oracle_elem_tet_mass.argtypes = [C.c_double, _f64p]
@@ -155,6 +157,18 @@ def sparse(I, J, V, nrows: int, ncols: int):
     vals = np.zeros(max(n, 1), np.float64)
     nnz = _check(_load().oracle_sparse(nrows, ncols, n, I, J, V, row_ptr, col_idx, vals))
     return row_ptr, col_idx[:nnz].copy(), vals[:nnz].copy()
+
+
+def adjoint_elas(q, me, slot_e, G, lam: float, mu: float):
+    """(dq [nq][2], dL/dlambda, dL/dmu) of L = <G, K(q; lambda, mu)> on the
+    elasticity pattern whose slot map slot_e [36][nme] is given."""
+    q, me, slot_e, G = _f64(q), _i32(me), _i32(slot_e), _f64(G)
+    nq = q.shape[0]
+    dq = np.zeros(2 * nq)
+    dlm = np.zeros(2)
+    _check(_load().oracle_adjoint_elas(nq, me.shape[0], q.reshape(-1), me.reshape(-1),
+                                       slot_e.reshape(-1), G, float(lam), float(mu), dq, dlm))
+    return dq.reshape(nq, 2), float(dlm[0]), float(dlm[1])
 
 
 def tet_det(x0, x1, x2, x3) -> float:

@@ -789,3 +789,158 @@ int64_t oracle_assemble_tet(int op, int32_t nq, int32_t nme, const double *q, co
     free(V);
     return nnz;
 }
+
+/* ------------------------------------------------------------------ */
+/* Adjoint of the elasticity assembly                                 */
+/* ------------------------------------------------------------------ */
+/* Gradient of L = sum_ij G_ij K_ij(q; lambda, mu) over the elasticity
+ * pattern (slot_e [36][nme] from oracle_pattern_elas).  dL/dq is obtained by
+ * forward-mode differentiation (dual numbers over the six coordinates of a
+ * triangle) of the very steps of oracle_elem_elas, so it needs no formula of
+ * its own; K is linear in (lambda, mu), so dL/dlambda = <G, K(1, 0)> and
+ * dL/dmu = <G, K(0, 1)>.  Contributions are added in ascending k.  dq is
+ * [nq][2] and dlm [2] (dL/dlambda, dL/dmu); both are overwritten.          */
+
+typedef struct {
+    double v;
+    double d[6];
+} oracle_dual;
+
+static oracle_dual dl_const(double v)
+{
+    oracle_dual r;
+    r.v = v;
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = 0.0;
+    return r;
+}
+
+static oracle_dual dl_add(oracle_dual a, oracle_dual b)
+{
+    oracle_dual r;
+    r.v = a.v + b.v;
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = a.d[i] + b.d[i];
+    return r;
+}
+
+static oracle_dual dl_sub(oracle_dual a, oracle_dual b)
+{
+    oracle_dual r;
+    r.v = a.v - b.v;
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = a.d[i] - b.d[i];
+    return r;
+}
+
+static oracle_dual dl_mul(oracle_dual a, oracle_dual b)
+{
+    oracle_dual r;
+    r.v = a.v * b.v;
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+    return r;
+}
+
+static oracle_dual dl_div(oracle_dual a, oracle_dual b)
+{
+    oracle_dual r;
+    r.v = a.v / b.v;
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v);
+    return r;
+}
+
+static oracle_dual dl_abs(oracle_dual a)
+{
+    const double s = a.v > 0.0 ? 1.0 : (a.v < 0.0 ? -1.0 : 0.0);
+    oracle_dual r;
+    r.v = fabs(a.v);
+    for (int i = 0; i < 6; ++i)
+        r.d[i] = s * a.d[i];
+    return r;
+}
+
+/* the steps of oracle_elem_elas, on dual numbers */
+static void dual_elem_elas(oracle_dual x[3][2], double lam, double mu, oracle_dual E[36])
+{
+    const oracle_dual D = dl_sub(dl_mul(dl_sub(x[1][0], x[0][0]), dl_sub(x[2][1], x[0][1])),
+                                 dl_mul(dl_sub(x[2][0], x[0][0]), dl_sub(x[1][1], x[0][1])));
+    const oracle_dual area = dl_div(dl_abs(D), dl_const(2.0));
+    const oracle_dual zero = dl_const(0.0);
+    oracle_dual u[2], v[2], w[2];
+    for (int c = 0; c < 2; ++c) {
+        u[c] = dl_sub(x[1][c], x[2][c]);
+        v[c] = dl_sub(x[2][c], x[0][c]);
+        w[c] = dl_sub(x[0][c], x[1][c]);
+    }
+    oracle_dual nu0 = dl_sub(zero, u[0]), nv0 = dl_sub(zero, v[0]), nw0 = dl_sub(zero, w[0]);
+    oracle_dual B[3][6] = {
+        {u[1], zero, v[1], zero, w[1], zero},
+        {zero, nu0, zero, nv0, zero, nw0},
+        {nu0, u[1], nv0, v[1], nw0, w[1]},
+    };
+    const oracle_dual two_area = dl_mul(dl_const(2.0), area);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 6; ++j)
+            B[i][j] = dl_div(B[i][j], two_area);
+    const double C[3][3] = {
+        {lam + 2.0 * mu, lam, 0.0},
+        {lam, lam + 2.0 * mu, 0.0},
+        {0.0, 0.0, mu},
+    };
+    oracle_dual CB[3][6];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 6; ++j) {
+            oracle_dual s = dl_const(0.0);
+            for (int l = 0; l < 3; ++l)
+                s = dl_add(s, dl_mul(dl_const(C[i][l]), B[l][j]));
+            CB[i][j] = s;
+        }
+    for (int jl = 0; jl < 6; ++jl)
+        for (int il = 0; il < 6; ++il) {
+            oracle_dual s = dl_const(0.0);
+            for (int l = 0; l < 3; ++l)
+                s = dl_add(s, dl_mul(B[l][il], CB[l][jl]));
+            E[6 * jl + il] = dl_mul(area, s);
+        }
+}
+
+int oracle_adjoint_elas(int32_t nq, int32_t nme, const double *q, const int32_t *me,
+                        const int32_t *slot_e, const double *G, double lam, double mu,
+                        double *dq, double *dlm)
+{
+    if (nq <= 0 || nme < 0 || !q || !me || !slot_e || !G || !dq || !dlm)
+        return ORACLE_EINVAL;
+    for (int64_t i = 0; i < 2 * (int64_t)nq; ++i)
+        dq[i] = 0.0;
+    dlm[0] = dlm[1] = 0.0;
+    for (int64_t k = 0; k < nme; ++k) {
+        const int32_t *t = me + 3 * k;
+        oracle_dual x[3][2];
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 2; ++c) {
+                x[a][c] = dl_const(q[2 * (int64_t)t[a] + c]);
+                x[a][c].d[2 * a + c] = 1.0;
+            }
+        oracle_dual E[36];
+        dual_elem_elas(x, lam, mu, E);
+        double El[36], Em[36];
+        const double *x0 = q + 2 * (int64_t)t[0], *x1 = q + 2 * (int64_t)t[1];
+        const double *x2 = q + 2 * (int64_t)t[2];
+        oracle_elem_elas(x0, x1, x2, 1.0, 0.0, El);
+        oracle_elem_elas(x0, x1, x2, 0.0, 1.0, Em);
+        double dL[6] = {0, 0, 0, 0, 0, 0};
+        for (int r = 0; r < 36; ++r) {
+            const double g = G[slot_e[(int64_t)r * nme + k]];
+            for (int i = 0; i < 6; ++i)
+                dL[i] += g * E[r].d[i];
+            dlm[0] += g * El[r];
+            dlm[1] += g * Em[r];
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 2; ++c)
+                dq[2 * (int64_t)t[a] + c] += dL[2 * a + c];
+    }
+    return ORACLE_OK;
+}
