@@ -383,6 +383,24 @@ int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *
                             const double *GS, const double *GM, double *dq, double *dw,
                             void *work, size_t work_bytes, int flags, void *stream);
 
+/* HOST ONLY.  Bytes of device workspace for fem_adjoint_elas: per-row
+ * partial sums (16 nq) and per-entry partial derivatives (16 nnz). */
+int fem_adjoint_elas_workspace(int32_t nq, int64_t nnz, size_t *bytes /* HOST */);
+
+/* Gradient of L = sum_e G_e K_e(q; lambda, mu) with respect to q and the
+ * Lame parameters (K the elasticity matrix of fem_assemble_elas, G [4 nnz]
+ * in its interleaved 2x2-block layout).
+ *   dq [nq][2] (overwritten, or added to with FEM_ACCUMULATE)
+ *   dlm [2] device or NULL: (dL/dlambda, dL/dmu), likewise
+ * Pattern arrays as for fem_assemble (FEM_DETERMINISTIC); tpos from
+ * fem_transpose_map or NULL (search).  Two passes over the rows plus a
+ * fixed-order reduction; no atomics, bitwise reproducible. */
+int fem_adjoint_elas(int32_t nq, int32_t nme, int64_t nnz, const double *q,
+                     const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
+                     const uint32_t *inc_pos, const int32_t *tpos, double lambda, double mu,
+                     const double *G, double *dq, double *dlm, void *work, size_t work_bytes,
+                     int flags, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

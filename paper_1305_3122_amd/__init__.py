@@ -33,8 +33,8 @@ __all__ = [
     "fem_assemble_stiff_wmass", "fem_assemble_elas", "fem_batch_globalize",
     "fem_assemble_stiff_mass_batched", "Graph", "SparseCSR", "fem_sparse", "fem_sparse_values",
     "TetPattern", "fem_tet_pattern", "fem_tet_assemble",
-    "fem_adjoint_workspace", "fem_adjoint_stiff_wmass",
-    "AssembleStiffWMass",
+    "fem_adjoint_workspace", "fem_adjoint_stiff_wmass", "fem_adjoint_elas",
+    "AssembleStiffWMass", "AssembleElas",
     "library_path",
 ]
 
@@ -485,6 +485,27 @@ def fem_adjoint_stiff_wmass(pat: Pattern, q, w, GS, GM, *, dq=None, dw=None, fla
     return dq, dw
 
 
+def fem_adjoint_elas(pat: Pattern, q, lam: float, mu: float, G, *, dq=None, dlm=None,
+                     flags: int = 0, stream=None):
+    """(dq [nq][2], dlm [2] = (dL/dlambda, dL/dmu)) of L = <G, K(q; lambda, mu)>,
+    G [4 nnz] in the elasticity layout (C: fem_adjoint_elas)."""
+    torch = _torch()
+    lib = _lib.load()
+    dev = pat.row_ptr.device
+    _q(pat, q)
+    _dev(G, torch.float64, "G", (4 * pat.nnz,))
+    dq = torch.empty((pat.nq, 2), dtype=torch.float64, device=dev) if dq is None else dq
+    dlm = torch.empty(2, dtype=torch.float64, device=dev) if dlm is None else dlm
+    ws = C.c_size_t(0)
+    _lib.check(lib.fem_adjoint_elas_workspace(pat.nq, pat.nnz, C.byref(ws)))
+    work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
+    _lib.check(lib.fem_adjoint_elas(pat.nq, pat.nme, pat.nnz, _ptr(q), _ptr(pat.row_ptr),
+                                    _ptr(pat.col_idx), _ptr(pat.inc_ptr), _ptr(pat.inc_pos),
+                                    _ptr(pat.tpos), float(lam), float(mu), _ptr(G), _ptr(dq),
+                                    _ptr(dlm), _ptr(work), int(ws.value), flags, _stream(stream)))
+    return dq, dlm
+
+
 def _autograd_function():
     torch = _torch()
 
@@ -516,16 +537,37 @@ def _autograd_function():
             ctx.work = None
             return dq, (dw if gM is not None else None), None
 
-    return AssembleStiffWMass
+    class AssembleElas(torch.autograd.Function):
+        """Elasticity values K(q; lambda, mu) [4 nnz] on a fixed pattern, with
+        lambda and mu as 0-dim tensors; backward runs fem_adjoint_elas."""
+
+        @staticmethod
+        def forward(ctx, q, lam, mu, pat):
+            K = fem_assemble_elas(pat, q.contiguous(), float(lam), float(mu))
+            ctx.pat = pat
+            ctx.save_for_backward(q, lam, mu)
+            return K
+
+        @staticmethod
+        def backward(ctx, gK):
+            q, lam, mu = ctx.saved_tensors
+            dq, dlm = fem_adjoint_elas(ctx.pat, q.contiguous(), float(lam), float(mu), gK.contiguous())
+            return dq, dlm[0].to(lam.dtype), dlm[1].to(mu.dtype), None
+
+    return AssembleStiffWMass, AssembleElas
 
 
 class _Lazy:
-    _fn = None
+    _fns = None
 
-    def apply(self, q, w, pat):
-        if _Lazy._fn is None:
-            _Lazy._fn = _autograd_function()
-        return _Lazy._fn.apply(q, w, pat)
+    def __init__(self, which):
+        self.which = which
+
+    def apply(self, *args):
+        if _Lazy._fns is None:
+            _Lazy._fns = _autograd_function()
+        return _Lazy._fns[self.which].apply(*args)
 
 
-AssembleStiffWMass = _Lazy()
+AssembleStiffWMass = _Lazy(0)
+AssembleElas = _Lazy(1)

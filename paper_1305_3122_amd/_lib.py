@@ -91,6 +91,9 @@ SIGNATURES = {
     "fem_tet_assemble_workspace": (_int, [_i32, _int, _szp]),
     "fem_tet_assemble": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 C.c_size_t, _int, _vp]),
+    "fem_adjoint_elas_workspace": (_int, [_i32, _i64, _szp]),
+    "fem_adjoint_elas": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _vp, _vp,
+                                _vp, _vp, C.c_size_t, _int, _vp]),
     "fem_adjoint_workspace": (_int, [_i32, _i64, _szp]),
     "fem_adjoint_stiff_wmass": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                        _vp, _vp, _vp, _vp, C.c_size_t, _int, _vp]),

@@ -382,6 +382,392 @@ __global__ __launch_bounds__(WAVE) void k_adj_cols_tpos(int32_t nq, const int32_
     }
 }
 
+// ------------------------------------------------------------------ elasticity
+//
+// L = <G, K(q; lambda, mu)> on the interleaved elasticity pattern (G[e] for
+// the entry (2i + alpha, 2j + beta) of the scalar entry j = k-th column of
+// row i at 4 row_ptr[i] + 2 alpha len_i + 2 k + beta).  Row-owner split as
+// above: L = sum_i sum_{T around i} tau(i, T), with, for the triangle
+// (x0, x1, x2) rotated to start at i, r0 = x1 - x2, r1 = x2 - x0,
+// r2 = x0 - x1, rho_c = perp(r_c) = (r_c,y, -r_c,x), D = (x1-x0) x (x2-x0):
+//   K^e block (0, b) = P(rho_0, rho_b) / (2|D|), P the bilinear form of
+//   B^T C B, so tau = N / (2|D|) with N = rho_0 . R, R = sum_b W_b rho_b and
+//     W_b = [[(l+2m) gxx + m gyy, l gxy + m gyx],
+//            [m gxy + l gyx,      m gxx + (l+2m) gyy]]   (g = G block (i, b))
+//   dN: gamma_0 = R + W_0^T rho_0, gamma_b = W_b^T rho_0 (b = 1, 2),
+//       h_b = (-gamma_b,y, gamma_b,x) (d rho = perp d r),
+//       dN/dx0 = h2 - h1, dN/dx1 = h0 - h2, dN/dx2 = h1 - h0
+//   dtau/dx_c = dN/dx_c / (2|D|) - N / (2|D|^2) sign(D) rho_c
+//   lambda, mu: W is linear in them, W = l W_l + m W_m, and
+//     dtau/dl = rho_0 . sum_b W_l,b rho_b / (2|D|) (same for m).
+struct ElasTau {
+    double n, nl, nm;          // N, N_lambda, N_mu
+    double d[3][2];            // dN / dx_c
+};
+
+__device__ __forceinline__ void elas_tau(const double (&x)[3][2], const double (&g)[3][4], double lam,
+                                         double mu, ElasTau &o) {
+    double rho[3][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        const double rx = x[c1][0] - x[c2][0], ry = x[c1][1] - x[c2][1];
+        rho[c][0] = ry;
+        rho[c][1] = -rx;
+    }
+    const double l2m = lam + 2.0 * mu;
+    double R[2] = {0.0, 0.0}, Rl[2] = {0.0, 0.0}, Rm[2] = {0.0, 0.0};
+    double W[3][4];   // xx, xy, yx, yy
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const double gxx = g[b][0], gxy = g[b][1], gyx = g[b][2], gyy = g[b][3];
+        W[b][0] = l2m * gxx + mu * gyy;
+        W[b][1] = lam * gxy + mu * gyx;
+        W[b][2] = mu * gxy + lam * gyx;
+        W[b][3] = mu * gxx + l2m * gyy;
+        R[0] += W[b][0] * rho[b][0] + W[b][1] * rho[b][1];
+        R[1] += W[b][2] * rho[b][0] + W[b][3] * rho[b][1];
+        Rl[0] += gxx * rho[b][0] + gxy * rho[b][1];
+        Rl[1] += gyx * rho[b][0] + gyy * rho[b][1];
+        Rm[0] += (2.0 * gxx + gyy) * rho[b][0] + gyx * rho[b][1];
+        Rm[1] += gxy * rho[b][0] + (gxx + 2.0 * gyy) * rho[b][1];
+    }
+    o.n = rho[0][0] * R[0] + rho[0][1] * R[1];
+    o.nl = rho[0][0] * Rl[0] + rho[0][1] * Rl[1];
+    o.nm = rho[0][0] * Rm[0] + rho[0][1] * Rm[1];
+    double h[3][2];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        double gx = W[b][0] * rho[0][0] + W[b][2] * rho[0][1];
+        double gy = W[b][1] * rho[0][0] + W[b][3] * rho[0][1];
+        if (b == 0) {
+            gx += R[0];
+            gy += R[1];
+        }
+        h[b][0] = -gy;
+        h[b][1] = gx;
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        o.d[0][c] = h[2][c] - h[1][c];
+        o.d[1][c] = h[0][c] - h[2][c];
+        o.d[2][c] = h[1][c] - h[0][c];
+    }
+    // finish: dtau/dx_c, with |D| and its derivative
+    const double D = (x[1][0] - x[0][0]) * (x[2][1] - x[0][1]) - (x[2][0] - x[0][0]) * (x[1][1] - x[0][1]);
+    const double aD = fabs(D);
+    const double sg = D > 0.0 ? 1.0 : (D < 0.0 ? -1.0 : 0.0);
+    const double inv = 1.0 / (2.0 * aD);
+    const double k = o.n * inv / aD;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        o.d[c][0] = o.d[c][0] * inv - k * sg * rho[c][0];
+        o.d[c][1] = o.d[c][1] * inv - k * sg * rho[c][1];
+    }
+    o.nl *= inv;
+    o.nm *= inv;
+}
+
+// Pass 1 of the elasticity adjoint: tile of 64 rows (one per lane).  LDS:
+// q (x, y) | the tile's 4 Ew values of G | ipos; H accumulators (x, y) of the
+// lane's row in registers, then transposed through LDS and written as
+// (hx, hy) records; the row's dtau/dlambda, dtau/dmu sums go to lm[i].
+template <int U, int LMAX>
+__global__ __launch_bounds__(WAVE) void k_adj_elas_rows(
+    int32_t nq, const double *__restrict__ q, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ col_idx, const int32_t *__restrict__ inc_ptr,
+    const uint32_t *__restrict__ inc_pos, const double *__restrict__ G, double lam, double mu,
+    double2 *__restrict__ H, double2 *__restrict__ lm, int64_t ntiles) {
+    constexpr int EB = U * WAVE;
+    extern __shared__ double smem[];
+    double2 *s_q = reinterpret_cast<double2 *>(smem);
+    double *s_g = smem + 2 * EB;
+    uint32_t *s_ip = reinterpret_cast<uint32_t *>(smem + 6 * EB);
+    double *s_stage = smem;   // 2 doubles per entry, after the sums
+    const int lane = threadIdx.x;
+    const double2 *q2 = reinterpret_cast<const double2 *>(q);
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * WAVE;
+        const int64_t r1 = (r0 + WAVE < nq) ? r0 + WAVE : nq;
+        const int64_t i = r0 + lane;
+        const bool active = i < nq;
+        const int32_t E0 = row_ptr[r0], E1 = row_ptr[r1], Ew = E1 - E0;
+        const int32_t I0 = inc_ptr[r0], I1 = inc_ptr[r1], Iw = I1 - I0;
+        const int32_t rs = active ? row_ptr[i] : 0;
+        const int32_t len = active ? row_ptr[i + 1] - rs : 0;
+        const int32_t is = active ? inc_ptr[i] : 0;
+        const int32_t ie = active ? inc_ptr[i + 1] : 0;
+        const bool tile_fits = Ew <= EB && Iw <= EB;
+        if (tile_fits) {
+            int32_t cidx[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                cidx[u] = e < Ew ? __builtin_nontemporal_load(col_idx + E0 + e) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = lane + u * WAVE;
+                if (t < Iw) s_ip[t] = __builtin_nontemporal_load(inc_pos + I0 + t);
+            }
+            const double *gt = G + 4 * (int64_t)E0;
+            for (int e = lane; e < 4 * Ew; e += WAVE) s_g[e] = __builtin_nontemporal_load(gt + e);
+            double2 qv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                qv[u] = e < Ew ? q2[cidx[u]] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                if (e < Ew) s_q[e] = qv[u];
+            }
+            __syncthreads();
+        }
+        const bool in_regs = tile_fits && active && len > 0 && len <= LMAX;
+        double hx[LMAX], hy[LMAX];
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k) hx[k] = hy[k] = 0.0;
+        double sl = 0.0, sm = 0.0;
+        if (in_regs) {
+            const int32_t off = rs - E0;
+            uint64_t seen = 0;
+            for (int32_t t = is - I0; t < ie - I0; ++t) {
+                const uint32_t pp = s_ip[t];
+                seen |= (1ull << (pp & 0xffffu)) | (1ull << (pp >> 16));
+            }
+            const int32_t pd = __builtin_ctzll(~seen);
+            const double *gr = s_g + 4 * off;   // row 2i at gr[2k + beta], row 2i+1 at gr[2len + 2k + beta]
+            double x[3][2], g[3][4];
+            x[0][0] = s_q[off + pd].x;
+            x[0][1] = s_q[off + pd].y;
+            g[0][0] = gr[2 * pd];
+            g[0][1] = gr[2 * pd + 1];
+            g[0][2] = gr[2 * len + 2 * pd];
+            g[0][3] = gr[2 * len + 2 * pd + 1];
+            double ox = 0.0, oy = 0.0;
+            for (int32_t t = is - I0; t < ie - I0; ++t) {
+                const uint32_t pp = s_ip[t];
+                const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
+                x[1][0] = s_q[off + p1].x;
+                x[1][1] = s_q[off + p1].y;
+                x[2][0] = s_q[off + p2].x;
+                x[2][1] = s_q[off + p2].y;
+                g[1][0] = gr[2 * p1];
+                g[1][1] = gr[2 * p1 + 1];
+                g[1][2] = gr[2 * len + 2 * p1];
+                g[1][3] = gr[2 * len + 2 * p1 + 1];
+                g[2][0] = gr[2 * p2];
+                g[2][1] = gr[2 * p2 + 1];
+                g[2][2] = gr[2 * len + 2 * p2];
+                g[2][3] = gr[2 * len + 2 * p2 + 1];
+                ElasTau o;
+                elas_tau(x, g, lam, mu, o);
+                ox += o.d[0][0];
+                oy += o.d[0][1];
+                sl += o.nl;
+                sm += o.nm;
+#pragma unroll
+                for (int k = 0; k < LMAX; ++k) {
+                    const bool a1 = k == p1, a2 = k == p2;
+                    hx[k] += a1 ? o.d[1][0] : (a2 ? o.d[2][0] : 0.0);
+                    hy[k] += a1 ? o.d[1][1] : (a2 ? o.d[2][1] : 0.0);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < LMAX; ++k)
+                if (k == pd) {
+                    hx[k] += ox;
+                    hy[k] += oy;
+                }
+        }
+        if (tile_fits) {
+            __syncthreads();   // everyone is done reading the staged inputs
+            const int32_t off = rs - E0;
+            if (in_regs) {
+#pragma unroll
+                for (int k = 0; k < LMAX; ++k)
+                    if (k < len) {
+                        s_stage[2 * (off + k)] = hx[k];
+                        s_stage[2 * (off + k) + 1] = hy[k];
+                    }
+            } else if (active && len > 0) {
+                for (int k = 0; k < 2 * len; ++k) s_stage[2 * off + k] = 0.0;
+            }
+            __syncthreads();
+            for (int e = lane; e < Ew; e += WAVE)
+                H[E0 + e] = make_double2(s_stage[2 * e], s_stage[2 * e + 1]);
+            __syncthreads();
+        }
+        if (!in_regs && active && len > 0) {
+            // long row or tile too large: own row in global memory, same order
+            for (int e = 0; e < len; ++e) H[rs + e] = make_double2(0.0, 0.0);
+            const int32_t *cr = col_idx + rs;
+            int32_t pd = 0;
+            while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
+            const double *gr = G + 4 * (int64_t)rs;
+            double x[3][2], g[3][4];
+            x[0][0] = q[2 * i];
+            x[0][1] = q[2 * i + 1];
+            g[0][0] = gr[2 * pd];
+            g[0][1] = gr[2 * pd + 1];
+            g[0][2] = gr[2 * len + 2 * pd];
+            g[0][3] = gr[2 * len + 2 * pd + 1];
+            double ox = 0.0, oy = 0.0;
+            for (int32_t t = is; t < ie; ++t) {
+                const uint32_t pp = inc_pos[t];
+                const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
+                const int64_t j1 = cr[p1], j2 = cr[p2];
+                x[1][0] = q[2 * j1];
+                x[1][1] = q[2 * j1 + 1];
+                x[2][0] = q[2 * j2];
+                x[2][1] = q[2 * j2 + 1];
+                g[1][0] = gr[2 * p1];
+                g[1][1] = gr[2 * p1 + 1];
+                g[1][2] = gr[2 * len + 2 * p1];
+                g[1][3] = gr[2 * len + 2 * p1 + 1];
+                g[2][0] = gr[2 * p2];
+                g[2][1] = gr[2 * p2 + 1];
+                g[2][2] = gr[2 * len + 2 * p2];
+                g[2][3] = gr[2 * len + 2 * p2 + 1];
+                ElasTau o;
+                elas_tau(x, g, lam, mu, o);
+                ox += o.d[0][0];
+                oy += o.d[0][1];
+                sl += o.nl;
+                sm += o.nm;
+                double2 h1 = H[rs + p1], h2 = H[rs + p2];
+                h1.x += o.d[1][0];
+                h1.y += o.d[1][1];
+                H[rs + p1] = h1;
+                h2.x += o.d[2][0];
+                h2.y += o.d[2][1];
+                H[rs + p2] = h2;
+            }
+            double2 hd = H[rs + pd];
+            hd.x += ox;
+            hd.y += oy;
+            H[rs + pd] = hd;
+        }
+        if (active) lm[i] = make_double2(sl, sm);
+    }
+}
+
+// Pass 2 of the elasticity adjoint: dq[u] = sum over row u of H at the
+// transposed positions, ascending position (tpos, or a search without it).
+template <int U>
+__global__ __launch_bounds__(WAVE) void k_adj_elas_cols(int32_t nq, const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col_idx,
+                                                        const int32_t *__restrict__ tpos,
+                                                        const double2 *__restrict__ H,
+                                                        double *__restrict__ dq, int accumulate,
+                                                        int64_t ntiles) {
+    constexpr int EB = U * WAVE;
+    __shared__ double s_h[2 * EB];
+    const int lane = threadIdx.x;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * WAVE;
+        const int64_t r1 = (r0 + WAVE < nq) ? r0 + WAVE : nq;
+        const int64_t u = r0 + lane;
+        const bool active = u < nq;
+        const int32_t E0 = row_ptr[r0], E1 = row_ptr[r1], Ew = E1 - E0;
+        const int32_t rs = active ? row_ptr[u] : 0;
+        const int32_t re = active ? row_ptr[u + 1] : 0;
+        double gx = 0.0, gy = 0.0;
+        if (tpos && Ew <= EB) {
+            int32_t t[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int e = lane + k * WAVE;
+                t[k] = e < Ew ? __builtin_nontemporal_load(tpos + E0 + e) : 0;
+            }
+            double2 h[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int e = lane + k * WAVE;
+                h[k] = e < Ew ? H[t[k]] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int e = lane + k * WAVE;
+                if (e < Ew) {
+                    s_h[2 * e] = h[k].x;
+                    s_h[2 * e + 1] = h[k].y;
+                }
+            }
+            __syncthreads();
+            for (int32_t e = rs - E0; e < re - E0; ++e) {
+                gx += s_h[2 * e];
+                gy += s_h[2 * e + 1];
+            }
+            __syncthreads();
+        } else {
+            for (int32_t p = rs; p < re; ++p) {
+                int32_t tp;
+                if (tpos) {
+                    tp = tpos[p];
+                } else {
+                    const int32_t v = col_idx[p];
+                    int32_t lo = row_ptr[v], hi = row_ptr[v + 1];
+                    while (lo < hi) {
+                        const int32_t mid = (lo + hi) >> 1;
+                        if (col_idx[mid] < (int32_t)u) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    tp = lo;
+                }
+                const double2 hv = H[tp];
+                gx += hv.x;
+                gy += hv.y;
+            }
+        }
+        if (!active) continue;
+        if (accumulate) {
+            dq[2 * u] += gx;
+            dq[2 * u + 1] += gy;
+        } else {
+            dq[2 * u] = gx;
+            dq[2 * u + 1] = gy;
+        }
+    }
+}
+
+// dL/dlambda, dL/dmu: the per-row sums in a fixed order (each thread a
+// contiguous chunk, then a fixed pairwise tree), so the result is bitwise
+// reproducible.
+__global__ __launch_bounds__(1024) void k_adj_lm_reduce(int32_t nq, const double2 *__restrict__ lm,
+                                                        double *__restrict__ out, int accumulate) {
+    __shared__ double s_l[1024], s_m[1024];
+    const int tid = threadIdx.x;
+    const int64_t chunk = ((int64_t)nq + 1023) / 1024;
+    const int64_t a = tid * chunk, b = (a + chunk < nq) ? a + chunk : nq;
+    double l = 0.0, m = 0.0;
+    for (int64_t i = a; i < b; ++i) {
+        l += lm[i].x;
+        m += lm[i].y;
+    }
+    s_l[tid] = l;
+    s_m[tid] = m;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (tid < w) {
+            s_l[tid] += s_l[tid + w];
+            s_m[tid] += s_m[tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (accumulate) {
+            out[0] += s_l[0];
+            out[1] += s_m[0];
+        } else {
+            out[0] = s_l[0];
+            out[1] = s_m[0];
+        }
+    }
+}
+
 namespace {
 constexpr int ADJ_U = 8;
 
@@ -456,5 +842,47 @@ extern "C" int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, con
                            col_idx, tpos, H, dq, dw, acc);
     }
     FEM_LAUNCH_CHECK();
+    return FEM_OK;
+}
+
+extern "C" int fem_adjoint_elas_workspace(int32_t nq, int64_t nnz, size_t *bytes) {
+    clear_error();
+    FEM_REQUIRE(bytes && nq >= 1 && nnz >= 0, FEM_EINVAL, "fem_adjoint_elas_workspace: bad arguments");
+    *bytes = align256(sizeof(double2) * (size_t)nq) + sizeof(double2) * (size_t)(nnz > 0 ? nnz : 1);
+    return FEM_OK;
+}
+
+extern "C" int fem_adjoint_elas(int32_t nq, int32_t nme, int64_t nnz, const double *q,
+                                const int32_t *row_ptr, const int32_t *col_idx,
+                                const int32_t *inc_ptr, const uint32_t *inc_pos, const int32_t *tpos,
+                                double lambda, double mu, const double *G, double *dq, double *dlm,
+                                void *work, size_t work_bytes, int flags, void *stream) {
+    clear_error();
+    FEM_REQUIRE(nq >= 1 && nme >= 0 && nnz >= 0 && 4 * nnz <= INT32_MAX, FEM_EINVAL,
+                "fem_adjoint_elas: bad sizes");
+    FEM_REQUIRE((flags & ~FEM_ACCUMULATE) == 0, FEM_EINVAL,
+                "fem_adjoint_elas: only FEM_ACCUMULATE is supported");
+    FEM_REQUIRE(q && row_ptr && dq && work, FEM_EINVAL, "fem_adjoint_elas: NULL q, row_ptr, dq or work");
+    FEM_REQUIRE(nnz == 0 || (col_idx && inc_ptr && inc_pos && G), FEM_EINVAL,
+                "fem_adjoint_elas: NULL pattern array or G");
+    size_t need = 0;
+    fem_adjoint_elas_workspace(nq, nnz, &need);
+    FEM_REQUIRE(work_bytes >= need, FEM_ENOSPC, "fem_adjoint_elas: workspace %zu < %zu", work_bytes, need);
+    hipStream_t s = as_stream(stream);
+    double2 *lm = static_cast<double2 *>(work);
+    double2 *H = reinterpret_cast<double2 *>(static_cast<char *>(work) + align256(sizeof(double2) * (size_t)nq));
+    const int64_t ntiles = (nq + WAVE - 1) / WAVE;
+    const size_t lds = (size_t)ADJ_U * WAVE * (6 * 8 + 4);
+    hipLaunchKernelGGL((k_adj_elas_rows<ADJ_U, ADJ_LMAX>), dim3((unsigned)ntiles), dim3(WAVE), lds, s, nq,
+                       q, row_ptr, col_idx, inc_ptr, inc_pos, G, lambda, mu, H, lm, ntiles);
+    FEM_LAUNCH_CHECK();
+    const int acc = (flags & FEM_ACCUMULATE) ? 1 : 0;
+    hipLaunchKernelGGL(k_adj_elas_cols<ADJ_U>, dim3((unsigned)ntiles), dim3(WAVE), 0, s, nq, row_ptr,
+                       col_idx, tpos, H, dq, acc, ntiles);
+    FEM_LAUNCH_CHECK();
+    if (dlm) {
+        hipLaunchKernelGGL(k_adj_lm_reduce, dim3(1), dim3(1024), 0, s, nq, lm, dlm, acc);
+        FEM_LAUNCH_CHECK();
+    }
     return FEM_OK;
 }
