@@ -384,7 +384,7 @@ int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *
                             void *work, size_t work_bytes, int flags, void *stream);
 
 /* HOST ONLY.  Bytes of device workspace for fem_adjoint_elas: per-row
- * partial sums (16 nq) and per-entry partial derivatives (16 nnz). */
+ * partial sums (at most 16 nq) and per-entry partial derivatives (16 nnz). */
 int fem_adjoint_elas_workspace(int32_t nq, int64_t nnz, size_t *bytes /* HOST */);
 
 /* Gradient of L = sum_e G_e K_e(q; lambda, mu) with respect to q and the

@@ -471,7 +471,7 @@ __device__ __forceinline__ void elas_tau(const double (&x)[3][2], const double (
 // Pass 1 of the elasticity adjoint: tile of 64 rows (one per lane).  LDS:
 // q (x, y) | the tile's 4 Ew values of G | ipos; H accumulators (x, y) of the
 // lane's row in registers, then transposed through LDS and written as
-// (hx, hy) records; the row's dtau/dlambda, dtau/dmu sums go to lm[i].
+// (hx, hy) records; the tile's dtau/dlambda, dtau/dmu sums go to lm[tile].
 template <int U, int LMAX>
 __global__ __launch_bounds__(WAVE) void k_adj_elas_rows(
     int32_t nq, const double *__restrict__ q, const int32_t *__restrict__ row_ptr,
@@ -510,8 +510,21 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_rows(
                 const int t = lane + u * WAVE;
                 if (t < Iw) s_ip[t] = __builtin_nontemporal_load(inc_pos + I0 + t);
             }
+            // the tile's 4 Ew values of G, eight loads in flight per lane
             const double *gt = G + 4 * (int64_t)E0;
-            for (int e = lane; e < 4 * Ew; e += WAVE) s_g[e] = __builtin_nontemporal_load(gt + e);
+            for (int e0 = 0; e0 < 4 * Ew; e0 += 8 * WAVE) {
+                double gv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + lane + u * WAVE;
+                    gv[u] = e < 4 * Ew ? __builtin_nontemporal_load(gt + e) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + lane + u * WAVE;
+                    if (e < 4 * Ew) s_g[e] = gv[u];
+                }
+            }
             double2 qv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -650,7 +663,9 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_rows(
             hd.y += oy;
             H[rs + pd] = hd;
         }
-        if (active) lm[i] = make_double2(sl, sm);
+        // the tile's dtau/dlambda, dtau/dmu sums (a fixed shuffle tree)
+        const double tl = wave_sum(sl), tm = wave_sum(sm);
+        if (lane == 0) lm[tile] = make_double2(tl, tm);
     }
 }
 
@@ -733,19 +748,26 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_cols(int32_t nq, const int32_
     }
 }
 
-// dL/dlambda, dL/dmu: the per-row sums in a fixed order (each thread a
-// contiguous chunk, then a fixed pairwise tree), so the result is bitwise
-// reproducible.
-__global__ __launch_bounds__(1024) void k_adj_lm_reduce(int32_t nq, const double2 *__restrict__ lm,
+// dL/dlambda, dL/dmu: the per-tile sums in a fixed order (thread t takes
+// entries t, t + 1024, ... in turn, then a fixed pairwise tree), so the
+// result is bitwise reproducible.
+__global__ __launch_bounds__(1024) void k_adj_lm_reduce(int64_t n, const double2 *__restrict__ lm,
                                                         double *__restrict__ out, int accumulate) {
     __shared__ double s_l[1024], s_m[1024];
     const int tid = threadIdx.x;
-    const int64_t chunk = ((int64_t)nq + 1023) / 1024;
-    const int64_t a = tid * chunk, b = (a + chunk < nq) ? a + chunk : nq;
     double l = 0.0, m = 0.0;
-    for (int64_t i = a; i < b; ++i) {
-        l += lm[i].x;
-        m += lm[i].y;
+    for (int64_t i0 = tid; i0 < n; i0 += 4 * 1024) {
+        double2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * 1024;
+            v[u] = i < n ? lm[i] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            l += v[u].x;
+            m += v[u].y;
+        }
     }
     s_l[tid] = l;
     s_m[tid] = m;
@@ -881,7 +903,7 @@ extern "C" int fem_adjoint_elas(int32_t nq, int32_t nme, int64_t nnz, const doub
                        col_idx, tpos, H, dq, acc, ntiles);
     FEM_LAUNCH_CHECK();
     if (dlm) {
-        hipLaunchKernelGGL(k_adj_lm_reduce, dim3(1), dim3(1024), 0, s, nq, lm, dlm, acc);
+        hipLaunchKernelGGL(k_adj_lm_reduce, dim3(1), dim3(1024), 0, s, ntiles, lm, dlm, acc);
         FEM_LAUNCH_CHECK();
     }
     return FEM_OK;
