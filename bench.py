@@ -65,10 +65,16 @@ CALL_KERNEL = {
 }
 
 
-def source_hash():
-    """sha256 over the HIP sources and headers the library is built from."""
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1305_3122_amd", "csrc", "*")) +
-                   glob.glob(os.path.join(ROOT, "include", "*.h")))
+# the sources whose kernels each profile covers
+PROFILE_SOURCES = {
+    "step_square2048": ("fem_common.hip", "fem_internal.h", "fem_pattern.hip", "fem_numeric.hip"),
+    "sparse_optv2_square2048": ("fem_common.hip", "fem_internal.h", "fem_sparse.hip"),
+}
+
+
+def source_hash(name="step_square2048"):
+    """sha256 over the HIP sources of the kernels a profile covers."""
+    files = [os.path.join(ROOT, "paper_1305_3122_amd", "csrc", f) for f in PROFILE_SOURCES[name]]
     h = hashlib.sha256()
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -141,12 +147,12 @@ def summarize_profiles(kt_dir, pf_dir, pw_dir, command, name="step_square2048"):
 
     stats = one(kt_dir, "*kernel_stats.csv")
     total = sum(float(r["TotalDurationNs"]) for r in stats)
-    sh = source_hash()
+    sh = source_hash(name)
     lines = [f"# Kernel statistics: {title}",
              "",
              workload,
              "",
-             f"source-sha256: {sh}",
+             f"source-sha256: {sh}  (sha256 of {', '.join(PROFILE_SOURCES[name])})",
              "",
              "Commands (from the repository root; rocprofv3 writes csv under gpurun_out/):",
              "", "```", command, "```", "",
@@ -181,7 +187,7 @@ def summarize_profiles(kt_dir, pf_dir, pw_dir, command, name="step_square2048"):
              "each scaled by what the same counter reads for a plain 1 GiB device-to-device copy",
              "(1 GiB read, 1 GiB written).  Scaled MB = raw KiB x 1024 x scale / 1e6.",
              "",
-             f"source-sha256: {sh}",
+             f"source-sha256: {sh}  (sha256 of {', '.join(PROFILE_SOURCES[name])})",
              "",
              f"fetch-scale: {sf:.4f}  (copy of 1 GiB: FETCH_SIZE {cf:.1f} KiB)",
              f"write-scale: {sw:.4f}  (copy of 1 GiB: WRITE_SIZE {cw:.1f} KiB)",
@@ -541,6 +547,34 @@ def run_adjoint(torch, fem, args):
            "fwd_us": round(tf, 1), "bwd_us": round(tb, 1), "fwd_bwd_us": round(tfb, 1),
            "ratio": round(tfb / tf, 2)}
     log(f"[bench] adjoint fwd {tf:.1f}us bwd {tb:.1f}us fwd+bwd {tfb:.1f}us ratio {tfb / tf:.2f}")
+    # elasticity: K(q; lambda, mu) forward, adjoint for dq, dlambda, dmu
+    lam, mu = 1.0, 0.5
+    K = torch.empty(4 * pat.nnz, dtype=torch.float64, device=dev)
+    GK = torch.from_numpy(mg.normal_seed(4 * pat.nnz, seed=mg.BASE_SEED + 56)).to(dev)
+    ew = C.c_size_t(0)
+    fem._lib.check(lib.fem_adjoint_elas_workspace(m.nq, pat.nnz, C.byref(ew)))
+    ework = torch.empty(int(ew.value), dtype=torch.uint8, device=dev)
+    dlm = torch.empty(2, dtype=torch.float64, device=dev)
+
+    def efwd():
+        fem._lib.check(lib.fem_assemble(
+            fem.FEM_OP_ELAS, m.nq, pat.nme, pat.nnz, q.data_ptr(), None, pat.me.data_ptr(), *P,
+            None, lam, mu, None, None, None, K.data_ptr(), None, 0, None, 0, s))
+
+    def ebwd():
+        fem._lib.check(lib.fem_adjoint_elas(
+            m.nq, pat.nme, pat.nnz, q.data_ptr(), *P, pat.tpos.data_ptr(), lam, mu, GK.data_ptr(),
+            dq.data_ptr(), dlm.data_ptr(), ework.data_ptr(), ework.numel(), 0, s))
+
+    ef = t(efwd)
+    eb = t(ebwd)
+    efb = t(lambda: (efwd(), ebwd()))
+    out["elasticity"] = {"workload": "same mesh, K (lambda=1, mu=0.5) forward, adjoint of <G, K> "
+                                     "(dq, dlambda, dmu)",
+                         "fwd_us": round(ef, 1), "bwd_us": round(eb, 1), "fwd_bwd_us": round(efb, 1),
+                         "ratio": round(efb / ef, 2)}
+    log(f"[bench] elasticity adjoint fwd {ef:.1f}us bwd {eb:.1f}us fwd+bwd {efb:.1f}us "
+        f"ratio {efb / ef:.2f}")
     return out
 
 
