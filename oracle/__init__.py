@@ -75,6 +75,13 @@ def _load():
     lib.oracle_assemble_tet.restype = C.c_int64
     lib.oracle_assemble_tet.argtypes = [C.c_int, C.c_int32, C.c_int32, _f64p, _i32p, _i32p, _i32p,
                                         _f64p]
+    lib.oracle_elem_p2_mass.argtypes = [C.c_double, _f64p]
+    lib.oracle_elem_p2_stiff.argtypes = [_f64p, _f64p, _f64p, _f64p]
+    lib.oracle_p2_dofs.restype = C.c_int64
+    lib.oracle_p2_dofs.argtypes = [C.c_int32, C.c_int32, _i32p, _i32p, _i32p]
+    lib.oracle_assemble_p2.restype = C.c_int64
+    lib.oracle_assemble_p2.argtypes = [C.c_int, C.c_int32, C.c_int32, _f64p, _i32p, _i32p, _i32p,
+                                       _i32p, _f64p]
     lib.oracle_pattern.restype = C.c_int64
     lib.oracle_pattern.argtypes = [C.c_int32, C.c_int32, _i32p, _i32p, _i32p, vp, vp, vp]
     lib.oracle_pattern_elas.restype = C.c_int64
@@ -199,6 +206,47 @@ def assemble_tet(op: str, q, me):
     nnz = _check(_load().oracle_assemble_tet({"mass": 0, "stiff": 1}[op], nq, nme, q.reshape(-1),
                                              me.reshape(-1), row_ptr, col_idx, vals))
     return row_ptr, col_idx[:nnz].copy(), vals[:nnz].copy()
+
+
+def elem_p2_mass(area_: float):
+    """6x6 P2 mass matrix [a][b] (vertices 0..2, then the edge opposite each)."""
+    E = np.zeros(36)
+    _load().oracle_elem_p2_mass(float(area_), E)
+    return E.reshape(6, 6).T.copy()
+
+
+def elem_p2_stiff(x0, x1, x2):
+    E = np.zeros(36)
+    _load().oracle_elem_p2_stiff(_f64(x0), _f64(x1), _f64(x2), E)
+    return E.reshape(6, 6).T.copy()
+
+
+def p2_dofs(nq: int, me):
+    """(dofs [nme][6], edges [ne][2]): P2 degrees of freedom, vertices first,
+    then nq + e for the edge opposite each local vertex; edges numbered in
+    lexicographic order of (lower, higher) vertex."""
+    me = _i32(me)
+    nme = me.shape[0]
+    dofs = np.zeros((nme, 6), np.int32)
+    edges = np.zeros((max(3 * nme, 1), 2), np.int32)
+    ne = _check(_load().oracle_p2_dofs(nq, nme, me.reshape(-1), dofs.reshape(-1), edges.reshape(-1)))
+    return dofs, edges[:ne].copy()
+
+
+def assemble_p2(op: str, q, me):
+    """Global P2 mass ("mass") or stiffness ("stiff") as CSR over nq + ne
+    DOFs: (row_ptr, col_idx, values, dofs, edges); OptV2 triplets
+    t = r nme + k (r = 6 b + a), then sparse()."""
+    q, me = _f64(q), _i32(me)
+    nq, nme = q.shape[0], me.shape[0]
+    dofs, edges = p2_dofs(nq, me)
+    ndof = nq + edges.shape[0]
+    row_ptr = np.zeros(ndof + 1, np.int32)
+    col_idx = np.zeros(max(36 * nme, 1), np.int32)
+    vals = np.zeros(max(36 * nme, 1), np.float64)
+    nnz = _check(_load().oracle_assemble_p2({"mass": 0, "stiff": 1}[op], ndof, nme, q.reshape(-1),
+                                            me.reshape(-1), dofs.reshape(-1), row_ptr, col_idx, vals))
+    return row_ptr, col_idx[:nnz].copy(), vals[:nnz].copy(), dofs, edges
 
 
 def sparse_positions(I, J, nrows: int, ncols: int):

@@ -22,6 +22,14 @@
  *   - the compressed format is CSR (the paper's Section 4 describes CSC; the
  *     four matrices are symmetric, so CSR of A is CSC of A^T = A).
  *
+ * Extensions named in the Conclusion, in the same OptV2 shape (triplets
+ * t = r nme + k, then sparse()): P1 tetrahedra (mass, stiffness) and P2
+ * triangles (mass, stiffness; edge degrees of freedom numbered in
+ * lexicographic order of their vertex pairs, element matrices integrated
+ * exactly in barycentric coordinates).  Also the adjoints (gradients with
+ * respect to the vertex coordinates, the weight and the Lame parameters) of
+ * the stiffness, weighted-mass and elasticity assemblies.
+ *
  * Conventions: 0-based indices; q is [nq][2] (x0, y0, x1, y1, ...), me is
  * [nme][3]; triangle areas are computed here as |det| / 2 (the paper takes
  * them as an input).  Values of each entry are summed in ascending (k, r)
@@ -943,4 +951,223 @@ int oracle_adjoint_elas(int32_t nq, int32_t nme, const double *q, const int32_t 
                 dq[2 * (int64_t)t[a] + c] += dL[2 * a + c];
     }
     return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* P2 (quadratic) triangles (the P_k extension named in the Conclusion) */
+/* ------------------------------------------------------------------ */
+/* Degrees of freedom: the nq vertices, then the ne edges, edge e being
+ * DOF nq + e; edges are numbered in ascending lexicographic order of
+ * (lower vertex, higher vertex).  On the triangle (x0, x1, x2) the local
+ * DOFs are the vertices 0, 1, 2 and then 3 + a = the edge opposite vertex a
+ * (between the other two).  The basis, in barycentric coordinates, is
+ *   phi_a = lambda_a (2 lambda_a - 1),  phi_{3+a} = 4 lambda_b lambda_c,
+ * the Lagrange basis of the vertices and the edge midpoints.  Element
+ * matrices are integrated exactly: each integrand is a polynomial in
+ * (lambda_0, lambda_1, lambda_2) and
+ *   int_T lambda_0^i lambda_1^j lambda_2^l = 2 |T| i! j! l! / (i + j + l + 2)!. */
+
+#define BP_DEG 5   /* exponents 0..4 per coordinate */
+typedef struct {
+    double c[BP_DEG][BP_DEG][BP_DEG];   /* c[i][j][l]: coefficient of l0^i l1^j l2^l */
+} bary_poly;
+
+static void bp_basis_p2(int n, bary_poly *p)
+{
+    memset(p, 0, sizeof *p);
+    if (n < 3) {
+        int e2[3] = {0, 0, 0}, e1[3] = {0, 0, 0};
+        e2[n] = 2;
+        e1[n] = 1;
+        p->c[e2[0]][e2[1]][e2[2]] += 2.0;
+        p->c[e1[0]][e1[1]][e1[2]] -= 1.0;
+    } else {
+        int e[3] = {1, 1, 1};
+        e[n - 3] = 0;
+        p->c[e[0]][e[1]][e[2]] += 4.0;
+    }
+}
+
+static void bp_mul(const bary_poly *a, const bary_poly *b, bary_poly *o)
+{
+    memset(o, 0, sizeof *o);
+    for (int i1 = 0; i1 < BP_DEG; ++i1)
+        for (int j1 = 0; j1 < BP_DEG; ++j1)
+            for (int l1 = 0; l1 < BP_DEG; ++l1) {
+                const double ca = a->c[i1][j1][l1];
+                if (ca == 0.0)
+                    continue;
+                for (int i2 = 0; i1 + i2 < BP_DEG; ++i2)
+                    for (int j2 = 0; j1 + j2 < BP_DEG; ++j2)
+                        for (int l2 = 0; l1 + l2 < BP_DEG; ++l2)
+                            o->c[i1 + i2][j1 + j2][l1 + l2] += ca * b->c[i2][j2][l2];
+            }
+}
+
+/* partial derivative with respect to lambda_m */
+static void bp_diff(const bary_poly *a, int m, bary_poly *o)
+{
+    memset(o, 0, sizeof *o);
+    for (int i = 0; i < BP_DEG; ++i)
+        for (int j = 0; j < BP_DEG; ++j)
+            for (int l = 0; l < BP_DEG; ++l) {
+                const int e[3] = {i, j, l};
+                if (e[m] == 0)
+                    continue;
+                int d[3] = {i, j, l};
+                d[m] -= 1;
+                o->c[d[0]][d[1]][d[2]] += e[m] * a->c[i][j][l];
+            }
+}
+
+static double bp_integrate(const bary_poly *p, double area)
+{
+    static const double fact[13] = {1, 1, 2, 6, 24, 120, 720, 5040, 40320, 362880,
+                                    3628800, 39916800, 479001600};
+    double s = 0.0;
+    for (int i = 0; i < BP_DEG; ++i)
+        for (int j = 0; j < BP_DEG; ++j)
+            for (int l = 0; l < BP_DEG; ++l)
+                if (p->c[i][j][l] != 0.0)
+                    s += p->c[i][j][l] * fact[i] * fact[j] * fact[l] / fact[i + j + l + 2];
+    return 2.0 * area * s;
+}
+
+/* Mass: E[6 b + a] = int_T phi_a phi_b. */
+void oracle_elem_p2_mass(double area, double E[36])
+{
+    bary_poly pa, pb, prod;
+    for (int b = 0; b < 6; ++b)
+        for (int a = 0; a < 6; ++a) {
+            bp_basis_p2(a, &pa);
+            bp_basis_p2(b, &pb);
+            bp_mul(&pa, &pb, &prod);
+            E[6 * b + a] = bp_integrate(&prod, area);
+        }
+}
+
+/* Stiffness: E[6 b + a] = int_T grad phi_a . grad phi_b, with
+ * grad phi = sum_m (d phi / d lambda_m) grad lambda_m and grad lambda_1,
+ * grad lambda_2 the rows of B^{-1}, B = [x1 - x0 | x2 - x0],
+ * grad lambda_0 = -(grad lambda_1 + grad lambda_2). */
+void oracle_elem_p2_stiff(const double *x0, const double *x1, const double *x2, double E[36])
+{
+    const double b00 = x1[0] - x0[0], b01 = x2[0] - x0[0];
+    const double b10 = x1[1] - x0[1], b11 = x2[1] - x0[1];
+    const double det = b00 * b11 - b01 * b10;
+    double g[3][2];
+    g[1][0] = b11 / det;
+    g[1][1] = -b01 / det;
+    g[2][0] = -b10 / det;
+    g[2][1] = b00 / det;
+    g[0][0] = -(g[1][0] + g[2][0]);
+    g[0][1] = -(g[1][1] + g[2][1]);
+    const double area = fabs(det) / 2.0;
+    bary_poly pa, pb, da, db, prod;
+    for (int b = 0; b < 6; ++b)
+        for (int a = 0; a < 6; ++a) {
+            bp_basis_p2(a, &pa);
+            bp_basis_p2(b, &pb);
+            double s = 0.0;
+            for (int m = 0; m < 3; ++m)
+                for (int n = 0; n < 3; ++n) {
+                    bp_diff(&pa, m, &da);
+                    bp_diff(&pb, n, &db);
+                    bp_mul(&da, &db, &prod);
+                    s += (g[m][0] * g[n][0] + g[m][1] * g[n][1]) * bp_integrate(&prod, area);
+                }
+            E[6 * b + a] = s;
+        }
+}
+
+/* The P2 degrees of freedom of a triangle mesh: dofs [nme][6] (vertices,
+ * then nq + the edge opposite local vertex 0, 1, 2) and edges [ne][2]
+ * (lower, higher vertex; edges must hold 3 nme pairs).  The edge number is
+ * the rank of its vertex pair among all distinct pairs in lexicographic
+ * order.  Returns ne, or a negative status. */
+int64_t oracle_p2_dofs(int32_t nq, int32_t nme, const int32_t *me, int32_t *dofs,
+                       int32_t *edges)
+{
+    const int st = oracle_validate(nq, nme, me);
+    if (st != ORACLE_OK)
+        return st;
+    const int64_t nt = 3 * (int64_t)nme;
+    const size_t n = (size_t)(nt > 0 ? nt : 1);
+    int32_t *I = (int32_t *)malloc(sizeof(int32_t) * n);
+    int32_t *Jv = (int32_t *)malloc(sizeof(int32_t) * n);
+    int32_t *cols = (int32_t *)malloc(sizeof(int32_t) * n);
+    int32_t *rp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nq + 1));
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * n);
+    int64_t ne = ORACLE_ENOMEM;
+    if (I && Jv && cols && rp && pos) {
+        for (int64_t k = 0; k < nme; ++k)
+            for (int a = 0; a < 3; ++a) {
+                const int32_t u = me[3 * k + (a + 1) % 3], v = me[3 * k + (a + 2) % 3];
+                I[a * nme + k] = u < v ? u : v;
+                Jv[a * nme + k] = u < v ? v : u;
+            }
+        ne = oracle_csr_pattern(nq, nq, nt, I, Jv, rp, cols, pos);
+        if (ne >= 0) {
+            for (int64_t k = 0; k < nme; ++k)
+                for (int a = 0; a < 3; ++a) {
+                    dofs[6 * k + a] = me[3 * k + a];
+                    dofs[6 * k + 3 + a] = (int32_t)(nq + pos[a * nme + k]);
+                }
+            for (int32_t i = 0; i < nq; ++i)
+                for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+                    edges[2 * (int64_t)e] = i;
+                    edges[2 * (int64_t)e + 1] = cols[e];
+                }
+        }
+    }
+    free(I);
+    free(Jv);
+    free(cols);
+    free(rp);
+    free(pos);
+    return ne;
+}
+
+/* Global P2 matrices the OptV2 way: Ig, Jg, Kg of all 36 local entries,
+ * triplet t = r nme + k for local entry r = 6 b + a of element k (row
+ * dofs[k][a], column dofs[k][b]), then sparse() (values summed in ascending
+ * t).  op: 0 mass, 1 stiffness.  row_ptr [ndof + 1]; col_idx and values
+ * hold 36 nme entries.  Returns nnz, or a negative status. */
+int64_t oracle_assemble_p2(int op, int32_t ndof, int32_t nme, const double *q, const int32_t *me,
+                           const int32_t *dofs, int32_t *row_ptr, int32_t *col_idx, double *values)
+{
+    if (ndof <= 0 || nme < 0 || (op != 0 && op != 1))
+        return ORACLE_EINVAL;
+    const int64_t nt = 36 * (int64_t)nme;
+    const size_t n = (size_t)(nt > 0 ? nt : 1);
+    int32_t *I = (int32_t *)malloc(sizeof(int32_t) * n);
+    int32_t *Jv = (int32_t *)malloc(sizeof(int32_t) * n);
+    double *V = (double *)malloc(sizeof(double) * n);
+    if (!I || !Jv || !V) {
+        free(I);
+        free(Jv);
+        free(V);
+        return ORACLE_ENOMEM;
+    }
+    for (int64_t k = 0; k < nme; ++k) {
+        const int32_t *t = me + 3 * k;
+        const double *x0 = q + 2 * (int64_t)t[0], *x1 = q + 2 * (int64_t)t[1];
+        const double *x2 = q + 2 * (int64_t)t[2];
+        double E[36];
+        if (op == 0)
+            oracle_elem_p2_mass(oracle_area(x0, x1, x2), E);
+        else
+            oracle_elem_p2_stiff(x0, x1, x2, E);
+        for (int r = 0; r < 36; ++r) {
+            const int64_t s = (int64_t)r * nme + k;
+            I[s] = dofs[6 * k + r % 6];
+            Jv[s] = dofs[6 * k + r / 6];
+            V[s] = E[r];
+        }
+    }
+    const int64_t nnz = oracle_sparse(ndof, ndof, nt, I, Jv, V, row_ptr, col_idx, values);
+    free(I);
+    free(Jv);
+    free(V);
+    return nnz;
 }
