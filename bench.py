@@ -715,6 +715,97 @@ def run_tet(torch, fem, args):
     return out
 
 
+def run_p2(torch, fem, args):
+    """P2 triangles on the 2048^2-cell unit square of the headline workload:
+    edge numbering, pattern over nq + ne DOFs, fused mass + stiffness."""
+    from paper_1305_3122_amd import meshgen as mg
+    lib = fem._lib.load()
+    dev = torch.device("cuda:0")
+    m = mg.config_mesh(2)
+    me = torch.from_numpy(m.me).to(dev)
+    q = torch.from_numpy(m.q).to(dev)
+    s = torch.cuda.current_stream().cuda_stream
+    i32 = dict(dtype=torch.int32, device=dev)
+    ws = C.c_size_t(0)
+    fem._lib.check(lib.fem_p2_dofs_workspace(m.nq, m.nme, C.byref(ws)))
+    dwork = torch.empty(int(ws.value), dtype=torch.uint8, device=dev)
+    dofs = torch.empty((m.nme, 6), **i32)
+    edges = torch.empty((3 * m.nme, 2), **i32)
+    ne = C.c_int64(0)
+
+    def dofs_call():
+        fem._lib.check(lib.fem_p2_dofs(m.nq, m.nme, me.data_ptr(), dofs.data_ptr(), edges.data_ptr(),
+                                       3 * m.nme, dwork.data_ptr(), int(ws.value), C.byref(ne), s))
+
+    dofs_call()
+    ndof = m.nq + int(ne.value)
+    pw = C.c_size_t(0)
+    fem._lib.check(lib.fem_p2_pattern_workspace(ndof, m.nme, C.byref(pw)))
+    pwork = torch.empty(int(pw.value), dtype=torch.uint8, device=dev)
+    cap = ndof + 30 * m.nme
+    row_ptr = torch.empty(ndof + 1, **i32)
+    col = torch.empty(cap, **i32)
+    cptr = torch.empty(cap + 1, **i32)
+    ctb = torch.empty(36 * m.nme, **i32)
+    nnz = C.c_int64(0)
+
+    def pattern():
+        fem._lib.check(lib.fem_p2_pattern(ndof, m.nme, dofs.data_ptr(), row_ptr.data_ptr(), col.data_ptr(),
+                                          cap, cptr.data_ptr(), ctb.data_ptr(), pwork.data_ptr(),
+                                          int(pw.value), C.byref(nnz), s))
+
+    pattern()
+    k = int(nnz.value)
+    ops = fem.FEM_OP_MASS | fem.FEM_OP_STIFF
+    aw = C.c_size_t(0)
+    fem._lib.check(lib.fem_p2_assemble_workspace(m.nme, C.byref(aw)))
+    awork = torch.empty(int(aw.value), dtype=torch.uint8, device=dev)
+    M = torch.empty(k, dtype=torch.float64, device=dev)
+    S = torch.empty_like(M)
+
+    def assemble():
+        fem._lib.check(lib.fem_p2_assemble(ops, m.nq, m.nme, k, q.data_ptr(), me.data_ptr(),
+                                           cptr.data_ptr(), ctb.data_ptr(), M.data_ptr(), S.data_ptr(),
+                                           awork.data_ptr(), awork.numel(), 0, s))
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            ea = torch.cuda.Event(enable_timing=True)
+            eb = torch.cuda.Event(enable_timing=True)
+            ea.record()
+            fn()
+            eb.record()
+            torch.cuda.synchronize()
+            out.append(ea.elapsed_time(eb) * 1e3)
+        return float(np.median(out))
+
+    pattern()       # re-run once so that every buffer is touched before timing
+    torch.cuda.synchronize()
+    td = timed(dofs_call, 3)
+    tp = timed(pattern, 3)
+    ta = timed(assemble, 10)
+    # inputs once (me, q), outputs once (two value arrays)
+    alg = 12 * m.nme + 16 * m.nq + 16 * k
+    # plus what the contributor design reads: contrib, contrib_ptr, the four
+    # numbers per triangle (written once, read back)
+    design = alg + 4 * 36 * m.nme + 4 * (k + 1) + 2 * 32 * m.nme
+    out = {"workload": "unit square 2048x2048 cells (8.4M triangles, jitter 0.2h, random relabelling); "
+                       "P2 Lagrange, DOFs = vertices + edges; mass + stiffness FP64",
+           "nq": m.nq, "ne": int(ne.value), "ndof": ndof, "nme": m.nme, "nnz": k,
+           "dofs_us": round(td, 1), "pattern_us": round(tp, 1), "assemble_us": round(ta, 1),
+           "Mtri_per_s_assemble": round(m.nme / ta, 1),
+           "Mtri_per_s_total": round(m.nme / (td + tp + ta), 1),
+           "assemble_alg_bytes": alg, "assemble_alg_GBps": round(alg / (ta * 1e-6) / 1e9, 1),
+           "assemble_design_bytes": design,
+           "assemble_design_GBps": round(design / (ta * 1e-6) / 1e9, 1)}
+    log(f"[bench] p2 square2048 nme={m.nme} ndof={ndof} nnz={k}: dofs {td:.0f}us, pattern {tp:.0f}us, "
+        f"mass+stiffness {ta:.0f}us ({m.nme / ta:.0f} Mtri/s)")
+    return out
+
+
 def run_cpu_baseline(args):
     """The oracle, as it stands, on a bounded sample: the same recipe at
     1448 x 1448 cells (half of the workload), one full step."""
@@ -753,7 +844,7 @@ def main():
     ap.add_argument("--command", default="", help="command text recorded by --summarize")
     ap.add_argument("--profile-name", default="step_square2048", choices=sorted(PROFILE_TITLES),
                     help="which summary --summarize writes")
-    ap.add_argument("--only", choices=("sparse", "adjoint", "batched", "tet"),
+    ap.add_argument("--only", choices=("sparse", "adjoint", "batched", "tet", "p2"),
                     help="run one of the extra measurements alone and print its JSON (profiling)")
     args = ap.parse_args()
     if args.summarize:
@@ -777,7 +868,7 @@ def main():
         del src, dst
     if args.only:
         fn = {"sparse": run_sparse, "adjoint": run_adjoint, "batched": run_batched,
-              "tet": run_tet}[args.only]
+              "tet": run_tet, "p2": run_p2}[args.only]
         print(json.dumps({args.only: fn(torch, fem, args)}), flush=True)
         return
     m, st, ms, kern = run_main(torch, fem, args)
@@ -787,6 +878,7 @@ def main():
         extras["adjoint"] = run_adjoint(torch, fem, args)
         extras["sparse"] = run_sparse(torch, fem, args)
         extras["tet"] = run_tet(torch, fem, args)
+        extras["p2"] = run_p2(torch, fem, args)
     traffic = read_traffic()
 
     def roof(p):

@@ -362,6 +362,69 @@ int fem_tet_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const double
                      void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* P2 (quadratic Lagrange) triangles                                         */
+/* ------------------------------------------------------------------------ */
+
+/* HOST ONLY.  Bytes of device workspace fem_p2_dofs needs. */
+int fem_p2_dofs_workspace(int32_t nq, int32_t nme, size_t *bytes /* HOST */);
+
+/* Degrees of freedom of the P2 triangle (the P_k extension named in the
+ * Conclusion): the nq vertices, then the ne edges, edge e being DOF nq + e,
+ * with edges numbered in ascending lexicographic order of (lower vertex,
+ * higher vertex).
+ *   me [nme][3] int32
+ *   dofs [nme][6] int32 (8-byte aligned): v0, v1, v2, then nq + the edge
+ *        opposite local vertex 0, 1, 2
+ *   edges [edge_cap][2] int32 (8-byte aligned) or NULL: (lower, higher)
+ *        vertex of each edge; ne <= 3 nme, and ne = nq + nme - 1 on a
+ *        simply connected mesh
+ *   work [work_bytes] >= fem_p2_dofs_workspace(nq, nme); ne_out HOST
+ * Requires 36 nme <= 2^31 - 1 and nq + ne <= 2^31 - 1 (FEM_EOVERFLOW).
+ * FEM_ERANGE / FEM_EDEGEN for an invalid me, FEM_ENOSPC if edges is given and
+ * edge_cap < ne.  Synchronises `stream`. */
+int fem_p2_dofs(int32_t nq, int32_t nme, const int32_t *me, int32_t *dofs, int32_t *edges,
+                int64_t edge_cap, void *work, size_t work_bytes, int64_t *ne_out /* HOST */,
+                void *stream);
+
+/* HOST ONLY.  Bytes of device workspace fem_p2_pattern needs. */
+int fem_p2_pattern_workspace(int32_t ndof, int32_t nme, size_t *bytes /* HOST */);
+
+/* Pattern of the P2 matrices over ndof = nq + ne DOFs, built the OptV2 way:
+ * the index arrays of all 36 local entries, triplet t = r nme + k for entry
+ * r = 6 b + a of element k (row dofs[k][a], column dofs[k][b]), compressed by
+ * fem_sparse.
+ *   dofs [nme][6] int32 from fem_p2_dofs (8-byte aligned)
+ *   row_ptr [ndof+1], col_idx [col_cap]; nnz <= ndof + 30 nme
+ *   contrib_ptr [col_cap+1], contrib [36 nme]: the triplets of each entry,
+ *                ascending (what fem_p2_assemble sums)
+ *   work [work_bytes] >= fem_p2_pattern_workspace(ndof, nme); nnz_out HOST
+ * FEM_ERANGE for a DOF outside [0, ndof), FEM_ENOSPC if col_cap < nnz.
+ * Synchronises `stream`. */
+int fem_p2_pattern(int32_t ndof, int32_t nme, const int32_t *dofs, int32_t *row_ptr,
+                   int32_t *col_idx, int64_t col_cap, int32_t *contrib_ptr, int32_t *contrib,
+                   void *work, size_t work_bytes, int64_t *nnz_out /* HOST */, void *stream);
+
+/* HOST ONLY.  Bytes of device workspace fem_p2_assemble needs (32 nme). */
+int fem_p2_assemble_workspace(int32_t nme, size_t *bytes /* HOST */);
+
+/* P2 mass (FEM_OP_MASS: int phi_a phi_b) and / or stiffness (FEM_OP_STIFF:
+ * int grad phi_a . grad phi_b) on the pattern of fem_p2_pattern, with the
+ * basis phi_a = lambda_a (2 lambda_a - 1), phi_{3+a} = 4 lambda_b lambda_c
+ * (the edge opposite vertex a).  Four numbers per triangle (|T| / 180 and
+ * the three P1 off-diagonal stiffness entries / 3), then for every entry the
+ * sum of its contributors in ascending t, each an integer combination of
+ * those numbers (bitwise reproducible).
+ *   q [nq][2] f64 (16-byte aligned); me [nme][3] int32 as validated by
+ *   fem_p2_dofs; vals_M / vals_S [nnz]
+ *   work [work_bytes] >= fem_p2_assemble_workspace(nme), 32-byte aligned
+ * flags: 0 or FEM_ACCUMULATE.  Contributors outside [0, 36 nme) are
+ * skipped. */
+int fem_p2_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q,
+                    const int32_t *me, const int32_t *contrib_ptr, const int32_t *contrib,
+                    double *vals_M, double *vals_S, void *work, size_t work_bytes, int flags,
+                    void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Adjoint                                                                   */
 /* ------------------------------------------------------------------------ */
 

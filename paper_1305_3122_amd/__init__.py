@@ -32,7 +32,7 @@ __all__ = [
     "fem_assemble_wmass", "fem_assemble_stiff", "fem_assemble_stiff_mass",
     "fem_assemble_stiff_wmass", "fem_assemble_elas", "fem_batch_globalize",
     "fem_assemble_stiff_mass_batched", "Graph", "SparseCSR", "fem_sparse", "fem_sparse_values",
-    "TetPattern", "fem_tet_pattern", "fem_tet_assemble",
+    "TetPattern", "fem_tet_pattern", "fem_tet_assemble", "P2Pattern", "fem_p2_pattern", "fem_p2_assemble",
     "fem_adjoint_workspace", "fem_adjoint_stiff_wmass", "fem_adjoint_elas",
     "AssembleStiffWMass", "AssembleElas",
     "library_path",
@@ -441,6 +441,94 @@ def fem_tet_assemble(pat: TetPattern, q, ops: int = FEM_OP_MASS | FEM_OP_STIFF, 
                                     _ptr(pat.contrib_ptr), _ptr(pat.contrib), _ptr(out.get("M")),
                                     _ptr(out.get("S")), _ptr(work), work.numel() * work.element_size(),
                                     flags, _stream(stream)))
+    return out
+
+
+@dataclasses.dataclass
+class P2Pattern:
+    """Result of fem_p2_pattern (device tensors): P2 DOFs (vertices, then
+    nq + edge) and the CSR pattern over them."""
+    nq: int
+    ne: int
+    nme: int
+    nnz: int
+    me: object               # [nme][3] int32
+    dofs: object             # [nme][6] int32
+    edges: object            # [ne][2] int32
+    row_ptr: object          # [ndof+1] int32
+    col_idx: object          # [nnz] int32
+    contrib_ptr: object      # [nnz+1] int32
+    contrib: object          # [36 nme] int32
+
+    @property
+    def ndof(self) -> int:
+        return self.nq + self.ne
+
+    def csr(self, values):
+        torch = _torch()
+        return torch.sparse_csr_tensor(self.row_ptr, self.col_idx, values, (self.ndof, self.ndof))
+
+
+def fem_p2_pattern(me, nq: int, *, stream=None) -> P2Pattern:
+    """P2 triangle DOFs and pattern (C: fem_p2_dofs, then fem_p2_pattern).
+    me: [nme][3] int32 on the GPU."""
+    torch = _torch()
+    lib = _lib.load()
+    _dev(me, torch.int32, "me")
+    if me.dim() != 2 or me.shape[1] != 3:
+        raise ValueError("me must have shape [nme, 3]")
+    nme = int(me.shape[0])
+    dev = me.device
+    i32 = dict(dtype=torch.int32, device=dev)
+    ws = C.c_size_t(0)
+    _lib.check(lib.fem_p2_dofs_workspace(int(nq), nme, C.byref(ws)))
+    work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
+    dofs = torch.empty((max(nme, 1), 6), **i32)[:nme]
+    ecap = 3 * nme
+    edges = torch.empty((max(ecap, 1), 2), **i32)
+    ne = C.c_int64(0)
+    _lib.check(lib.fem_p2_dofs(int(nq), nme, _ptr(me), _ptr(dofs), _ptr(edges), ecap, _ptr(work),
+                               int(ws.value), C.byref(ne), _stream(stream)))
+    ne = int(ne.value)
+    del work
+    ndof = int(nq) + ne
+    _lib.check(lib.fem_p2_pattern_workspace(ndof, nme, C.byref(ws)))
+    work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
+    cap = min(36 * nme, ndof + 30 * nme)
+    row_ptr = torch.empty(ndof + 1, **i32)
+    col = torch.empty(max(cap, 1), **i32)
+    cptr = torch.empty(cap + 1, **i32)
+    ctb = torch.empty(max(36 * nme, 1), **i32)
+    nnz = C.c_int64(0)
+    _lib.check(lib.fem_p2_pattern(ndof, nme, _ptr(dofs), _ptr(row_ptr), _ptr(col), cap, _ptr(cptr),
+                                  _ptr(ctb), _ptr(work), int(ws.value), C.byref(nnz), _stream(stream)))
+    k = int(nnz.value)
+    return P2Pattern(int(nq), ne, nme, k, me, dofs, edges[:ne], row_ptr, col[:k], cptr[:k + 1],
+                     ctb[:36 * nme])
+
+
+def fem_p2_assemble(pat: P2Pattern, q, ops: int = FEM_OP_MASS | FEM_OP_STIFF, *, out=None,
+                    work=None, flags: int = 0, stream=None):
+    """P2 triangle mass / stiffness values on `pat` (C: fem_p2_assemble).
+    q: [nq][2] float64 on the GPU.  Returns {"M": ..., "S": ...} for the
+    requested operators."""
+    torch = _torch()
+    lib = _lib.load()
+    _dev(q, torch.float64, "q", (pat.nq, 2))
+    dev = q.device
+    out = {} if out is None else dict(out)
+    f64 = dict(dtype=torch.float64, device=dev)
+    for key, bit in (("M", FEM_OP_MASS), ("S", FEM_OP_STIFF)):
+        if ops & bit and key not in out:
+            out[key] = torch.empty(max(pat.nnz, 1), **f64)[:pat.nnz]
+    if work is None:
+        ws = C.c_size_t(0)
+        _lib.check(lib.fem_p2_assemble_workspace(pat.nme, C.byref(ws)))
+        work = torch.empty(max(int(ws.value), 32), dtype=torch.uint8, device=dev)
+    _lib.check(lib.fem_p2_assemble(int(ops), pat.nq, pat.nme, pat.nnz, _ptr(q), _ptr(pat.me),
+                                   _ptr(pat.contrib_ptr), _ptr(pat.contrib), _ptr(out.get("M")),
+                                   _ptr(out.get("S")), _ptr(work), work.numel() * work.element_size(),
+                                   flags, _stream(stream)))
     return out
 
 

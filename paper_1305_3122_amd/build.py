@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfem_p1.so")
 SOURCES = ["fem_common.hip", "fem_pattern.hip", "fem_numeric.hip", "fem_adjoint.hip",
-           "fem_sparse.hip", "fem_tet.hip"]
+           "fem_sparse.hip", "fem_tet.hip", "fem_p2.hip"]
 ARCH = os.environ.get("FEM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -9,15 +9,18 @@
 //                                      value; 256 to 512 coarse buckets, so the
 //                                      runs are long and the count matrix small
 //   k_sp_split                         one workgroup per coarse bucket splits
-//                                      it into fine buckets of Rf rows (about
-//                                      SP_CAP / 2 triplets each) -> fine_off
-//   k_sp_rows (LDS) / k_sp_rows_big    one workgroup per fine bucket: counting
-//                                      sort by row, then each row sorted by
-//                                      (column, t), duplicates summed in
-//                                      ascending t; rows staged per bucket,
-//                                      sorted triplet order written as the
-//                                      contributor list (every step parallel
-//                                      over the triplets)
+//                                      it into fine buckets of 2^rf rows, rf
+//                                      chosen per coarse bucket from its own
+//                                      row density (the largest whose fullest
+//                                      bucket fits in LDS) -> fine_off, cshift
+//   k_sp_rows (LDS) / k_sp_rows_big    a workgroup per fine bucket at a time:
+//                                      counting sort by row, then each row
+//                                      sorted by (column, t) as 64-bit keys,
+//                                      duplicates summed in ascending t; rows
+//                                      staged per bucket at slots from a block
+//                                      scan of run starts, sorted triplet
+//                                      order written as the contributor list
+//                                      (every step parallel over the triplets)
 //   scan of bucket totals / k_sp_copy  rows -> col_idx / values, row_ptr
 // Every value is the sum of its triplets' values in ascending t, so the result
 // is bitwise reproducible and equal to a sequential left-to-right sum.
@@ -37,6 +40,9 @@ constexpr int SP_COARSE_TARGET = 512; // coarse buckets: long runs in the first 
 constexpr int SP_COARSE_MAX = 4096;   // coarse buckets the partition's LDS holds
 constexpr int SP_SPLIT_MAX_SHIFT = 12;  // at most 4096 fine buckets per coarse one
 constexpr int SP_NBLK_TARGET = 512;   // triplet workgroups of the partition pass (2 per CU)
+constexpr int SP_COPY_GRID = 4096;    // workgroups looping over the fine bucket slots
+constexpr int SP_ADAPT_SHIFT = 2;     // fine buckets down to 1/4 of the planned rows where the
+                                      // rows are denser than average
 
 enum : int { SP_ERR_RANGE = 1, SP_ERR_OVERFLOW = 4, SP_ERR_NOSPC = 32 };
 
@@ -239,21 +245,45 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_scatter(int64_t nt, const in
 // One workgroup per coarse bucket: its triplets, sorted into nf = Rc / Rf
 // fine buckets (counting sort, tiles multisplit in order), and the fine
 // buckets' starts fine_off[cb * nf + j].
+// Row range of fine bucket b: coarse bucket cb = b >> fshift uses the first
+// 2^(rc - cshift[cb]) of its 2^fshift slots, 2^cshift[cb] rows each; the
+// other slots are empty (R = 0).  Without a split (cshift NULL) the fine
+// buckets are the coarse ones.
+__device__ __forceinline__ void fine_rows(int32_t b, int rc, int fshift, const int32_t *cshift,
+                                          int32_t *v0, int32_t *R) {
+    const int32_t cb = b >> fshift, j = b & ((1 << fshift) - 1);
+    const int rfc = cshift ? cshift[cb] : rc;
+    if (j >= (1 << (rc - rfc))) {
+        *v0 = cb << rc;
+        *R = 0;
+        return;
+    }
+    *v0 = (cb << rc) + (j << rfc);
+    *R = 1 << rfc;
+}
+
+// One workgroup per coarse bucket: triplets counted per sub-bucket of
+// 2^rmin rows, then the bucket's fine size 2^rfc (rmin <= rfc <= rmax) is the
+// largest whose fullest fine bucket holds at most SP_CAP triplets (rmin if
+// none does); its triplets are split into those fine buckets.
 __global__ __launch_bounds__(SPP_THREADS) void k_sp_split(
-    int32_t nbkt_c, int32_t nblk, int32_t nbkt_f, int rf, int nf_shift,
+    int32_t nbkt_c, int32_t nblk, int rc, int rmin, int rmax,
     const int32_t *__restrict__ offs, const int32_t *__restrict__ total_ptr,
     const int32_t *__restrict__ rl, const int2 *__restrict__ ct, const double *__restrict__ rval,
     int has_val, int32_t *__restrict__ rl2, int2 *__restrict__ ct2, double *__restrict__ rval2,
-    int32_t *__restrict__ fine_off) {
+    int32_t *__restrict__ fine_off, int32_t *__restrict__ cshift) {
     __shared__ int32_t s_wsum[SPP_THREADS / WAVE];
+    __shared__ int32_t s_lmax[SP_SPLIT_MAX_SHIFT + 1];
     const int tid = threadIdx.x;
     const int32_t cb = blockIdx.x;
-    const int32_t nf = 1 << nf_shift;
-    const TileLds L = tile_lds(nf);
+    const int fshift = rc - rmin;
+    const int32_t nsub = 1 << fshift;
+    const TileLds L = tile_lds(nsub);
     const int64_t total = *total_ptr;
     const int64_t e0 = offs[(int64_t)cb * nblk];
     const int64_t e1 = (cb + 1 < nbkt_c) ? offs[(int64_t)(cb + 1) * nblk] : total;
-    for (int j = tid; j < nf; j += SPP_THREADS) L.cnt[j] = 0;
+    for (int j = tid; j < nsub; j += SPP_THREADS) L.cnt[j] = 0;
+    if (tid <= SP_SPLIT_MAX_SHIFT) s_lmax[tid] = 0;
     __syncthreads();
     for (int64_t xb = e0 + tid; xb < e1; xb += 8 * SPP_THREADS) {
         int32_t r0[8];
@@ -264,19 +294,42 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_split(
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            if (r0[u] >= 0) atomicAdd(&L.cnt[r0[u] >> rf], 1);
+            if (r0[u] >= 0) atomicAdd(&L.cnt[r0[u] >> rmin], 1);
     }
     __syncthreads();
-    block_scan_counts(L.cnt, nf, s_wsum);
-    for (int j = tid; j < nf; j += SPP_THREADS) {
-        const int64_t fb = ((int64_t)cb << nf_shift) + j;
-        const int32_t st = static_cast<int32_t>(e0 + L.cnt[j]);
-        if (fb < nbkt_f) fine_off[fb] = st;
-        L.gcur[j] = st;
+    block_scan_counts(L.cnt, nsub, s_wsum);   // L.cnt[j]: triplets before sub-bucket j
+    const int lmax = rmax - rmin;
+    for (int l = 0; l <= lmax; ++l) {
+        int32_t mx = 0;
+        for (int32_t g = tid; g < (nsub >> l); g += SPP_THREADS)
+            mx = max(mx, L.cnt[(g + 1) << l] - L.cnt[g << l]);
+#pragma unroll
+        for (int o = WAVE / 2; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, WAVE));
+        if ((tid & (WAVE - 1)) == 0 && mx > 0) atomicMax(&s_lmax[l], mx);
     }
-    if (cb == nbkt_c - 1 && tid == 0) fine_off[nbkt_f] = static_cast<int32_t>(total);
     __syncthreads();
-    const int32_t fmask = (1 << rf) - 1;
+    int lb = 0;
+    for (int l = lmax; l > 0; --l)
+        if (s_lmax[l] <= SP_CAP) {
+            lb = l;
+            break;
+        }
+    const int rfc = rmin + lb;
+    const int32_t nk = nsub >> lb;
+    for (int32_t j = tid; j < nsub; j += SPP_THREADS) {
+        const int64_t fb = ((int64_t)cb << fshift) + j;
+        if (j < nk) {
+            const int32_t st = static_cast<int32_t>(e0 + L.cnt[j << lb]);
+            fine_off[fb] = st;
+            L.gcur[j] = st;
+        } else {
+            fine_off[fb] = static_cast<int32_t>(e1);
+        }
+    }
+    if (tid == 0) cshift[cb] = rfc;
+    if (cb == nbkt_c - 1 && tid == 0) fine_off[(int64_t)nbkt_c << fshift] = static_cast<int32_t>(total);
+    __syncthreads();
+    const int32_t fmask = (1 << rfc) - 1;
     for (int64_t xb = e0; xb < e1; xb += TILE) {
         int32_t key[IPT], prl[IPT];
         int2 pct[IPT];
@@ -285,17 +338,15 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_split(
         for (int u = 0; u < IPT; ++u) {
             const int64_t x = xb + tid + u * SPP_THREADS;
             const int32_t r0 = x < e1 ? rl[x] : -1;
-            key[u] = r0 >= 0 ? (r0 >> rf) : -1;
+            key[u] = r0 >= 0 ? (r0 >> rfc) : -1;
             prl[u] = r0 & fmask;
             pct[u] = x < e1 ? ct[x] : make_int2(0, 0);
             pval[u] = (has_val && x < e1) ? rval[x] : 0.0;
         }
-        tile_multisplit(L, nf, key, prl, pct, pval, has_val != 0, s_wsum, rl2, ct2, rval2);
+        tile_multisplit(L, nk, key, prl, pct, pval, has_val != 0, s_wsum, rl2, ct2, rval2);
     }
 }
 
-// Without a split (one fine bucket per coarse bucket): the fine starts are
-// the coarse ones.
 __global__ void k_sp_fine_off(int32_t nbkt, int32_t nblk, const int32_t *__restrict__ offs,
                               const int32_t *__restrict__ total_ptr, int32_t *__restrict__ fine_off) {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -331,174 +382,204 @@ __device__ __forceinline__ int32_t row_of(const int32_t *s_rs, int32_t R, int32_
     return lo;
 }
 
-// The rows of one bucket, with the bucket's triplets (grouped by row) in
-// arrays `col`, `tt`, `val` (LDS or global scratch) at [0, nb), every step
-// parallel over the triplets, whatever the row lengths:
-//   1 each triplet's place in its row in (column, t) order -- t breaks ties,
-//     so the order is the stable one -- is the number of smaller keys in the
-//     row: perm[s + rank] = its position; triplets with no equal column of
-//     smaller t start a run and count the row's unique columns (s_len)
-//   2 scan of the row lengths -> offsets of the rows inside the bucket
-//   3 in sorted order: the contributor list (the triplets' t), and at each
-//     run start its slot in the row, the sum of the run (ascending t) and the
-//     run's first place, staged at e0 + offset
-template <typename ColT, typename ValT, typename PermT>
+// (column, t) of a triplet as one key whose unsigned order is the (column, t)
+// order (t breaks ties, so the order is the stable one).
+__device__ __forceinline__ uint64_t sp_key(int32_t c, int32_t t) {
+    return ((uint64_t)(uint32_t)c << 32) | (uint32_t)t;
+}
+__device__ __forceinline__ int32_t key_col(uint64_t k) { return (int32_t)(k >> 32); }
+__device__ __forceinline__ int32_t key_t(uint64_t k) { return (int32_t)(uint32_t)k; }
+
+// The rows of one bucket, with the bucket's triplets (grouped by row, row r at
+// [s_rs[r], s_rs[r+1])) as keys and values in `key`, `val` (LDS or global
+// scratch) at [0, nb), every step parallel over the triplets:
+//   1 each triplet's place in its row is the number of smaller keys in the
+//     row: perm[s + rank] = its index
+//   2 every sorted position writes its triplet's t as the contributor list;
+//     a position starts a run (an entry of the CSR row) if it is the first
+//     of its row or its column differs from the previous position's; with a
+//     contiguous range of positions per thread, a block scan of the threads'
+//     run counts gives each run its slot among the bucket's entries, staged
+//     at e0 + slot with the sum of the run (ascending t) and the run's first
+//     place; rows record their first slot (rowoff), the bucket its entry
+//     count (btot)
+template <typename KeyT, typename ValT, typename PermT>
 __device__ void sp_bucket_rows(int32_t R, int32_t nb, int32_t v0, int32_t m, int64_t e0,
-                               const int32_t *s_rs, ColT *col, ColT *tt, ValT *val, PermT *perm,
-                               bool has_val, int32_t *s_len, int32_t *s_wsum,
+                               const int32_t *s_rs, const KeyT *key, const ValT *val, PermT *perm,
+                               bool has_val, int32_t *s_wsum,
                                int32_t *__restrict__ stage_col, double *__restrict__ stage_val,
                                int32_t *__restrict__ stage_cptr, int32_t *__restrict__ contrib,
                                int32_t *__restrict__ rowoff, int32_t *__restrict__ btot,
                                int32_t b) {
     const int tid = threadIdx.x;
-    for (int32_t r = tid; r < R; r += SP_THREADS) s_len[r] = 0;
-    __syncthreads();
     for (int32_t x = tid; x < nb; x += SP_THREADS) {
         const int32_t r = row_of(s_rs, R, x);
         const int32_t s = s_rs[r], e = s_rs[r + 1];
-        const int32_t ck = col[x], tk = tt[x];
-        int32_t rank = 0;
-        bool first = true;
-        for (int32_t j = s; j < e; ++j) {
-            const int32_t cj = col[j], tj = tt[j];
-            const bool same_before = cj == ck && tj < tk;
-            rank += (cj < ck || same_before) ? 1 : 0;
-            first = first && !same_before;
+        const uint64_t kx = key[x];
+        int32_t rank = 0, j = s;
+        for (; j + 4 <= e; j += 4) {
+            const uint64_t k0 = key[j], k1 = key[j + 1], k2 = key[j + 2], k3 = key[j + 3];
+            rank += (k0 < kx ? 1 : 0) + (k1 < kx ? 1 : 0) + (k2 < kx ? 1 : 0) + (k3 < kx ? 1 : 0);
         }
-        perm[s + rank] = static_cast<PermT>(x - s);
-        if (first) atomicAdd(&s_len[r], 1);
+        for (; j < e; ++j) rank += key[j] < kx ? 1 : 0;
+        perm[s + rank] = static_cast<PermT>(x);
     }
     __syncthreads();
-    // offsets of the rows inside the bucket (R / 256 rows per thread, in order)
-    const int per = (R + SP_THREADS - 1) / SP_THREADS;
-    int32_t mine = 0;
-    for (int k = 0; k < per; ++k) {
-        const int32_t r = tid * per + k;
-        if (r < R) mine += s_len[r];
+    // the contributor list, in sorted order (coalesced)
+    if (contrib)
+        for (int32_t y = tid; y < nb; y += SP_THREADS) contrib[e0 + y] = key_t(key[perm[y]]);
+    // each thread a contiguous range of sorted positions: count its run
+    // starts, scan, then stage them
+    const int32_t per = (nb + SP_THREADS - 1) / SP_THREADS;
+    const int32_t y0 = min(nb, tid * per), y1 = min(nb, y0 + per);
+    int32_t nrun = 0;
+    if (y0 < y1) {
+        int32_t r = row_of(s_rs, R, y0);
+        int32_t pc = y0 > s_rs[r] ? key_col(key[perm[y0 - 1]]) : 0;
+        for (int32_t y = y0; y < y1; ++y) {
+            while (s_rs[r + 1] <= y) ++r;
+            const int32_t c = key_col(key[perm[y]]);
+            nrun += (y == s_rs[r] || c != pc) ? 1 : 0;
+            pc = c;
+        }
     }
     int32_t T;
-    int32_t run = block_scan_sp(mine, s_wsum, &T);
-    for (int k = 0; k < per; ++k) {
-        const int32_t r = tid * per + k;
-        if (r < R) {
-            const int32_t L = s_len[r];
-            s_len[r] = run;   // now the row's offset inside the bucket
-            if (v0 + r < m) rowoff[v0 + r] = run;
-            run += L;
+    int32_t slot = block_scan_sp(nrun, s_wsum, &T);
+    if (y0 < y1) {
+        int32_t r = row_of(s_rs, R, y0);
+        int32_t pc = y0 > s_rs[r] ? key_col(key[perm[y0 - 1]]) : 0;
+        for (int32_t y = y0; y < y1; ++y) {
+            while (s_rs[r + 1] <= y) ++r;
+            const int32_t c = key_col(key[perm[y]]);
+            const bool rs = y == s_rs[r];
+            if (rs) {
+                // this row and the empty rows just before it start at slot
+                if (v0 + r < m) rowoff[v0 + r] = slot;
+                for (int32_t q = r - 1; q >= 0 && s_rs[q] == y; --q)
+                    if (v0 + q < m) rowoff[v0 + q] = slot;
+            }
+            if (rs || c != pc) {
+                const int64_t o = e0 + slot;
+                stage_col[o] = c;
+                if (stage_cptr) stage_cptr[o] = static_cast<int32_t>(e0 + y);
+                if (has_val) {
+                    const int32_t e = s_rs[r + 1];
+                    double acc = static_cast<double>(val[perm[y]]);
+                    for (int32_t z = y + 1; z < e && key_col(key[perm[z]]) == c; ++z)
+                        acc += static_cast<double>(val[perm[z]]);
+                    stage_val[o] = acc;
+                }
+                ++slot;
+            }
+            pc = c;
         }
     }
+    // rows after the bucket's last triplet (and all rows of an empty bucket)
+    for (int32_t r = tid; r < R; r += SP_THREADS)
+        if (s_rs[r] == nb && v0 + r < m) rowoff[v0 + r] = T;
     if (tid == 0) btot[b] = T;
-    __syncthreads();
-    for (int32_t y = tid; y < nb; y += SP_THREADS) {
-        const int32_t r = row_of(s_rs, R, y);
-        const int32_t s = s_rs[r], e = s_rs[r + 1];
-        auto at = [&](int32_t z) { return s + static_cast<int32_t>(perm[z]); };
-        const int32_t p = at(y), c = col[p];
-        if (contrib) contrib[e0 + y] = tt[p];
-        if (y > s && col[at(y - 1)] == c) continue;   // not a run start
-        int32_t slot = 0;                              // run starts before y
-        for (int32_t z = s + 1; z <= y; ++z) slot += col[at(z)] != col[at(z - 1)] ? 1 : 0;
-        double acc = 0.0;
-        if (has_val)
-            for (int32_t z = y; z < e && col[at(z)] == c; ++z) acc += static_cast<double>(val[at(z)]);
-        const int64_t o = e0 + s_len[r] + slot;
-        stage_col[o] = c;
-        if (has_val) stage_val[o] = acc;
-        if (stage_cptr) stage_cptr[o] = static_cast<int32_t>(e0 + y);
-    }
 }
 
-// One workgroup per bucket whose triplets fit in LDS; larger buckets are
-// listed for k_sp_rows_big.
+// One workgroup per fine bucket slot (unused slots return at once); a bucket
+// whose triplets fit in LDS is done here, larger ones are listed for
+// k_sp_rows_big.
+template <bool HV>
 __global__ __launch_bounds__(SP_THREADS) void k_sp_rows(
-    int32_t m, int rs, const int32_t *__restrict__ fine_off, const int32_t *__restrict__ rl,
-    const int2 *__restrict__ ct, const double *__restrict__ rval, int has_val,
+    int32_t m, int32_t nbkt, int rc, int fshift, const int32_t *__restrict__ cshift,
+    const int32_t *__restrict__ fine_off, const int32_t *__restrict__ rl,
+    const int2 *__restrict__ ct, const double *__restrict__ rval,
     int32_t *__restrict__ stage_col,
     double *__restrict__ stage_val, int32_t *__restrict__ stage_cptr, int32_t *__restrict__ contrib,
     int32_t *__restrict__ rowoff, int32_t *__restrict__ btot, int32_t *__restrict__ big,
     SparseCounters *cnt) {
-    __shared__ int32_t s_col[SP_CAP], s_t[SP_CAP];
-    __shared__ double s_val[SP_CAP];
+    __shared__ uint64_t s_key[SP_CAP];
+    __shared__ double s_val[HV ? SP_CAP : 1];
     __shared__ uint16_t s_perm[SP_CAP];
     __shared__ int32_t s_rs[(1 << SP_RMAX_SHIFT) + 1];
     __shared__ int32_t s_len[1 << SP_RMAX_SHIFT];
     __shared__ int32_t s_wsum[SP_THREADS / WAVE];
     const int tid = threadIdx.x;
     const int32_t b = blockIdx.x;
-    const int32_t R = 1 << rs;
-    const int64_t e0 = fine_off[b], e1 = fine_off[b + 1];
-    const int32_t nb = static_cast<int32_t>(e1 - e0);
-    if (e1 - e0 > SP_CAP) {
-        if (tid == 0) big[atomicAdd(&cnt->big_count, 1)] = b;
-        return;
-    }
-    const int32_t v0 = b << rs;
-    // 1 the bucket's triplets into registers (all loads in flight), triplets
-    // per row, scan -> row starts
-    constexpr int EPT = (SP_CAP + SP_THREADS - 1) / SP_THREADS;
-    int32_t xr[EPT];
-    int2 xc[EPT];
-    double xv[EPT];
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        const int32_t x = tid + u * SP_THREADS;
-        xr[u] = x < nb ? rl[e0 + x] : -1;
-        xc[u] = x < nb ? ct[e0 + x] : make_int2(0, 0);
-        xv[u] = (has_val && x < nb) ? rval[e0 + x] : 0.0;
-    }
-    for (int32_t r = tid; r < R; r += SP_THREADS) s_len[r] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < EPT; ++u)
-        if (xr[u] >= 0) atomicAdd(&s_len[xr[u]], 1);
-    __syncthreads();
-    const int per = (R + SP_THREADS - 1) / SP_THREADS;
-    int32_t mine = 0, mx = 0;
-    for (int k = 0; k < per; ++k) {
-        const int32_t r = tid * per + k;
-        if (r < R) {
-            mine += s_len[r];
-            mx = max(mx, s_len[r]);
+    int32_t mxrow = 0;
+    {
+        int32_t v0, R;
+        fine_rows(b, rc, fshift, cshift, &v0, &R);
+        if (R == 0) {   // an unused slot of its coarse bucket
+            if (tid == 0) btot[b] = 0;
+            return;
         }
-    }
-    int32_t T;
-    int32_t run = block_scan_sp(mine, s_wsum, &T);
-    for (int k = 0; k < per; ++k) {
-        const int32_t r = tid * per + k;
-        if (r < R) {
-            const int32_t c = s_len[r];
-            s_rs[r] = run;
-            s_len[r] = run;   // cursor
-            run += c;
+        const int64_t e0 = fine_off[b], e1 = fine_off[b + 1];
+        const int32_t nb = static_cast<int32_t>(e1 - e0);
+        if (e1 - e0 > SP_CAP) {
+            if (tid == 0) big[atomicAdd(&cnt->big_count, 1)] = b;
+            return;
         }
-    }
-    if (tid == 0) s_rs[R] = nb;
+        // 1 the bucket's triplets into registers (all loads in flight),
+        // triplets per row, scan -> row starts
+        constexpr int EPT = (SP_CAP + SP_THREADS - 1) / SP_THREADS;
+        int32_t xr[EPT];
+        int2 xc[EPT];
+        double xv[HV ? EPT : 1];
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, WAVE));
-    if ((tid & (WAVE - 1)) == 0) max_into_sp(&cnt->max_row, mx);
-    __syncthreads();
-    // 2 counting sort by row into LDS
+        for (int u = 0; u < EPT; ++u) {
+            const int32_t x = tid + u * SP_THREADS;
+            xr[u] = x < nb ? rl[e0 + x] : -1;
+            xc[u] = x < nb ? ct[e0 + x] : make_int2(0, 0);
+            if constexpr (HV) xv[u] = x < nb ? rval[e0 + x] : 0.0;
+        }
+        for (int32_t r = tid; r < R; r += SP_THREADS) s_len[r] = 0;
+        __syncthreads();
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        if (xr[u] < 0) continue;
-        const int32_t p = atomicAdd(&s_len[xr[u]], 1);
-        s_col[p] = xc[u].x;
-        s_t[p] = xc[u].y;
-        if (has_val) s_val[p] = xv[u];
+        for (int u = 0; u < EPT; ++u)
+            if (xr[u] >= 0) atomicAdd(&s_len[xr[u]], 1);
+        __syncthreads();
+        const int per = (R + SP_THREADS - 1) / SP_THREADS;
+        int32_t mine = 0;
+        for (int k = 0; k < per; ++k) {
+            const int32_t r = tid * per + k;
+            if (r < R) {
+                mine += s_len[r];
+                mxrow = max(mxrow, s_len[r]);
+            }
+        }
+        int32_t T;
+        int32_t run = block_scan_sp(mine, s_wsum, &T);
+        for (int k = 0; k < per; ++k) {
+            const int32_t r = tid * per + k;
+            if (r < R) {
+                const int32_t c = s_len[r];
+                s_rs[r] = run;
+                s_len[r] = run;   // cursor
+                run += c;
+            }
+        }
+        if (tid == 0) s_rs[R] = nb;
+        __syncthreads();
+        // 2 counting sort by row into LDS
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            if (xr[u] < 0) continue;
+            const int32_t p = atomicAdd(&s_len[xr[u]], 1);
+            s_key[p] = sp_key(xc[u].x, xc[u].y);
+            if constexpr (HV) s_val[p] = xv[u];
+        }
+        __syncthreads();
+        sp_bucket_rows(R, nb, v0, m, e0, s_rs, s_key, s_val, s_perm, HV, s_wsum, stage_col, stage_val,
+                       stage_cptr, contrib, rowoff, btot, b);
     }
-    __syncthreads();
-    sp_bucket_rows(R, nb, v0, m, e0, s_rs, s_col, s_t, s_val, s_perm, has_val != 0, s_len, s_wsum,
-                   stage_col, stage_val, stage_cptr, contrib, rowoff, btot, b);
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) mxrow = max(mxrow, __shfl_xor(mxrow, o, WAVE));
+    if ((tid & (WAVE - 1)) == 0 && mxrow > 0) max_into_sp(&cnt->max_row, mxrow);
 }
 
 // Buckets listed by k_sp_rows (more than SP_CAP triplets): the same steps
-// with the triplets in global scratch (gcol, gt, gval at the bucket's own
+// with the triplets in global scratch (gkey, gval, gperm at the bucket's own
 // range [e0, e1)).  Slower, for skewed inputs only.
 __global__ __launch_bounds__(SP_THREADS) void k_sp_rows_big(
-    int32_t m, int rs, const int32_t *__restrict__ fine_off, const int32_t *__restrict__ rl,
+    int32_t m, int rc, int fshift, const int32_t *__restrict__ cshift,
+    const int32_t *__restrict__ fine_off, const int32_t *__restrict__ rl,
     const int2 *__restrict__ ct, const double *__restrict__ rval, int has_val,
-    int32_t *__restrict__ gcol,
-    int32_t *__restrict__ gt, double *__restrict__ gval, int32_t *__restrict__ gperm,
+    uint64_t *__restrict__ gkey, double *__restrict__ gval, int32_t *__restrict__ gperm,
     int32_t *__restrict__ stage_col,
     double *__restrict__ stage_val, int32_t *__restrict__ stage_cptr, int32_t *__restrict__ contrib,
     int32_t *__restrict__ rowoff, int32_t *__restrict__ btot, const int32_t *__restrict__ big,
@@ -508,12 +589,12 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_rows_big(
     __shared__ int32_t s_wsum[SP_THREADS / WAVE];
     const int tid = threadIdx.x;
     const int32_t nbig = cnt->big_count;
-    const int32_t R = 1 << rs;
     for (int32_t q = blockIdx.x; q < nbig; q += gridDim.x) {
         const int32_t b = big[q];
         const int64_t e0 = fine_off[b], e1 = fine_off[b + 1];
         const int32_t nb = static_cast<int32_t>(e1 - e0);
-        const int32_t v0 = b << rs;
+        int32_t v0, R;
+        fine_rows(b, rc, fshift, cshift, &v0, &R);
         for (int32_t r = tid; r < R; r += SP_THREADS) s_len[r] = 0;
         __syncthreads();
         for (int32_t x = tid; x < nb; x += SP_THREADS) atomicAdd(&s_len[rl[e0 + x]], 1);
@@ -543,50 +624,52 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_rows_big(
         for (int o = WAVE / 2; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, WAVE));
         if ((tid & (WAVE - 1)) == 0) max_into_sp(&cnt->max_row, mx);
         __syncthreads();
-        int32_t *bc = gcol + e0;
-        int32_t *bt = gt + e0;
+        uint64_t *bk = gkey + e0;
         double *bv = gval + e0;
         for (int32_t x = tid; x < nb; x += SP_THREADS) {
             const int2 c = ct[e0 + x];
             const int32_t p = atomicAdd(&s_len[rl[e0 + x]], 1);
-            bc[p] = c.x;
-            bt[p] = c.y;
+            bk[p] = sp_key(c.x, c.y);
             if (has_val) bv[p] = rval[e0 + x];
         }
         __syncthreads();
-        sp_bucket_rows(R, nb, v0, m, e0, s_rs, bc, bt, bv, gperm + e0, has_val != 0, s_len, s_wsum,
-                       stage_col, stage_val, stage_cptr, contrib, rowoff, btot, b);
+        sp_bucket_rows(R, nb, v0, m, e0, s_rs, bk, bv, gperm + e0, has_val != 0, s_wsum, stage_col,
+                       stage_val, stage_cptr, contrib, rowoff, btot, b);
         __syncthreads();
     }
 }
 
 // Bucket b's staged rows to col_idx / values / contrib_ptr at bptr[b], and
-// row_ptr of its rows.
+// row_ptr of its rows (workgroups loop over the slots).
 __global__ __launch_bounds__(SP_THREADS) void k_sp_copy(
-    int32_t m, int32_t nbkt, int rs, const int32_t *__restrict__ fine_off,
+    int32_t m, int32_t nbkt, int rc, int fshift, const int32_t *__restrict__ cshift,
+    const int32_t *__restrict__ fine_off,
     const int32_t *__restrict__ bptr, const int32_t *__restrict__ rowoff,
     const int32_t *__restrict__ stage_col, const double *__restrict__ stage_val,
     const int32_t *__restrict__ stage_cptr, int32_t *__restrict__ row_ptr,
     int32_t *__restrict__ col_idx, double *__restrict__ vals, int32_t *__restrict__ contrib_ptr,
     int64_t col_cap, int64_t nt, SparseCounters *cnt) {
-    const int32_t b = blockIdx.x;
-    const int64_t e0 = fine_off[b];
-    const int32_t v0 = b << rs, R = 1 << rs;
-    const int32_t P = bptr[b], T = bptr[b + 1] - P;
-    for (int32_t r = threadIdx.x; r < R; r += SP_THREADS)
-        if (v0 + r < m) row_ptr[v0 + r] = P + rowoff[v0 + r];
-    if (b == nbkt - 1 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         row_ptr[m] = bptr[nbkt];
         if (contrib_ptr && bptr[nbkt] <= col_cap) contrib_ptr[bptr[nbkt]] = static_cast<int32_t>(nt);
     }
-    if (P + (int64_t)T > col_cap) {
-        if (threadIdx.x == 0) atomicOr(&cnt->err, SP_ERR_NOSPC);
-        return;
-    }
-    for (int32_t x = threadIdx.x; x < T; x += SP_THREADS) {
-        col_idx[P + x] = stage_col[e0 + x];
-        if (vals) vals[P + x] = stage_val[e0 + x];
-        if (contrib_ptr) contrib_ptr[P + x] = stage_cptr[e0 + x];
+    for (int32_t b = blockIdx.x; b < nbkt; b += gridDim.x) {
+        int32_t v0, R;
+        fine_rows(b, rc, fshift, cshift, &v0, &R);
+        if (R == 0) continue;
+        const int64_t e0 = fine_off[b];
+        const int32_t P = bptr[b], T = bptr[b + 1] - P;
+        for (int32_t r = threadIdx.x; r < R; r += SP_THREADS)
+            if (v0 + r < m) row_ptr[v0 + r] = P + rowoff[v0 + r];
+        if (P + (int64_t)T > col_cap) {
+            if (threadIdx.x == 0) atomicOr(&cnt->err, SP_ERR_NOSPC);
+            continue;
+        }
+        for (int32_t x = threadIdx.x; x < T; x += SP_THREADS) {
+            col_idx[P + x] = stage_col[e0 + x];
+            if (vals) vals[P + x] = stage_val[e0 + x];
+            if (contrib_ptr) contrib_ptr[P + x] = stage_cptr[e0 + x];
+        }
     }
 }
 
@@ -605,10 +688,11 @@ __global__ __launch_bounds__(256) void k_sp_values(int64_t nnz, const int32_t *_
 }
 
 struct SparsePlan {
-    int rf, rc;            // log2 rows per fine / coarse bucket
-    int32_t nbkt_f, nbkt_c, nblk;
+    int rf, rc;            // log2 rows per fine bucket at the average density / per coarse bucket
+    int rmin, rmax;        // log2 rows per fine bucket: the range the split chooses from
+    int32_t nbkt_f, nbkt_c, nblk;   // nbkt_f: fine bucket slots, 2^(rc - rmin) per coarse bucket
     int64_t tpb;
-    int nf_shift() const { return rc - rf; }
+    int fshift() const { return rc - rmin; }
     int64_t ncounts() const { return (int64_t)nbkt_c * nblk; }
 };
 
@@ -627,10 +711,14 @@ bool plan_sparse(int32_t m, int64_t nt, SparsePlan *p) {
         --rc;
     if (rc - rf > SP_SPLIT_MAX_SHIFT) rf = rc - SP_SPLIT_MAX_SHIFT;
     if (rf > SP_RMAX_SHIFT) return false;
+    int rmin = rf > SP_ADAPT_SHIFT ? rf - SP_ADAPT_SHIFT : 0;
+    if (rc - rmin > SP_SPLIT_MAX_SHIFT) rmin = rc - SP_SPLIT_MAX_SHIFT;
     p->rf = rf;
     p->rc = rc;
-    p->nbkt_f = (int32_t)(((int64_t)m + (1ll << rf) - 1) >> rf);
+    p->rmin = rmin;
+    p->rmax = rc < SP_RMAX_SHIFT ? rc : SP_RMAX_SHIFT;
     p->nbkt_c = (int32_t)(((int64_t)m + (1ll << rc) - 1) >> rc);
+    p->nbkt_f = p->nbkt_c << (rc - rmin);
     int64_t tpb = (nt + SP_NBLK_TARGET - 1) / SP_NBLK_TARGET;
     tpb = (tpb + SPP_THREADS - 1) / SPP_THREADS * SPP_THREADS;
     if (tpb < SPP_THREADS) tpb = SPP_THREADS;
@@ -642,8 +730,9 @@ bool plan_sparse(int32_t m, int64_t nt, SparsePlan *p) {
 
 struct SparseWork {
     SparseCounters *cnt;
-    int32_t *counts, *rl, *rl2, *gcol, *gt, *gperm, *stage_col, *stage_cptr, *rowoff, *btot, *bptr,
-        *big, *fine_off;
+    int32_t *counts, *rl, *rl2, *gperm, *stage_col, *stage_cptr, *rowoff, *btot, *bptr,
+        *big, *fine_off, *cshift;
+    uint64_t *gkey;
     int2 *ct, *ct2;
     double *rval, *rval2, *gval, *stage_val;
     long long *part;
@@ -669,16 +758,16 @@ SparseWork carve_sparse(int32_t m, int64_t nt, const SparsePlan &P, char *base) 
     w.btot = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(P.nbkt_f + 1)));
     w.bptr = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(P.nbkt_f + 1)));
     w.big = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)P.nbkt_f));
+    w.cshift = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)P.nbkt_c));
     w.rowoff = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
     w.rl = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc));
     w.ct = reinterpret_cast<int2 *>(take(sizeof(int2) * ntc));
     w.rval = reinterpret_cast<double *>(take(sizeof(double) * ntc));
-    const bool split = P.nf_shift() > 0;
+    const bool split = P.fshift() > 0;
     w.rl2 = split ? reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc)) : w.rl;
     w.ct2 = split ? reinterpret_cast<int2 *>(take(sizeof(int2) * ntc)) : w.ct;
     w.rval2 = split ? reinterpret_cast<double *>(take(sizeof(double) * ntc)) : w.rval;
-    w.gcol = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc));
-    w.gt = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc));
+    w.gkey = reinterpret_cast<uint64_t *>(take(sizeof(uint64_t) * ntc));
     w.gperm = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc));
     w.gval = reinterpret_cast<double *>(take(sizeof(double) * ntc));
     w.stage_col = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * ntc));
@@ -746,27 +835,39 @@ extern "C" int fem_sparse(int32_t m, int32_t n, int64_t nt, const int32_t *I, co
         FEM_LAUNCH_CHECK();
     }
     const int32_t *total_ptr = W.counts + P.ncounts();
-    if (P.nf_shift() > 0) {
+    const int32_t *cshift = P.fshift() > 0 ? W.cshift : nullptr;
+    if (P.fshift() > 0) {
         hipLaunchKernelGGL(k_sp_split, dim3(P.nbkt_c), dim3(SPP_THREADS),
-                           tile_lds_bytes(1 << P.nf_shift()), s, P.nbkt_c, P.nblk,
-                           P.nbkt_f, P.rf, P.nf_shift(), W.counts, total_ptr, W.rl, W.ct, W.rval,
-                           has_val ? 1 : 0, W.rl2, W.ct2, W.rval2, W.fine_off);
+                           tile_lds_bytes(1 << P.fshift()), s, P.nbkt_c, P.nblk, P.rc, P.rmin,
+                           P.rmax, W.counts, total_ptr, W.rl, W.ct, W.rval, has_val ? 1 : 0, W.rl2,
+                           W.ct2, W.rval2, W.fine_off, W.cshift);
     } else {
         hipLaunchKernelGGL(k_sp_fine_off, dim3(grid_for((int64_t)P.nbkt_f + 1, 256)), dim3(256), 0, s,
                            P.nbkt_f, P.nblk, W.counts, total_ptr, W.fine_off);
     }
     FEM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sp_rows, dim3(P.nbkt_f), dim3(SP_THREADS), 0, s, m, P.rf, W.fine_off,
-                       W.rl2, W.ct2, W.rval2, has_val ? 1 : 0, W.stage_col, W.stage_val,
-                       contrib_ptr ? W.stage_cptr : nullptr, contrib, W.rowoff, W.btot, W.big, W.cnt);
+    const unsigned grows = (unsigned)P.nbkt_f;
+    if (has_val)
+        hipLaunchKernelGGL(k_sp_rows<true>, dim3(grows), dim3(SP_THREADS), 0, s, m, P.nbkt_f, P.rc,
+                           P.fshift(), cshift, W.fine_off, W.rl2, W.ct2, W.rval2, W.stage_col,
+                           W.stage_val, contrib_ptr ? W.stage_cptr : nullptr, contrib, W.rowoff, W.btot,
+                           W.big, W.cnt);
+    else
+        hipLaunchKernelGGL(k_sp_rows<false>, dim3(grows), dim3(SP_THREADS), 0, s, m, P.nbkt_f, P.rc,
+                           P.fshift(), cshift, W.fine_off, W.rl2, W.ct2, W.rval2, W.stage_col,
+                           W.stage_val, contrib_ptr ? W.stage_cptr : nullptr, contrib, W.rowoff, W.btot,
+                           W.big, W.cnt);
     FEM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sp_rows_big, dim3(256), dim3(SP_THREADS), 0, s, m, P.rf, W.fine_off, W.rl2,
-                       W.ct2, W.rval2, has_val ? 1 : 0, W.gcol, W.gt, W.gval, W.gperm, W.stage_col, W.stage_val,
+    hipLaunchKernelGGL(k_sp_rows_big, dim3(256), dim3(SP_THREADS), 0, s, m, P.rc, P.fshift(), cshift,
+                       W.fine_off, W.rl2,
+                       W.ct2, W.rval2, has_val ? 1 : 0, W.gkey, W.gval, W.gperm, W.stage_col, W.stage_val,
                        contrib_ptr ? W.stage_cptr : nullptr, contrib, W.rowoff, W.btot, W.big, W.cnt);
     FEM_LAUNCH_CHECK();
     if ((st = exclusive_scan_i32(W.btot, W.bptr, P.nbkt_f, W.part, &W.cnt->total[1], &W.cnt->err, s)))
         return st;
-    hipLaunchKernelGGL(k_sp_copy, dim3(P.nbkt_f), dim3(SP_THREADS), 0, s, m, P.nbkt_f, P.rf,
+    const unsigned gcopy = (unsigned)(P.nbkt_f < SP_COPY_GRID ? P.nbkt_f : SP_COPY_GRID);
+    hipLaunchKernelGGL(k_sp_copy, dim3(gcopy), dim3(SP_THREADS), 0, s, m, P.nbkt_f, P.rc,
+                       P.fshift(), cshift,
                        W.fine_off, W.bptr, W.rowoff, W.stage_col, has_val ? W.stage_val : nullptr,
                        W.stage_cptr, row_ptr, col_idx, vals, contrib_ptr, col_cap, nt, W.cnt);
     FEM_LAUNCH_CHECK();

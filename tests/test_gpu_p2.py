@@ -1,0 +1,194 @@
+"""GPU P2 triangles (mass, stiffness) against the oracle, through the C ABI.
+
+DOFs, edges, pattern and contributor lists bit-exact; values within 1e-13 per
+row (max norm): both sides add the same triplets in the same order
+(ascending t) and differ only in the rounding of the element matrices."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1305_3122_amd import meshgen as mg
+from tests.helpers import RTOL_ROW, fan_mesh, row_rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1305_3122_amd as fem  # noqa: E402
+from paper_1305_3122_amd import _lib  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _up(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def p2_triplets(dofs):
+    """Ig, Jg of the 36 local entries, t = r nme + k, r = 6 b + a."""
+    a = np.tile(np.arange(6), 6)
+    b = np.repeat(np.arange(6), 6)
+    return dofs[:, a].T.reshape(-1).astype(np.int32), dofs[:, b].T.reshape(-1).astype(np.int32)
+
+
+def _check(m, contrib=True):
+    pat = fem.fem_p2_pattern(_up(m.me), m.nq)
+    q = _up(m.q)
+    both = fem.fem_p2_assemble(pat, q)
+    onlyM = fem.fem_p2_assemble(pat, q, fem.FEM_OP_MASS)["M"]
+    onlyS = fem.fem_p2_assemble(pat, q, fem.FEM_OP_STIFF)["S"]
+    torch.cuda.synchronize()
+    rp, ci, M, dofs, edges = oracle.assemble_p2("mass", m.q, m.me)
+    _, _, S, _, _ = oracle.assemble_p2("stiff", m.q, m.me)
+    assert pat.ne == edges.shape[0]
+    np.testing.assert_array_equal(_np(pat.dofs), dofs)
+    np.testing.assert_array_equal(_np(pat.edges), edges)
+    assert pat.nnz == ci.shape[0]
+    np.testing.assert_array_equal(_np(pat.row_ptr), rp)
+    np.testing.assert_array_equal(_np(pat.col_idx), ci)
+    if contrib:
+        I, J = p2_triplets(dofs)
+        _, _, pos = oracle.sparse_positions(I, J, pat.ndof, pat.ndof)
+        np.testing.assert_array_equal(_np(pat.contrib), np.argsort(pos, kind="stable"))
+        np.testing.assert_array_equal(
+            _np(pat.contrib_ptr), np.concatenate([[0], np.cumsum(np.bincount(pos, minlength=pat.nnz))]))
+    assert row_rel_err(rp, _np(both["M"]), M) <= RTOL_ROW
+    assert row_rel_err(rp, _np(both["S"]), S) <= RTOL_ROW
+    # one pass for both operators adds the same terms as the single ones
+    assert torch.equal(both["M"], onlyM) and torch.equal(both["S"], onlyS)
+    return pat, both
+
+
+def _cases():
+    out = [("square1", mg.unit_square(1, seed=1)), ("square3_flat", mg.unit_square(3, jitter=0.0, seed=2)),
+           ("square7", mg.unit_square(7, seed=3)), ("disk5", mg.unit_disk(5, seed=4))]
+    for n_fan in (12, 40):
+        q, me = fan_mesh(n_fan, 2, seed=n_fan)
+        out.append((f"fan{n_fan}", mg.Mesh(q, me, "fan")))
+    rng = np.random.default_rng(91)
+    for s in range(3):
+        out.append((f"tiny{s}", mg.random_tiny_mesh(np.random.default_rng(rng.integers(1 << 30)))))
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name,m", CASES, ids=[n for n, _ in CASES])
+def test_p2_matches_oracle(name, m):
+    print(f"[case] p2 {name} nq={m.nq} nme={m.nme}", flush=True)
+    _check(m)
+
+
+def test_p2_square96_full_parity_and_accumulate():
+    # several tiles of every kernel and a ragged tail (nnz not a multiple of 256)
+    m = mg.unit_square(96, seed=mg.BASE_SEED + 96)
+    print(f"[case] p2 square96 nq={m.nq} nme={m.nme}", flush=True)
+    pat, both = _check(m, contrib=False)
+    assert pat.nnz % 256 != 0
+    out = {"M": both["M"].clone(), "S": both["S"].clone()}
+    fem.fem_p2_assemble(pat, _up(m.q), out=out, flags=fem.FEM_ACCUMULATE)
+    torch.cuda.synchronize()
+    assert torch.equal(out["M"], 2 * both["M"]) and torch.equal(out["S"], 2 * both["S"])
+
+
+def _row_ids(rp, n):
+    rp = rp.long()
+    return torch.repeat_interleave(torch.arange(n, device=DEV), rp[1:] - rp[:-1])
+
+
+def test_p2_full_size():
+    # the 2048^2 square (8.4M triangles, 302M triplets): Euler's count of the
+    # edges, the closed form of nnz, the area, the null space of S, the
+    # exactness of P2 for a quadratic field, and rows computed one by one from
+    # the oracle's element matrices
+    n = 2048
+    m = mg.config_mesh(2)
+    print(f"[case] p2 cfg2 nq={m.nq} nme={m.nme}", flush=True)
+    pat = fem.fem_p2_pattern(_up(m.me), m.nq)
+    q = _up(m.q)
+    vals = fem.fem_p2_assemble(pat, q)
+    torch.cuda.synchronize()
+    assert pat.ne == 3 * n * n + 2 * n
+    e_int = pat.ne - 4 * n
+    assert pat.nnz == pat.ndof + 2 * (15 * m.nme - 3 * e_int)
+    M, S = vals["M"], vals["S"]
+    assert float(M.sum()) == pytest.approx(1.0, rel=1e-11)
+    rows = _row_ids(pat.row_ptr, pat.ndof)
+    cols = pat.col_idx.long()
+    rs = torch.zeros(pat.ndof, dtype=torch.float64, device=DEV).index_add_(0, rows, S)
+    diag = S[rows == cols]               # positive, the scale of its row
+    assert diag.numel() == pat.ndof
+    assert float((rs.abs() / diag).max()) <= 1e-12
+    # u = 1 + x - 2y + 3x^2 - xy + 0.5y^2 at the vertices and edge midpoints
+    e = pat.edges.long()
+    pts = torch.cat([q, (q[e[:, 0]] + q[e[:, 1]]) / 2])
+    x, y = pts[:, 0], pts[:, 1]
+    u = 1 + x - 2 * y + 3 * x * x - x * y + 0.5 * y * y
+    Mu = torch.zeros(pat.ndof, dtype=torch.float64, device=DEV).index_add_(0, rows, M * u[cols])
+    Su = torch.zeros(pat.ndof, dtype=torch.float64, device=DEV).index_add_(0, rows, S * u[cols])
+    # exact integrals over [0, 1]^2 of u^2 and |grad u|^2
+    c = {(0, 0): 1.0, (1, 0): 1.0, (0, 1): -2.0, (2, 0): 3.0, (1, 1): -1.0, (0, 2): 0.5}
+    ux = {(0, 0): 1.0, (1, 0): 6.0, (0, 1): -1.0}
+    uy = {(0, 0): -2.0, (1, 0): -1.0, (0, 1): 1.0}
+
+    def isq(a, b):
+        return sum(ca * cb / ((i1 + i2 + 1) * (j1 + j2 + 1))
+                   for (i1, j1), ca in a.items() for (i2, j2), cb in b.items())
+
+    assert float(u @ Mu) == pytest.approx(isq(c, c), rel=1e-11)
+    assert float(u @ Su) == pytest.approx(isq(ux, ux) + isq(uy, uy), rel=1e-10)
+    # sampled rows, one by one, from the oracle's DOF numbering and element
+    # matrices, summed in ascending t = (6 b + a) nme + k
+    dofs, edges = oracle.p2_dofs(m.nq, m.me)
+    np.testing.assert_array_equal(_np(pat.dofs), dofs)
+    rph, cih = _np(pat.row_ptr), _np(pat.col_idx)
+    Mh, Sh = _np(M), _np(S)
+    rng = np.random.default_rng(2048)
+    sample = np.concatenate([rng.choice(m.nq, 16, replace=False),
+                             m.nq + rng.choice(pat.ne, 16, replace=False)])
+    for d in sample:
+        ks, As = np.nonzero(dofs == d)
+        trip = []
+        for k, a in zip(ks, As):
+            xk = m.q[m.me[k]]
+            EM = oracle.elem_p2_mass(abs(oracle.det(*xk)) / 2)
+            ES = oracle.elem_p2_stiff(*xk)
+            for b in range(6):
+                trip.append(((6 * b + a) * m.nme + k, dofs[k, b], EM[a, b], ES[a, b]))
+        trip.sort()
+        cols_ref = sorted({t[1] for t in trip})
+        got_cols = cih[rph[d]:rph[d + 1]]
+        np.testing.assert_array_equal(got_cols, cols_ref)
+        refM = np.zeros(len(cols_ref))
+        refS = np.zeros(len(cols_ref))
+        for _, col, vm, vs in trip:
+            j = cols_ref.index(col)
+            refM[j] += vm
+            refS[j] += vs
+        gM, gS = Mh[rph[d]:rph[d + 1]], Sh[rph[d]:rph[d + 1]]
+        assert np.abs(gM - refM).max() <= RTOL_ROW * np.abs(refM).max(), d
+        assert np.abs(gS - refS).max() <= RTOL_ROW * np.abs(refS).max(), d
+
+
+def test_p2_errors_and_empty():
+    q = np.zeros((5, 2))
+    with pytest.raises(fem.FemError) as e:
+        fem.fem_p2_pattern(_up(np.array([[0, 1, 5]], np.int32)), 5)
+    assert e.value.status == _lib.FEM_ERANGE
+    with pytest.raises(fem.FemError) as e:
+        fem.fem_p2_pattern(_up(np.array([[0, 1, 2], [0, 3, 3]], np.int32)), 5)
+    assert e.value.status == _lib.FEM_EDEGEN
+    pat = fem.fem_p2_pattern(torch.zeros((0, 3), dtype=torch.int32, device=DEV), 5)
+    vals = fem.fem_p2_assemble(pat, _up(q))
+    torch.cuda.synchronize()
+    assert pat.ne == 0 and pat.nnz == 0 and vals["M"].numel() == 0
+    np.testing.assert_array_equal(_np(pat.row_ptr), np.zeros(6, np.int32))
+    # and the library keeps working
+    _check(mg.unit_square(2, seed=8))
