@@ -69,6 +69,8 @@ CALL_KERNEL = {
 PROFILE_SOURCES = {
     "step_square2048": ("fem_common.hip", "fem_internal.h", "fem_pattern.hip", "fem_numeric.hip"),
     "sparse_optv2_square2048": ("fem_common.hip", "fem_internal.h", "fem_sparse.hip"),
+    "p2_square2048": ("fem_common.hip", "fem_internal.h", "fem_sparse.hip", "fem_p2.hip"),
+    "tet_cube128": ("fem_common.hip", "fem_internal.h", "fem_sparse.hip", "fem_tet.hip"),
 }
 
 
@@ -131,6 +133,17 @@ PROFILE_TITLES = {
                                 "triplets, random FP64 values) compressed to the 29,372,417-entry CSR; calls with\n"
                                 "and without contributor lists, and re-summations (fem_sparse_values).  The 1 GiB\n"
                                 "fill and copy calibrate the counters."),
+    "p2_square2048": ("P2 triangles on the 2048x2048-cell unit square",
+                      "Workload: 8,388,608 triangles, 4,198,401 vertices + 12,587,008 edges = 16,785,409\n"
+                      "P2 DOFs (jitter 0.2h, random vertex relabelling), nnz 192,970,753; 5 edge\n"
+                      "numberings (25.2M side triplets), 6 patterns (302M triplets), 11 mass + stiffness\n"
+                      "assemblies; FP64 values, int32 indices.  The 1 GiB fill and copy calibrate the\n"
+                      "counters."),
+    "tet_cube128": ("P1 tetrahedra on the 128^3-cell unit cube",
+                    "Workload: 12,582,912 Kuhn tetrahedra, 2,146,689 vertices (jitter 0.1h, random\n"
+                    "relabelling), nnz 31,802,497; 5 patterns (201M triplets), 11 mass + stiffness\n"
+                    "assemblies; FP64 values, int32 indices.  The 1 GiB fill and copy calibrate the\n"
+                    "counters."),
 }
 
 
