@@ -565,64 +565,88 @@ __global__ __launch_bounds__(WAVE) void k_rows_reg(
             }
         }
         if (!in_regs && active && len > 0) {
-            // ---- long row or tile too large: the lane's own row in global
-            // memory, same order of additions.  The tile stores above wrote 0
-            // (or added 0) at this row, and the workgroup barrier after them
-            // made those stores complete before these.
-            double *os[NSA];
-#pragma unroll
-            for (int m = 0; m < NSA; ++m) os[m] = m < NS ? out.o[m] + rs : nullptr;
-            double *ok = O::K ? out.o[3] + 4 * (int64_t)rs : nullptr;
-            if (!accumulate) {
-                for (int e = 0; e < len; ++e) {
-#pragma unroll
-                    for (int m = 0; m < NS; ++m) os[m][e] = 0.0;
-                }
-                if constexpr (O::K)
-                    for (int e = 0; e < 4 * len; ++e) ok[e] = 0.0;
-            }
+            // ---- long row or tile too large: the lane's own row, LMAX
+            // entries at a time in registers.  Each chunk is summed from zero
+            // over the triangles in the same order as the register path, then
+            // stored (or added), so a row's values do not depend on the path
+            // it takes.  The tile stores above wrote 0 (or added 0) at this
+            // row, and the workgroup barrier after them made those stores
+            // complete before these.
             const int32_t *cr = col_idx + rs;
             int32_t pd = 0;
             while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
             const double x0 = q[2 * i], y0 = q[2 * i + 1];
             const double w0 = O::W ? w[i] : 0.0;
-            double dg[NSA], dk[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int32_t c0 = 0; c0 < len; c0 += LMAX) {
+                double ch[NV][LMAX];
 #pragma unroll
-            for (int m = 0; m < NSA; ++m) dg[m] = 0.0;
-            for (int32_t t = is; t < ie; ++t) {
-                const uint32_t pp = inc_pos[t];
-                const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
-                const int64_t j1 = cr[p1], j2 = cr[p2];
-                double c[NSA][3];
-                double ce[3][4];
-                elem_row<MASK>(x0, y0, q[2 * j1], q[2 * j1 + 1], q[2 * j2], q[2 * j2 + 1], w0,
-                               O::W ? w[j1] : 0.0, O::W ? w[j2] : 0.0, L, c, ce);
+                for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int m = 0; m < NS; ++m) {
-                    dg[m] += c[m][0];
-                    os[m][p1] += c[m][1];
-                    os[m][p2] += c[m][2];
+                    for (int k = 0; k < LMAX; ++k) ch[v][k] = 0.0;
+                double dg[NSA], dk[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int m = 0; m < NSA; ++m) dg[m] = 0.0;
+                for (int32_t t = is; t < ie; ++t) {
+                    const uint32_t pp = inc_pos[t];
+                    const int32_t p1 = (int32_t)(pp & 0xffffu) - c0, p2 = (int32_t)(pp >> 16) - c0;
+                    const int64_t j1 = cr[p1 + c0], j2 = cr[p2 + c0];
+                    double c[NSA][3];
+                    double ce[3][4];
+                    elem_row<MASK>(x0, y0, q[2 * j1], q[2 * j1 + 1], q[2 * j2], q[2 * j2 + 1], w0,
+                                   O::W ? w[j1] : 0.0, O::W ? w[j2] : 0.0, L, c, ce);
+#pragma unroll
+                    for (int m = 0; m < NS; ++m) dg[m] += c[m][0];
+                    if constexpr (O::K) {
+#pragma unroll
+                        for (int z = 0; z < 4; ++z) dk[z] += ce[0][z];
+                    }
+#pragma unroll
+                    for (int k = 0; k < LMAX; ++k) {
+                        const bool h1 = k == p1, h2 = k == p2;
+#pragma unroll
+                        for (int m = 0; m < NS; ++m) {
+                            const double a = h1 ? c[m][1] : (h2 ? c[m][2] : 0.0);
+                            ch[m][k] += a;
+                        }
+                        if constexpr (O::K) {
+#pragma unroll
+                            for (int z = 0; z < 4; ++z) {
+                                const double a = h1 ? ce[1][z] : (h2 ? ce[2][z] : 0.0);
+                                ch[NS + z][k] += a;
+                            }
+                        }
+                    }
                 }
-                if constexpr (O::K) {
 #pragma unroll
-                    for (int z = 0; z < 4; ++z) dk[z] += ce[0][z];
-                    ok[2 * p1] += ce[1][0];
-                    ok[2 * p1 + 1] += ce[1][1];
-                    ok[2 * len + 2 * p1] += ce[1][2];
-                    ok[2 * len + 2 * p1 + 1] += ce[1][3];
-                    ok[2 * p2] += ce[2][0];
-                    ok[2 * p2 + 1] += ce[2][1];
-                    ok[2 * len + 2 * p2] += ce[2][2];
-                    ok[2 * len + 2 * p2 + 1] += ce[2][3];
+                for (int k = 0; k < LMAX; ++k) {
+                    const int32_t e = c0 + k;
+                    if (e >= len) break;
+                    if (e == pd) {
+#pragma unroll
+                        for (int m = 0; m < NS; ++m) ch[m][k] += dg[m];
+                        if constexpr (O::K) {
+#pragma unroll
+                            for (int z = 0; z < 4; ++z) ch[NS + z][k] += dk[z];
+                        }
+                    }
+#pragma unroll
+                    for (int m = 0; m < NS; ++m) {
+                        double *o = out.o[m] + rs + e;
+                        if (accumulate) *o += ch[m][k];
+                        else *o = ch[m][k];
+                    }
+                    if constexpr (O::K) {
+                        // row 2i: [4 rs + 2e + beta], row 2i+1: [4 rs + 2 len + 2e + beta]
+                        double *ok = out.o[3] + 4 * (int64_t)rs;
+                        const double kv[4] = {ch[NS][k], ch[NS + 1][k], ch[NS + 2][k], ch[NS + 3][k]};
+                        const int64_t at[4] = {2 * e, 2 * e + 1, 2 * len + 2 * e, 2 * len + 2 * e + 1};
+#pragma unroll
+                        for (int z = 0; z < 4; ++z) {
+                            if (accumulate) ok[at[z]] += kv[z];
+                            else ok[at[z]] = kv[z];
+                        }
+                    }
                 }
-            }
-#pragma unroll
-            for (int m = 0; m < NS; ++m) os[m][pd] += dg[m];
-            if constexpr (O::K) {
-                ok[2 * pd] += dk[0];
-                ok[2 * pd + 1] += dk[1];
-                ok[2 * len + 2 * pd] += dk[2];
-                ok[2 * len + 2 * pd + 1] += dk[3];
             }
         }
     }

@@ -937,8 +937,8 @@ __global__ __launch_bounds__(WAVE) void k_elas_pattern(int32_t nq, const int32_t
     __syncthreads();
     if (lane < nr) {
         const int32_t rs = s_rs[lane], L = s_rs[lane + 1] - rs;
-        row_ptr_e[2 * i] = 4 * rs;
-        row_ptr_e[2 * i + 1] = 4 * rs + 2 * L;
+        __builtin_nontemporal_store(4 * rs, row_ptr_e + 2 * i);
+        __builtin_nontemporal_store(4 * rs + 2 * L, row_ptr_e + 2 * i + 1);
     }
     if (r0 + nr == nq && lane == 0) row_ptr_e[2 * (int64_t)nq] = 4 * s_rs[nr];
     const int32_t E0 = s_rs[0], Ew = s_rs[nr] - E0;
@@ -964,9 +964,10 @@ __global__ __launch_bounds__(WAVE) void k_elas_pattern(int32_t nq, const int32_t
     }
     if (staged) {
         __syncthreads();
-        int4 *dst = reinterpret_cast<int4 *>(col_idx_e + 4 * (int64_t)E0);
-        const int4 *src = reinterpret_cast<const int4 *>(s_out);
-        for (int32_t t = lane; t < Ew; t += WAVE) dst[t] = src[t];
+        typedef int v4i __attribute__((ext_vector_type(4)));
+        v4i *dst = reinterpret_cast<v4i *>(col_idx_e + 4 * (int64_t)E0);
+        const v4i *src = reinterpret_cast<const v4i *>(s_out);
+        for (int32_t t = lane; t < Ew; t += WAVE) __builtin_nontemporal_store(src[t], dst + t);
     }
 }
 

@@ -159,6 +159,27 @@ def test_deterministic_bitwise_and_accumulate():
     assert torch.equal(K2, 2 * K)
 
 
+@pytest.mark.parametrize("n_fan", [12, 40, 700])
+def test_long_rows_accumulate_bitwise(n_fan):
+    # rows longer than the register path (the hub of a fan, and a row longer
+    # than a whole tile at 700) are summed in register chunks from zero, so
+    # accumulating twice gives exactly 2x on every path, and a tile too small
+    # for any row gives the same bits as the default
+    q, me = fan_mesh(n_fan, 2, seed=n_fan)
+    pat = fem.fem_pattern(_up(me), q.shape[0])
+    qd = _up(q)
+    w = _up(mg.weight_quadratic(q))
+    ops = fem.FEM_OP_MASS | fem.FEM_OP_WMASS | fem.FEM_OP_STIFF | fem.FEM_OP_ELAS
+    a = fem.fem_assemble(pat, qd, ops, w=w, lam=1.3, mu=0.7)
+    b = {k: v.clone() for k, v in a.items()}
+    fem.fem_assemble(pat, qd, ops, w=w, lam=1.3, mu=0.7, out=b, flags=fem.FEM_ACCUMULATE)
+    c = fem.fem_assemble(pat, qd, ops, w=w, lam=1.3, mu=0.7, tune=fem.fem_tune(256, 0))
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(b[k], 2 * a[k]), k
+        assert torch.equal(c[k], a[k]), k
+
+
 def test_small_lds_tile_takes_the_global_memory_path():
     # lds_entries = 256 < 64 rows x ~7 entries: every tile uses the fallback
     m = mg.unit_square(40, seed=2)
