@@ -68,11 +68,15 @@ enum {
     FEM_ATOMIC = 1,        /* one lane per triangle, FP64 atomic adds through the slot map
                               (needs me and slot); order of additions unspecified */
     FEM_ACCUMULATE = 2,    /* add into values instead of overwriting them */
-    FEM_PACKED_QW = 4      /* fem_adjoint_stiff_wmass only: the first 32 nq bytes of its
+    FEM_PACKED_QW = 4,     /* fem_adjoint_stiff_wmass only: the first 32 nq bytes of its
                               workspace already hold the (x, y, w, 0) record of every vertex
                               for these q and w, as fem_assemble leaves them in its own
                               workspace when it assembles Mw (pass the same buffer to both);
                               the packing pass is skipped */
+    FEM_CHECK_AREA = 8     /* fem_assemble only: also test every triangle for zero area
+                              (det = (q2-q3) x (q3-q1) == 0, where the element formulas
+                              divide by zero) and return FEM_EDEGEN if one has it; uses the
+                              workspace of fem_assemble_workspace and waits for the stream */
 };
 
 /* Tunable launch shape of the row-owner kernels. */
@@ -82,7 +86,7 @@ typedef struct fem_tune {
     int32_t grid_blocks;   /* persistent grid: number of one-wave workgroups that loop over
                               the tiles (0: one workgroup per tile) */
     int32_t variant;       /* 0: row accumulators in registers for rows of <= 8 entries,
-                              longer rows per lane from global memory (default);
+                              longer rows per lane in register chunks of 8 (default);
                               1: row accumulators in LDS */
 } fem_tune;
 
@@ -201,9 +205,10 @@ int fem_assemble_stiff(int32_t nq, int32_t nme, int64_t nnz, const double *q, co
 /* Operator bits of fem_assemble. */
 enum { FEM_OP_MASS = 1, FEM_OP_WMASS = 2, FEM_OP_STIFF = 4, FEM_OP_ELAS = 8 };
 
-/* HOST ONLY.  Optional workspace bytes of fem_assemble for the operator set
- * `ops`: 32 nq when FEM_OP_WMASS is requested (packed (x, y, w) records, one
- * random access per column instead of two), else 0. */
+/* HOST ONLY.  Workspace bytes of fem_assemble for the operator set `ops`:
+ * 32 nq (rounded up to 256) when FEM_OP_WMASS is requested (packed (x, y, w)
+ * records, one random access per column instead of two), plus 256 bytes for
+ * the flag of FEM_CHECK_AREA.  The workspace is optional without that flag. */
 int fem_assemble_workspace(int32_t nq, int ops, size_t *bytes /* HOST */);
 
 /* Any nonzero subset `ops` of {M, Mw, S, K} in ONE pass over the mesh: the

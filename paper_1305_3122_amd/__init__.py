@@ -20,12 +20,13 @@ import dataclasses
 from typing import Optional
 
 from . import _lib
-from ._lib import (FEM_ACCUMULATE, FEM_ATOMIC, FEM_DETERMINISTIC, FEM_OP_ELAS,  # noqa: F401
+from ._lib import (FEM_ACCUMULATE, FEM_ATOMIC, FEM_CHECK_AREA, FEM_DETERMINISTIC, FEM_OP_ELAS,  # noqa: F401
                    FEM_OP_MASS, FEM_OP_STIFF, FEM_OP_WMASS, FEM_PATTERN_ATOMIC, FEM_PATTERN_AUTO,
                    FEM_PATTERN_COARSE, FemError, fem_tune)
 
 __all__ = [
-    "Pattern", "FemError", "FEM_ATOMIC", "FEM_DETERMINISTIC", "FEM_ACCUMULATE", "fem_tune",
+    "Pattern", "FemError", "FEM_ATOMIC", "FEM_DETERMINISTIC", "FEM_ACCUMULATE", "FEM_CHECK_AREA",
+    "fem_tune",
     "FEM_OP_MASS", "FEM_OP_WMASS", "FEM_OP_STIFF", "FEM_OP_ELAS",
     "FEM_PATTERN_AUTO", "FEM_PATTERN_COARSE", "FEM_PATTERN_ATOMIC", "fem_pattern_set_path",
     "fem_pattern", "fem_transpose_map", "fem_elas_pattern", "fem_assemble", "fem_assemble_mass",

@@ -20,6 +20,7 @@ FEM_DETERMINISTIC = 0
 FEM_ATOMIC = 1
 FEM_ACCUMULATE = 2
 FEM_PACKED_QW = 4
+FEM_CHECK_AREA = 8
 
 FEM_PATTERN_AUTO = 0
 FEM_PATTERN_COARSE = 1

@@ -110,6 +110,17 @@ __global__ __launch_bounds__(256) void k_pack_qw(int32_t nq, const double2 *__re
     qw[v] = make_double4(a.x, a.y, w ? w[v] : 0.0, 0.0);
 }
 
+// FEM_CHECK_AREA: flag triangles of zero area (det of the edge vectors
+// u = q2 - q3, v = q3 - q1), where the element formulas divide by zero.
+__global__ __launch_bounds__(256) void k_check_area(int32_t nme, const double2 *__restrict__ q,
+                                                    const int32_t *__restrict__ me, int *flag) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nme) return;
+    const double2 x1 = q[me[3 * k]], x2 = q[me[3 * k + 1]], x3 = q[me[3 * k + 2]];
+    const double ux = x2.x - x3.x, uy = x2.y - x3.y, vx = x3.x - x1.x, vy = x3.y - x1.y;
+    if (ux * vy - uy * vx == 0.0) atomicOr(flag, 1);
+}
+
 // ------------------------------------------------------------------ row owner
 //
 // Tile = 64 consecutive rows (one per lane) = a contiguous slice of col_idx /
@@ -831,14 +842,18 @@ int run_mask(const Args &a, const double4 *qw, const fem_tune *tune) {
     return launch_reg<MASK>(a, qw, eb, grid);
 }
 
+inline size_t qw_bytes(int32_t nq) { return (sizeof(double4) * (size_t)nq + 255) & ~size_t(255); }
+
+int run_ops(const Args &a, const fem_tune *tune);
+
 int run(const char *fn, const Args &a, const fem_tune *tune) {
     FEM_REQUIRE(a.ops >= 1 && a.ops <= 15, FEM_EINVAL, "%s: ops must be a nonzero subset of FEM_OP_*", fn);
     FEM_REQUIRE(a.nq >= 1 && a.nme >= 0 && a.nnz >= 0, FEM_EINVAL, "%s: bad sizes nq=%d nme=%d nnz=%lld",
                 fn, a.nq, a.nme, (long long)a.nnz);
     FEM_REQUIRE(a.nnz <= INT32_MAX && (!(a.ops & K_BIT) || 4 * a.nnz <= INT32_MAX), FEM_EOVERFLOW,
                 "%s: nnz exceeds int32 indexing", fn);
-    FEM_REQUIRE((a.flags & ~(FEM_ATOMIC | FEM_ACCUMULATE)) == 0, FEM_EINVAL, "%s: unknown flags 0x%x", fn,
-                a.flags);
+    FEM_REQUIRE((a.flags & ~(FEM_ATOMIC | FEM_ACCUMULATE | FEM_CHECK_AREA)) == 0, FEM_EINVAL,
+                "%s: unknown flags 0x%x", fn, a.flags);
     FEM_REQUIRE(a.q && a.row_ptr, FEM_EINVAL, "%s: NULL q or row_ptr", fn);
     for (int b = 0; b < 4; ++b)
         FEM_REQUIRE(!(a.ops & (1 << b)) || a.nnz == 0 || a.vals[b], FEM_EINVAL, "%s: NULL output", fn);
@@ -851,6 +866,32 @@ int run(const char *fn, const Args &a, const fem_tune *tune) {
         FEM_REQUIRE(a.nnz == 0 || (a.col_idx && a.inc_ptr && a.inc_pos), FEM_EINVAL,
                     "%s: NULL col_idx, inc_ptr or inc_pos", fn);
     }
+    // zero-area check: its flag lives after the packed records
+    int *area_flag = nullptr;
+    if (a.flags & FEM_CHECK_AREA) {
+        const size_t off = (a.ops & W_BIT) ? qw_bytes(a.nq) : 0;
+        FEM_REQUIRE(a.work && a.work_bytes >= off + sizeof(int), FEM_ENOSPC,
+                    "%s: FEM_CHECK_AREA needs the workspace of fem_assemble_workspace", fn);
+        FEM_REQUIRE(a.nme == 0 || a.me, FEM_EINVAL, "%s: FEM_CHECK_AREA needs me", fn);
+        area_flag = reinterpret_cast<int *>(static_cast<char *>(a.work) + off);
+        int st;
+        if ((st = fill_i32(area_flag, 1, 0, a.s))) return st;
+        if (a.nme > 0) {
+            hipLaunchKernelGGL(k_check_area, dim3(grid_for(a.nme, 256)), dim3(256), 0, a.s, a.nme,
+                               reinterpret_cast<const double2 *>(a.q), a.me, area_flag);
+            FEM_LAUNCH_CHECK();
+        }
+    }
+    const int st = run_ops(a, tune);
+    if (st || !area_flag) return st;
+    int hflag = 0;
+    FEM_HIP_CHECK(hipMemcpyAsync(&hflag, area_flag, sizeof(int), hipMemcpyDeviceToHost, a.s));
+    FEM_HIP_CHECK(hipStreamSynchronize(a.s));
+    FEM_REQUIRE(!hflag, FEM_EDEGEN, "%s: a triangle has zero area", fn);
+    return FEM_OK;
+}
+
+int run_ops(const Args &a, const fem_tune *tune) {
     // packed (x, y, w) records when the weighted mass is requested and a
     // workspace is given: one random access per column instead of two
     const double4 *qw = nullptr;
@@ -919,7 +960,7 @@ using namespace fem;
 extern "C" int fem_assemble_workspace(int32_t nq, int ops, size_t *bytes) {
     clear_error();
     FEM_REQUIRE(bytes && nq >= 1, FEM_EINVAL, "fem_assemble_workspace: bad arguments");
-    *bytes = (ops & FEM_OP_WMASS) ? sizeof(double4) * (size_t)nq : 0;
+    *bytes = ((ops & FEM_OP_WMASS) ? qw_bytes(nq) : 0) + 256;
     return FEM_OK;
 }
 

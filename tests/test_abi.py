@@ -70,6 +70,13 @@ def test_host_validation_before_any_launch(lib):
     st = lib.fem_assemble_stiff(4, 2, 10, fake, fake, fake, fake, fake, fake, None, fake,
                                 _lib.FEM_ATOMIC, None)
     assert st == _lib.FEM_EINVAL
+    # FEM_CHECK_AREA needs a workspace for its flag (the single-operator calls have none)
+    st = lib.fem_assemble_stiff(4, 2, 10, fake, fake, fake, fake, fake, fake, None, fake,
+                                _lib.FEM_CHECK_AREA, None)
+    assert st == _lib.FEM_ENOSPC and b"FEM_CHECK_AREA" in lib.fem_last_error()
+    ws = C.c_size_t(0)
+    assert lib.fem_assemble_workspace(4, _lib.FEM_OP_WMASS, C.byref(ws)) == _lib.FEM_OK
+    assert ws.value == 256 + 256
     # unknown flag bits
     st = lib.fem_assemble_mass(4, 2, 10, fake, fake, fake, fake, fake, fake, None, fake, 64, None)
     assert st == _lib.FEM_EINVAL

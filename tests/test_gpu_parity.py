@@ -192,6 +192,31 @@ def test_small_lds_tile_takes_the_global_memory_path():
     assert torch.equal(S0, S2) and torch.equal(M0, M2)
 
 
+def test_check_area_flag():
+    # three collinear vertices: the element formulas divide by the zero area,
+    # FEM_CHECK_AREA reports it as FEM_EDEGEN
+    q = np.array([[0.0, 0.0], [1.0, 0.0], [2.0, 0.0], [0.0, 1.0]])
+    me = np.array([[0, 1, 3], [0, 1, 2]], np.int32)
+    pat = fem.fem_pattern(_up(me), 4)
+    qd = _up(q)
+    with pytest.raises(fem.FemError) as e:
+        fem.fem_assemble(pat, qd, fem.FEM_OP_STIFF, flags=fem.FEM_CHECK_AREA)
+    assert e.value.status == fem._lib.FEM_EDEGEN
+    S = fem.fem_assemble(pat, qd, fem.FEM_OP_STIFF)["S"]
+    torch.cuda.synchronize()
+    assert not bool(torch.isfinite(S).all())
+    # a valid mesh: no error and the same values, also behind the packed records
+    m = mg.unit_square(20, seed=3)
+    pat = fem.fem_pattern(_up(m.me), m.nq)
+    qd, w = _up(m.q), _up(mg.weight_quadratic(m.q))
+    for ops in (fem.FEM_OP_STIFF | fem.FEM_OP_MASS, fem.FEM_OP_WMASS | fem.FEM_OP_STIFF):
+        a = fem.fem_assemble(pat, qd, ops, w=w)
+        b = fem.fem_assemble(pat, qd, ops, w=w, flags=fem.FEM_CHECK_AREA)
+        torch.cuda.synchronize()
+        for k in a:
+            assert torch.equal(a[k], b[k]), k
+
+
 def test_error_paths():
     bad = _up(np.array([[0, 1, 5]], np.int32))
     with pytest.raises(fem.FemError) as e:
