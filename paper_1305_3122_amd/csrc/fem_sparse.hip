@@ -39,7 +39,8 @@ constexpr int SP_COARSE_TARGET = 512; // coarse buckets: long runs in the first 
                                       // one split workgroup per CU or more
 constexpr int SP_COARSE_MAX = 4096;   // coarse buckets the partition's LDS holds
 constexpr int SP_SPLIT_MAX_SHIFT = 12;  // at most 4096 fine buckets per coarse one
-constexpr int SP_NBLK_TARGET = 512;   // triplet workgroups of the partition pass (2 per CU)
+constexpr int SP_NBLK_TARGET = 256;   // triplet workgroups of the partition pass (one per CU,
+                                      // so that the runs they fill fit the L2 of their XCD)
 constexpr int SP_COPY_GRID = 4096;    // workgroups looping over the fine bucket slots
 constexpr int SP_ADAPT_SHIFT = 2;     // fine buckets down to 1/4 of the planned rows where the
                                       // rows are denser than average
@@ -104,8 +105,9 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_count(int64_t nt, const int3
 // (advanced by the segment).  Consecutive tiles extend the same runs, so the
 // runs' lines fill while they are still in L2.  LDS (dynamic): cnt [nk+1] |
 // gcur [nk] | key [TILE] | rl [TILE] | ct [TILE] | val [TILE].
-constexpr int TILE = 2048;
-constexpr int IPT = TILE / SPP_THREADS;
+constexpr int TILE = 4096;        // the first-level scatter (one workgroup per CU)
+constexpr int TILE_SPLIT = 4096;  // the split (one workgroup per coarse bucket): the per-tile
+                                  // work on the fine counters is amortised over more triplets
 
 struct TileLds {
     int32_t *cnt, *gcur, *rl;
@@ -114,6 +116,7 @@ struct TileLds {
     double *val;
 };
 
+template <int T>
 __device__ inline TileLds tile_lds(int32_t nk) {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     TileLds L;
@@ -125,17 +128,18 @@ __device__ inline TileLds tile_lds(int32_t nk) {
     };
     L.cnt = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (nk + 1)));
     L.gcur = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * nk));
-    L.key = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * TILE));
-    L.rl = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * TILE));
-    L.ct = reinterpret_cast<int2 *>(take(sizeof(int2) * TILE));
-    L.val = reinterpret_cast<double *>(take(sizeof(double) * TILE));
+    L.key = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * T));
+    L.rl = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * T));
+    L.ct = reinterpret_cast<int2 *>(take(sizeof(int2) * T));
+    L.val = reinterpret_cast<double *>(take(sizeof(double) * T));
     return L;
 }
 
+template <int T>
 inline size_t tile_lds_bytes(int32_t nk) {
     auto up = [](size_t b) { return (b + 15) & ~size_t(15); };
-    return up(4 * (size_t)(nk + 1)) + up(4 * (size_t)nk) + up(2 * TILE) + up(4 * TILE) + up(8 * TILE) +
-           up(8 * TILE);
+    return up(4 * (size_t)(nk + 1)) + up(4 * (size_t)nk) + up(2 * (size_t)T) + up(4 * (size_t)T) +
+           up(8 * (size_t)T) + up(8 * (size_t)T);
 }
 
 // Exclusive scan of cnt[0, nk) in place over the workgroup; cnt[nk] = total.
@@ -168,6 +172,7 @@ __device__ inline void block_scan_counts(int32_t *cnt, int32_t nk, int32_t *s_ws
     __syncthreads();
 }
 
+template <int IPT>
 __device__ inline void tile_multisplit(const TileLds &L, int32_t nk, const int32_t (&key)[IPT],
                                        const int32_t (&prl)[IPT], const int2 (&pct)[IPT],
                                        const double (&pval)[IPT], bool has_val, int32_t *s_wsum,
@@ -215,7 +220,8 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_scatter(int64_t nt, const in
                                                            int32_t *__restrict__ rl, int2 *__restrict__ ct,
                                                            double *__restrict__ rval) {
     __shared__ int32_t s_wsum[SPP_THREADS / WAVE];
-    const TileLds L = tile_lds(nbkt);
+    constexpr int IPT = TILE / SPP_THREADS;
+    const TileLds L = tile_lds<TILE>(nbkt);
     const int32_t nblk = gridDim.x;
     for (int b = threadIdx.x; b < nbkt; b += SPP_THREADS)
         L.gcur[b] = offs[(int64_t)b * nblk + blockIdx.x];
@@ -278,7 +284,8 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_split(
     const int32_t cb = blockIdx.x;
     const int fshift = rc - rmin;
     const int32_t nsub = 1 << fshift;
-    const TileLds L = tile_lds(nsub);
+    constexpr int IPT = TILE_SPLIT / SPP_THREADS;
+    const TileLds L = tile_lds<TILE_SPLIT>(nsub);
     const int64_t total = *total_ptr;
     const int64_t e0 = offs[(int64_t)cb * nblk];
     const int64_t e1 = (cb + 1 < nbkt_c) ? offs[(int64_t)(cb + 1) * nblk] : total;
@@ -330,7 +337,7 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_split(
     if (cb == nbkt_c - 1 && tid == 0) fine_off[(int64_t)nbkt_c << fshift] = static_cast<int32_t>(total);
     __syncthreads();
     const int32_t fmask = (1 << rfc) - 1;
-    for (int64_t xb = e0; xb < e1; xb += TILE) {
+    for (int64_t xb = e0; xb < e1; xb += TILE_SPLIT) {
         int32_t key[IPT], prl[IPT];
         int2 pct[IPT];
         double pval[IPT];
@@ -828,7 +835,7 @@ extern "C" int fem_sparse(int32_t m, int32_t n, int64_t nt, const int32_t *I, co
                                  &W.cnt->err, s)))
         return st;
     if (nt > 0) {
-        hipLaunchKernelGGL(k_sp_scatter, dim3(P.nblk), dim3(SPP_THREADS), tile_lds_bytes(P.nbkt_c), s,
+        hipLaunchKernelGGL(k_sp_scatter, dim3(P.nblk), dim3(SPP_THREADS), tile_lds_bytes<TILE>(P.nbkt_c), s,
                            nt, I, J,
                            has_val ? V : nullptr, m, n, P.rc, P.nbkt_c, P.tpb, W.counts, W.rl, W.ct,
                            W.rval);
@@ -838,7 +845,7 @@ extern "C" int fem_sparse(int32_t m, int32_t n, int64_t nt, const int32_t *I, co
     const int32_t *cshift = P.fshift() > 0 ? W.cshift : nullptr;
     if (P.fshift() > 0) {
         hipLaunchKernelGGL(k_sp_split, dim3(P.nbkt_c), dim3(SPP_THREADS),
-                           tile_lds_bytes(1 << P.fshift()), s, P.nbkt_c, P.nblk, P.rc, P.rmin,
+                           tile_lds_bytes<TILE_SPLIT>(1 << P.fshift()), s, P.nbkt_c, P.nblk, P.rc, P.rmin,
                            P.rmax, W.counts, total_ptr, W.rl, W.ct, W.rval, has_val ? 1 : 0, W.rl2,
                            W.ct2, W.rval2, W.fine_off, W.cshift);
     } else {
