@@ -107,7 +107,8 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_count(int64_t nt, const int3
 // gcur [nk] | key [TILE] | rl [TILE] | ct [TILE] | val [TILE].
 constexpr int TILE = 4096;        // the first-level scatter (one workgroup per CU)
 constexpr int TILE_SPLIT = 4096;  // the split (one workgroup per coarse bucket): the per-tile
-                                  // work on the fine counters is amortised over more triplets
+                                  // work on the fine counters is amortised over more triplets;
+constexpr int TILE_SPLIT_NV = 8192;  // twice that without values (no value array in LDS)
 
 struct TileLds {
     int32_t *cnt, *gcur, *rl;
@@ -116,7 +117,7 @@ struct TileLds {
     double *val;
 };
 
-template <int T>
+template <int T, bool HV = true>
 __device__ inline TileLds tile_lds(int32_t nk) {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     TileLds L;
@@ -131,15 +132,15 @@ __device__ inline TileLds tile_lds(int32_t nk) {
     L.key = reinterpret_cast<uint16_t *>(take(sizeof(uint16_t) * T));
     L.rl = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * T));
     L.ct = reinterpret_cast<int2 *>(take(sizeof(int2) * T));
-    L.val = reinterpret_cast<double *>(take(sizeof(double) * T));
+    L.val = HV ? reinterpret_cast<double *>(take(sizeof(double) * T)) : nullptr;
     return L;
 }
 
-template <int T>
+template <int T, bool HV = true>
 inline size_t tile_lds_bytes(int32_t nk) {
     auto up = [](size_t b) { return (b + 15) & ~size_t(15); };
     return up(4 * (size_t)(nk + 1)) + up(4 * (size_t)nk) + up(2 * (size_t)T) + up(4 * (size_t)T) +
-           up(8 * (size_t)T) + up(8 * (size_t)T);
+           up(8 * (size_t)T) + (HV ? up(8 * (size_t)T) : 0);
 }
 
 // Exclusive scan of cnt[0, nk) in place over the workgroup; cnt[nk] = total.
@@ -272,11 +273,12 @@ __device__ __forceinline__ void fine_rows(int32_t b, int rc, int fshift, const i
 // 2^rmin rows, then the bucket's fine size 2^rfc (rmin <= rfc <= rmax) is the
 // largest whose fullest fine bucket holds at most SP_CAP triplets (rmin if
 // none does); its triplets are split into those fine buckets.
+template <int TS, bool HV>
 __global__ __launch_bounds__(SPP_THREADS) void k_sp_split(
     int32_t nbkt_c, int32_t nblk, int rc, int rmin, int rmax,
     const int32_t *__restrict__ offs, const int32_t *__restrict__ total_ptr,
     const int32_t *__restrict__ rl, const int2 *__restrict__ ct, const double *__restrict__ rval,
-    int has_val, int32_t *__restrict__ rl2, int2 *__restrict__ ct2, double *__restrict__ rval2,
+    int32_t *__restrict__ rl2, int2 *__restrict__ ct2, double *__restrict__ rval2,
     int32_t *__restrict__ fine_off, int32_t *__restrict__ cshift) {
     __shared__ int32_t s_wsum[SPP_THREADS / WAVE];
     __shared__ int32_t s_lmax[SP_SPLIT_MAX_SHIFT + 1];
@@ -284,8 +286,8 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_split(
     const int32_t cb = blockIdx.x;
     const int fshift = rc - rmin;
     const int32_t nsub = 1 << fshift;
-    constexpr int IPT = TILE_SPLIT / SPP_THREADS;
-    const TileLds L = tile_lds<TILE_SPLIT>(nsub);
+    constexpr int IPT = TS / SPP_THREADS;
+    const TileLds L = tile_lds<TS, HV>(nsub);
     const int64_t total = *total_ptr;
     const int64_t e0 = offs[(int64_t)cb * nblk];
     const int64_t e1 = (cb + 1 < nbkt_c) ? offs[(int64_t)(cb + 1) * nblk] : total;
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_split(
     if (cb == nbkt_c - 1 && tid == 0) fine_off[(int64_t)nbkt_c << fshift] = static_cast<int32_t>(total);
     __syncthreads();
     const int32_t fmask = (1 << rfc) - 1;
-    for (int64_t xb = e0; xb < e1; xb += TILE_SPLIT) {
+    for (int64_t xb = e0; xb < e1; xb += TS) {
         int32_t key[IPT], prl[IPT];
         int2 pct[IPT];
         double pval[IPT];
@@ -348,9 +350,9 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_split(
             key[u] = r0 >= 0 ? (r0 >> rfc) : -1;
             prl[u] = r0 & fmask;
             pct[u] = x < e1 ? ct[x] : make_int2(0, 0);
-            pval[u] = (has_val && x < e1) ? rval[x] : 0.0;
+            pval[u] = (HV && x < e1) ? rval[x] : 0.0;
         }
-        tile_multisplit(L, nk, key, prl, pct, pval, has_val != 0, s_wsum, rl2, ct2, rval2);
+        tile_multisplit(L, nk, key, prl, pct, pval, HV, s_wsum, rl2, ct2, rval2);
     }
 }
 
@@ -844,10 +846,18 @@ extern "C" int fem_sparse(int32_t m, int32_t n, int64_t nt, const int32_t *I, co
     const int32_t *total_ptr = W.counts + P.ncounts();
     const int32_t *cshift = P.fshift() > 0 ? W.cshift : nullptr;
     if (P.fshift() > 0) {
-        hipLaunchKernelGGL(k_sp_split, dim3(P.nbkt_c), dim3(SPP_THREADS),
-                           tile_lds_bytes<TILE_SPLIT>(1 << P.fshift()), s, P.nbkt_c, P.nblk, P.rc, P.rmin,
-                           P.rmax, W.counts, total_ptr, W.rl, W.ct, W.rval, has_val ? 1 : 0, W.rl2,
-                           W.ct2, W.rval2, W.fine_off, W.cshift);
+        const size_t lds_v = tile_lds_bytes<TILE_SPLIT, true>(1 << P.fshift());
+        const size_t lds_nv = tile_lds_bytes<TILE_SPLIT_NV, false>(1 << P.fshift());
+        if (has_val)
+            hipLaunchKernelGGL((k_sp_split<TILE_SPLIT, true>), dim3(P.nbkt_c), dim3(SPP_THREADS),
+                               lds_v, s, P.nbkt_c, P.nblk,
+                               P.rc, P.rmin, P.rmax, W.counts, total_ptr, W.rl, W.ct, W.rval, W.rl2,
+                               W.ct2, W.rval2, W.fine_off, W.cshift);
+        else
+            hipLaunchKernelGGL((k_sp_split<TILE_SPLIT_NV, false>), dim3(P.nbkt_c), dim3(SPP_THREADS),
+                               lds_nv, s, P.nbkt_c,
+                               P.nblk, P.rc, P.rmin, P.rmax, W.counts, total_ptr, W.rl, W.ct, W.rval,
+                               W.rl2, W.ct2, W.rval2, W.fine_off, W.cshift);
     } else {
         hipLaunchKernelGGL(k_sp_fine_off, dim3(grid_for((int64_t)P.nbkt_f + 1, 256)), dim3(256), 0, s,
                            P.nbkt_f, P.nblk, W.counts, total_ptr, W.fine_off);
