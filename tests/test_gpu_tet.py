@@ -121,6 +121,39 @@ def test_tet_full_size_properties():
     assert float(u @ Mu) == pytest.approx(exact, rel=1e-11)
 
 
+def test_tet_full_size_sampled_rows():
+    # 32 rows of the 128^3 cube recomputed one by one from the oracle's
+    # element matrices, summed in ascending t = (4 b + a) nme + k
+    m = mg.unit_cube(128, seed=mg.BASE_SEED + 128)
+    print(f"[case] tet cube128 sampled rows nq={m.nq} nme={m.nme}", flush=True)
+    pat = fem.fem_tet_pattern(_up(m.me), m.nq)
+    vals = fem.fem_tet_assemble(pat, _up(m.q))
+    torch.cuda.synchronize()
+    rp, ci = _np(pat.row_ptr), _np(pat.col_idx)
+    Mh, Sh = _np(vals["M"]), _np(vals["S"])
+    rng = np.random.default_rng(128)
+    for v in rng.choice(m.nq, 32, replace=False):
+        ks, As = np.nonzero(m.me == v)
+        trip = []
+        for k, a in zip(ks, As):
+            x = [m.q[m.me[k, c]] for c in range(4)]
+            EM = oracle.elem_tet_mass(abs(oracle.tet_det(*x)) / 6)
+            ES = oracle.elem_tet_stiff(*x)
+            for b in range(4):
+                trip.append(((4 * b + a) * m.nme + k, m.me[k, b], EM[a, b], ES[a, b]))
+        trip.sort()
+        cols = sorted({t[1] for t in trip})
+        np.testing.assert_array_equal(ci[rp[v]:rp[v + 1]], cols)
+        refM = np.zeros(len(cols))
+        refS = np.zeros(len(cols))
+        for _, c, vm, vs in trip:
+            j = cols.index(c)
+            refM[j] += vm
+            refS[j] += vs
+        assert np.abs(Mh[rp[v]:rp[v + 1]] - refM).max() <= RTOL_ROW * np.abs(refM).max(), v
+        assert np.abs(Sh[rp[v]:rp[v + 1]] - refS).max() <= RTOL_ROW * np.abs(refS).max(), v
+
+
 def test_tet_errors_and_empty():
     q = np.zeros((5, 3))
     with pytest.raises(fem.FemError) as e:
