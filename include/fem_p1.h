@@ -349,15 +349,16 @@ int fem_tet_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *row_ptr
                     int32_t *col_idx, int64_t col_cap, int32_t *contrib_ptr, int32_t *contrib,
                     void *work, size_t work_bytes, int64_t *nnz_out /* HOST */, void *stream);
 
-/* HOST ONLY.  Bytes of device workspace fem_tet_assemble needs (16 nme values
- * per requested operator). */
+/* HOST ONLY.  Bytes of device workspace fem_tet_assemble needs (per
+ * tetrahedron: 1 value for the mass, 10 for the stiffness). */
 int fem_tet_assemble_workspace(int32_t nme, int ops, size_t *bytes /* HOST */);
 
 /* P1 tetrahedron mass (FEM_OP_MASS: |K| (1 + delta_ab) / 20) and / or
  * stiffness (FEM_OP_STIFF: |K| grad lambda_a . grad lambda_b) on the pattern
- * of fem_tet_pattern: the element matrices of every tetrahedron at their
- * triplet positions (the paper's Kg), then for every entry the sum of its
- * contributors in ascending t (bitwise reproducible).
+ * of fem_tet_pattern: what the element matrices of every tetrahedron hold
+ * (the paper's Kg, reduced to |K| / 20 and the 10 distinct stiffness entries),
+ * then for every entry the sum of its contributors in ascending t (bitwise
+ * reproducible).
  *   q [nq][3] f64; me [nme][4] int32 (16-byte aligned); vals_M / vals_S [nnz]
  *   work [work_bytes] >= fem_tet_assemble_workspace(nme, ops), 16-byte aligned
  * flags: 0 or FEM_ACCUMULATE. */

@@ -6,8 +6,9 @@
 //                      me[k][a], column me[k][b]) compressed by fem_sparse into
 //                      the CSR pattern and the contributor lists (the triplets
 //                      of each entry, ascending)
-//   fem_tet_assemble   k_tet_elem: one lane per tetrahedron writes its element
-//                      matrices at their triplet positions (the paper's Kg);
+//   fem_tet_assemble   k_tet_elem: one lane per tetrahedron writes what its
+//                      element matrices hold (the paper's Kg, reduced to the
+//                      mass factor and the 10 distinct stiffness entries);
 //                      k_tet_sum: one lane per CSR entry adds its contributors
 //                      in ascending t (bitwise reproducible)
 //
@@ -72,13 +73,24 @@ __device__ __forceinline__ void cross3(const double *u, const double *w, double 
     o[2] = u[0] * w[1] - u[1] * w[0];
 }
 
-// Element matrices of element k at their triplet positions: Kg[r nme + k].
-// Both operators: (M, S) pairs, so that the sums fetch one record per
-// contributor.
+// Record of element k: |K| / 20 = |D| / 120 (the mass is that times 1 + delta_ab)
+// and / or the 10 distinct entries of the symmetric stiffness, a <= b, at
+// 1 + sym(a, b) (or sym(a, b) without the mass).  c_a . c_b is summed over the
+// components in the same order for (a, b) and (b, a), so the two are equal
+// bit for bit and one of them stands for both.
+template <int MASK>
+struct TetRec {
+    static constexpr int M = (MASK & TET_M) ? 1 : 0;
+    static constexpr int N = M + ((MASK & TET_S) ? 10 : 0);   // doubles per element
+};
+
+__host__ __device__ constexpr int tet_sym(int i, int j) { return i * (7 - i) / 2 + j; }   // i <= j
+
 template <int MASK>
 __global__ __launch_bounds__(256) void k_tet_elem(int32_t nme, const double *__restrict__ q,
                                                   const int32_t *__restrict__ me,
                                                   double *__restrict__ kg) {
+    using R = TetRec<MASK>;
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= nme) return;
     const int4 t = reinterpret_cast<const int4 *>(me)[k];
@@ -103,48 +115,50 @@ __global__ __launch_bounds__(256) void k_tet_elem(int32_t nme, const double *__r
     for (int c = 0; c < 3; ++c) cv[0][c] = -(cv[1][c] + cv[2][c] + cv[3][c]);
     const double D = e[0][0] * cv[1][0] + e[0][1] * cv[1][1] + e[0][2] * cv[1][2];
     const double aD = fabs(D);
-    const double s6 = 1.0 / (6.0 * aD);
-    const double m1 = aD / 120.0, m2 = 2.0 * aD / 120.0;
+    double *rec = kg + R::N * k;
+    if constexpr (R::M) rec[0] = aD / 120.0;
+    if constexpr ((MASK & TET_S) != 0) {
+        const double s6 = 1.0 / (6.0 * aD);
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int64_t s = (int64_t)(4 * b + a) * nme + k;
-            const double mv = a == b ? m2 : m1;
-            const double sv =
-                (cv[a][0] * cv[b][0] + cv[a][1] * cv[b][1] + cv[a][2] * cv[b][2]) * s6;
-            if constexpr (MASK == (TET_M | TET_S)) {
-                reinterpret_cast<double2 *>(kg)[s] = make_double2(mv, sv);
-            } else if constexpr (MASK == TET_M) {
-                kg[s] = mv;
-            } else {
-                kg[s] = sv;
-            }
-        }
+            for (int b = a; b < 4; ++b)
+                rec[R::M + tet_sym(a, b)] =
+                    (cv[a][0] * cv[b][0] + cv[a][1] * cv[b][1] + cv[a][2] * cv[b][2]) * s6;
+    }
 }
 
-// One lane per CSR entry: the sum of its contributors in ascending t.
+// One lane per CSR entry: the sum of its contributors in ascending t; the
+// contributor t = r nme + k (r = 4 b + a) is element k's entry (a, b).
 template <int MASK>
 __global__ __launch_bounds__(256) void k_tet_sum(int64_t nnz, const int32_t *__restrict__ cptr,
-                                                 const int32_t *__restrict__ contrib,
-                                                 const double *__restrict__ kg,
+                                                 const int32_t *__restrict__ contrib, int32_t nme,
+                                                 double inv_nme, const double *__restrict__ kg,
                                                  double *__restrict__ vm, double *__restrict__ vs,
                                                  int accumulate) {
+    using R = TetRec<MASK>;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= nnz) return;
+    const uint32_t ntr = 16u * (uint32_t)nme;
     double am = 0.0, as = 0.0;
     const int32_t k0 = cptr[p], k1 = cptr[p + 1];
     for (int32_t k = k0; k < k1; ++k) {
-        const int32_t t = contrib[k];
-        if constexpr (MASK == (TET_M | TET_S)) {
-            const double2 r = reinterpret_cast<const double2 *>(kg)[t];
-            am += r.x;
-            as += r.y;
-        } else if constexpr (MASK == TET_M) {
-            am += kg[t];
-        } else {
-            as += kg[t];
+        const int32_t tc = contrib[k];
+        if ((uint32_t)tc >= ntr) continue;   // not a triplet of these nme elements
+        // r = tc / nme: the double quotient is off by at most one
+        int32_t rq = (int32_t)((double)tc * inv_nme);
+        int32_t e = tc - rq * nme;
+        if (e < 0) {
+            --rq;
+            e += nme;
+        } else if (e >= nme) {
+            ++rq;
+            e -= nme;
         }
+        const int a = rq & 3, b = rq >> 2;
+        const double *rec = kg + R::N * (int64_t)e;
+        if constexpr (R::M) am += a == b ? 2.0 * rec[0] : rec[0];
+        if constexpr ((MASK & TET_S) != 0) as += rec[R::M + tet_sym(min(a, b), max(a, b))];
     }
     if (MASK & TET_M) {
         if (accumulate) vm[p] += am;
@@ -243,8 +257,8 @@ extern "C" int fem_tet_assemble_workspace(int32_t nme, int ops, size_t *bytes) {
     FEM_REQUIRE(bytes != nullptr && nme >= 0, FEM_EINVAL, "fem_tet_assemble_workspace: bad arguments");
     FEM_REQUIRE(ops == TET_M || ops == TET_S || ops == (TET_M | TET_S), FEM_EINVAL,
                 "fem_tet_assemble_workspace: ops must be FEM_OP_MASS and/or FEM_OP_STIFF");
-    const int nops = (ops & TET_M ? 1 : 0) + (ops & TET_S ? 1 : 0);
-    *bytes = align_up(sizeof(double) * nops * 16 * (size_t)(nme > 0 ? nme : 1));
+    const int per = (ops & TET_M ? 1 : 0) + (ops & TET_S ? 10 : 0);   // doubles per element
+    *bytes = align_up(sizeof(double) * per * (size_t)(nme > 0 ? nme : 1));
     return FEM_OK;
 }
 
@@ -272,21 +286,22 @@ extern "C" int fem_tet_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, c
     double *kg = static_cast<double *>(work);
     const int acc = (flags & FEM_ACCUMULATE) ? 1 : 0;
     const unsigned ge = grid_for(nme, 256), gs = grid_for(nnz, 256);
+    const double inv = nme > 0 ? 1.0 / (double)nme : 0.0;
     if (ops == (TET_M | TET_S)) {
         if (nme > 0) hipLaunchKernelGGL(k_tet_elem<TET_M | TET_S>, dim3(ge), dim3(256), 0, s, nme, q, me, kg);
         if (nnz > 0)
             hipLaunchKernelGGL(k_tet_sum<TET_M | TET_S>, dim3(gs), dim3(256), 0, s, nnz, contrib_ptr,
-                               contrib, kg, vals_M, vals_S, acc);
+                               contrib, nme, inv, kg, vals_M, vals_S, acc);
     } else if (ops == TET_M) {
         if (nme > 0) hipLaunchKernelGGL(k_tet_elem<TET_M>, dim3(ge), dim3(256), 0, s, nme, q, me, kg);
         if (nnz > 0)
             hipLaunchKernelGGL(k_tet_sum<TET_M>, dim3(gs), dim3(256), 0, s, nnz, contrib_ptr, contrib,
-                               kg, vals_M, nullptr, acc);
+                               nme, inv, kg, vals_M, nullptr, acc);
     } else {
         if (nme > 0) hipLaunchKernelGGL(k_tet_elem<TET_S>, dim3(ge), dim3(256), 0, s, nme, q, me, kg);
         if (nnz > 0)
             hipLaunchKernelGGL(k_tet_sum<TET_S>, dim3(gs), dim3(256), 0, s, nnz, contrib_ptr, contrib,
-                               kg, nullptr, vals_S, acc);
+                               nme, inv, kg, nullptr, vals_S, acc);
     }
     FEM_LAUNCH_CHECK();
     return FEM_OK;
