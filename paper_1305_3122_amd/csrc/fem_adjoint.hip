@@ -677,11 +677,45 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_cols(int32_t nq, const int32_
                                                         const int32_t *__restrict__ tpos,
                                                         const double2 *__restrict__ H,
                                                         double *__restrict__ dq, int accumulate,
-                                                        int64_t ntiles) {
+                                                        int64_t ntiles, const double2 *__restrict__ lm,
+                                                        double *__restrict__ dlm) {
     constexpr int EB = U * WAVE;
     __shared__ double s_h[2 * EB];
     const int lane = threadIdx.x;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // dL/dlambda, dL/dmu: workgroup 0 (dispatched first, beside the column
+    // sums) adds pass 1's per-tile sums in a fixed order -- lane t takes
+    // entries t, t + 64, ... in turn, then a fixed butterfly over the wave --
+    // so the result is bitwise reproducible.
+    const int lead = dlm ? 1 : 0;
+    if (dlm && blockIdx.x == 0) {
+        double l = 0.0, m = 0.0;
+        for (int64_t i0 = lane; i0 < ntiles; i0 += 4 * WAVE) {
+            double2 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t i = i0 + k * WAVE;
+                v[k] = i < ntiles ? lm[i] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                l += v[k].x;
+                m += v[k].y;
+            }
+        }
+        l = wave_sum(l);
+        m = wave_sum(m);
+        if (lane == 0) {
+            if (accumulate) {
+                dlm[0] += l;
+                dlm[1] += m;
+            } else {
+                dlm[0] = l;
+                dlm[1] = m;
+            }
+        }
+        return;
+    }
+    for (int64_t tile = blockIdx.x - lead; tile < ntiles; tile += gridDim.x - lead) {
         const int64_t r0 = tile * WAVE;
         const int64_t r1 = (r0 + WAVE < nq) ? r0 + WAVE : nq;
         const int64_t u = r0 + lane;
@@ -744,48 +778,6 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_cols(int32_t nq, const int32_
         } else {
             dq[2 * u] = gx;
             dq[2 * u + 1] = gy;
-        }
-    }
-}
-
-// dL/dlambda, dL/dmu: the per-tile sums in a fixed order (thread t takes
-// entries t, t + 1024, ... in turn, then a fixed pairwise tree), so the
-// result is bitwise reproducible.
-__global__ __launch_bounds__(1024) void k_adj_lm_reduce(int64_t n, const double2 *__restrict__ lm,
-                                                        double *__restrict__ out, int accumulate) {
-    __shared__ double s_l[1024], s_m[1024];
-    const int tid = threadIdx.x;
-    double l = 0.0, m = 0.0;
-    for (int64_t i0 = tid; i0 < n; i0 += 4 * 1024) {
-        double2 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t i = i0 + u * 1024;
-            v[u] = i < n ? lm[i] : make_double2(0.0, 0.0);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            l += v[u].x;
-            m += v[u].y;
-        }
-    }
-    s_l[tid] = l;
-    s_m[tid] = m;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (tid < w) {
-            s_l[tid] += s_l[tid + w];
-            s_m[tid] += s_m[tid + w];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        if (accumulate) {
-            out[0] += s_l[0];
-            out[1] += s_m[0];
-        } else {
-            out[0] = s_l[0];
-            out[1] = s_m[0];
         }
     }
 }
@@ -899,12 +891,8 @@ extern "C" int fem_adjoint_elas(int32_t nq, int32_t nme, int64_t nnz, const doub
                        q, row_ptr, col_idx, inc_ptr, inc_pos, G, lambda, mu, H, lm, ntiles);
     FEM_LAUNCH_CHECK();
     const int acc = (flags & FEM_ACCUMULATE) ? 1 : 0;
-    hipLaunchKernelGGL(k_adj_elas_cols<ADJ_U>, dim3((unsigned)ntiles), dim3(WAVE), 0, s, nq, row_ptr,
-                       col_idx, tpos, H, dq, acc, ntiles);
+    hipLaunchKernelGGL(k_adj_elas_cols<ADJ_U>, dim3((unsigned)(ntiles + (dlm ? 1 : 0))), dim3(WAVE), 0, s,
+                       nq, row_ptr, col_idx, tpos, H, dq, acc, ntiles, lm, dlm);
     FEM_LAUNCH_CHECK();
-    if (dlm) {
-        hipLaunchKernelGGL(k_adj_lm_reduce, dim3(1), dim3(1024), 0, s, ntiles, lm, dlm, acc);
-        FEM_LAUNCH_CHECK();
-    }
     return FEM_OK;
 }
