@@ -83,6 +83,15 @@ def _cases():
     # all triplets on one entry
     out.append(("one_entry", np.zeros(777, np.int32), np.full(777, 3, np.int32),
                 rng.standard_normal(777), 1, 4))
+    # uneven density over many coarse buckets: dense rows (40 triplets), then
+    # sparse ones (2), then empty ones, so that the coarse buckets choose
+    # different fine sizes and leave slots empty
+    m = 300_000
+    dense = np.repeat(np.arange(50_000), 40)
+    sparse_rows = np.repeat(np.arange(50_000, 250_000), 2)
+    I = rng.permutation(np.concatenate([dense, sparse_rows])).astype(np.int32)
+    J = rng.integers(0, 60_000, I.shape[0]).astype(np.int32)
+    out.append(("uneven_density", I, J, rng.standard_normal(I.shape[0]), m, 60_000))
     return out
 
 
