@@ -167,7 +167,7 @@ def summarize_profiles(kt_dir, pf_dir, pw_dir, command, name="step_square2048"):
              "",
              f"source-sha256: {sh}  (sha256 of {', '.join(PROFILE_SOURCES[name])})",
              "",
-             "Commands (from the repository root; rocprofv3 writes csv under gpurun_out/):",
+             "Commands (from the repository root; rocprofv3 writes csv into the -d directories):",
              "", "```", command, "```", "",
              "| kernel | calls | avg us | min us | max us | share of GPU time |",
              "|---|---|---|---|---|---|"]
@@ -376,7 +376,20 @@ def run_main(torch, fem, args):
         b.record()
         torch.cuda.synchronize()
         cold.append(a.elapsed_time(b) * 1e3)
-    del flush
+    # practical ceiling: a plain 1 GiB device-to-device copy (1 GiB read + 1 GiB written)
+    src = flush
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(10):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 10 / (a.elapsed_time(b) * 1e-3) / 1e9
+    del flush, src, dst
     db = design_bytes(m.nq, m.nme, st.nnz)
     kern = {}
     for p, t in us.items():
@@ -387,6 +400,7 @@ def run_main(torch, fem, args):
             kern[p]["design_bytes"] = db[p]
             kern[p]["design_frac_hbm"] = round(db[p] / (t * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     kern["stiff_mass"]["us_cold"] = round(float(np.median(cold)), 2)
+    st.copy_gbs = round(copy_gbs, 1)
     log(f"[bench] step {ms_per_step:.3f} ms; " +
         ", ".join(f"{p} {kern[p]['us']:.0f}us" for p in kern))
     return m, st, ms_per_step, kern
@@ -864,8 +878,8 @@ def main():
         summarize_profiles(*args.summarize, args.command, args.profile_name)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (the assembly of one mesh runs on one "
-              "GPU; a multi-GPU split is described in DESIGN.md but not built)", file=sys.stderr)
+        print("bench.py measures one GPU: the assembly of one mesh runs on one GPU, and no "
+              "multi-GPU split is implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -925,6 +939,8 @@ def main():
         "roofline": roof("assemble_k"),
         # the metric's K+M: stiffness and mass in one fused kernel
         "roofline_stiff_mass": roof("stiff_mass"),
+        # measured practical ceiling: a plain 1 GiB device-to-device copy
+        "stream_copy_GBps": st.copy_gbs,
         "kernels": kern,
     }
     line.update(extras)
