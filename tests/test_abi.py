@@ -93,6 +93,33 @@ def test_host_validation_before_any_launch(lib):
     assert st == _lib.FEM_EINVAL
 
 
+def test_extension_size_limits_before_any_launch(lib):
+    # the triplet counts of the extensions must fit int32: refused on the
+    # host with FEM_EOVERFLOW, nothing enqueued
+    fake = C.c_void_p(0x1000)   # never dereferenced
+    out = C.c_int64(0)
+    ws = C.c_size_t(0)
+    big_p2 = 60_000_000         # 36 nme > 2^31 - 1
+    assert lib.fem_p2_dofs_workspace(10, big_p2, C.byref(ws)) == _lib.FEM_EOVERFLOW
+    assert lib.fem_p2_dofs(10, big_p2, fake, fake, None, 0, fake, 1 << 20, C.byref(out),
+                           None) == _lib.FEM_EOVERFLOW
+    assert lib.fem_p2_pattern(10, big_p2, fake, fake, fake, 0, fake, fake, fake, 1 << 20, C.byref(out),
+                              None) == _lib.FEM_EOVERFLOW
+    assert lib.fem_p2_assemble(5, 10, big_p2, 10, fake, fake, fake, fake, fake, fake, fake, 1 << 20, 0,
+                               None) == _lib.FEM_EOVERFLOW
+    big_tet = 140_000_000       # 16 nme > 2^31 - 1
+    assert lib.fem_tet_pattern_workspace(10, big_tet, C.byref(ws)) == _lib.FEM_EOVERFLOW
+    assert lib.fem_tet_pattern(10, big_tet, fake, fake, fake, 0, fake, fake, fake, 1 << 20, C.byref(out),
+                               None) == _lib.FEM_EOVERFLOW
+    assert lib.fem_sparse_workspace(10, 10, 1 << 31, C.byref(ws)) == _lib.FEM_EOVERFLOW
+    assert lib.fem_sparse(10, 10, 1 << 31, fake, fake, None, fake, fake, None, 0, None, None, fake,
+                          1 << 20, C.byref(out), None) == _lib.FEM_EOVERFLOW
+    # and the workspace queries at sizes that fit answer
+    assert lib.fem_p2_dofs_workspace(10, 1000, C.byref(ws)) == _lib.FEM_OK and ws.value > 0
+    assert lib.fem_tet_assemble_workspace(1000, 5, C.byref(ws)) == _lib.FEM_OK
+    assert ws.value >= 8 * 11 * 1000
+
+
 def test_python_binding_refuses_cpu_tensors():
     torch = pytest.importorskip("torch")
     import paper_1305_3122_amd as fem
