@@ -68,11 +68,14 @@ enum {
     FEM_ATOMIC = 1,        /* one lane per triangle, FP64 atomic adds through the slot map
                               (needs me and slot); order of additions unspecified */
     FEM_ACCUMULATE = 2,    /* add into values instead of overwriting them */
-    FEM_PACKED_QW = 4,     /* fem_adjoint_stiff_wmass only: the first 32 nq bytes of its
+    FEM_PACKED_QW = 4,     /* fem_adjoint_stiff_wmass, and fem_assemble with FEM_OP_WMASS
+                              in the row-owner scheme: the first 32 nq bytes of the
                               workspace already hold the (x, y, w, 0) record of every vertex
                               for these q and w, as fem_assemble leaves them in its own
-                              workspace when it assembles Mw (pass the same buffer to both);
-                              the packing pass is skipped */
+                              workspace when it assembles Mw (pass the same buffer again);
+                              the packing pass is skipped.  fem_assemble returns FEM_EINVAL
+                              for it without FEM_OP_WMASS or with FEM_ATOMIC, FEM_ENOSPC
+                              without a workspace of 32 nq bytes */
     FEM_CHECK_AREA = 8     /* fem_assemble only: also test every triangle for zero area
                               (det = (q2-q3) x (q3-q1) == 0, where the element formulas
                               divide by zero) and return FEM_EDEGEN if one has it; uses the

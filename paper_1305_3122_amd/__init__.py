@@ -21,12 +21,12 @@ from typing import Optional
 
 from . import _lib
 from ._lib import (FEM_ACCUMULATE, FEM_ATOMIC, FEM_CHECK_AREA, FEM_DETERMINISTIC, FEM_OP_ELAS,  # noqa: F401
-                   FEM_OP_MASS, FEM_OP_STIFF, FEM_OP_WMASS, FEM_PATTERN_ATOMIC, FEM_PATTERN_AUTO,
-                   FEM_PATTERN_COARSE, FemError, fem_tune)
+                   FEM_OP_MASS, FEM_OP_STIFF, FEM_OP_WMASS, FEM_PACKED_QW, FEM_PATTERN_ATOMIC,
+                   FEM_PATTERN_AUTO, FEM_PATTERN_COARSE, FemError, fem_tune)
 
 __all__ = [
     "Pattern", "FemError", "FEM_ATOMIC", "FEM_DETERMINISTIC", "FEM_ACCUMULATE", "FEM_CHECK_AREA",
-    "fem_tune",
+    "FEM_PACKED_QW", "fem_tune",
     "FEM_OP_MASS", "FEM_OP_WMASS", "FEM_OP_STIFF", "FEM_OP_ELAS",
     "FEM_PATTERN_AUTO", "FEM_PATTERN_COARSE", "FEM_PATTERN_ATOMIC", "fem_pattern_set_path",
     "fem_pattern", "fem_transpose_map", "fem_elas_pattern", "fem_assemble", "fem_assemble_mass",
@@ -175,7 +175,9 @@ def fem_assemble(pat: Pattern, q, ops: int, *, w=None, lam: float = 0.0, mu: flo
     """Any subset of {M, Mw, S, K} in one pass (C: fem_assemble).  Returns a
     dict with keys "M", "Mw", "S", "K" for the requested operators; `out` may
     supply preallocated tensors under the same keys.  A packing workspace for
-    the weighted mass is allocated here unless `work` is given."""
+    the weighted mass is allocated here unless `work` is given; with
+    FEM_PACKED_QW in `flags`, `work` is the one a previous call with the same
+    q and w filled, and the packing pass is skipped."""
     torch = _torch()
     lib = _lib.load()
     out = dict(out or {})

@@ -39,6 +39,7 @@ template <int MASK> struct Ops {
     static constexpr bool S = (MASK & S_BIT) != 0, K = (MASK & K_BIT) != 0;
     static constexpr int NS = (M ? 1 : 0) + (W ? 1 : 0) + (S ? 1 : 0);   // scalar accumulators
     static constexpr int IM = 0, IW = M ? 1 : 0, IS = (M ? 1 : 0) + (W ? 1 : 0);
+    static constexpr int NV = NS + (K ? 4 : 0);                           // accumulators per entry
 };
 
 struct Lame {
@@ -382,8 +383,104 @@ __global__ __launch_bounds__(WAVE) void k_rows_numeric(
 // adds each triangle's terms into slots p1 / p2), so LDS only stages the
 // gathered coordinates and the triangle positions, and is then reused to
 // transpose the accumulators for coalesced stores.  Far more waves fit per CU
-// than with LDS accumulators.  Lanes whose row is longer than LMAX take the
-// per-lane global-memory path; the order of additions is the same everywhere.
+// than with LDS accumulators.
+//
+// The scalar operators and the elasticity blocks are summed in two phases
+// over the same staged tile: the gathers are paid once, and the registers
+// held at any time are those of one phase (3 x LMAX or 4 x LMAX
+// accumulators, not 7 x LMAX).  Lanes whose row is longer than LMAX, or whose
+// tile does not fit the stage, sum LMAX entries at a time from global memory;
+// the order of additions is the same everywhere.
+
+// Adds the row terms of one triangle (owner x0, the other two vertices at row
+// slots p1 / p2) to the slot registers and to the diagonal sums.
+template <int PM, int LMAX>
+__device__ __forceinline__ void add_tri(double x0, double y0, double x1, double y1, double x2,
+                                        double y2, double w0, double w1, double w2, Lame L,
+                                        int32_t p1, int32_t p2, double (&acc)[Ops<PM>::NV][LMAX],
+                                        double (&dg)[Ops<PM>::NV]) {
+    using O = Ops<PM>;
+    double c[O::NS > 0 ? O::NS : 1][3];
+    double ce[3][4];
+    elem_row<PM>(x0, y0, x1, y1, x2, y2, w0, w1, w2, L, c, ce);
+#pragma unroll
+    for (int m = 0; m < O::NS; ++m) dg[m] += c[m][0];
+    if constexpr (O::K) {
+#pragma unroll
+        for (int z = 0; z < 4; ++z) dg[O::NS + z] += ce[0][z];
+    }
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+        const bool h1 = k == p1, h2 = k == p2;
+#pragma unroll
+        for (int m = 0; m < O::NS; ++m) acc[m][k] += h1 ? c[m][1] : (h2 ? c[m][2] : 0.0);
+        if constexpr (O::K) {
+#pragma unroll
+            for (int z = 0; z < 4; ++z) acc[O::NS + z][k] += h1 ? ce[1][z] : (h2 ? ce[2][z] : 0.0);
+        }
+    }
+}
+
+// Row sums of the operators in PM from the staged tile (zero when the lane's
+// row is not summed here); the diagonal slot pd gets its sums last.
+template <int PM, int LMAX>
+__device__ __forceinline__ void tile_sum(bool in_regs, const double2 *s_q, const double *s_w,
+                                         const uint32_t *s_ip, int32_t off, int32_t t0, int32_t t1,
+                                         int32_t pd, double2 x0, double w0, Lame L,
+                                         double (&acc)[Ops<PM>::NV][LMAX]) {
+    using O = Ops<PM>;
+#pragma unroll
+    for (int v = 0; v < O::NV; ++v)
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k) acc[v][k] = 0.0;
+    if (!in_regs) return;
+    double dg[O::NV];
+#pragma unroll
+    for (int v = 0; v < O::NV; ++v) dg[v] = 0.0;
+    for (int32_t t = t0; t < t1; ++t) {
+        const uint32_t pp = s_ip[t];
+        const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
+        const double2 x1 = s_q[off + p1], x2 = s_q[off + p2];
+        add_tri<PM, LMAX>(x0.x, x0.y, x1.x, x1.y, x2.x, x2.y, w0, O::W ? s_w[off + p1] : 0.0,
+                          O::W ? s_w[off + p2] : 0.0, L, p1, p2, acc, dg);
+    }
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k)
+        if (k == pd) {
+#pragma unroll
+            for (int v = 0; v < O::NV; ++v) acc[v][k] += dg[v];
+        }
+}
+
+// Row entries [c0, c0 + LMAX) of the operators in PM, summed from global
+// memory over the lane's triangles in the same order as tile_sum.
+template <int PM, int LMAX>
+__device__ __forceinline__ void chunk_sum(const double *q, const double *w, const int32_t *cr,
+                                          const uint32_t *inc_pos, int32_t is, int32_t ie,
+                                          int32_t c0, int32_t pd, double x0, double y0, double w0,
+                                          Lame L, double (&ch)[Ops<PM>::NV][LMAX]) {
+    using O = Ops<PM>;
+#pragma unroll
+    for (int v = 0; v < O::NV; ++v)
+#pragma unroll
+        for (int k = 0; k < LMAX; ++k) ch[v][k] = 0.0;
+    double dg[O::NV];
+#pragma unroll
+    for (int v = 0; v < O::NV; ++v) dg[v] = 0.0;
+    for (int32_t t = is; t < ie; ++t) {
+        const uint32_t pp = inc_pos[t];
+        const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
+        const int64_t j1 = cr[p1], j2 = cr[p2];
+        add_tri<PM, LMAX>(x0, y0, q[2 * j1], q[2 * j1 + 1], q[2 * j2], q[2 * j2 + 1], w0,
+                          O::W ? w[j1] : 0.0, O::W ? w[j2] : 0.0, L, p1 - c0, p2 - c0, ch, dg);
+    }
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k)
+        if (c0 + k == pd) {
+#pragma unroll
+            for (int v = 0; v < O::NV; ++v) ch[v][k] += dg[v];
+        }
+}
 
 template <int MASK, int U, int LMAX>
 __global__ __launch_bounds__(WAVE) void k_rows_reg(
@@ -392,17 +489,20 @@ __global__ __launch_bounds__(WAVE) void k_rows_reg(
     const int32_t *__restrict__ col_idx, const int32_t *__restrict__ inc_ptr,
     const uint32_t *__restrict__ inc_pos, Outs out, Lame L, int accumulate, int64_t ntiles) {
     using O = Ops<MASK>;
+    constexpr int MS = MASK & (M_BIT | W_BIT | S_BIT);   // scalar operators (phase 1)
     constexpr int NS = O::NS;
-    constexpr int NSA = NS > 0 ? NS : 1;
-    constexpr int NV = NS + (O::K ? 4 : 0);      // accumulators per entry
     constexpr int EB = U * WAVE;
-    // LDS: stage [EB] (24 or 32 B per entry: q (16) + w (8), reused to
-    // transpose the outputs, 4 doubles per entry when K is requested) | ipos
+    // LDS: stage [EB] | ipos [EB].  The stage holds q (16 B) and w (8 B) of
+    // each entry; with K it is 32 B per entry, the 4 doubles of the K
+    // transposition, and its last 8 B are the scalar transposition buffer
+    // (the staged coordinates must outlive phase 1).  Without K the scalar
+    // transposition reuses the stage.
     constexpr int SD = O::K ? 4 : (O::W ? 3 : 2); // doubles per entry in the stage
     extern __shared__ double smem[];
     double *s_stage = smem;
     double2 *s_q = reinterpret_cast<double2 *>(smem);
     double *s_w = smem + 2 * EB;
+    double *s_t = O::K ? smem + 3 * EB : smem;
     uint32_t *s_ip = reinterpret_cast<uint32_t *>(smem + SD * EB);
     const int lane = threadIdx.x;
     const double2 *q2 = reinterpret_cast<const double2 *>(q);
@@ -462,105 +562,65 @@ __global__ __launch_bounds__(WAVE) void k_rows_reg(
             }
             __syncthreads();
         }
-        // ---- each lane sums its row (registers when it fits)
         const bool in_regs = tile_fits && active && len > 0 && len <= LMAX;
-        double acc[NV][LMAX];
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int k = 0; k < LMAX; ++k) acc[v][k] = 0.0;
+        // rows not summed in registers stage zeros in the tile stores (their
+        // lane writes them after the tile, below)
+        const bool zero_row = !in_regs && active && len > 0;
+        const int32_t off = rs - E0;
+        int32_t pd = 0;
+        double2 x0 = make_double2(0.0, 0.0);
+        double w0 = 0.0;
         if (in_regs) {
-            const int32_t off = rs - E0;
             uint64_t seen = 0;
             for (int32_t t = is - I0; t < ie - I0; ++t) {
                 const uint32_t pp = s_ip[t];
                 seen |= (1ull << (pp & 0xffffu)) | (1ull << (pp >> 16));
             }
-            const int32_t pd = __builtin_ctzll(~seen);
-            const double2 x0 = s_q[off + pd];
-            const double w0 = O::W ? s_w[off + pd] : 0.0;
-            double dg[NSA], dk[4] = {0.0, 0.0, 0.0, 0.0};
+            pd = __builtin_ctzll(~seen);
+            x0 = s_q[off + pd];
+            if constexpr (O::W) w0 = s_w[off + pd];
+        }
+        if constexpr (MS != 0) {
+            // ---- phase 1: scalar operators, one transposition per operator
+            double acc[NS][LMAX];
+            tile_sum<MS, LMAX>(in_regs, s_q, s_w, s_ip, off, is - I0, ie - I0, pd, x0, w0, L, acc);
+            if (tile_fits) {
+                if constexpr (!O::K) __syncthreads();   // s_t is the stage: all reads done
 #pragma unroll
-            for (int m = 0; m < NSA; ++m) dg[m] = 0.0;
-            for (int32_t t = is - I0; t < ie - I0; ++t) {
-                const uint32_t pp = s_ip[t];
-                const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
-                const double2 x1 = s_q[off + p1], x2 = s_q[off + p2];
-                double c[NSA][3];
-                double ce[3][4];
-                elem_row<MASK>(x0.x, x0.y, x1.x, x1.y, x2.x, x2.y, w0,
-                               O::W ? s_w[off + p1] : 0.0, O::W ? s_w[off + p2] : 0.0, L, c, ce);
+                for (int m = 0; m < NS; ++m) {
+                    if (in_regs) {
 #pragma unroll
-                for (int m = 0; m < NS; ++m) dg[m] += c[m][0];
-                if constexpr (O::K) {
-#pragma unroll
-                    for (int z = 0; z < 4; ++z) dk[z] += ce[0][z];
-                }
-#pragma unroll
-                for (int k = 0; k < LMAX; ++k) {
-                    const bool h1 = k == p1, h2 = k == p2;
-#pragma unroll
-                    for (int m = 0; m < NS; ++m) {
-                        const double a = h1 ? c[m][1] : (h2 ? c[m][2] : 0.0);
-                        acc[m][k] += a;
+                        for (int k = 0; k < LMAX; ++k)
+                            if (k < len) s_t[off + k] = acc[m][k];
+                    } else if (zero_row) {
+                        for (int k = 0; k < len; ++k) s_t[off + k] = 0.0;
                     }
-                    if constexpr (O::K) {
-#pragma unroll
-                        for (int z = 0; z < 4; ++z) {
-                            const double a = h1 ? ce[1][z] : (h2 ? ce[2][z] : 0.0);
-                            acc[NS + z][k] += a;
-                        }
+                    __syncthreads();
+                    double *o = out.o[m] + E0;
+                    for (int e = lane; e < Ew; e += WAVE) {
+                        const double v = s_t[e];
+                        if (accumulate) o[e] += v;
+                        else __builtin_nontemporal_store(v, o + e);
                     }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < LMAX; ++k) {
-                if (k == pd) {
-#pragma unroll
-                    for (int m = 0; m < NS; ++m) acc[m][k] += dg[m];
-                    if constexpr (O::K) {
-#pragma unroll
-                        for (int z = 0; z < 4; ++z) acc[NS + z][k] += dk[z];
-                    }
+                    __syncthreads();
                 }
             }
         }
-        if (tile_fits) {
-            // ---- transpose through LDS, coalesced stores (rows in registers);
-            // rows in the fallback write their own entries below
-            __syncthreads();   // everyone is done reading the staged coordinates
-            const int32_t off = rs - E0;
-            // rows not in registers stage zeros here (their lane writes them
-            // after the tile, below)
-            const bool zero_row = !in_regs && active && len > 0;
-#pragma unroll
-            for (int m = 0; m < NS; ++m) {
-                if (in_regs) {
-#pragma unroll
-                    for (int k = 0; k < LMAX; ++k)
-                        if (k < len) s_stage[off + k] = acc[m][k];
-                } else if (zero_row) {
-                    for (int k = 0; k < len; ++k) s_stage[off + k] = 0.0;
-                }
-                __syncthreads();
-                double *o = out.o[m] + E0;
-                for (int e = lane; e < Ew; e += WAVE) {
-                    const double v = s_stage[e];
-                    if (accumulate) o[e] += v;
-                    else __builtin_nontemporal_store(v, o + e);
-                }
-                __syncthreads();
-            }
-            if constexpr (O::K) {
+        if constexpr (O::K) {
+            // ---- phase 2: elasticity 2x2 blocks from the same staged tile
+            double acc[4][LMAX];
+            tile_sum<K_BIT, LMAX>(in_regs, s_q, s_w, s_ip, off, is - I0, ie - I0, pd, x0, w0, L, acc);
+            if (tile_fits) {
+                __syncthreads();   // everyone is done reading the staged coordinates
                 if (in_regs) {
                     // row 2i: [4 off + 2k + beta], row 2i+1: [4 off + 2 len + 2k + beta]
 #pragma unroll
                     for (int k = 0; k < LMAX; ++k)
                         if (k < len) {
-                            s_stage[4 * off + 2 * k] = acc[NS + 0][k];
-                            s_stage[4 * off + 2 * k + 1] = acc[NS + 1][k];
-                            s_stage[4 * off + 2 * len + 2 * k] = acc[NS + 2][k];
-                            s_stage[4 * off + 2 * len + 2 * k + 1] = acc[NS + 3][k];
+                            s_stage[4 * off + 2 * k] = acc[0][k];
+                            s_stage[4 * off + 2 * k + 1] = acc[1][k];
+                            s_stage[4 * off + 2 * len + 2 * k] = acc[2][k];
+                            s_stage[4 * off + 2 * len + 2 * k + 1] = acc[3][k];
                         }
                 } else if (zero_row) {
                     for (int k = 0; k < 4 * len; ++k) s_stage[4 * off + k] = 0.0;
@@ -575,86 +635,48 @@ __global__ __launch_bounds__(WAVE) void k_rows_reg(
                 __syncthreads();
             }
         }
-        if (!in_regs && active && len > 0) {
+        if (zero_row) {
             // ---- long row or tile too large: the lane's own row, LMAX
-            // entries at a time in registers.  Each chunk is summed from zero
-            // over the triangles in the same order as the register path, then
-            // stored (or added), so a row's values do not depend on the path
-            // it takes.  The tile stores above wrote 0 (or added 0) at this
-            // row, and the workgroup barrier after them made those stores
-            // complete before these.
+            // entries at a time, each chunk summed from zero over the
+            // triangles in the register path's order and then stored (or
+            // added), so a row's values do not depend on the path it takes.
+            // The tile stores above wrote 0 (or added 0) at this row, and the
+            // workgroup barrier after them made those stores complete first.
             const int32_t *cr = col_idx + rs;
-            int32_t pd = 0;
-            while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
-            const double x0 = q[2 * i], y0 = q[2 * i + 1];
-            const double w0 = O::W ? w[i] : 0.0;
+            int32_t pdg = 0;
+            while (pdg < len - 1 && cr[pdg] != (int32_t)i) ++pdg;
+            const double xg = q[2 * i], yg = q[2 * i + 1];
+            const double wg = O::W ? w[i] : 0.0;
             for (int32_t c0 = 0; c0 < len; c0 += LMAX) {
-                double ch[NV][LMAX];
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-#pragma unroll
-                    for (int k = 0; k < LMAX; ++k) ch[v][k] = 0.0;
-                double dg[NSA], dk[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int m = 0; m < NSA; ++m) dg[m] = 0.0;
-                for (int32_t t = is; t < ie; ++t) {
-                    const uint32_t pp = inc_pos[t];
-                    const int32_t p1 = (int32_t)(pp & 0xffffu) - c0, p2 = (int32_t)(pp >> 16) - c0;
-                    const int64_t j1 = cr[p1 + c0], j2 = cr[p2 + c0];
-                    double c[NSA][3];
-                    double ce[3][4];
-                    elem_row<MASK>(x0, y0, q[2 * j1], q[2 * j1 + 1], q[2 * j2], q[2 * j2 + 1], w0,
-                                   O::W ? w[j1] : 0.0, O::W ? w[j2] : 0.0, L, c, ce);
-#pragma unroll
-                    for (int m = 0; m < NS; ++m) dg[m] += c[m][0];
-                    if constexpr (O::K) {
-#pragma unroll
-                        for (int z = 0; z < 4; ++z) dk[z] += ce[0][z];
-                    }
+                if constexpr (MS != 0) {
+                    double ch[NS][LMAX];
+                    chunk_sum<MS, LMAX>(q, w, cr, inc_pos, is, ie, c0, pdg, xg, yg, wg, L, ch);
 #pragma unroll
                     for (int k = 0; k < LMAX; ++k) {
-                        const bool h1 = k == p1, h2 = k == p2;
+                        const int32_t e = c0 + k;
+                        if (e >= len) break;
 #pragma unroll
                         for (int m = 0; m < NS; ++m) {
-                            const double a = h1 ? c[m][1] : (h2 ? c[m][2] : 0.0);
-                            ch[m][k] += a;
-                        }
-                        if constexpr (O::K) {
-#pragma unroll
-                            for (int z = 0; z < 4; ++z) {
-                                const double a = h1 ? ce[1][z] : (h2 ? ce[2][z] : 0.0);
-                                ch[NS + z][k] += a;
-                            }
+                            double *o = out.o[m] + rs + e;
+                            if (accumulate) *o += ch[m][k];
+                            else *o = ch[m][k];
                         }
                     }
                 }
+                if constexpr (O::K) {
+                    double ch[4][LMAX];
+                    chunk_sum<K_BIT, LMAX>(q, w, cr, inc_pos, is, ie, c0, pdg, xg, yg, wg, L, ch);
+                    // row 2i: [4 rs + 2e + beta], row 2i+1: [4 rs + 2 len + 2e + beta]
+                    double *ok = out.o[3] + 4 * (int64_t)rs;
 #pragma unroll
-                for (int k = 0; k < LMAX; ++k) {
-                    const int32_t e = c0 + k;
-                    if (e >= len) break;
-                    if (e == pd) {
-#pragma unroll
-                        for (int m = 0; m < NS; ++m) ch[m][k] += dg[m];
-                        if constexpr (O::K) {
-#pragma unroll
-                            for (int z = 0; z < 4; ++z) ch[NS + z][k] += dk[z];
-                        }
-                    }
-#pragma unroll
-                    for (int m = 0; m < NS; ++m) {
-                        double *o = out.o[m] + rs + e;
-                        if (accumulate) *o += ch[m][k];
-                        else *o = ch[m][k];
-                    }
-                    if constexpr (O::K) {
-                        // row 2i: [4 rs + 2e + beta], row 2i+1: [4 rs + 2 len + 2e + beta]
-                        double *ok = out.o[3] + 4 * (int64_t)rs;
-                        const double kv[4] = {ch[NS][k], ch[NS + 1][k], ch[NS + 2][k], ch[NS + 3][k]};
+                    for (int k = 0; k < LMAX; ++k) {
+                        const int32_t e = c0 + k;
+                        if (e >= len) break;
                         const int64_t at[4] = {2 * e, 2 * e + 1, 2 * len + 2 * e, 2 * len + 2 * e + 1};
 #pragma unroll
                         for (int z = 0; z < 4; ++z) {
-                            if (accumulate) ok[at[z]] += kv[z];
-                            else ok[at[z]] = kv[z];
+                            if (accumulate) ok[at[z]] += ch[z][k];
+                            else ok[at[z]] = ch[z][k];
                         }
                     }
                 }
@@ -852,8 +874,14 @@ int run(const char *fn, const Args &a, const fem_tune *tune) {
                 fn, a.nq, a.nme, (long long)a.nnz);
     FEM_REQUIRE(a.nnz <= INT32_MAX && (!(a.ops & K_BIT) || 4 * a.nnz <= INT32_MAX), FEM_EOVERFLOW,
                 "%s: nnz exceeds int32 indexing", fn);
-    FEM_REQUIRE((a.flags & ~(FEM_ATOMIC | FEM_ACCUMULATE | FEM_CHECK_AREA)) == 0, FEM_EINVAL,
-                "%s: unknown flags 0x%x", fn, a.flags);
+    FEM_REQUIRE((a.flags & ~(FEM_ATOMIC | FEM_ACCUMULATE | FEM_CHECK_AREA | FEM_PACKED_QW)) == 0,
+                FEM_EINVAL, "%s: unknown flags 0x%x", fn, a.flags);
+    if (a.flags & FEM_PACKED_QW) {
+        FEM_REQUIRE((a.ops & W_BIT) && !(a.flags & FEM_ATOMIC), FEM_EINVAL,
+                    "%s: FEM_PACKED_QW needs FEM_OP_WMASS and the row-owner scheme", fn);
+        FEM_REQUIRE(a.work && a.work_bytes >= sizeof(double4) * (size_t)a.nq, FEM_ENOSPC,
+                    "%s: FEM_PACKED_QW needs the workspace that holds the packed records", fn);
+    }
     FEM_REQUIRE(a.q && a.row_ptr, FEM_EINVAL, "%s: NULL q or row_ptr", fn);
     for (int b = 0; b < 4; ++b)
         FEM_REQUIRE(!(a.ops & (1 << b)) || a.nnz == 0 || a.vals[b], FEM_EINVAL, "%s: NULL output", fn);
@@ -893,14 +921,17 @@ int run(const char *fn, const Args &a, const fem_tune *tune) {
 
 int run_ops(const Args &a, const fem_tune *tune) {
     // packed (x, y, w) records when the weighted mass is requested and a
-    // workspace is given: one random access per column instead of two
+    // workspace is given: one random access per column instead of two.
+    // FEM_PACKED_QW: the workspace holds them already (same q and w)
     const double4 *qw = nullptr;
     if ((a.ops & W_BIT) && !(a.flags & FEM_ATOMIC) && a.work &&
         a.work_bytes >= sizeof(double4) * (size_t)a.nq) {
         double4 *p = static_cast<double4 *>(a.work);
-        hipLaunchKernelGGL(k_pack_qw, dim3(grid_for(a.nq, 256)), dim3(256), 0, a.s, a.nq,
-                           reinterpret_cast<const double2 *>(a.q), a.w, p);
-        FEM_LAUNCH_CHECK();
+        if (!(a.flags & FEM_PACKED_QW)) {
+            hipLaunchKernelGGL(k_pack_qw, dim3(grid_for(a.nq, 256)), dim3(256), 0, a.s, a.nq,
+                               reinterpret_cast<const double2 *>(a.q), a.w, p);
+            FEM_LAUNCH_CHECK();
+        }
         qw = p;
     }
     switch (a.ops) {

@@ -77,6 +77,19 @@ def test_host_validation_before_any_launch(lib):
     ws = C.c_size_t(0)
     assert lib.fem_assemble_workspace(4, _lib.FEM_OP_WMASS, C.byref(ws)) == _lib.FEM_OK
     assert ws.value == 256 + 256
+    # FEM_PACKED_QW: only with the weighted mass in the row-owner scheme, and
+    # only with the workspace that holds the packed records
+    args = (4, 2, 10, fake, fake, fake, fake, fake, fake, fake, None, 0.0, 0.0, fake, fake, fake,
+            fake)
+    st = lib.fem_assemble(_lib.FEM_OP_STIFF, *args, fake, 4096, None, _lib.FEM_PACKED_QW, None)
+    assert st == _lib.FEM_EINVAL and b"FEM_PACKED_QW" in lib.fem_last_error()
+    st = lib.fem_assemble(_lib.FEM_OP_WMASS, *args, fake, 4096, None,
+                          _lib.FEM_PACKED_QW | _lib.FEM_ATOMIC, None)
+    assert st == _lib.FEM_EINVAL
+    st = lib.fem_assemble(_lib.FEM_OP_WMASS, *args, None, 0, None, _lib.FEM_PACKED_QW, None)
+    assert st == _lib.FEM_ENOSPC and b"FEM_PACKED_QW" in lib.fem_last_error()
+    st = lib.fem_assemble(_lib.FEM_OP_WMASS, *args, fake, 32 * 4 - 8, None, _lib.FEM_PACKED_QW, None)
+    assert st == _lib.FEM_ENOSPC
     # unknown flag bits
     st = lib.fem_assemble_mass(4, 2, 10, fake, fake, fake, fake, fake, fake, None, fake, 64, None)
     assert st == _lib.FEM_EINVAL

@@ -5,6 +5,8 @@ FP64 values within 1e-13 relative per row (max norm).  Full-size workloads
 are checked on sampled rows that the oracle computes one by one, plus
 properties that hold at any size.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -192,6 +194,24 @@ def test_small_lds_tile_takes_the_global_memory_path():
     assert torch.equal(S0, S2) and torch.equal(M0, M2)
 
 
+def test_packed_qw_reuses_the_records():
+    # a second call with FEM_PACKED_QW reads the (x, y, w) records the first
+    # call left in the workspace: same bits, no packing pass
+    m = mg.unit_square(48, seed=12)
+    pat = fem.fem_pattern(_up(m.me), m.nq)
+    qd, wd = _up(m.q), _up(mg.weight_quadratic(m.q))
+    ws = C.c_size_t(0)
+    fem._lib.check(fem._lib.load().fem_assemble_workspace(m.nq, 15, C.byref(ws)))
+    work = torch.empty(int(ws.value), dtype=torch.uint8, device=DEV)
+    a = fem.fem_assemble(pat, qd, 15, w=wd, lam=1.0, mu=0.5, work=work)
+    b = fem.fem_assemble(pat, qd, 15, w=wd, lam=1.0, mu=0.5, work=work, flags=fem.FEM_PACKED_QW)
+    c = fem.fem_assemble(pat, qd, fem.FEM_OP_WMASS, w=wd, work=work, flags=fem.FEM_PACKED_QW)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+    assert torch.equal(c["Mw"], a["Mw"])
+
+
 def test_check_area_flag():
     # three collinear vertices: the element formulas divide by the zero area,
     # FEM_CHECK_AREA reports it as FEM_EDEGEN
@@ -252,7 +272,13 @@ def test_full_size_sampled_rows(cfg):
     S, M = fem.fem_assemble_stiff_mass(pat, qd)
     Mw = fem.fem_assemble_wmass(pat, qd, wd)
     K = fem.fem_assemble_elas(pat, qd, lam, mu)
+    # the timed call: all four operators in one pass, bitwise equal to the
+    # single calls checked against the oracle below
+    allv = fem.fem_assemble(pat, qd, 15, w=wd, lam=lam, mu=mu)
     torch.cuda.synchronize()
+    for k, v in (("M", M), ("Mw", Mw), ("S", S), ("K", K)):
+        assert torch.equal(allv[k], v), k
+    del allv
     rng = np.random.default_rng(cfg)
     rows = _sample_rows(m.nq, rng)
     for op, got in (("stiff", S), ("mass", M), ("wmass", Mw)):
