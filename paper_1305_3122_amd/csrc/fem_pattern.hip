@@ -82,9 +82,9 @@ __device__ inline void max_into(int *dst, int v) {
 // each workgroup of triangles writes one contiguous run per bucket).  Then
 // either
 //   fine buckets (512 vertices): k_bkt_rows does everything for a bucket in
-//     LDS -- counting sort by vertex, per-vertex rows -- and a decoupled
-//     look-back over the buckets gives its offset in col_idx, so row_ptr and
-//     col_idx are written directly;
+//     LDS -- counting sort by vertex, per-vertex rows -- and stages the
+//     bucket's rows; a scan of the bucket totals then gives each bucket's
+//     offset in col_idx, and k_bkt_copy writes row_ptr and col_idx;
 //   coarse buckets (4096 vertices, very large meshes or a bucket too large for
 //     LDS): k_bkt_sort writes the triangle lists, then the per-vertex kernels.
 
@@ -156,20 +156,36 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_count(int32_t nme, const in
     int bad = 0;
     const int64_t k0 = (int64_t)blockIdx.x * tpb;
     const int64_t k1 = (k0 + tpb < nme) ? k0 + tpb : nme;
-#pragma unroll 4
-    for (int64_t k = k0 + threadIdx.x; k < k1; k += BKT_THREADS) {
-        const int32_t a = me[3 * k], b = me[3 * k + 1], c = me[3 * k + 2];
-        if ((uint32_t)a >= (uint32_t)nq || (uint32_t)b >= (uint32_t)nq || (uint32_t)c >= (uint32_t)nq) {
-            bad |= ERR_RANGE;
-            continue;
+    constexpr int H = 16;   // triangles with independent loads in flight per thread
+    for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += H * BKT_THREADS) {
+        int32_t v[H][3];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int64_t k = kb + j * BKT_THREADS;
+            v[j][0] = v[j][1] = v[j][2] = 0;
+            if (k < k1) {
+                v[j][0] = me[3 * k];
+                v[j][1] = me[3 * k + 1];
+                v[j][2] = me[3 * k + 2];
+            }
         }
-        if (a == b || b == c || a == c) {
-            bad |= ERR_DEGEN;
-            continue;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            if (kb + j * BKT_THREADS >= k1) continue;
+            const int32_t a = v[j][0], b = v[j][1], c = v[j][2];
+            if ((uint32_t)a >= (uint32_t)nq || (uint32_t)b >= (uint32_t)nq ||
+                (uint32_t)c >= (uint32_t)nq) {
+                bad |= ERR_RANGE;
+                continue;
+            }
+            if (a == b || b == c || a == c) {
+                bad |= ERR_DEGEN;
+                continue;
+            }
+            atomicAdd(&s_hist[a >> bs], 1);
+            atomicAdd(&s_hist[b >> bs], 1);
+            atomicAdd(&s_hist[c >> bs], 1);
         }
-        atomicAdd(&s_hist[a >> bs], 1);
-        atomicAdd(&s_hist[b >> bs], 1);
-        atomicAdd(&s_hist[c >> bs], 1);
     }
     if (bad) atomicOr(&cnt->err, bad);
     __syncthreads();
@@ -192,7 +208,7 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_scatter(int32_t nme, const 
     __syncthreads();
     const int64_t k0 = (int64_t)blockIdx.x * tpb;
     const int64_t k1 = (k0 + tpb < nme) ? k0 + tpb : nme;
-    constexpr int H = 4;   // triangles with independent loads in flight per thread
+    constexpr int H = 16;   // triangles with independent loads in flight per thread
     for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += H * BKT_THREADS) {
         int32_t v[H][3];
 #pragma unroll
