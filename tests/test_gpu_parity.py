@@ -144,6 +144,39 @@ def test_empty_mesh_and_unused_vertices():
     del me
 
 
+def test_four_operators_with_unused_vertices():
+    # half the vertex ids unused: empty rows between used ones in every tile,
+    # on the one-pass path for all four operators (register path, tile
+    # fallback and accumulation), against the oracle
+    m = mg.unit_square(12, seed=21)
+    rng = np.random.default_rng(21)
+    nq2 = 2 * m.nq
+    ids = rng.permutation(nq2)[:m.nq].astype(np.int32)
+    q2 = rng.uniform(-5.0, 5.0, size=(nq2, 2))
+    q2[ids] = m.q
+    me2 = ids[m.me]
+    w = rng.uniform(0.5, 2.0, size=nq2)
+    print(f"[case] unused vertices nq={nq2} nme={me2.shape[0]}", flush=True)
+    P = oracle.pattern(nq2, me2)
+    pat = fem.fem_pattern(_up(me2), nq2)
+    _check_pattern(pat, P, me2)
+    rpe, cie, se = oracle.pattern_elas(nq2, me2)
+    ref = {"M": oracle.assemble("mass", q2, me2, P.slot, P.nnz),
+           "Mw": oracle.assemble("wmass", q2, me2, P.slot, P.nnz, w=w),
+           "S": oracle.assemble("stiff", q2, me2, P.slot, P.nnz),
+           "K": oracle.assemble("elas", q2, me2, se, int(rpe[-1]), lam=LAM, mu=MU)}
+    qd, wd = _up(q2), _up(w)
+    a = fem.fem_assemble(pat, qd, 15, w=wd, lam=LAM, mu=MU)
+    b = fem.fem_assemble(pat, qd, 15, w=wd, lam=LAM, mu=MU, tune=fem.fem_tune(256, 0))
+    c = {k: v.clone() for k, v in a.items()}
+    fem.fem_assemble(pat, qd, 15, w=wd, lam=LAM, mu=MU, out=c, flags=fem.FEM_ACCUMULATE)
+    torch.cuda.synchronize()
+    for k in ref:
+        assert row_rel_err(rpe if k == "K" else P.row_ptr, _np(a[k]), ref[k]) <= RTOL_ROW, k
+        assert torch.equal(b[k], a[k]), k
+        assert torch.equal(c[k], 2 * a[k]), k
+
+
 def test_deterministic_bitwise_and_accumulate():
     m = mg.unit_disk(40, seed=9)
     pat = fem.fem_pattern(_up(m.me), m.nq)
