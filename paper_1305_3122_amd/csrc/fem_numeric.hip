@@ -492,10 +492,11 @@ __global__ __launch_bounds__(WAVE) void k_rows_reg(
     constexpr int MS = MASK & (M_BIT | W_BIT | S_BIT);   // scalar operators (phase 1)
     constexpr int NS = O::NS;
     constexpr int EB = U * WAVE;
-    // LDS: stage [EB] | ipos [EB].  The stage holds q (16 B) and w (8 B) of
-    // each entry; with K it is 32 B per entry, the 4 doubles of the K
-    // transposition, and its last 8 B are the scalar transposition buffer
-    // (the staged coordinates must outlive phase 1).  Without K the scalar
+    // LDS: stage [SD EB doubles] | ipos [EB words].  The stage holds q
+    // (doubles [0, 2 EB)) and w ([2 EB, 3 EB)).  With K it has 4 EB doubles:
+    // [3 EB, 4 EB) is the scalar transposition buffer (the staged coordinates
+    // must outlive phase 1), and the whole stage takes the K transposition (4
+    // doubles per entry) once phase 2 has summed.  Without K the scalar
     // transposition reuses the stage.
     constexpr int SD = O::K ? 4 : (O::W ? 3 : 2); // doubles per entry in the stage
     extern __shared__ double smem[];
