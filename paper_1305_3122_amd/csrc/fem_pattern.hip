@@ -618,7 +618,20 @@ __global__ __launch_bounds__(256) void k_bkt_copy(int32_t nq, int32_t nbkt, int3
         return;
     }
     const int32_t *src = stage + 2 * e0 + v0;
-    for (int i = threadIdx.x; i < T; i += 256) col_idx[P + i] = src[i];
+    constexpr int H = 8;   // loads in flight per thread
+    for (int i0 = threadIdx.x; i0 < T; i0 += H * 256) {
+        int32_t x[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int i = i0 + j * 256;
+            x[j] = i < T ? src[i] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int i = i0 + j * 256;
+            if (i < T) col_idx[P + i] = x[j];
+        }
+    }
 }
 
 // Per-lane LDS arrays are stored [slot][lane] so that the 64 lanes of a wave
@@ -930,7 +943,7 @@ __global__ __launch_bounds__(256) void k_transpose(int32_t nq, const int32_t *__
     }
 }
 
-constexpr int ELAS_STAGE = 8 * WAVE;   // scalar entries of a tile staged in LDS (8 KiB)
+constexpr int ELAS_STAGE = 8 * WAVE;   // scalar entries of a tile staged in LDS (2 + 8 KiB)
 
 // Tile of 64 scalar rows = a contiguous slice of Ew scalar entries and of
 // 4 Ew elasticity entries.  One lane per scalar entry (coalesced read of
@@ -942,7 +955,9 @@ __global__ __launch_bounds__(WAVE) void k_elas_pattern(int32_t nq, const int32_t
                                                        int32_t *__restrict__ row_ptr_e,
                                                        int32_t *__restrict__ col_idx_e,
                                                        int aligned16) {
+    constexpr int U = ELAS_STAGE / WAVE;
     __shared__ int32_t s_rs[WAVE + 1];
+    __shared__ int32_t s_col[ELAS_STAGE];
     __shared__ __align__(16) int32_t s_out[4 * ELAS_STAGE];
     const int lane = threadIdx.x;
     const int64_t r0 = blockIdx.x * (int64_t)WAVE;
@@ -958,10 +973,43 @@ __global__ __launch_bounds__(WAVE) void k_elas_pattern(int32_t nq, const int32_t
     }
     if (r0 + nr == nq && lane == 0) row_ptr_e[2 * (int64_t)nq] = 4 * s_rs[nr];
     const int32_t E0 = s_rs[0], Ew = s_rs[nr] - E0;
-    // tiles of at most ELAS_STAGE entries are assembled in LDS and written
-    // as int4 (the tile's output starts at 4 E0 ints: 16-byte aligned when
-    // col_idx_e is)
-    const bool staged = aligned16 && Ew <= ELAS_STAGE;
+    // tiles of at most ELAS_STAGE entries: the tile's columns are loaded with
+    // all loads in flight, each lane expands its own row in LDS, and the
+    // tile's output (from 4 E0 ints: 16-byte aligned when col_idx_e is) is
+    // written as int4
+    if (aligned16 && Ew <= ELAS_STAGE) {
+        int32_t cv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = lane + u * WAVE;
+            cv[u] = e < Ew ? __builtin_nontemporal_load(col_idx + E0 + e) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = lane + u * WAVE;
+            if (e < Ew) s_col[e] = cv[u];
+        }
+        __syncthreads();
+        if (lane < nr) {
+            // row 2i: [4 off + 2k + beta], row 2i+1: [4 off + 2 L + 2k + beta]
+            const int32_t off = s_rs[lane] - E0, L = s_rs[lane + 1] - s_rs[lane];
+            int2 *o0 = reinterpret_cast<int2 *>(s_out + 4 * off);
+            int2 *o1 = reinterpret_cast<int2 *>(s_out + 4 * off + 2 * L);
+            for (int32_t k = 0; k < L; ++k) {
+                const int32_t c = s_col[off + k];
+                const int2 v = make_int2(2 * c, 2 * c + 1);
+                o0[k] = v;
+                o1[k] = v;
+            }
+        }
+        __syncthreads();
+        typedef int v4i __attribute__((ext_vector_type(4)));
+        v4i *dst = reinterpret_cast<v4i *>(col_idx_e + 4 * (int64_t)E0);
+        const v4i *src = reinterpret_cast<const v4i *>(s_out);
+        for (int32_t t = lane; t < Ew; t += WAVE) __builtin_nontemporal_store(src[t], dst + t);
+        return;
+    }
+    // otherwise one lane per scalar entry, int2 stores straight to col_idx_e
     for (int32_t e = lane; e < Ew; e += WAVE) {
         const int32_t g = E0 + e;
         const int32_t c = col_idx[g];
@@ -974,16 +1022,9 @@ __global__ __launch_bounds__(WAVE) void k_elas_pattern(int32_t nq, const int32_t
         }
         const int32_t rs = s_rs[lo], L = s_rs[lo + 1] - rs, k = g - rs;
         const int2 v = make_int2(2 * c, 2 * c + 1);
-        int32_t *base = staged ? s_out + 4 * (rs - E0) + 2 * k : col_idx_e + 4 * (int64_t)rs + 2 * k;
+        int32_t *base = col_idx_e + 4 * (int64_t)rs + 2 * k;
         *reinterpret_cast<int2 *>(base) = v;
         *reinterpret_cast<int2 *>(base + 2 * L) = v;
-    }
-    if (staged) {
-        __syncthreads();
-        typedef int v4i __attribute__((ext_vector_type(4)));
-        v4i *dst = reinterpret_cast<v4i *>(col_idx_e + 4 * (int64_t)E0);
-        const v4i *src = reinterpret_cast<const v4i *>(s_out);
-        for (int32_t t = lane; t < Ew; t += WAVE) __builtin_nontemporal_store(src[t], dst + t);
     }
 }
 
