@@ -674,10 +674,26 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_copy(
             if (threadIdx.x == 0) atomicOr(&cnt->err, SP_ERR_NOSPC);
             continue;
         }
-        for (int32_t x = threadIdx.x; x < T; x += SP_THREADS) {
-            col_idx[P + x] = stage_col[e0 + x];
-            if (vals) vals[P + x] = stage_val[e0 + x];
-            if (contrib_ptr) contrib_ptr[P + x] = stage_cptr[e0 + x];
+        constexpr int H = 4;   // entries with their loads in flight per thread
+        for (int32_t x0 = threadIdx.x; x0 < T; x0 += H * SP_THREADS) {
+            int32_t c[H], cp[H];
+            double v[H];
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const int32_t x = x0 + j * SP_THREADS;
+                const bool in = x < T;
+                c[j] = in ? stage_col[e0 + x] : 0;
+                v[j] = (in && vals) ? stage_val[e0 + x] : 0.0;
+                cp[j] = (in && contrib_ptr) ? stage_cptr[e0 + x] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const int32_t x = x0 + j * SP_THREADS;
+                if (x >= T) continue;
+                col_idx[P + x] = c[j];
+                if (vals) vals[P + x] = v[j];
+                if (contrib_ptr) contrib_ptr[P + x] = cp[j];
+            }
         }
     }
 }
