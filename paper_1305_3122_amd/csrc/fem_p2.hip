@@ -231,26 +231,45 @@ __global__ __launch_bounds__(256) void k_p2_sum(int64_t nnz, const int32_t *__re
     const uint32_t nt = 36u * (uint32_t)nme;
     double am = 0.0, as = 0.0;
     const int32_t i0 = cptr[p], i1 = cptr[p + 1];
-    for (int32_t i = i0; i < i1; ++i) {
-        const int32_t t = contrib[i];
-        if ((uint32_t)t >= nt) continue;   // not a triplet of these nme triangles
-        // r = t / nme: the double quotient is off by at most one
-        int32_t r = (int32_t)((double)t * inv_nme);
-        int32_t k = t - r * nme;
-        if (k < 0) {
-            --r;
-            k += nme;
-        } else if (k >= nme) {
-            ++r;
-            k -= nme;
+    // H contributors at a time: their triplet ids, then their element
+    // records, all loads in flight; the terms are then added in ascending
+    // order, as one at a time would
+    constexpr int H = 4;
+    const double *edx = reinterpret_cast<const double *>(ed);
+    for (int32_t i = i0; i < i1; i += H) {
+        int32_t tt[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) tt[j] = i + j < i1 ? contrib[i + j] : -1;
+        bool ok[H];
+        uint32_t w[H];
+        double4 e[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int32_t t = tt[j];
+            // past the list, or not a triplet of these nme triangles
+            ok[j] = (uint32_t)t < nt;
+            w[j] = 0;
+            e[j] = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (!ok[j]) continue;
+            // r = t / nme: the double quotient is off by at most one
+            int32_t r = (int32_t)((double)t * inv_nme);
+            int32_t k = t - r * nme;
+            if (k < 0) {
+                --r;
+                k += nme;
+            } else if (k >= nme) {
+                ++r;
+                k -= nme;
+            }
+            w[j] = tab[r];
+            if constexpr (MASK & P2_S) e[j] = ed[k];
+            else e[j].x = edx[4 * (int64_t)k];
         }
-        const uint32_t w = tab[r];
-        if constexpr (MASK & P2_S) {
-            const double4 e = ed[k];
-            if (MASK & P2_M) am += sbyte(w, 0) * e.x;
-            as += sbyte(w, 1) * e.y + sbyte(w, 2) * e.z + sbyte(w, 3) * e.w;
-        } else {
-            am += sbyte(w, 0) * ed[k].x;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            if (!ok[j]) continue;
+            if (MASK & P2_M) am += sbyte(w[j], 0) * e[j].x;
+            if (MASK & P2_S) as += sbyte(w[j], 1) * e[j].y + sbyte(w[j], 2) * e[j].z + sbyte(w[j], 3) * e[j].w;
         }
     }
     if (MASK & P2_M) {
