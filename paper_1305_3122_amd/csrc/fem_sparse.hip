@@ -707,7 +707,20 @@ __global__ __launch_bounds__(256) void k_sp_values(int64_t nnz, const int32_t *_
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= nnz) return;
     double acc = 0.0;
-    for (int32_t k = cptr[p]; k < cptr[p + 1]; ++k) acc += V[contrib[k]];
+    // H contributors at a time, all loads in flight, added in ascending order
+    constexpr int H = 4;
+    const int32_t k0 = cptr[p], k1 = cptr[p + 1];
+    for (int32_t k = k0; k < k1; k += H) {
+        int32_t c[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) c[j] = k + j < k1 ? contrib[k + j] : -1;
+        double x[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) x[j] = c[j] >= 0 ? V[c[j]] : 0.0;
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+            if (c[j] >= 0) acc += x[j];
+    }
     if (accumulate) vals[p] += acc;
     else vals[p] = acc;
 }

@@ -142,23 +142,45 @@ __global__ __launch_bounds__(256) void k_tet_sum(int64_t nnz, const int32_t *__r
     const uint32_t ntr = 16u * (uint32_t)nme;
     double am = 0.0, as = 0.0;
     const int32_t k0 = cptr[p], k1 = cptr[p + 1];
-    for (int32_t k = k0; k < k1; ++k) {
-        const int32_t tc = contrib[k];
-        if ((uint32_t)tc >= ntr) continue;   // not a triplet of these nme elements
-        // r = tc / nme: the double quotient is off by at most one
-        int32_t rq = (int32_t)((double)tc * inv_nme);
-        int32_t e = tc - rq * nme;
-        if (e < 0) {
-            --rq;
-            e += nme;
-        } else if (e >= nme) {
-            ++rq;
-            e -= nme;
+    // H contributors at a time: their triplet ids, then the record values
+    // they read, all loads in flight; the terms are then added in ascending
+    // order, as one at a time would
+    constexpr int H = 8;
+    for (int32_t k = k0; k < k1; k += H) {
+        int32_t tc[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) tc[j] = k + j < k1 ? contrib[k + j] : -1;
+        bool ok[H], diag[H];
+        double xm[H], xs[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            // past the list, or not a triplet of these nme elements
+            ok[j] = (uint32_t)tc[j] < ntr;
+            diag[j] = false;
+            xm[j] = xs[j] = 0.0;
+            if (!ok[j]) continue;
+            // r = tc / nme: the double quotient is off by at most one
+            int32_t rq = (int32_t)((double)tc[j] * inv_nme);
+            int32_t e = tc[j] - rq * nme;
+            if (e < 0) {
+                --rq;
+                e += nme;
+            } else if (e >= nme) {
+                ++rq;
+                e -= nme;
+            }
+            const int a = rq & 3, b = rq >> 2;
+            const double *rec = kg + R::N * (int64_t)e;
+            diag[j] = a == b;
+            if constexpr (R::M) xm[j] = rec[0];
+            if constexpr ((MASK & TET_S) != 0) xs[j] = rec[R::M + tet_sym(min(a, b), max(a, b))];
         }
-        const int a = rq & 3, b = rq >> 2;
-        const double *rec = kg + R::N * (int64_t)e;
-        if constexpr (R::M) am += a == b ? 2.0 * rec[0] : rec[0];
-        if constexpr ((MASK & TET_S) != 0) as += rec[R::M + tet_sym(min(a, b), max(a, b))];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            if (!ok[j]) continue;
+            if constexpr (R::M) am += diag[j] ? 2.0 * xm[j] : xm[j];
+            if constexpr ((MASK & TET_S) != 0) as += xs[j];
+        }
     }
     if (MASK & TET_M) {
         if (accumulate) vm[p] += am;
