@@ -161,6 +161,9 @@ def test_four_operators_with_unused_vertices():
     pat = fem.fem_pattern(_up(me2), nq2)
     _check_pattern(pat, P, me2)
     rpe, cie, se = oracle.pattern_elas(nq2, me2)
+    grpe, gcie = fem.fem_elas_pattern(pat)
+    np.testing.assert_array_equal(_np(grpe), rpe)
+    np.testing.assert_array_equal(_np(gcie), cie)
     ref = {"M": oracle.assemble("mass", q2, me2, P.slot, P.nnz),
            "Mw": oracle.assemble("wmass", q2, me2, P.slot, P.nnz, w=w),
            "S": oracle.assemble("stiff", q2, me2, P.slot, P.nnz),
