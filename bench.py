@@ -71,6 +71,9 @@ PROFILE_SOURCES = {
     "sparse_optv2_square2048": ("fem_common.hip", "fem_internal.h", "fem_sparse.hip"),
     "p2_square2048": ("fem_common.hip", "fem_internal.h", "fem_sparse.hip", "fem_p2.hip"),
     "tet_cube128": ("fem_common.hip", "fem_internal.h", "fem_sparse.hip", "fem_tet.hip"),
+    "adjoint_square512": ("fem_common.hip", "fem_internal.h", "fem_pattern.hip", "fem_numeric.hip",
+                          "fem_adjoint.hip"),
+    "batched_512meshes": ("fem_common.hip", "fem_internal.h", "fem_pattern.hip", "fem_numeric.hip"),
 }
 
 
@@ -144,12 +147,52 @@ PROFILE_TITLES = {
                     "relabelling), nnz 31,802,497; 5 patterns (201M triplets), 11 mass + stiffness\n"
                     "assemblies; FP64 values, int32 indices.  The 1 GiB fill and copy calibrate the\n"
                     "counters."),
+    "adjoint_square512": ("the adjoints on the 512x512-cell unit square",
+                          "Workload: 524,288 triangles, 263,169 vertices (jitter 0.2h, random vertex\n"
+                          "relabelling), nnz 1,838,081; FP64.  S + Mw forward and its adjoint (dq, dw),\n"
+                          "then K forward and its adjoint (dq, dlambda, dmu): 5 warm-up and 200 timed\n"
+                          "calls of each forward, each backward and each forward + backward.  The 1 GiB\n"
+                          "fill and copy calibrate the counters."),
+    "batched_512meshes": ("512 meshes assembled as one block-diagonal matrix",
+                          "Workload: 512 unit squares of 8 to 512 cells per side (log-uniform, seeded),\n"
+                          "16,010,429 vertices and 31,776,926 triangles in all; S + M FP64.  The batch\n"
+                          "pattern, the autotuner's trial launches, 13 replays of the graph-captured\n"
+                          "batched launch, the 512 per-mesh patterns, 13 loops of 512 per-mesh launches\n"
+                          "and 13 replays of that loop captured in a graph.  The 1 GiB fill and copy\n"
+                          "calibrate the counters."),
 }
+
+
+# the bench.py run each profile covers: (short name of the output folders, arguments)
+PROFILE_RUNS = {
+    "step_square2048": ("step", "--steps 5 --warmup 1 --no-cpu --no-extras --calib"),
+    "sparse_optv2_square2048": ("sparse", "--only sparse --calib"),
+    "p2_square2048": ("p2", "--only p2 --calib"),
+    "tet_cube128": ("tet", "--only tet --calib"),
+    "adjoint_square512": ("adjoint", "--only adjoint --calib"),
+    "batched_512meshes": ("batched", "--only batched --calib"),
+}
+
+
+def profile_command(name):
+    """The commands that produce the profiles/ summaries of `name`."""
+    key, args = PROFILE_RUNS[name]
+    run = f"python3 $ROOT/bench.py {args}"
+    out = "$ROOT/gpurun_out/" + key
+    return "\n".join([
+        "cd /tmp && export TMPDIR=/tmp",
+        f"rocprofv3 --kernel-trace --stats --output-format csv -d {out}_kt -o run -- {run}",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}_pf -o run -- {run}",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}_pw -o run -- {run}",
+        f"cd $ROOT && python3 bench.py --summarize gpurun_out/{key}_kt gpurun_out/{key}_pf "
+        f"gpurun_out/{key}_pw --profile-name {name}",
+        "($ROOT: the repository root; the library built beforehand by __graft_entry__.build())"])
 
 
 def summarize_profiles(kt_dir, pf_dir, pw_dir, command, name="step_square2048"):
     """Write the two profiles/ summaries from rocprofv3 csv output."""
     title, workload = PROFILE_TITLES[name]
+    command = command or profile_command(name)
     stats_path = os.path.join(ROOT, "profiles", f"{name}_kernel_stats.md")
     traffic_path = os.path.join(ROOT, "profiles", f"{name}_hbm_traffic.md")
     def one(d, pattern):
@@ -874,7 +917,8 @@ def main():
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
     ap.add_argument("--summarize", nargs=3, metavar=("KT", "PF", "PW"),
                     help="write the profiles/ summaries from rocprofv3 csv directories")
-    ap.add_argument("--command", default="", help="command text recorded by --summarize")
+    ap.add_argument("--command", default="",
+                    help="command text recorded by --summarize (default: that of the profile)")
     ap.add_argument("--profile-name", default="step_square2048", choices=sorted(PROFILE_TITLES),
                     help="which summary --summarize writes")
     ap.add_argument("--only", choices=("sparse", "adjoint", "batched", "tet", "p2"),
