@@ -7,11 +7,14 @@
 // GS and GM.  Pass 1 (one lane per row, the same tiling as the forward) walks
 // the triangles around i, differentiates tau(i, T) with respect to the three
 // vertices of T and the three weights, keeps the part for i in registers and
-// adds the parts for the two neighbours j into H[i, j] (LDS), then writes H
-// coalesced: H[i, j] = d(sum_T tau(i, T)) / d(q_j, w_j).  Pass 2 (one lane per
-// vertex u) sums column u of H: dL/d(q_u, w_u) = sum_v H[v, u], reading the
-// transposed positions.  No atomics; every sum has a fixed order, so the
-// result is bitwise reproducible.
+// adds the parts for the two neighbours j into H[i, j] (LDS), then writes H:
+// H[i, j] = d(sum_T tau(i, T)) / d(q_j, w_j).  Pass 2 (one lane per vertex u)
+// sums column u of H: dL/d(q_u, w_u) = sum_v H[v, u].  With the transpose map
+// tpos, pass 1 stores H[i, j] at the place of entry (j, i), so pass 2 reads
+// row u in place; without it, pass 1 stores H in row order and pass 2 finds
+// each transposed entry by search.  Either way the same values are added in
+// the same order.  No atomics; every sum has a fixed order, so the result is
+// bitwise reproducible.
 //
 // Derivatives for the triangle (x0, x1, x2) (cyclic rotation starting at i),
 // r0 = x1 - x2, r1 = x2 - x0, r2 = x0 - x1, D = (x1 - x0) x (x2 - x0),
@@ -102,6 +105,7 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__
                                                    const int32_t *__restrict__ col_idx,
                                                    const int32_t *__restrict__ inc_ptr,
                                                    const uint32_t *__restrict__ inc_pos,
+                                                   const int32_t *__restrict__ tpos,
                                                    const double *__restrict__ GS,
                                                    const double *__restrict__ GM,
                                                    double4 *__restrict__ H, int64_t ntiles) {
@@ -218,13 +222,26 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__
                 for (int k = 0; k < 3 * len; ++k) s_stage[3 * off + k] = 0.0;
             }
             __syncthreads();
-            for (int e = lane; e < Ew; e += WAVE)
-                H[E0 + e] = make_double4(s_stage[3 * e], s_stage[3 * e + 1], s_stage[3 * e + 2], 0.0);
+            // with tpos, each value goes to the place of its transposed entry
+            int32_t dst[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                dst[u] = e < Ew ? (tpos ? tpos[E0 + e] : E0 + e) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                if (e < Ew)
+                    H[dst[u]] = make_double4(s_stage[3 * e], s_stage[3 * e + 1], s_stage[3 * e + 2], 0.0);
+            }
             __syncthreads();
         }
         if (!in_regs && active && len > 0) {
             // long row or tile too large: own row in global memory, same order
-            for (int e = 0; e < len; ++e) H[rs + e] = make_double4(0.0, 0.0, 0.0, 0.0);
+            // (each entry at its own place, transposed with tpos)
+            auto hp = [&](int32_t e) -> double4 & { return H[tpos ? tpos[rs + e] : rs + e]; };
+            for (int e = 0; e < len; ++e) hp(e) = make_double4(0.0, 0.0, 0.0, 0.0);
             const int32_t *cr = col_idx + rs;
             int32_t pd = 0;
             while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
@@ -242,21 +259,21 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__
                 ox += o.gx[0];
                 oy += o.gy[0];
                 ow += o.gw[0];
-                double4 h1 = H[rs + p1], h2 = H[rs + p2];
+                double4 h1 = hp(p1), h2 = hp(p2);
                 h1.x += o.gx[1];
                 h1.y += o.gy[1];
                 h1.z += o.gw[1];
-                H[rs + p1] = h1;
+                hp(p1) = h1;
                 h2.x += o.gx[2];
                 h2.y += o.gy[2];
                 h2.z += o.gw[2];
-                H[rs + p2] = h2;
+                hp(p2) = h2;
             }
-            double4 hd = H[rs + pd];
+            double4 hd = hp(pd);
             hd.x += ox;
             hd.y += oy;
             hd.z += ow;
-            H[rs + pd] = hd;
+            hp(pd) = hd;
         }
     }
 }
@@ -310,10 +327,10 @@ __global__ __launch_bounds__(256) void k_adj_cols(int32_t nq, const int32_t *__r
     }
 }
 
-// Pass 2 with the transpose map: tile of 64 vertices u (one per lane); the
-// tile's entries are contiguous, so tpos is read coalesced and every lane has
-// U gathers of H in flight before anything waits; each lane then sums its
-// row from LDS in ascending position (the same order as k_adj_cols).
+// Pass 2 with the transpose map: tile of 64 vertices u (one per lane).  Pass
+// 1 has stored H transposed, so the tile's values are contiguous and read
+// coalesced; each lane then sums its row from LDS in ascending position (the
+// same order as k_adj_cols).
 template <int U>
 __global__ __launch_bounds__(WAVE) void k_adj_cols_tpos(int32_t nq, const int32_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ tpos,
@@ -333,17 +350,11 @@ __global__ __launch_bounds__(WAVE) void k_adj_cols_tpos(int32_t nq, const int32_
         const int32_t re = active ? row_ptr[u + 1] : 0;
         double gx = 0.0, gy = 0.0, gw = 0.0;
         if (Ew <= EB) {
-            int32_t t[U];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int e = lane + k * WAVE;
-                t[k] = e < Ew ? __builtin_nontemporal_load(tpos + E0 + e) : 0;
-            }
             double4 h[U];
 #pragma unroll
             for (int k = 0; k < U; ++k) {
                 const int e = lane + k * WAVE;
-                h[k] = e < Ew ? H[t[k]] : make_double4(0.0, 0.0, 0.0, 0.0);
+                h[k] = e < Ew ? H[E0 + e] : make_double4(0.0, 0.0, 0.0, 0.0);
             }
 #pragma unroll
             for (int k = 0; k < U; ++k) {
@@ -363,7 +374,7 @@ __global__ __launch_bounds__(WAVE) void k_adj_cols_tpos(int32_t nq, const int32_
             __syncthreads();
         } else {
             for (int32_t p = rs; p < re; ++p) {
-                const double4 hv = H[tpos[p]];
+                const double4 hv = H[p];   // already transposed by pass 1
                 gx += hv.x;
                 gy += hv.y;
                 gw += hv.z;
@@ -476,8 +487,9 @@ template <int U, int LMAX>
 __global__ __launch_bounds__(WAVE) void k_adj_elas_rows(
     int32_t nq, const double *__restrict__ q, const int32_t *__restrict__ row_ptr,
     const int32_t *__restrict__ col_idx, const int32_t *__restrict__ inc_ptr,
-    const uint32_t *__restrict__ inc_pos, const double *__restrict__ G, double lam, double mu,
-    double2 *__restrict__ H, double2 *__restrict__ lm, int64_t ntiles) {
+    const uint32_t *__restrict__ inc_pos, const int32_t *__restrict__ tpos,
+    const double *__restrict__ G, double lam, double mu, double2 *__restrict__ H,
+    double2 *__restrict__ lm, int64_t ntiles) {
     constexpr int EB = U * WAVE;
     extern __shared__ double smem[];
     double2 *s_q = reinterpret_cast<double2 *>(smem);
@@ -609,13 +621,25 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_rows(
                 for (int k = 0; k < 2 * len; ++k) s_stage[2 * off + k] = 0.0;
             }
             __syncthreads();
-            for (int e = lane; e < Ew; e += WAVE)
-                H[E0 + e] = make_double2(s_stage[2 * e], s_stage[2 * e + 1]);
+            // with tpos, each value goes to the place of its transposed entry
+            int32_t dst[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                dst[u] = e < Ew ? (tpos ? tpos[E0 + e] : E0 + e) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                if (e < Ew) H[dst[u]] = make_double2(s_stage[2 * e], s_stage[2 * e + 1]);
+            }
             __syncthreads();
         }
         if (!in_regs && active && len > 0) {
             // long row or tile too large: own row in global memory, same order
-            for (int e = 0; e < len; ++e) H[rs + e] = make_double2(0.0, 0.0);
+            // (each entry at its own place, transposed with tpos)
+            auto hp = [&](int32_t e) -> double2 & { return H[tpos ? tpos[rs + e] : rs + e]; };
+            for (int e = 0; e < len; ++e) hp(e) = make_double2(0.0, 0.0);
             const int32_t *cr = col_idx + rs;
             int32_t pd = 0;
             while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
@@ -650,18 +674,18 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_rows(
                 oy += o.d[0][1];
                 sl += o.nl;
                 sm += o.nm;
-                double2 h1 = H[rs + p1], h2 = H[rs + p2];
+                double2 h1 = hp(p1), h2 = hp(p2);
                 h1.x += o.d[1][0];
                 h1.y += o.d[1][1];
-                H[rs + p1] = h1;
+                hp(p1) = h1;
                 h2.x += o.d[2][0];
                 h2.y += o.d[2][1];
-                H[rs + p2] = h2;
+                hp(p2) = h2;
             }
-            double2 hd = H[rs + pd];
+            double2 hd = hp(pd);
             hd.x += ox;
             hd.y += oy;
-            H[rs + pd] = hd;
+            hp(pd) = hd;
         }
         // the tile's dtau/dlambda, dtau/dmu sums (a fixed shuffle tree)
         const double tl = wave_sum(sl), tm = wave_sum(sm);
@@ -670,7 +694,9 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_rows(
 }
 
 // Pass 2 of the elasticity adjoint: dq[u] = sum over row u of H at the
-// transposed positions, ascending position (tpos, or a search without it).
+// transposed positions, ascending position.  With tpos, pass 1 has already
+// stored every value at the place of its transposed entry, so row u is read
+// in place; without it, each transposed entry is found by search.
 template <int U>
 __global__ __launch_bounds__(WAVE) void k_adj_elas_cols(int32_t nq, const int32_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ col_idx,
@@ -725,17 +751,11 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_cols(int32_t nq, const int32_
         const int32_t re = active ? row_ptr[u + 1] : 0;
         double gx = 0.0, gy = 0.0;
         if (tpos && Ew <= EB) {
-            int32_t t[U];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int e = lane + k * WAVE;
-                t[k] = e < Ew ? __builtin_nontemporal_load(tpos + E0 + e) : 0;
-            }
             double2 h[U];
 #pragma unroll
             for (int k = 0; k < U; ++k) {
                 const int e = lane + k * WAVE;
-                h[k] = e < Ew ? H[t[k]] : make_double2(0.0, 0.0);
+                h[k] = e < Ew ? H[E0 + e] : make_double2(0.0, 0.0);
             }
 #pragma unroll
             for (int k = 0; k < U; ++k) {
@@ -755,7 +775,7 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_cols(int32_t nq, const int32_
             for (int32_t p = rs; p < re; ++p) {
                 int32_t tp;
                 if (tpos) {
-                    tp = tpos[p];
+                    tp = p;   // already transposed by pass 1
                 } else {
                     const int32_t v = col_idx[p];
                     int32_t lo = row_ptr[v], hi = row_ptr[v + 1];
@@ -789,12 +809,12 @@ constexpr int ADJ_LMAX = 8;
 
 template <bool HS, bool HM>
 int launch_adj(int32_t nq, const double4 *qw, const int32_t *row_ptr, const int32_t *col_idx,
-               const int32_t *inc_ptr, const uint32_t *inc_pos, const double *GS, const double *GM,
-               double4 *H, hipStream_t s) {
+               const int32_t *inc_ptr, const uint32_t *inc_pos, const int32_t *tpos, const double *GS,
+               const double *GM, double4 *H, hipStream_t s) {
     const int64_t ntiles = (nq + WAVE - 1) / WAVE;
     const size_t lds = (size_t)ADJ_U * WAVE * (5 * 8 + 4);
     hipLaunchKernelGGL((k_adj_rows<HS, HM, ADJ_U, ADJ_LMAX>), dim3((unsigned)ntiles), dim3(WAVE), lds,
-                       s, nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, ntiles);
+                       s, nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, tpos, GS, GM, H, ntiles);
     FEM_LAUNCH_CHECK();
     return FEM_OK;
 }
@@ -841,9 +861,12 @@ extern "C" int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, con
         FEM_LAUNCH_CHECK();
     }
     int st;
-    if (GS && GM) st = launch_adj<true, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, s);
-    else if (GS) st = launch_adj<true, false>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, s);
-    else if (GM) st = launch_adj<false, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, GS, GM, H, s);
+    if (GS && GM)
+        st = launch_adj<true, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, tpos, GS, GM, H, s);
+    else if (GS)
+        st = launch_adj<true, false>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, tpos, GS, GM, H, s);
+    else if (GM)
+        st = launch_adj<false, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, tpos, GS, GM, H, s);
     else st = fill_f64(reinterpret_cast<double *>(H), 4 * nnz, 0.0, s);
     if (st) return st;
     const int acc = (flags & FEM_ACCUMULATE) ? 1 : 0;
@@ -888,7 +911,7 @@ extern "C" int fem_adjoint_elas(int32_t nq, int32_t nme, int64_t nnz, const doub
     const int64_t ntiles = (nq + WAVE - 1) / WAVE;
     const size_t lds = (size_t)ADJ_U * WAVE * (6 * 8 + 4);
     hipLaunchKernelGGL((k_adj_elas_rows<ADJ_U, ADJ_LMAX>), dim3((unsigned)ntiles), dim3(WAVE), lds, s, nq,
-                       q, row_ptr, col_idx, inc_ptr, inc_pos, G, lambda, mu, H, lm, ntiles);
+                       q, row_ptr, col_idx, inc_ptr, inc_pos, tpos, G, lambda, mu, H, lm, ntiles);
     FEM_LAUNCH_CHECK();
     const int acc = (flags & FEM_ACCUMULATE) ? 1 : 0;
     hipLaunchKernelGGL(k_adj_elas_cols<ADJ_U>, dim3((unsigned)(ntiles + (dlm ? 1 : 0))), dim3(WAVE), 0, s,
