@@ -445,8 +445,10 @@ int fem_adjoint_workspace(int32_t nq, int64_t nnz, size_t *bytes /* HOST */);
 /* Gradient of L = sum_ij GS_ij S_ij(q) + sum_ij GM_ij Mw_ij(q, w) with
  * respect to q and w (GS, GM [nnz] on the scalar pattern; either may be NULL
  * to drop its term; w may be NULL only if GM is).  dq [nq][2] and dw [nq]
- * are overwritten (FEM_ACCUMULATE adds into them).  tpos from
- * fem_transpose_map, or NULL (then found by search).  flags: FEM_ACCUMULATE,
+ * are overwritten (FEM_ACCUMULATE adds into them).  tpos: the map that
+ * fem_transpose_map wrote for this pattern (the partial derivatives are then
+ * stored at the transposed places, which it must name), or NULL (then
+ * found by search).  flags: FEM_ACCUMULATE,
  * FEM_PACKED_QW.  Deterministic: two passes over the rows, no atomics; the
  * result does not depend on tpos, FEM_PACKED_QW or the launch shape. */
 int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
@@ -464,8 +466,9 @@ int fem_adjoint_elas_workspace(int32_t nq, int64_t nnz, size_t *bytes /* HOST */
  * in its interleaved 2x2-block layout).
  *   dq [nq][2] (overwritten, or added to with FEM_ACCUMULATE)
  *   dlm [2] device or NULL: (dL/dlambda, dL/dmu), likewise
- * Pattern arrays as for fem_assemble (FEM_DETERMINISTIC); tpos from
- * fem_transpose_map or NULL (search).  Two passes over the rows plus a
+ * Pattern arrays as for fem_assemble (FEM_DETERMINISTIC); tpos: the map that
+ * fem_transpose_map wrote for this pattern, or NULL (search), as for
+ * fem_adjoint_stiff_wmass.  Two passes over the rows plus a
  * fixed-order reduction; no atomics, bitwise reproducible. */
 int fem_adjoint_elas(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                      const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
