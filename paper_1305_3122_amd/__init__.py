@@ -602,7 +602,8 @@ def _autograd_function():
 
     class AssembleStiffWMass(torch.autograd.Function):
         """(S values, Mw values) = F(q, w) on a fixed pattern; backward runs the
-        hand-written adjoint kernels (fem_adjoint_stiff_wmass)."""
+        hand-written adjoint kernels (fem_adjoint_stiff_wmass), with the
+        pattern's transpose map (built on the first backward if missing)."""
 
         @staticmethod
         def forward(ctx, q, w, pat):
@@ -622,6 +623,10 @@ def _autograd_function():
             q, w = ctx.saved_tensors   # version-checked: q, w unchanged since forward
             gS = None if gS is None else gS.contiguous()
             gM = None if gM is None else gM.contiguous()
+            if ctx.pat.tpos is None and ctx.pat.nnz > 0:
+                # the transpose map, built once and kept on the pattern: the
+                # second pass then reads rows in place instead of searching
+                fem_transpose_map(ctx.pat)
             dq, dw = fem_adjoint_stiff_wmass(ctx.pat, q.contiguous(), w.contiguous(), gS, gM,
                                              work=ctx.work, packed=q.is_contiguous() and
                                              w.is_contiguous())
@@ -642,6 +647,8 @@ def _autograd_function():
         @staticmethod
         def backward(ctx, gK):
             q, lam, mu = ctx.saved_tensors
+            if ctx.pat.tpos is None and ctx.pat.nnz > 0:
+                fem_transpose_map(ctx.pat)   # once per pattern, as above
             dq, dlm = fem_adjoint_elas(ctx.pat, q.contiguous(), float(lam), float(mu), gK.contiguous())
             return dq, dlm[0].to(lam.dtype), dlm[1].to(mu.dtype), None
 

@@ -1,6 +1,8 @@
 """GPU adjoint of the elasticity assembly (dL/dq, dL/dlambda, dL/dmu for
 L = <G, K(q; lambda, mu)>) against the oracle, central differences and the
 identities of the forward map, through the C ABI."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -110,11 +112,18 @@ def test_elas_autograd_function():
     lam = torch.tensor(LAM, dtype=torch.float64, device=DEV, requires_grad=True)
     mu = torch.tensor(MU, dtype=torch.float64, device=DEV, requires_grad=True)
     G = _up(mg.normal_seed(4 * pat.nnz, seed=mg.BASE_SEED + 502))
+    assert pat.tpos is None
     K = fem.AssembleElas.apply(q, lam, mu, pat)
     Lv = (G * K).sum()
     gq, gl, gm = torch.autograd.grad(Lv, (q, lam, mu))
+    # the backward built the transpose map and kept it on the pattern
+    assert pat.tpos is not None
     dq, dlm = fem.fem_adjoint_elas(pat, q.detach(), LAM, MU, G)
     assert torch.equal(gq, dq)
+    # and the search variant (no map) gives the same bits
+    pat_s = dataclasses.replace(pat, tpos=None)
+    dq_s, dlm_s = fem.fem_adjoint_elas(pat_s, q.detach(), LAM, MU, G)
+    assert torch.equal(dq_s, dq) and torch.equal(dlm_s, dlm)
     assert float(gl) == float(dlm[0]) and float(gm) == float(dlm[1])
 
 
