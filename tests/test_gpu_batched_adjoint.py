@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from paper_1305_3122_amd import meshgen as mg
-from tests.helpers import RTOL_ROW, row_rel_err
+from tests.helpers import RTOL_ROW, fan_mesh, row_rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -146,6 +146,28 @@ def test_adjoint_matches_oracle(cfg5):
     torch.cuda.synchronize()
     assert np.max(np.abs(_np(dqS) - rS)) <= 1e-13 * np.max(np.abs(rS))
     pat.tpos = None
+
+
+@pytest.mark.parametrize("n_fan", [12, 40])
+def test_adjoint_long_rows(n_fan):
+    # the hub of a fan has a row longer than the register path: pass 1 sums
+    # it in memory, at the transposed places when the transpose map is given;
+    # both variants against the oracle and bitwise against each other
+    q0, me = fan_mesh(n_fan, 2, seed=n_fan)
+    nq = q0.shape[0]
+    w = mg.weight_uniform(nq, 0.5, 2.0, seed=mg.BASE_SEED + n_fan)
+    P = oracle.pattern(nq, me)
+    G = mg.normal_seed(P.nnz, seed=mg.BASE_SEED + 60 + n_fan)
+    rdq, rdw = oracle.adjoint_stiff_wmass(q0, me, w, P.slot, G, G)
+    pat = fem.fem_pattern(_up(me), nq)
+    q, wd, Gd = _up(q0), _up(w), _up(G)
+    dq_s, dw_s = fem.fem_adjoint_stiff_wmass(pat, q, wd, Gd, Gd)
+    fem.fem_transpose_map(pat)
+    dq_t, dw_t = fem.fem_adjoint_stiff_wmass(pat, q, wd, Gd, Gd)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(_np(dq_t) - rdq)) <= 1e-13 * np.max(np.abs(rdq))
+    assert np.max(np.abs(_np(dw_t) - rdw)) <= 1e-13 * np.max(np.abs(rdw))
+    assert torch.equal(dq_t, dq_s) and torch.equal(dw_t, dw_s)
 
 
 def test_adjoint_variants_bitwise_equal(cfg5):
