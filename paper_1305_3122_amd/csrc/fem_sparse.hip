@@ -230,6 +230,20 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_scatter(int64_t nt, const in
     const int64_t t0 = (int64_t)blockIdx.x * tpb;
     const int64_t t1 = (t0 + tpb < nt) ? t0 + tpb : nt;
     const int32_t rmask = (1 << rs) - 1;
+    // the next tile's loads are issued before this tile's multisplit, so
+    // they are in flight while it runs
+    int32_t ni[IPT], nj[IPT];
+    double nv[IPT];
+    auto load = [&](int64_t tb) {
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+            const int64_t t = tb + threadIdx.x + u * SPP_THREADS;
+            ni[u] = t < t1 ? I[t] : -1;
+            nj[u] = t < t1 ? J[t] : -1;
+            nv[u] = (V && t < t1) ? V[t] : 0.0;
+        }
+    };
+    if (t0 < t1) load(t0);
     for (int64_t tb = t0; tb < t1; tb += TILE) {
         int32_t key[IPT], prl[IPT];
         int2 pct[IPT];
@@ -237,14 +251,14 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_scatter(int64_t nt, const in
 #pragma unroll
         for (int u = 0; u < IPT; ++u) {
             const int64_t t = tb + threadIdx.x + u * SPP_THREADS;
-            const int32_t i = t < t1 ? I[t] : -1;
-            const int32_t j = t < t1 ? J[t] : -1;
-            pval[u] = (V && t < t1) ? V[t] : 0.0;
+            const int32_t i = ni[u], j = nj[u];
+            pval[u] = nv[u];
             const bool ok = (uint32_t)i < (uint32_t)m && (uint32_t)j < (uint32_t)n;
             key[u] = ok ? (i >> rs) : -1;
             prl[u] = i & rmask;
             pct[u] = make_int2(j, static_cast<int32_t>(t));
         }
+        if (tb + TILE < t1) load(tb + TILE);
         tile_multisplit(L, nbkt, key, prl, pct, pval, V != nullptr, s_wsum, rl, ct, rval);
     }
 }
@@ -339,19 +353,35 @@ __global__ __launch_bounds__(SPP_THREADS) void k_sp_split(
     if (cb == nbkt_c - 1 && tid == 0) fine_off[(int64_t)nbkt_c << fshift] = static_cast<int32_t>(total);
     __syncthreads();
     const int32_t fmask = (1 << rfc) - 1;
+    // the next tile's loads are issued before this tile's multisplit, so
+    // they are in flight while it runs
+    int32_t nr[IPT];
+    int2 nc[IPT];
+    double nv[HV ? IPT : 1];
+    auto load = [&](int64_t xb) {
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+            const int64_t x = xb + tid + u * SPP_THREADS;
+            nr[u] = x < e1 ? rl[x] : -1;
+            nc[u] = x < e1 ? ct[x] : make_int2(0, 0);
+            if constexpr (HV) nv[u] = x < e1 ? rval[x] : 0.0;
+        }
+    };
+    if (e0 < e1) load(e0);
     for (int64_t xb = e0; xb < e1; xb += TS) {
         int32_t key[IPT], prl[IPT];
         int2 pct[IPT];
         double pval[IPT];
 #pragma unroll
         for (int u = 0; u < IPT; ++u) {
-            const int64_t x = xb + tid + u * SPP_THREADS;
-            const int32_t r0 = x < e1 ? rl[x] : -1;
+            const int32_t r0 = nr[u];
             key[u] = r0 >= 0 ? (r0 >> rfc) : -1;
             prl[u] = r0 & fmask;
-            pct[u] = x < e1 ? ct[x] : make_int2(0, 0);
-            pval[u] = (HV && x < e1) ? rval[x] : 0.0;
+            pct[u] = nc[u];
+            if constexpr (HV) pval[u] = nv[u];
+            else pval[u] = 0.0;
         }
+        if (xb + TS < e1) load(xb + TS);
         tile_multisplit(L, nk, key, prl, pct, pval, HV, s_wsum, rl2, ct2, rval2);
     }
 }
