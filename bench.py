@@ -4,9 +4,9 @@ Step (timed): the whole assembly of the 2048 x 2048-cell unit square
 (8,388,608 triangles, jitter 0.2 h, random vertex relabelling, FP64 values,
 int32 indices) from (q, me) resident in HBM:
     fem_pattern        symbolic phase (CSR pattern + triangle lists)
-    fem_assemble       mass M, weighted mass Mw (w = 1 + x^2 + y^2) and
-                       stiffness S in one pass over the mesh
-    fem_assemble       elasticity K (lambda = 1, mu = 0.5), second pass
+    fem_assemble       mass M, weighted mass Mw (w = 1 + x^2 + y^2),
+                       stiffness S and elasticity K (lambda = 1, mu = 0.5),
+                       all four in one pass over the rows
     fem_elas_pattern   2x2-block elasticity pattern
 value = triangles / step time (M triangles per second).
 

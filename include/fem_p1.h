@@ -113,7 +113,7 @@ int64_t fem_nnz_bound(int32_t nq, int32_t nme);
 
 /* Builds the CSR pattern of the scalar matrices (replaces the index arrays
  * Ig = me([1 2 3 1 2 3 1 2 3], :), Jg = me([1 1 1 2 2 2 3 3 3], :) and the
- * sort/compress inside sparse(Ig, Jg, Kg, nq, nq) of Section 5), plus the
+ * sort/compress inside sparse(Ig, Jg, Kg, nq, nq) of Section 6), plus the
  * data the numeric calls read:
  *
  *   row_ptr [nq+1]       CSR row offsets
@@ -448,7 +448,9 @@ int fem_adjoint_workspace(int32_t nq, int64_t nnz, size_t *bytes /* HOST */);
  * are overwritten (FEM_ACCUMULATE adds into them).  tpos: the map that
  * fem_transpose_map wrote for this pattern (the partial derivatives are then
  * stored at the transposed places, which it must name), or NULL (then
- * found by search).  flags: FEM_ACCUMULATE,
+ * found by search).  Patterns of fem_pattern are symmetric, so their map
+ * has no -1; an entry whose map is -1 (no transposed entry) has no place
+ * and its partial derivative is dropped, never stored out of bounds.  flags: FEM_ACCUMULATE,
  * FEM_PACKED_QW.  Deterministic: two passes over the rows, no atomics; the
  * result does not depend on tpos, FEM_PACKED_QW or the launch shape. */
 int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q,

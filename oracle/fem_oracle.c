@@ -283,7 +283,7 @@ int oracle_validate(int32_t nq, int32_t nme, const int32_t *me)
 /* Symbolic assembly of a P1 mesh                                     */
 /* ------------------------------------------------------------------ */
 
-/* Global index arrays of Section 5 (Ig = me([1 2 3 1 2 3 1 2 3], :),
+/* Global index arrays of Section 6 (Ig = me([1 2 3 1 2 3 1 2 3], :),
  * Jg = me([1 1 1 2 2 2 3 3 3], :)), compressed:
  *   row_ptr [nq+1], col_idx [cap >= 9 nme]: the CSR pattern;
  *   slot [9][nme]: slot[r*nme + k] = CSR position of local entry r = 3b + a

@@ -630,7 +630,8 @@ def _autograd_function():
             dq, dw = fem_adjoint_stiff_wmass(ctx.pat, q.contiguous(), w.contiguous(), gS, gM,
                                              work=ctx.work, packed=q.is_contiguous() and
                                              w.is_contiguous())
-            ctx.work = None
+            # ctx.work is kept: a second backward through the same graph
+            # (retain_graph=True) reads the packed records again
             return dq, (dw if gM is not None else None), None
 
     class AssembleElas(torch.autograd.Function):

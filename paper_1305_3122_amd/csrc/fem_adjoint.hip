@@ -232,7 +232,7 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int e = lane + u * WAVE;
-                if (e < Ew)
+                if (e < Ew && dst[u] >= 0)   // tpos -1: no transposed entry, no place
                     H[dst[u]] = make_double4(s_stage[3 * e], s_stage[3 * e + 1], s_stage[3 * e + 2], 0.0);
             }
             __syncthreads();
@@ -240,8 +240,22 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__
         if (!in_regs && active && len > 0) {
             // long row or tile too large: own row in global memory, same order
             // (each entry at its own place, transposed with tpos)
-            auto hp = [&](int32_t e) -> double4 & { return H[tpos ? tpos[rs + e] : rs + e]; };
-            for (int e = 0; e < len; ++e) hp(e) = make_double4(0.0, 0.0, 0.0, 0.0);
+            // (an entry without a transposed partner, tpos -1, has no place:
+            // nothing would read it, and it is skipped)
+            auto hat = [&](int32_t e) -> int32_t { return tpos ? tpos[rs + e] : rs + e; };
+            auto hadd = [&](int32_t e, double gx, double gy, double gw) {
+                const int32_t d = hat(e);
+                if (d < 0) return;
+                double4 h = H[d];
+                h.x += gx;
+                h.y += gy;
+                h.z += gw;
+                H[d] = h;
+            };
+            for (int e = 0; e < len; ++e) {
+                const int32_t d = hat(e);
+                if (d >= 0) H[d] = make_double4(0.0, 0.0, 0.0, 0.0);
+            }
             const int32_t *cr = col_idx + rs;
             int32_t pd = 0;
             while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
@@ -259,21 +273,10 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__
                 ox += o.gx[0];
                 oy += o.gy[0];
                 ow += o.gw[0];
-                double4 h1 = hp(p1), h2 = hp(p2);
-                h1.x += o.gx[1];
-                h1.y += o.gy[1];
-                h1.z += o.gw[1];
-                hp(p1) = h1;
-                h2.x += o.gx[2];
-                h2.y += o.gy[2];
-                h2.z += o.gw[2];
-                hp(p2) = h2;
+                hadd(p1, o.gx[1], o.gy[1], o.gw[1]);
+                hadd(p2, o.gx[2], o.gy[2], o.gw[2]);
             }
-            double4 hd = hp(pd);
-            hd.x += ox;
-            hd.y += oy;
-            hd.z += ow;
-            hp(pd) = hd;
+            hadd(pd, ox, oy, ow);
         }
     }
 }
@@ -631,15 +634,28 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_rows(
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int e = lane + u * WAVE;
-                if (e < Ew) H[dst[u]] = make_double2(s_stage[2 * e], s_stage[2 * e + 1]);
+                if (e < Ew && dst[u] >= 0)   // tpos -1: no transposed entry, no place
+                    H[dst[u]] = make_double2(s_stage[2 * e], s_stage[2 * e + 1]);
             }
             __syncthreads();
         }
         if (!in_regs && active && len > 0) {
             // long row or tile too large: own row in global memory, same order
             // (each entry at its own place, transposed with tpos)
-            auto hp = [&](int32_t e) -> double2 & { return H[tpos ? tpos[rs + e] : rs + e]; };
-            for (int e = 0; e < len; ++e) hp(e) = make_double2(0.0, 0.0);
+            // (an entry without a transposed partner, tpos -1, is skipped)
+            auto hat = [&](int32_t e) -> int32_t { return tpos ? tpos[rs + e] : rs + e; };
+            auto hadd = [&](int32_t e, double gx, double gy) {
+                const int32_t d = hat(e);
+                if (d < 0) return;
+                double2 h = H[d];
+                h.x += gx;
+                h.y += gy;
+                H[d] = h;
+            };
+            for (int e = 0; e < len; ++e) {
+                const int32_t d = hat(e);
+                if (d >= 0) H[d] = make_double2(0.0, 0.0);
+            }
             const int32_t *cr = col_idx + rs;
             int32_t pd = 0;
             while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
@@ -674,18 +690,10 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_rows(
                 oy += o.d[0][1];
                 sl += o.nl;
                 sm += o.nm;
-                double2 h1 = hp(p1), h2 = hp(p2);
-                h1.x += o.d[1][0];
-                h1.y += o.d[1][1];
-                hp(p1) = h1;
-                h2.x += o.d[2][0];
-                h2.y += o.d[2][1];
-                hp(p2) = h2;
+                hadd(p1, o.d[1][0], o.d[1][1]);
+                hadd(p2, o.d[2][0], o.d[2][1]);
             }
-            double2 hd = hp(pd);
-            hd.x += ox;
-            hd.y += oy;
-            hp(pd) = hd;
+            hadd(pd, ox, oy);
         }
         // the tile's dtau/dlambda, dtau/dmu sums (a fixed shuffle tree)
         const double tl = wave_sum(sl), tm = wave_sum(sm);

@@ -2,28 +2,36 @@
 // row-relative positions and the optional slot map.
 //
 // Replaces the global index arrays Ig, Jg of the vectorised assembly
-// (Section 5, Remark on Ig/Jg) and the sort/compress that sparse(Ig,Jg,Kg)
-// performs.  Instead of sorting 9 nme triplets, the 3 nme (vertex, triangle)
-// incidences are grouped by vertex, and every vertex sorts/uniques its own
-// short neighbour list in LDS (a P1 row holds the vertex and its neighbours).
+// (Section 6, the remark that Ig and Jg need no loop) and the sort/compress
+// that sparse(Ig, Jg, Kg) performs.  Instead of sorting 9 nme triplets, the
+// 3 nme (vertex, triangle) incidences are grouped by vertex, and every vertex
+// sorts/uniques its own short neighbour list (a P1 row holds the vertex and
+// its neighbours).
 //
 // Grouping by vertex (the transpose of me) without global atomics: a
-// two-level counting sort.
-//   1 bucket count    one workgroup per 4096 triangles: mesh checks, LDS
-//                     histogram of the buckets (4096 consecutive vertex ids)
+// two-level counting sort over buckets of consecutive vertex ids.
+//   1 bucket count    about 256 workgroups of 512 threads, each over a
+//                     contiguous range of triangles: mesh checks and an LDS
+//                     histogram of the buckets
 //   2 scan            bucket-major offsets of every (bucket, workgroup) run
-//   3 bucket scatter  the same workgroups write each incidence
-//                     (v, 3k + a, other two vertices) into its bucket run
-//   4 bucket sort     one workgroup per bucket: LDS counting sort by vertex
-//                     -> inc_ptr, triangle lists and neighbour pairs
-// (meshes with more than 2^26 vertices use a global-atomic count/fill instead)
-//   5 rows       one lane per vertex: sort its triangles by id, sort+unique
-//                its neighbours in LDS -> row length, row-relative positions
-//                (inc_pos), sorted columns (staged)
-//   5w rows_wide one workgroup per vertex with more than LANE_MAX triangles
-//   6 scan       -> row_ptr, nnz            (host waits here once)
-//   7 copy       staged columns -> col_idx
-//   8 slot       one lane per triangle: binary search of its 9 entries
+//   3 bucket scatter  the same workgroups write each incidence (3k + a and
+//                     the other two vertices) into its (bucket, workgroup) run
+// Fine path (default while nq <= 512 * HIST_MAX, about 18.9M vertices):
+// buckets of 512 vertices.
+//   4 bucket rows     one workgroup per bucket, everything in LDS: counting
+//                     sort by vertex -> inc_ptr; per vertex the triangles by
+//                     id and the distinct neighbours (sorting networks in
+//                     registers up to 8 triangles, LDS up to 64) -> inc,
+//                     inc_pos; the bucket's rows staged in its own region
+//   5 scan            of the bucket totals
+//   6 bucket copy     staged rows -> col_idx, and row_ptr
+// Coarse path (a bucket above 4096 incidences or a vertex above 64
+// triangles, or nq above 18.9M): buckets of 4096 vertices sorted by
+// k_bkt_sort, then one lane per vertex (k_rows), a lane with its list in LDS
+// (k_rows_mid) or a workgroup per vertex (k_rows_wide), a scan of the row
+// lengths and k_copy_cols.  Beyond 4096 * HIST_MAX (about 151M) vertices the
+// grouping is a global-atomic count and fill (k_count, k_fill) instead.
+//   slot    one lane per triangle: binary search of its 9 entries
 #include "fem_internal.h"
 
 namespace fem {
