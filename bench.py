@@ -309,6 +309,7 @@ class Step:
         self.inc_ptr = torch.empty(m.nq + 1, **i32)
         self.inc = torch.empty(3 * m.nme, **i32)
         self.inc_pos = torch.empty(3 * m.nme, **i32)
+        self.fan = torch.empty(m.nq, dtype=torch.int64, device=dev)
         self.work = torch.empty(self.ws, dtype=torch.uint8, device=dev)
         self.rpe = torch.empty(2 * m.nq + 1, **i32)
         self.nnz = None
@@ -333,10 +334,13 @@ class Step:
             self.cap, self.inc_ptr.data_ptr(), self.inc.data_ptr(), self.inc_pos.data_ptr(), None,
             self.work.data_ptr(), self.ws, C.byref(n), s))
         self.nnz = int(n.value)
+        self.fem._lib.check(self.lib.fem_fan_plan(
+            self.nq, self.nme, self.row_ptr.data_ptr(), self.inc_ptr.data_ptr(),
+            self.inc_pos.data_ptr(), self.fan.data_ptr(), s))
 
     def _pat(self):
         return (self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.inc_ptr.data_ptr(),
-                self.inc_pos.data_ptr(), None)
+                self.inc_pos.data_ptr(), self.fan.data_ptr(), None)
 
     def assemble(self):
         # M, Mw, S and K in one pass (the gathers of q and w shared)
@@ -499,8 +503,8 @@ def run_batched(torch, fem, args):
         for pm, qm, Sm, Mm in per:
             fem._lib.check(lib.fem_assemble_stiff_mass(
                 pm.nq, pm.nme, pm.nnz, qm.data_ptr(), None, pm.row_ptr.data_ptr(),
-                pm.col_idx.data_ptr(), pm.inc_ptr.data_ptr(), pm.inc_pos.data_ptr(), None,
-                Sm.data_ptr(), Mm.data_ptr(), 0, s_ptr))
+                pm.col_idx.data_ptr(), pm.inc_ptr.data_ptr(), pm.inc_pos.data_ptr(),
+                pm.fan.data_ptr(), None, Sm.data_ptr(), Mm.data_ptr(), 0, s_ptr))
 
     def batched():
         g.replay(side)
@@ -591,8 +595,9 @@ def run_adjoint(torch, fem, args):
 
     def fwd():
         fem._lib.check(lib.fem_assemble(
-            ops, m.nq, pat.nme, pat.nnz, q.data_ptr(), wd.data_ptr(), pat.me.data_ptr(), *P, None,
-            0.0, 0.0, None, Mw.data_ptr(), S.data_ptr(), None, awork.data_ptr(), awork.numel(),
+            ops, m.nq, pat.nme, pat.nnz, q.data_ptr(), wd.data_ptr(), pat.me.data_ptr(), *P,
+            pat.fan.data_ptr(), None, 0.0, 0.0, None, Mw.data_ptr(), S.data_ptr(), None,
+            awork.data_ptr(), awork.numel(),
             None, 0, s))
 
     def bwd():
@@ -635,7 +640,7 @@ def run_adjoint(torch, fem, args):
     def efwd():
         fem._lib.check(lib.fem_assemble(
             fem.FEM_OP_ELAS, m.nq, pat.nme, pat.nnz, q.data_ptr(), None, pat.me.data_ptr(), *P,
-            None, lam, mu, None, None, None, K.data_ptr(), None, 0, None, 0, s))
+            pat.fan.data_ptr(), None, lam, mu, None, None, None, K.data_ptr(), None, 0, None, 0, s))
 
     def ebwd():
         fem._lib.check(lib.fem_adjoint_elas(

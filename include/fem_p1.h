@@ -168,6 +168,23 @@ int fem_pattern_set_path(int path);
 int fem_transpose_map(int32_t nq, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                       int32_t *tpos, void *stream);
 
+/* Fan codes: for every row i, the order in which turning around vertex i
+ * meets its triangles (one uint64 per row, fan [nq]).  Step j of the walk is
+ * the triangle (i, s_j, s_{j+1}) in its own vertex order, so an off-diagonal
+ * entry receives exactly the two terms of consecutive steps and the numeric
+ * kernels need no search of the row per triangle.  Built from the arrays
+ * fem_pattern wrote (row_ptr, inc_ptr, inc_pos; no other input), once per
+ * mesh.  A row gets code 0 -- and is then summed in ascending triangle
+ * order -- unless its triangles form a single consistently oriented fan
+ * (closed around an inner vertex, open at a boundary vertex) of at most 13
+ * neighbours; so on a mesh whose triangles are all counter-clockwise (or all
+ * clockwise) every manifold row with up to 13 neighbours has one.  Layout:
+ *   bits 0..3 n (slots on the walk, 0: none), bit 4 closed, bits 5..8 the
+ *   diagonal's slot, bits 9 + 4j.. slot s_j (positions relative to
+ *   row_ptr[i]). */
+int fem_fan_plan(int32_t nq, int32_t nme, const int32_t *row_ptr, const int32_t *inc_ptr,
+                 const uint32_t *inc_pos, uint64_t *fan, void *stream);
+
 /* Elasticity pattern over the 2 nq degrees of freedom psi_{2i} = (phi_i, 0),
  * psi_{2i+1} = (0, phi_i) (the paper's interleaved basis, 0-based): row
  * 2i + alpha holds columns 2j, 2j + 1 for every column j of scalar row i.
@@ -183,8 +200,13 @@ int fem_elas_pattern(int32_t nq, int64_t nnz, const int32_t *row_ptr, const int3
 /* Numeric phase                                                             */
 /* ------------------------------------------------------------------------ */
 /* Common arguments: nq, nme, nnz and the arrays written by fem_pattern.
- * FEM_DETERMINISTIC reads q (w), row_ptr, col_idx, inc_ptr, inc_pos; me and
- * slot may be NULL.  FEM_ATOMIC reads q (w), me, slot (and row_ptr for the
+ * FEM_DETERMINISTIC reads q (w), row_ptr, col_idx, inc_ptr, inc_pos and, if
+ * not NULL, the fan codes of fem_fan_plan for the same pattern; me and slot
+ * may be NULL.  The order of additions is fixed by these arrays: with fan
+ * codes, the diagonal of a row that has one sums its triangles in walk
+ * order (every off-diagonal value is a sum of two terms, whose order does
+ * not matter), otherwise in ascending triangle order; either way the values
+ * do not depend on the launch shape or on which operators share the call.  FEM_ATOMIC reads q (w), me, slot (and row_ptr for the
  * elasticity layout); it clears values first unless FEM_ACCUMULATE.  values
  * has nnz entries (4 nnz for elasticity, in the layout of fem_elas_pattern).
  * Element formulas: Section 2 (MassElem, MassWElem, StiffMatElem) and the
@@ -192,17 +214,17 @@ int fem_elas_pattern(int32_t nq, int64_t nnz, const int32_t *row_ptr, const int3
 
 int fem_assemble_mass(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
                       const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
-                      const uint32_t *inc_pos, const int32_t *slot,
+                      const uint32_t *inc_pos, const uint64_t *fan, const int32_t *slot,
                       double *values, int flags, void *stream);
 
 int fem_assemble_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
                        const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
-                       const uint32_t *inc_pos, const int32_t *slot, const double *w,
-                       double *values, int flags, void *stream);
+                       const uint32_t *inc_pos, const uint64_t *fan, const int32_t *slot,
+                       const double *w, double *values, int flags, void *stream);
 
 int fem_assemble_stiff(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
                        const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
-                       const uint32_t *inc_pos, const int32_t *slot,
+                       const uint32_t *inc_pos, const uint64_t *fan, const int32_t *slot,
                        double *values, int flags, void *stream);
 
 /* Operator bits of fem_assemble. */
@@ -225,29 +247,31 @@ int fem_assemble_workspace(int32_t nq, int ops, size_t *bytes /* HOST */);
  * as in the single-operator calls below, which are this call with one bit. */
 int fem_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q, const double *w,
                  const int32_t *me, const int32_t *row_ptr, const int32_t *col_idx,
-                 const int32_t *inc_ptr, const uint32_t *inc_pos, const int32_t *slot,
-                 double lambda, double mu, double *vals_M, double *vals_Mw, double *vals_S,
+                 const int32_t *inc_ptr, const uint32_t *inc_pos, const uint64_t *fan,
+                 const int32_t *slot, double lambda, double mu, double *vals_M, double *vals_Mw,
+                 double *vals_S,
                  double *vals_K, void *work, size_t work_bytes, const struct fem_tune *tune,
                  int flags, void *stream);
 
 /* S and M in one pass over the mesh (shared gathers of q). */
 int fem_assemble_stiff_mass(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
                             const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
-                            const uint32_t *inc_pos, const int32_t *slot,
+                            const uint32_t *inc_pos, const uint64_t *fan, const int32_t *slot,
                             double *vals_S, double *vals_M, int flags, void *stream);
 
 /* S and Mw in one pass (the forward of the differentiable assembly). */
 int fem_assemble_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
                              const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
-                             const uint32_t *inc_pos, const int32_t *slot, const double *w,
-                             double *vals_S, double *vals_Mw, int flags, void *stream);
+                             const uint32_t *inc_pos, const uint64_t *fan, const int32_t *slot,
+                             const double *w, double *vals_S, double *vals_Mw, int flags,
+                             void *stream);
 
 /* Elasticity stiffness (requires lambda + mu > 0); values_e [4 nnz] in the
  * layout of fem_elas_pattern. */
 int fem_assemble_elas(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
                       const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
-                      const uint32_t *inc_pos, const int32_t *slot, double lambda, double mu,
-                      double *values_e, int flags, void *stream);
+                      const uint32_t *inc_pos, const uint64_t *fan, const int32_t *slot,
+                      double lambda, double mu, double *values_e, int flags, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batched assembly                                                          */
@@ -271,7 +295,7 @@ int fem_batch_globalize(int32_t nb, int32_t nme, const int64_t *vtx_off, const i
 int fem_assemble_stiff_mass_batched(int32_t nb, int32_t nq, int64_t nnz, const double *q,
                                     const int32_t *row_ptr, const int32_t *col_idx,
                                     const int32_t *inc_ptr, const uint32_t *inc_pos,
-                                    double *vals_S, double *vals_M,
+                                    const uint64_t *fan, double *vals_S, double *vals_M,
                                     const fem_tune *tune /* HOST, nullable */, int flags,
                                     void *stream);
 

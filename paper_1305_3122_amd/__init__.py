@@ -29,7 +29,7 @@ __all__ = [
     "FEM_PACKED_QW", "fem_tune",
     "FEM_OP_MASS", "FEM_OP_WMASS", "FEM_OP_STIFF", "FEM_OP_ELAS",
     "FEM_PATTERN_AUTO", "FEM_PATTERN_COARSE", "FEM_PATTERN_ATOMIC", "fem_pattern_set_path",
-    "fem_pattern", "fem_transpose_map", "fem_elas_pattern", "fem_assemble", "fem_assemble_mass",
+    "fem_pattern", "fem_fan_plan", "fem_transpose_map", "fem_elas_pattern", "fem_assemble", "fem_assemble_mass",
     "fem_assemble_wmass", "fem_assemble_stiff", "fem_assemble_stiff_mass",
     "fem_assemble_stiff_wmass", "fem_assemble_elas", "fem_batch_globalize",
     "fem_assemble_stiff_mass_batched", "Graph", "SparseCSR", "fem_sparse", "fem_sparse_values",
@@ -88,6 +88,7 @@ class Pattern:
     inc_pos: object       # [3 nme]  uint32 stored as int32 (p1 | p2 << 16)
     slot: object = None   # [9][nme] int32 or None
     tpos: object = None   # [nnz]    int32 or None (fem_transpose_map)
+    fan: object = None    # [nq]     int64 (uint64 fan codes of fem_fan_plan) or None
 
     def csr(self, values):
         """torch.sparse_csr_tensor sharing row_ptr / col_idx / values."""
@@ -96,11 +97,12 @@ class Pattern:
 
     def args(self):
         return (_ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.inc_ptr), _ptr(self.inc_pos),
-                _ptr(self.slot))
+                _ptr(self.fan), _ptr(self.slot))
 
 
-def fem_pattern(me, nq: int, *, slot: bool = False, stream=None) -> Pattern:
-    """Symbolic phase (C: fem_pattern).  me: [nme][3] int32 on the GPU."""
+def fem_pattern(me, nq: int, *, slot: bool = False, fan: bool = True, stream=None) -> Pattern:
+    """Symbolic phase (C: fem_pattern, then fem_fan_plan unless fan=False).
+    me: [nme][3] int32 on the GPU."""
     torch = _torch()
     lib = _lib.load()
     _dev(me, torch.int32, "me")
@@ -124,8 +126,22 @@ def fem_pattern(me, nq: int, *, slot: bool = False, stream=None) -> Pattern:
                                _ptr(inc_ptr), _ptr(inc), _ptr(inc_pos), _ptr(sl), _ptr(work),
                                int(ws.value), C.byref(nnz), _stream(stream)))
     n = int(nnz.value)
-    return Pattern(int(nq), nme, n, me, row_ptr, col_buf[:n], inc_ptr, inc[:3 * nme],
-                   inc_pos[:3 * nme], None if sl is None else sl[:9 * nme].view(9, nme))
+    pat = Pattern(int(nq), nme, n, me, row_ptr, col_buf[:n], inc_ptr, inc[:3 * nme],
+                  inc_pos[:3 * nme], None if sl is None else sl[:9 * nme].view(9, nme))
+    if fan:
+        fem_fan_plan(pat, stream=stream)
+    return pat
+
+
+def fem_fan_plan(pat: Pattern, *, stream=None):
+    """Fan codes of every row (C: fem_fan_plan), kept on the pattern; the
+    numeric calls then walk each row's triangles around its vertex."""
+    torch = _torch()
+    fan = torch.empty(pat.nq, dtype=torch.int64, device=pat.row_ptr.device)
+    _lib.check(_lib.load().fem_fan_plan(pat.nq, pat.nme, _ptr(pat.row_ptr), _ptr(pat.inc_ptr),
+                                        _ptr(pat.inc_pos), _ptr(fan), _stream(stream)))
+    pat.fan = fan
+    return fan
 
 
 def fem_pattern_set_path(path: int) -> None:
@@ -275,7 +291,8 @@ def fem_assemble_stiff_mass_batched(pat: Pattern, q, nb: int, *, tune: Optional[
     t = C.byref(tune) if tune is not None else None
     _lib.check(_lib.load().fem_assemble_stiff_mass_batched(
         int(nb), pat.nq, pat.nnz, _ptr(_q(pat, q)), _ptr(pat.row_ptr), _ptr(pat.col_idx),
-        _ptr(pat.inc_ptr), _ptr(pat.inc_pos), _ptr(S), _ptr(M), t, flags, _stream(stream)))
+        _ptr(pat.inc_ptr), _ptr(pat.inc_pos), _ptr(pat.fan), _ptr(S), _ptr(M), t, flags,
+        _stream(stream)))
     return S, M
 
 

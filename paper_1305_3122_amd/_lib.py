@@ -52,7 +52,7 @@ _int = C.c_int
 _dbl = C.c_double
 _szp = C.POINTER(C.c_size_t)
 
-_PAT = [_vp, _vp, _vp, _vp, _vp]  # row_ptr, col_idx, inc_ptr, inc_pos, slot
+_PAT = [_vp, _vp, _vp, _vp, _vp, _vp]  # row_ptr, col_idx, inc_ptr, inc_pos, fan, slot
 _NUM_HEAD = [_i32, _i32, _i64, _vp, _vp]  # nq, nme, nnz, q, me
 
 SIGNATURES = {
@@ -64,11 +64,12 @@ SIGNATURES = {
                            C.POINTER(_i64), _vp]),
     "fem_pattern_set_path": (_int, [_int]),
     "fem_transpose_map": (_int, [_i32, _i64, _vp, _vp, _vp, _vp]),
+    "fem_fan_plan": (_int, [_i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "fem_elas_pattern": (_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp]),
     "fem_assemble_workspace": (_int, [_i32, _int, _szp]),
-    "fem_assemble": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl,
-                            _dbl, _vp, _vp, _vp, _vp, _vp, C.c_size_t, C.POINTER(fem_tune), _int,
-                            _vp]),
+    "fem_assemble": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                            _dbl, _dbl, _vp, _vp, _vp, _vp, _vp, C.c_size_t, C.POINTER(fem_tune),
+                            _int, _vp]),
     "fem_assemble_mass": (_int, _NUM_HEAD + _PAT + [_vp, _int, _vp]),
     "fem_assemble_wmass": (_int, _NUM_HEAD + _PAT + [_vp, _vp, _int, _vp]),
     "fem_assemble_stiff": (_int, _NUM_HEAD + _PAT + [_vp, _int, _vp]),
@@ -77,7 +78,7 @@ SIGNATURES = {
     "fem_assemble_elas": (_int, _NUM_HEAD + _PAT + [_dbl, _dbl, _vp, _int, _vp]),
     "fem_batch_globalize": (_int, [_i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "fem_assemble_stiff_mass_batched": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                               C.POINTER(fem_tune), _int, _vp]),
+                                               _vp, C.POINTER(fem_tune), _int, _vp]),
     "fem_graph_begin": (_int, [_vp]),
     "fem_graph_end": (_int, [_vp, C.POINTER(_vp)]),
     "fem_graph_launch": (_int, [_vp, _vp]),

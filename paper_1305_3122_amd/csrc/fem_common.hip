@@ -170,7 +170,7 @@ int exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, long long *pa
 
 extern "C" const char *fem_last_error(void) { return fem::last_error(); }
 
-extern "C" int fem_version(void) { return 100; }
+extern "C" int fem_version(void) { return 200; }
 
 extern "C" int fem_graph_begin(void *stream) {
     fem::clear_error();

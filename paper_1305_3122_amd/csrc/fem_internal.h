@@ -62,6 +62,25 @@ struct PatternCounters {
     long long total[4];   // totals written by the scans
 };
 
+// ---------------------------------------------------------------- fan codes
+//
+// Fan code of a CSR row i (fem_fan_plan, one uint64 per row): the neighbour
+// slots of vertex i in the order its triangles are met turning around i,
+// such that step j of the walk is the triangle (i, s_j, s_{j+1}) in that
+// triangle's own vertex order (indices mod n for a closed fan).
+//   bits 0..3       n, the number of neighbour slots; 0: the row has no
+//                   single consistently oriented fan (or is too long), and
+//                   is summed in ascending triangle order instead
+//   bit  4          closed (vertex inside the mesh: n triangles; else n - 1)
+//   bits 5..8       the row slot of the diagonal entry
+//   bits 9 + 4j ..  slot s_j, j < n <= FAN_NMAX
+constexpr int FAN_NMAX = 13;
+
+__host__ __device__ inline int fan_n(uint64_t c) { return (int)(c & 15u); }
+__host__ __device__ inline bool fan_closed(uint64_t c) { return ((c >> 4) & 1u) != 0; }
+__host__ __device__ inline int fan_pd(uint64_t c) { return (int)((c >> 5) & 15u); }
+__host__ __device__ inline int fan_slot(uint64_t c, int j) { return (int)((c >> (9 + 4 * j)) & 15u); }
+
 // ---------------------------------------------------------------- device helpers
 
 // Inclusive prefix sum over the 64 lanes of a wave.

@@ -686,6 +686,327 @@ __global__ __launch_bounds__(WAVE) void k_rows_reg(
     }
 }
 
+// ------------------------------------------------------------------ row owner, fan order
+//
+// With the fan codes of fem_fan_plan, a lane walks the triangles of its row
+// in the order they are met turning around the vertex: step j is the
+// triangle (i, s_j, s_{j+1}), so slot s_j receives the c2 term of step j-1
+// and the c1 term of step j -- two terms, whose floating-point sum does not
+// depend on their order, hence the same bits as the ascending-triangle sum
+// -- and no per-triangle search over the row's slots is needed.  The
+// diagonal sums its terms in walk order.  Each neighbour is gathered once,
+// into a register of its walk position (the row's own coordinates are read
+// coalesced), so the gathered records need no LDS; LDS only transposes the
+// finished values for coalesced stores.  Rows without a fan code are summed
+// per lane in ascending triangle order (the chunk path of k_rows_reg).
+
+// One walk over the fan: v[m][j] = value of operator m at slot s_j,
+// dg[m] = diagonal value (zeros when `on` is false).
+template <int PM, int N>
+__device__ __forceinline__ void fan_walk(bool on, int n, bool closed, double2 xi, double wi,
+                                         const double2 (&x)[N], const double (&wn)[N], Lame L,
+                                         double (&v)[Ops<PM>::NV][N], double (&dg)[Ops<PM>::NV]) {
+    using O = Ops<PM>;
+#pragma unroll
+    for (int m = 0; m < O::NV; ++m) {
+        dg[m] = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[m][j] = 0.0;
+    }
+    if (!on) return;
+    const int d = closed ? n : n - 1;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (j < d) {
+            const bool wrap = j + 1 >= n;   // last step of a closed fan: back to s_0
+            const int jn = j + 1 < N ? j + 1 : 0;
+            const double2 x2 = wrap ? x[0] : x[jn];
+            const double w2 = wrap ? wn[0] : wn[jn];
+            double c[O::NS > 0 ? O::NS : 1][3];
+            double ce[3][4];
+            elem_row<PM>(xi.x, xi.y, x[j].x, x[j].y, x2.x, x2.y, wi, wn[j], w2, L, c, ce);
+#pragma unroll
+            for (int m = 0; m < O::NS; ++m) {
+                dg[m] += c[m][0];
+                v[m][j] += c[m][1];
+                if (j + 1 < N && !wrap) v[m][jn] = c[m][2];
+                if (wrap) v[m][0] += c[m][2];
+            }
+            if constexpr (O::K) {
+#pragma unroll
+                for (int z = 0; z < 4; ++z) {
+                    dg[O::NS + z] += ce[0][z];
+                    v[O::NS + z][j] += ce[1][z];
+                    if (j + 1 < N && !wrap) v[O::NS + z][jn] = ce[2][z];
+                    if (wrap) v[O::NS + z][0] += ce[2][z];
+                }
+            }
+        }
+    }
+}
+
+// Stores one value of the lane's own row (fallback paths).
+__device__ __forceinline__ void put(double *o, int64_t e, double v, int accumulate) {
+    if (accumulate) o[e] += v;
+    else o[e] = v;
+}
+
+// The fan walk of one row from global memory, every value stored directly
+// (fan rows longer than the register walk, or in a tile too large for LDS).
+// Same steps and order of additions as fan_walk.
+template <int MASK>
+__device__ void fan_row_global(int64_t i, int32_t rs, int32_t len, uint64_t code,
+                               const double2 *__restrict__ q2, const double *__restrict__ w,
+                               const int32_t *__restrict__ col_idx, Outs out, Lame L,
+                               int accumulate) {
+    using O = Ops<MASK>;
+    constexpr int NS = O::NS, NV = O::NV;
+    const int n = fan_n(code);
+    const bool closed = fan_closed(code);
+    const int d = closed ? n : n - 1;
+    const int32_t *cr = col_idx + rs;
+    const double2 xi = q2[i];
+    const double wi = O::W ? w[i] : 0.0;
+    const int64_t j0 = cr[fan_slot(code, 0)];
+    const double2 x0 = q2[j0];
+    const double w0 = O::W ? w[j0] : 0.0;
+    double2 xa = x0;
+    double wa = w0;
+    double dg[NV], carry[NV], first[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) dg[m] = carry[m] = first[m] = 0.0;
+    // slot s of operator m (K: z-th value of the 2 x 2 block) of this row
+    auto store = [&](int m, int sl, double val) {
+        if (m < NS) {
+            put(out.o[m] + rs, sl, val, accumulate);
+        } else {
+            const int z = m - NS;
+            const int64_t at = 4 * (int64_t)rs + (z >= 2 ? 2 * len : 0) + 2 * sl + (z & 1);
+            put(out.o[3], at, val, accumulate);
+        }
+    };
+    for (int j = 0; j < d; ++j) {
+        const bool wrap = j + 1 >= n;
+        double2 xb = x0;
+        double wb = w0;
+        if (!wrap) {
+            const int64_t jb = cr[fan_slot(code, j + 1)];
+            xb = q2[jb];
+            wb = O::W ? w[jb] : 0.0;
+        }
+        double c[NS > 0 ? NS : 1][3];
+        double ce[3][4];
+        elem_row<MASK>(xi.x, xi.y, xa.x, xa.y, xb.x, xb.y, wi, wa, wb, L, c, ce);
+        double c0[NV], c1[NV], c2[NV];
+#pragma unroll
+        for (int m = 0; m < NS; ++m) {
+            c0[m] = c[m][0];
+            c1[m] = c[m][1];
+            c2[m] = c[m][2];
+        }
+        if constexpr (O::K) {
+#pragma unroll
+            for (int z = 0; z < 4; ++z) {
+                c0[NS + z] = ce[0][z];
+                c1[NS + z] = ce[1][z];
+                c2[NS + z] = ce[2][z];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            dg[m] += c0[m];
+            if (j == 0) first[m] = c1[m];
+            else store(m, fan_slot(code, j), carry[m] + c1[m]);
+            carry[m] = c2[m];
+        }
+        xa = xb;
+        wa = wb;
+    }
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        if (closed) {
+            store(m, fan_slot(code, 0), first[m] + carry[m]);
+        } else {
+            store(m, fan_slot(code, 0), first[m]);
+            store(m, fan_slot(code, n - 1), carry[m]);
+        }
+        store(m, fan_pd(code), dg[m]);
+    }
+}
+
+template <int MASK, int U, int N>
+__global__ __launch_bounds__(WAVE) void k_rows_fan(
+    int32_t nq, const double *__restrict__ q, const double *__restrict__ w,
+    const double4 *__restrict__ qw, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ col_idx, const int32_t *__restrict__ inc_ptr,
+    const uint32_t *__restrict__ inc_pos, const uint64_t *__restrict__ fan, Outs out, Lame L,
+    int accumulate, int64_t ntiles) {
+    using O = Ops<MASK>;
+    constexpr int MS = MASK & (M_BIT | W_BIT | S_BIT);   // scalar operators (phase 1)
+    constexpr int NS = O::NS;
+    constexpr int EB = U * WAVE;
+    // LDS: the transposition buffer, EB doubles (one scalar operator at a
+    // time), 4 EB with K (the 2 x 2 blocks of the tile).
+    extern __shared__ double smem[];
+    const int lane = threadIdx.x;
+    const double2 *q2 = reinterpret_cast<const double2 *>(q);
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * WAVE;
+        const int64_t r1 = (r0 + WAVE < nq) ? r0 + WAVE : nq;
+        const int64_t i = r0 + lane;
+        const bool active = i < nq;
+        const int32_t E0 = row_ptr[r0], E1 = row_ptr[r1];
+        const int32_t rs = active ? row_ptr[i] : 0;
+        const int32_t re = active ? row_ptr[i + 1] : 0;
+        const uint64_t code = active ? fan[i] : 0;
+        const int32_t Ew = E1 - E0, len = re - rs;
+        const int n = fan_n(code);
+        const bool closed = fan_closed(code);
+        const bool tile_fits = Ew <= EB;
+        const bool fan_row = active && n >= 2 && len == n + 1;
+        const bool in_regs = tile_fits && fan_row && n <= N;
+        const int32_t off = rs - E0;
+
+        // ---- gathers: the neighbours in walk order, the row's own vertex
+        int32_t cj[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) cj[j] = (in_regs && j < n) ? col_idx[rs + fan_slot(code, j)] : -1;
+        double2 x[N];
+        double wn[N];
+        double2 xi = make_double2(0.0, 0.0);
+        double wi = 0.0;
+        if (O::W && qw) {
+            double4 r[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) r[j] = cj[j] >= 0 ? qw[cj[j]] : make_double4(0.0, 0.0, 0.0, 0.0);
+            const double4 ri = in_regs ? qw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                x[j] = make_double2(r[j].x, r[j].y);
+                wn[j] = r[j].z;
+            }
+            xi = make_double2(ri.x, ri.y);
+            wi = ri.z;
+        } else {
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                x[j] = cj[j] >= 0 ? q2[cj[j]] : make_double2(0.0, 0.0);
+                wn[j] = (O::W && cj[j] >= 0) ? w[cj[j]] : 0.0;
+            }
+            if (in_regs) {
+                xi = q2[i];
+                if constexpr (O::W) wi = w[i];
+            }
+        }
+        const bool zero_row = !in_regs && active && len > 0;
+
+        if constexpr (MS != 0) {
+            // ---- phase 1: scalar operators, one transposition each
+            double v[NS][N], dg[NS];
+            fan_walk<MS, N>(in_regs, n, closed, xi, wi, x, wn, L, v, dg);
+            if (tile_fits) {
+                double *s_t = smem;
+#pragma unroll
+                for (int m = 0; m < NS; ++m) {
+                    if (in_regs) {
+#pragma unroll
+                        for (int j = 0; j < N; ++j)
+                            if (j < n) s_t[off + fan_slot(code, j)] = v[m][j];
+                        s_t[off + fan_pd(code)] = dg[m];
+                    } else if (zero_row) {
+                        for (int k = 0; k < len; ++k) s_t[off + k] = 0.0;
+                    }
+                    __syncthreads();
+                    double *o = out.o[m] + E0;
+                    for (int e = lane; e < Ew; e += WAVE) {
+                        const double val = s_t[e];
+                        if (accumulate) o[e] += val;
+                        else __builtin_nontemporal_store(val, o + e);
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        if constexpr (O::K) {
+            // ---- phase 2: elasticity 2 x 2 blocks.  Row 2i: [4 off + 2 s + beta],
+            // row 2i+1: [4 off + 2 len + 2 s + beta]
+            double v[4][N], dg[4];
+            fan_walk<K_BIT, N>(in_regs, n, closed, xi, wi, x, wn, L, v, dg);
+            if (tile_fits) {
+                double *s_k = smem;
+                if (in_regs) {
+#pragma unroll
+                    for (int j = 0; j <= N; ++j) {
+                        if (j < n || j == N) {
+                            const int sl = j < N ? fan_slot(code, j) : fan_pd(code);
+                            const double a0 = j < N ? v[0][j] : dg[0], a1 = j < N ? v[1][j] : dg[1];
+                            const double a2 = j < N ? v[2][j] : dg[2], a3 = j < N ? v[3][j] : dg[3];
+                            *reinterpret_cast<double2 *>(s_k + 4 * off + 2 * sl) = make_double2(a0, a1);
+                            *reinterpret_cast<double2 *>(s_k + 4 * off + 2 * len + 2 * sl) =
+                                make_double2(a2, a3);
+                        }
+                    }
+                } else if (zero_row) {
+                    for (int k = 0; k < 4 * len; ++k) s_k[4 * off + k] = 0.0;
+                }
+                __syncthreads();
+                double *o = out.o[3] + 4 * (int64_t)E0;
+                for (int e = lane; e < 4 * Ew; e += WAVE) {
+                    const double val = s_k[e];
+                    if (accumulate) o[e] += val;
+                    else __builtin_nontemporal_store(val, o + e);
+                }
+                __syncthreads();
+            }
+        }
+        if (zero_row) {
+            // ---- fan rows the registers or the tile cannot hold: the same walk
+            // from global memory; rows without a fan: ascending triangle order,
+            // LMAX_REG entries at a time (as k_rows_reg).  The tile stores above
+            // wrote 0 (or added 0) here, and their barrier ordered them first.
+            if (fan_row) {
+                fan_row_global<MASK>(i, rs, len, code, q2, w, col_idx, out, L, accumulate);
+            } else {
+                constexpr int LM = 8;
+                const int32_t *cr = col_idx + rs;
+                const int32_t is = inc_ptr[i], ie = inc_ptr[i + 1];
+                int32_t pdg = 0;
+                while (pdg < len - 1 && cr[pdg] != (int32_t)i) ++pdg;
+                const double xg = q[2 * i], yg = q[2 * i + 1];
+                const double wg = O::W ? w[i] : 0.0;
+                for (int32_t c0 = 0; c0 < len; c0 += LM) {
+                    if constexpr (MS != 0) {
+                        double ch[NS][LM];
+                        chunk_sum<MS, LM>(q, w, cr, inc_pos, is, ie, c0, pdg, xg, yg, wg, L, ch);
+#pragma unroll
+                        for (int k = 0; k < LM; ++k) {
+                            const int32_t e = c0 + k;
+                            if (e >= len) break;
+#pragma unroll
+                            for (int m = 0; m < NS; ++m) put(out.o[m] + rs, e, ch[m][k], accumulate);
+                        }
+                    }
+                    if constexpr (O::K) {
+                        double ch[4][LM];
+                        chunk_sum<K_BIT, LM>(q, w, cr, inc_pos, is, ie, c0, pdg, xg, yg, wg, L, ch);
+                        double *ok = out.o[3] + 4 * (int64_t)rs;
+#pragma unroll
+                        for (int k = 0; k < LM; ++k) {
+                            const int32_t e = c0 + k;
+                            if (e >= len) break;
+                            put(ok, 2 * e, ch[0][k], accumulate);
+                            put(ok, 2 * e + 1, ch[1][k], accumulate);
+                            put(ok, 2 * len + 2 * e, ch[2][k], accumulate);
+                            put(ok, 2 * len + 2 * e + 1, ch[3][k], accumulate);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ triangle + atomics
 
 template <int MASK>
@@ -755,6 +1076,7 @@ struct Args {
     const double *q, *w;
     const int32_t *me, *row_ptr, *col_idx, *inc_ptr, *slot;
     const uint32_t *inc_pos;
+    const uint64_t *fan;   // fan codes of fem_fan_plan, or NULL
     double *vals[4];   // M, Mw, S, K
     Lame L;
     void *work;
@@ -812,6 +1134,33 @@ int launch_reg(const Args &a, const double4 *qw, int eb, int grid_blocks) {
     return launch_reg_u<MASK, 16>(a, qw, grid_blocks);
 }
 
+constexpr int FAN_REG = 8;   // neighbour slots walked in registers by k_rows_fan
+
+template <int MASK, int U>
+int launch_fan_u(const Args &a, const double4 *qw, int grid_blocks) {
+    const int64_t ntiles = (a.nq + WAVE - 1) / WAVE;
+    const int64_t grid = grid_blocks > 0 ? (grid_blocks < ntiles ? grid_blocks : ntiles) : ntiles;
+    FEM_REQUIRE(grid <= INT32_MAX, FEM_EOVERFLOW, "too many tiles");
+    const size_t lds = (size_t)U * WAVE * (Ops<MASK>::K ? 32 : 8);
+    hipLaunchKernelGGL((k_rows_fan<MASK, U, FAN_REG>), dim3((unsigned)grid), dim3(WAVE), lds, a.s,
+                       a.nq, a.q, a.w, qw, a.row_ptr, a.col_idx, a.inc_ptr, a.inc_pos, a.fan,
+                       outs_for(a), a.L, (a.flags & FEM_ACCUMULATE) ? 1 : 0, ntiles);
+    FEM_LAUNCH_CHECK();
+    return FEM_OK;
+}
+
+template <int MASK>
+int launch_fan(const Args &a, const double4 *qw, int eb, int grid_blocks) {
+    if (eb <= 0) eb = DEFAULT_EB;
+    const int u = (eb + WAVE - 1) / WAVE;
+    if (u <= 4) return launch_fan_u<MASK, 4>(a, qw, grid_blocks);
+    if (u <= 7) return launch_fan_u<MASK, 7>(a, qw, grid_blocks);
+    if (u <= 8) return launch_fan_u<MASK, 8>(a, qw, grid_blocks);
+    if (u <= 10) return launch_fan_u<MASK, 10>(a, qw, grid_blocks);
+    if (u <= 12) return launch_fan_u<MASK, 12>(a, qw, grid_blocks);
+    return launch_fan_u<MASK, 16>(a, qw, grid_blocks);
+}
+
 template <int MASK, int U>
 int launch_rows_u(const Args &a, const double4 *qw, int grid_blocks) {
     const int64_t ntiles = (a.nq + WAVE - 1) / WAVE;
@@ -862,6 +1211,7 @@ int run_mask(const Args &a, const double4 *qw, const fem_tune *tune) {
     if (a.flags & FEM_ATOMIC) return launch_atomic<MASK>(a);
     const int eb = tune ? tune->lds_entries : 0, grid = tune ? tune->grid_blocks : 0;
     if (tune && tune->variant == 1) return launch_rows<MASK>(a, qw, eb, grid);
+    if (a.fan) return launch_fan<MASK>(a, qw, eb, grid);
     return launch_reg<MASK>(a, qw, eb, grid);
 }
 
@@ -956,9 +1306,9 @@ int run_ops(const Args &a, const fem_tune *tune) {
 
 Args make_args(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q, const double *w,
                const int32_t *me, const int32_t *row_ptr, const int32_t *col_idx,
-               const int32_t *inc_ptr, const uint32_t *inc_pos, const int32_t *slot, double lam,
-               double mu, double *vM, double *vW, double *vS, double *vK, void *work,
-               size_t work_bytes, int flags, void *stream) {
+               const int32_t *inc_ptr, const uint32_t *inc_pos, const uint64_t *fan,
+               const int32_t *slot, double lam, double mu, double *vM, double *vW, double *vS,
+               double *vK, void *work, size_t work_bytes, int flags, void *stream) {
     Args a{};
     a.ops = ops;
     a.nq = nq;
@@ -971,6 +1321,7 @@ Args make_args(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q, c
     a.col_idx = col_idx;
     a.inc_ptr = inc_ptr;
     a.inc_pos = inc_pos;
+    a.fan = fan;
     a.slot = slot;
     a.L = {lam, mu};
     a.vals[0] = vM;
@@ -999,92 +1350,100 @@ extern "C" int fem_assemble_workspace(int32_t nq, int ops, size_t *bytes) {
 extern "C" int fem_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q,
                             const double *w, const int32_t *me, const int32_t *row_ptr,
                             const int32_t *col_idx, const int32_t *inc_ptr, const uint32_t *inc_pos,
-                            const int32_t *slot, double lambda, double mu, double *vals_M,
+                            const uint64_t *fan, const int32_t *slot, double lambda, double mu,
+                            double *vals_M,
                             double *vals_Mw, double *vals_S, double *vals_K, void *work,
                             size_t work_bytes, const fem_tune *tune, int flags, void *stream) {
     clear_error();
-    Args a = make_args(ops, nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, inc_pos, slot, lambda,
-                       mu, vals_M, vals_Mw, vals_S, vals_K, work, work_bytes, flags, stream);
+    Args a = make_args(ops, nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, inc_pos, fan, slot,
+                       lambda, mu, vals_M, vals_Mw, vals_S, vals_K, work, work_bytes, flags, stream);
     return run("fem_assemble", a, tune);
 }
 
 extern "C" int fem_assemble_mass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                                  const int32_t *me, const int32_t *row_ptr, const int32_t *col_idx,
                                  const int32_t *inc_ptr, const uint32_t *inc_pos,
-                                 const int32_t *slot, double *values, int flags, void *stream) {
+                                 const uint64_t *fan, const int32_t *slot, double *values, int flags,
+                                 void *stream) {
     clear_error();
-    Args a = make_args(M_BIT, nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, inc_pos, slot,
-                       0, 0, values, nullptr, nullptr, nullptr, nullptr, 0, flags, stream);
+    Args a = make_args(M_BIT, nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, inc_pos, fan,
+                       slot, 0, 0, values, nullptr, nullptr, nullptr, nullptr, 0, flags, stream);
     return run("fem_assemble_mass", a, nullptr);
 }
 
 extern "C" int fem_assemble_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                                   const int32_t *me, const int32_t *row_ptr, const int32_t *col_idx,
                                   const int32_t *inc_ptr, const uint32_t *inc_pos,
-                                  const int32_t *slot, const double *w, double *values, int flags,
+                                  const uint64_t *fan, const int32_t *slot, const double *w,
+                                  double *values, int flags,
                                   void *stream) {
     clear_error();
-    Args a = make_args(W_BIT, nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, inc_pos, slot, 0, 0,
-                       nullptr, values, nullptr, nullptr, nullptr, 0, flags, stream);
+    Args a = make_args(W_BIT, nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, inc_pos, fan, slot,
+                       0, 0, nullptr, values, nullptr, nullptr, nullptr, 0, flags, stream);
     return run("fem_assemble_wmass", a, nullptr);
 }
 
 extern "C" int fem_assemble_stiff(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                                   const int32_t *me, const int32_t *row_ptr, const int32_t *col_idx,
                                   const int32_t *inc_ptr, const uint32_t *inc_pos,
-                                  const int32_t *slot, double *values, int flags, void *stream) {
+                                  const uint64_t *fan, const int32_t *slot, double *values,
+                                  int flags, void *stream) {
     clear_error();
-    Args a = make_args(S_BIT, nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, inc_pos, slot,
-                       0, 0, nullptr, nullptr, values, nullptr, nullptr, 0, flags, stream);
+    Args a = make_args(S_BIT, nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, inc_pos, fan,
+                       slot, 0, 0, nullptr, nullptr, values, nullptr, nullptr, 0, flags, stream);
     return run("fem_assemble_stiff", a, nullptr);
 }
 
 extern "C" int fem_assemble_stiff_mass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                                        const int32_t *me, const int32_t *row_ptr,
                                        const int32_t *col_idx, const int32_t *inc_ptr,
-                                       const uint32_t *inc_pos, const int32_t *slot,
-                                       double *vals_S, double *vals_M, int flags, void *stream) {
+                                       const uint32_t *inc_pos, const uint64_t *fan,
+                                       const int32_t *slot, double *vals_S, double *vals_M,
+                                       int flags, void *stream) {
     clear_error();
     Args a = make_args(S_BIT | M_BIT, nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr,
-                       inc_pos, slot, 0, 0, vals_M, nullptr, vals_S, nullptr, nullptr, 0, flags, stream);
+                       inc_pos, fan, slot, 0, 0, vals_M, nullptr, vals_S, nullptr, nullptr, 0, flags,
+                       stream);
     return run("fem_assemble_stiff_mass", a, nullptr);
 }
 
 extern "C" int fem_assemble_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                                         const int32_t *me, const int32_t *row_ptr,
                                         const int32_t *col_idx, const int32_t *inc_ptr,
-                                        const uint32_t *inc_pos, const int32_t *slot,
-                                        const double *w, double *vals_S, double *vals_Mw, int flags,
+                                        const uint32_t *inc_pos, const uint64_t *fan,
+                                        const int32_t *slot, const double *w, double *vals_S,
+                                        double *vals_Mw, int flags,
                                         void *stream) {
     clear_error();
     Args a = make_args(S_BIT | W_BIT, nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, inc_pos,
-                       slot, 0, 0, nullptr, vals_Mw, vals_S, nullptr, nullptr, 0, flags, stream);
+                       fan, slot, 0, 0, nullptr, vals_Mw, vals_S, nullptr, nullptr, 0, flags, stream);
     return run("fem_assemble_stiff_wmass", a, nullptr);
 }
 
 extern "C" int fem_assemble_elas(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                                  const int32_t *me, const int32_t *row_ptr, const int32_t *col_idx,
                                  const int32_t *inc_ptr, const uint32_t *inc_pos,
-                                 const int32_t *slot, double lambda, double mu, double *values_e,
+                                 const uint64_t *fan, const int32_t *slot, double lambda, double mu,
+                                 double *values_e,
                                  int flags, void *stream) {
     clear_error();
-    Args a = make_args(K_BIT, nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, inc_pos, slot,
-                       lambda, mu, nullptr, nullptr, nullptr, values_e, nullptr, 0, flags, stream);
+    Args a = make_args(K_BIT, nq, nme, nnz, q, nullptr, me, row_ptr, col_idx, inc_ptr, inc_pos, fan,
+                       slot, lambda, mu, nullptr, nullptr, nullptr, values_e, nullptr, 0, flags, stream);
     return run("fem_assemble_elas", a, nullptr);
 }
 
 extern "C" int fem_assemble_stiff_mass_batched(int32_t nb, int32_t nq, int64_t nnz, const double *q,
                                                const int32_t *row_ptr, const int32_t *col_idx,
                                                const int32_t *inc_ptr, const uint32_t *inc_pos,
-                                               double *vals_S, double *vals_M,
+                                               const uint64_t *fan, double *vals_S, double *vals_M,
                                                const fem_tune *tune, int flags, void *stream) {
     clear_error();
     FEM_REQUIRE(nb >= 1, FEM_EINVAL, "fem_assemble_stiff_mass_batched: nb must be >= 1");
     FEM_REQUIRE((flags & FEM_ATOMIC) == 0, FEM_EINVAL,
                 "fem_assemble_stiff_mass_batched: only the row-owner scheme is batched");
     Args a = make_args(S_BIT | M_BIT, nq, 0, nnz, q, nullptr, nullptr, row_ptr, col_idx, inc_ptr,
-                       inc_pos, nullptr, 0, 0, vals_M, nullptr, vals_S, nullptr, nullptr, 0, flags,
-                       stream);
+                       inc_pos, fan, nullptr, 0, 0, vals_M, nullptr, vals_S, nullptr, nullptr, 0,
+                       flags, stream);
     return run("fem_assemble_stiff_mass_batched", a, tune);
 }
 

@@ -951,6 +951,72 @@ __global__ __launch_bounds__(256) void k_transpose(int32_t nq, const int32_t *__
     }
 }
 
+// Fan code of every row (layout in fem_internal.h) from the triangle lists:
+// triangle t of vertex i links its two neighbour slots p1 -> p2 (next and
+// previous vertex in the triangle's own order), and the fan is the chain of
+// these links.  A row gets a code only if every slot is left by at most one
+// triangle and entered by at most one, the links form one closed cycle or
+// one open path through all of the row's triangles, and every off-diagonal
+// slot is on it; otherwise (inconsistent orientation, several fans meeting
+// at the vertex, a non-manifold edge, more than FAN_NMAX neighbours) it
+// gets 0.  A closed fan starts at the first triangle's p1 (lowest id), an
+// open one at its only slot that no triangle enters.
+__global__ __launch_bounds__(256) void k_fan_plan(int32_t nq, const int32_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ inc_ptr,
+                                                  const uint32_t *__restrict__ inc_pos,
+                                                  uint64_t *__restrict__ fan) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const int32_t is = inc_ptr[i], d = inc_ptr[i + 1] - is;
+    const int32_t len = row_ptr[i + 1] - row_ptr[i];
+    uint64_t code = 0;
+    if (d >= 1 && d <= FAN_NMAX && len >= 3 && len <= FAN_NMAX + 1) {
+        uint64_t succ = 0, p2t = 0;   // nibble tables: slot -> triangle, triangle -> p2
+        uint32_t outm = 0, inm = 0;
+        bool ok = true;
+        for (int t = 0; t < d && ok; ++t) {
+            const uint32_t pp = inc_pos[is + t];
+            const uint32_t p1 = pp & 0xffffu, p2 = pp >> 16;
+            ok = p1 < 16 && p2 < 16 && !((outm >> p1) & 1u) && !((inm >> p2) & 1u);
+            if (ok) {
+                outm |= 1u << p1;
+                inm |= 1u << p2;
+                succ |= (uint64_t)t << (4 * p1);
+                p2t |= (uint64_t)p2 << (4 * t);
+            }
+        }
+        const uint32_t used = outm | inm, starts = outm & ~inm;
+        const bool closed = starts == 0;
+        ok = ok && __builtin_popcount(used) + 1 == len &&
+             (closed ? outm == inm
+                     : (__builtin_popcount(starts) == 1 && __builtin_popcount(inm & ~outm) == 1));
+        if (ok) {
+            const int s0 = closed ? (int)(inc_pos[is] & 0xffffu) : __builtin_ctz(starts);
+            int s = s0, n = 0;
+            uint64_t slots = 0;
+            for (int j = 0; j < d && ok; ++j) {
+                // every step leaves its slot; a closed walk meets s0 again only at the end
+                ok = ((outm >> s) & 1u) && !(j > 0 && s == s0);
+                if (ok) {
+                    slots |= (uint64_t)s << (4 * n++);
+                    s = (int)((p2t >> (4 * ((succ >> (4 * s)) & 15u))) & 15u);
+                }
+            }
+            if (ok) {
+                if (closed) ok = s == s0;
+                else slots |= (uint64_t)s << (4 * n++);
+                ok = ok && n + 1 == len && n <= FAN_NMAX;
+            }
+            if (ok) {
+                const int pd = __builtin_ctz(~used);
+                code = (uint64_t)n | ((uint64_t)(closed ? 1 : 0) << 4) | ((uint64_t)pd << 5) |
+                       (slots << 9);
+            }
+        }
+    }
+    fan[i] = code;
+}
+
 constexpr int ELAS_STAGE = 8 * WAVE;   // scalar entries of a tile staged in LDS (2 + 8 KiB)
 
 // Tile of 64 scalar rows = a contiguous slice of Ew scalar entries and of
@@ -1298,6 +1364,18 @@ extern "C" int fem_transpose_map(int32_t nq, int64_t nnz, const int32_t *row_ptr
     FEM_REQUIRE(row_ptr && (nnz == 0 || (col_idx && tpos)), FEM_EINVAL, "fem_transpose_map: NULL array");
     hipLaunchKernelGGL(k_transpose, dim3(grid_for(nq, 256)), dim3(256), 0, as_stream(stream), nq,
                        row_ptr, col_idx, tpos);
+    FEM_LAUNCH_CHECK();
+    return FEM_OK;
+}
+
+extern "C" int fem_fan_plan(int32_t nq, int32_t nme, const int32_t *row_ptr, const int32_t *inc_ptr,
+                            const uint32_t *inc_pos, uint64_t *fan, void *stream) {
+    clear_error();
+    FEM_REQUIRE(nq >= 1 && nme >= 0, FEM_EINVAL, "fem_fan_plan: bad sizes");
+    FEM_REQUIRE(row_ptr && inc_ptr && fan && (nme == 0 || inc_pos), FEM_EINVAL,
+                "fem_fan_plan: NULL array");
+    hipLaunchKernelGGL(k_fan_plan, dim3(grid_for(nq, 256)), dim3(256), 0, as_stream(stream), nq,
+                       row_ptr, inc_ptr, inc_pos, fan);
     FEM_LAUNCH_CHECK();
     return FEM_OK;
 }

@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_bounds(lib):
-    assert lib.fem_version() == 100
+    assert lib.fem_version() == 200
     assert lib.fem_nnz_bound(10, 7) == 10 + 42
     sz = C.c_size_t(0)
     assert lib.fem_pattern_workspace(1089, 2048, C.byref(sz)) == 0
@@ -63,15 +63,15 @@ def test_host_validation_before_any_launch(lib):
                          C.byref(nnz), None)
     assert st == _lib.FEM_ENOSPC
     # elasticity: lambda + mu must be positive (elasticity section)
-    st = lib.fem_assemble_elas(4, 2, 10, fake, fake, fake, fake, fake, fake, None, -1.0, 0.5,
+    st = lib.fem_assemble_elas(4, 2, 10, fake, fake, fake, fake, fake, fake, None, None, -1.0, 0.5,
                                fake, 0, None)
     assert st == _lib.FEM_EINVAL and b"lambda" in lib.fem_last_error()
     # FEM_ATOMIC needs the slot map
-    st = lib.fem_assemble_stiff(4, 2, 10, fake, fake, fake, fake, fake, fake, None, fake,
+    st = lib.fem_assemble_stiff(4, 2, 10, fake, fake, fake, fake, fake, fake, None, None, fake,
                                 _lib.FEM_ATOMIC, None)
     assert st == _lib.FEM_EINVAL
     # FEM_CHECK_AREA needs a workspace for its flag (the single-operator calls have none)
-    st = lib.fem_assemble_stiff(4, 2, 10, fake, fake, fake, fake, fake, fake, None, fake,
+    st = lib.fem_assemble_stiff(4, 2, 10, fake, fake, fake, fake, fake, fake, None, None, fake,
                                 _lib.FEM_CHECK_AREA, None)
     assert st == _lib.FEM_ENOSPC and b"FEM_CHECK_AREA" in lib.fem_last_error()
     ws = C.c_size_t(0)
@@ -79,8 +79,8 @@ def test_host_validation_before_any_launch(lib):
     assert ws.value == 256 + 256
     # FEM_PACKED_QW: only with the weighted mass in the row-owner scheme, and
     # only with the workspace that holds the packed records
-    args = (4, 2, 10, fake, fake, fake, fake, fake, fake, fake, None, 0.0, 0.0, fake, fake, fake,
-            fake)
+    args = (4, 2, 10, fake, fake, fake, fake, fake, fake, fake, None, None, 0.0, 0.0, fake, fake,
+            fake, fake)
     st = lib.fem_assemble(_lib.FEM_OP_STIFF, *args, fake, 4096, None, _lib.FEM_PACKED_QW, None)
     assert st == _lib.FEM_EINVAL and b"FEM_PACKED_QW" in lib.fem_last_error()
     st = lib.fem_assemble(_lib.FEM_OP_WMASS, *args, fake, 4096, None,
@@ -91,11 +91,12 @@ def test_host_validation_before_any_launch(lib):
     st = lib.fem_assemble(_lib.FEM_OP_WMASS, *args, fake, 32 * 4 - 8, None, _lib.FEM_PACKED_QW, None)
     assert st == _lib.FEM_ENOSPC
     # unknown flag bits
-    st = lib.fem_assemble_mass(4, 2, 10, fake, fake, fake, fake, fake, fake, None, fake, 64, None)
+    st = lib.fem_assemble_mass(4, 2, 10, fake, fake, fake, fake, fake, fake, None, None, fake, 64,
+                               None)
     assert st == _lib.FEM_EINVAL
     # the weighted mass needs w
-    st = lib.fem_assemble_wmass(4, 2, 10, fake, fake, fake, fake, fake, fake, None, None, fake, 0,
-                                None)
+    st = lib.fem_assemble_wmass(4, 2, 10, fake, fake, fake, fake, fake, fake, None, None, None, fake,
+                                0, None)
     assert st == _lib.FEM_EINVAL
     # graphs cannot capture the NULL stream
     assert lib.fem_graph_begin(None) == _lib.FEM_EINVAL

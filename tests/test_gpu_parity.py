@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_1305_3122_amd import meshgen as mg
-from tests.helpers import RTOL_ROW, fan_mesh, row_rel_err
+from tests.helpers import RTOL_ROW, check_fan_codes, fan_mesh, row_rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -286,6 +286,100 @@ def test_error_paths():
     m = mg.unit_square(2, seed=1)
     pat = fem.fem_pattern(_up(m.me), m.nq)
     assert pat.nnz == oracle.pattern(m.nq, m.me).nnz
+
+
+# ------------------------------------------------------------ fan order
+
+def _flip_some(me, every):
+    """Reverse the vertex order of every `every`-th triangle (same mesh, mixed
+    orientation: the rows around a flipped triangle have no consistent fan)."""
+    me = me.copy()
+    me[::every] = me[::every, ::-1]
+    return me
+
+
+def _bowtie():
+    # two triangles and a square meeting only at vertex 0: vertex 0 has two
+    # separate fans, so its row gets no fan code
+    q = np.array([[0, 0], [1, 0], [0.5, 1], [-1, 0], [-0.5, -1], [1, -1], [1, -2]], np.float64)
+    me = np.array([[0, 1, 2], [0, 3, 4], [4, 6, 5], [0, 4, 5]], np.int32)
+    return q, me
+
+
+FAN_CASES = [
+    ("cfg1_square32", lambda: mg.config_mesh(1), "all"),
+    ("disk24", lambda: mg.unit_disk(24, seed=5), "all"),
+    ("fan9", lambda: mg.Mesh(*fan_mesh(9, 1, seed=9), "fan"), "used"),
+    ("fan13", lambda: mg.Mesh(*fan_mesh(13, 0, seed=13), "fan"), "used"),
+    ("fan14", lambda: mg.Mesh(*fan_mesh(14, 0, seed=14), "fan"), "rim"),
+    ("fan40", lambda: mg.Mesh(*fan_mesh(40, 2, seed=40), "fan"), "rim"),
+    ("square10_mixed", lambda: mg.Mesh(mg.unit_square(10, seed=4).q,
+                                        _flip_some(mg.unit_square(10, seed=4).me, 3), "mixed"), "some"),
+    ("bowtie", lambda: mg.Mesh(*_bowtie(), "bowtie"), "some"),
+    ("tiny0", lambda: mg.random_tiny_mesh(np.random.default_rng(31), 40), "some"),
+]
+
+
+@pytest.mark.parametrize("name,make,expect", FAN_CASES, ids=[c[0] for c in FAN_CASES])
+def test_fan_codes_walk_the_mesh(name, make, expect):
+    # the fan codes of fem_fan_plan against the mesh: each coded walk visits
+    # triangles of the mesh in their own vertex order and covers its row; on
+    # consistently oriented manifold meshes every used row with at most 13
+    # neighbours has one
+    m = make()
+    print(f"[case] fan codes {name} nq={m.nq} nme={m.nme}", flush=True)
+    pat = fem.fem_pattern(_up(m.me), m.nq)
+    torch.cuda.synchronize()
+    rp, ci = _np(pat.row_ptr), _np(pat.col_idx)
+    coded = check_fan_codes(_np(pat.fan), rp, ci, m.me)
+    lens = np.diff(rp)
+    used = int((lens > 0).sum())
+    if expect in ("all", "used"):
+        assert coded == used
+    elif expect == "rim":
+        assert coded == used - 1          # the hub has more than 13 neighbours
+    if name == "bowtie":
+        assert _np(pat.fan)[0] == 0
+    if name == "square10_mixed":
+        assert 0 < coded < used
+
+
+@pytest.mark.parametrize("name,make,expect", FAN_CASES, ids=[c[0] for c in FAN_CASES])
+def test_fan_and_ascending_orders_agree(name, make, expect):
+    # the same values with and without the fan codes: off-diagonal entries
+    # bitwise (two terms each), diagonals within the tolerance, both against
+    # the oracle, for all four operators in one pass
+    m = make()
+    print(f"[case] fan vs ascending {name} nq={m.nq} nme={m.nme}", flush=True)
+    P = oracle.pattern(m.nq, m.me)
+    pat = fem.fem_pattern(_up(m.me), m.nq)
+    pat0 = fem.Pattern(**{**pat.__dict__, "fan": None})
+    w = np.random.default_rng(3).uniform(0.5, 2.0, size=m.nq)
+    qd, wd = _up(m.q), _up(w)
+    a = fem.fem_assemble(pat, qd, 15, w=wd, lam=LAM, mu=MU)
+    b = fem.fem_assemble(pat0, qd, 15, w=wd, lam=LAM, mu=MU)
+    torch.cuda.synchronize()
+    rows = np.repeat(np.arange(m.nq), np.diff(P.row_ptr))
+    off = P.col_idx != rows
+    # K: scalar entry e = row_ptr[i] + p owns 4 rs + 2 p + beta (row 2i) and
+    # 4 rs + 2 L + 2 p + beta (row 2i+1), rs = row_ptr[i], L its length
+    rs = P.row_ptr[rows].astype(np.int64)
+    L = np.diff(P.row_ptr)[rows].astype(np.int64)
+    pp = np.arange(P.nnz) - rs
+    offk = np.zeros(4 * P.nnz, bool)
+    for at in (4 * rs + 2 * pp, 4 * rs + 2 * pp + 1, 4 * rs + 2 * L + 2 * pp, 4 * rs + 2 * L + 2 * pp + 1):
+        offk[at] = off
+    rpe, _, se = oracle.pattern_elas(m.nq, m.me)
+    ref = {"M": oracle.assemble("mass", m.q, m.me, P.slot, P.nnz),
+           "Mw": oracle.assemble("wmass", m.q, m.me, P.slot, P.nnz, w=w),
+           "S": oracle.assemble("stiff", m.q, m.me, P.slot, P.nnz),
+           "K": oracle.assemble("elas", m.q, m.me, se, int(rpe[-1]), lam=LAM, mu=MU)}
+    for k in ref:
+        ga, gb = _np(a[k]), _np(b[k])
+        np.testing.assert_array_equal(ga[offk if k == "K" else off], gb[offk if k == "K" else off])
+        ptr = rpe if k == "K" else P.row_ptr
+        assert row_rel_err(ptr, ga, ref[k]) <= RTOL_ROW, k
+        assert row_rel_err(ptr, gb, ref[k]) <= RTOL_ROW, k
 
 
 # ------------------------------------------------------------ full size, sampled
