@@ -253,6 +253,25 @@ int fem_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q,
                  double *vals_K, void *work, size_t work_bytes, const struct fem_tune *tune,
                  int flags, void *stream);
 
+/* fem_assemble for callers that cannot allocate device memory (code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * allocation): the same arguments and results without the workspace.  The
+ * packed (x, y, w) records of the weighted mass and the FEM_CHECK_AREA flag
+ * live in a fixed device array of the library (32 FEM_NOALLOC_MAX_NQ + 256
+ * bytes, 32 MiB + 256; each GPU the library runs on holds its own copy until
+ * the process ends); the call allocates nothing.  With FEM_OP_WMASS (row-owner
+ * scheme) or FEM_CHECK_AREA, nq above FEM_NOALLOC_MAX_NQ returns FEM_ENOSPC;
+ * FEM_PACKED_QW returns FEM_EINVAL.  Every call on a GPU shares that GPU's
+ * array, so calls that overlap on one GPU (several streams or host threads)
+ * race: serialise them. */
+#define FEM_NOALLOC_MAX_NQ 1048576
+int fem_assemble_noalloc(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q,
+                         const double *w, const int32_t *me, const int32_t *row_ptr,
+                         const int32_t *col_idx, const int32_t *inc_ptr, const uint32_t *inc_pos,
+                         const uint64_t *fan, const int32_t *slot, double lambda, double mu,
+                         double *vals_M, double *vals_Mw, double *vals_S, double *vals_K,
+                         const struct fem_tune *tune, int flags, void *stream);
+
 /* S and M in one pass over the mesh (shared gathers of q). */
 int fem_assemble_stiff_mass(int32_t nq, int32_t nme, int64_t nnz, const double *q, const int32_t *me,
                             const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,

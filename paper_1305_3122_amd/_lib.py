@@ -70,6 +70,9 @@ SIGNATURES = {
     "fem_assemble": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                             _dbl, _dbl, _vp, _vp, _vp, _vp, _vp, C.c_size_t, C.POINTER(fem_tune),
                             _int, _vp]),
+    "fem_assemble_noalloc": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    _vp, _dbl, _dbl, _vp, _vp, _vp, _vp, C.POINTER(fem_tune), _int,
+                                    _vp]),
     "fem_assemble_mass": (_int, _NUM_HEAD + _PAT + [_vp, _int, _vp]),
     "fem_assemble_wmass": (_int, _NUM_HEAD + _PAT + [_vp, _vp, _int, _vp]),
     "fem_assemble_stiff": (_int, _NUM_HEAD + _PAT + [_vp, _int, _vp]),

@@ -29,6 +29,8 @@
 //   adds them through the slot map with FP64 atomics (global_atomic_add_f64).
 #include "fem_internal.h"
 
+#include <mutex>
+
 namespace fem {
 
 // operator bits (same values as FEM_OP_* of the C ABI)
@@ -1358,6 +1360,72 @@ extern "C" int fem_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const
     Args a = make_args(ops, nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, inc_pos, fan, slot,
                        lambda, mu, vals_M, vals_Mw, vals_S, vals_K, work, work_bytes, flags, stream);
     return run("fem_assemble", a, tune);
+}
+
+// ------------------------------------------------------------ allocation-free variant
+//
+// fem_assemble without a workspace argument: the packed (x, y, w) records of
+// the weighted mass and the FEM_CHECK_AREA flag live in one file-scope device
+// array instead.  Every GPU the library runs on holds its own copy for the
+// life of the process; host code addresses it only through the pointer
+// hipGetSymbolAddress returns on that device (the array's own name is a
+// host-side stand-in there, not a device address).
+namespace fem {
+constexpr size_t NOALLOC_BYTES = size_t(FEM_NOALLOC_MAX_NQ) * 32 + 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::once_flag g_scratch_once[NOALLOC_MAX_DEVICES];
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+hipError_t g_scratch_err[NOALLOC_MAX_DEVICES];
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+int scratch_for_current_device(void **out) {
+    int dev = -1;
+    FEM_HIP_CHECK(hipGetDevice(&dev));
+    FEM_REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, FEM_EUNSUPPORTED,
+                "fem_assemble_noalloc: device %d beyond the %d supported", dev, NOALLOC_MAX_DEVICES);
+    std::call_once(g_scratch_once[dev], [dev]() {
+        void *p = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? p : nullptr;
+    });
+    FEM_REQUIRE(g_scratch_err[dev] == hipSuccess && g_scratch_ptr[dev], FEM_EHIP,
+                "fem_assemble_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(g_scratch_err[dev]));
+    *out = g_scratch_ptr[dev];
+    return FEM_OK;
+}
+}  // namespace
+}  // namespace fem
+
+extern "C" int fem_assemble_noalloc(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q,
+                                    const double *w, const int32_t *me, const int32_t *row_ptr,
+                                    const int32_t *col_idx, const int32_t *inc_ptr,
+                                    const uint32_t *inc_pos, const uint64_t *fan,
+                                    const int32_t *slot, double lambda, double mu, double *vals_M,
+                                    double *vals_Mw, double *vals_S, double *vals_K,
+                                    const fem_tune *tune, int flags, void *stream) {
+    clear_error();
+    FEM_REQUIRE(!(flags & FEM_PACKED_QW), FEM_EINVAL,
+                "fem_assemble_noalloc: FEM_PACKED_QW is not accepted (the scratch is shared by every "
+                "call on the device)");
+    const bool packs = (ops & FEM_OP_WMASS) && !(flags & FEM_ATOMIC);
+    const bool needs = packs || (flags & FEM_CHECK_AREA);
+    FEM_REQUIRE(!needs || (nq >= 0 && nq <= FEM_NOALLOC_MAX_NQ), FEM_ENOSPC,
+                "fem_assemble_noalloc: nq = %d exceeds the %d vertices its scratch holds for the "
+                "weighted mass or FEM_CHECK_AREA",
+                nq, FEM_NOALLOC_MAX_NQ);
+    void *scr = nullptr;
+    if (needs) {
+        int st;
+        if ((st = scratch_for_current_device(&scr))) return st;
+    }
+    Args a = make_args(ops, nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, inc_pos, fan, slot,
+                       lambda, mu, vals_M, vals_Mw, vals_S, vals_K, scr, scr ? NOALLOC_BYTES : 0,
+                       flags, stream);
+    return run("fem_assemble_noalloc", a, tune);
 }
 
 extern "C" int fem_assemble_mass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
