@@ -4,6 +4,7 @@ Step (timed): the whole assembly of the 2048 x 2048-cell unit square
 (8,388,608 triangles, jitter 0.2 h, random vertex relabelling, FP64 values,
 int32 indices) from (q, me) resident in HBM:
     fem_pattern        symbolic phase (CSR pattern + triangle lists)
+    fem_fan_plan       the order of each row's triangles around its vertex
     fem_assemble       mass M, weighted mass Mw (w = 1 + x^2 + y^2),
                        stiffness S and elasticity K (lambda = 1, mu = 0.5),
                        all four in one pass over the rows
@@ -11,19 +12,24 @@ int32 indices) from (q, me) resident in HBM:
 value = triangles / step time (M triangles per second).
 
 Also reported: per-call HIP-event times and the roofline of each numeric
-kernel (algorithmic bytes), the stiffness + mass pair alone, the batched
+kernel (algorithmic bytes), the stiffness + mass pair alone, the gather floor
+(the kernels' random accesses without arithmetic), the same kernels on the
+square without the relabelling, the batched
 block-diagonal assembly of 512 meshes (one graph-captured launch) against a
 per-mesh launch loop, the forward + backward / forward ratio of the
 differentiable assembly, the general sparse(I, J, V) compression of the
-OptV2 triplet arrays, P1 tetrahedra on a 128^3 cube, and the CPU oracle timed
-on a bounded sample.
+OptV2 triplet arrays, P1 tetrahedra on a 128^3 cube, P2 triangles, and the
+CPU oracle timed on the step's mesh (stiffness + mass; single-threaded full
+and numeric-only runs, and an all-cores numeric run).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
 
-HBM traffic per launch comes from the rocprofv3 counter summaries committed
-under profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by what the same counters
-read for a plain 1 GiB device copy); it is reported only while the kernel
-sources hash to the value recorded there.  `--summarize KT PF PW` turns the
+L2 fetch and write traffic per launch comes from the rocprofv3 counter
+summaries committed under profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by what
+the same counters read for a plain 1 GiB device copy); for the gather kernels
+it counts the lines the L2 misses on, most of them served by the MALL rather
+than HBM.  It is reported only while the kernel sources hash to the value
+recorded there.  `--summarize KT PF PW` turns the
 csv output of the three rocprofv3 runs (kernel trace, FETCH_SIZE, WRITE_SIZE)
 of `bench.py --steps 5 --warmup 1 --no-cpu --no-extras --calib` into those
 summaries.
@@ -55,12 +61,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "step_square2048_hbm_traffic.md")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "step_square2048_l2_traffic.md")
 # the single kernel each timed call launches (deterministic row-owner kernels:
 # operator mask, unroll, register row length)
 CALL_KERNEL = {
-    "assemble_rows": "fem::k_rows_reg<15, 8, 8>",
-    "stiff_mass": "fem::k_rows_reg<5, 8, 8>",
+    "assemble_rows": "fem::k_rows_fan<15, 8, 8>",
+    "stiff_mass": "fem::k_rows_fan<5, 8, 8>",
     "elas_pattern": "fem::k_elas_pattern",
 }
 
@@ -194,7 +200,7 @@ def summarize_profiles(kt_dir, pf_dir, pw_dir, command, name="step_square2048"):
     title, workload = PROFILE_TITLES[name]
     command = command or profile_command(name)
     stats_path = os.path.join(ROOT, "profiles", f"{name}_kernel_stats.md")
-    traffic_path = os.path.join(ROOT, "profiles", f"{name}_hbm_traffic.md")
+    traffic_path = os.path.join(ROOT, "profiles", f"{name}_l2_traffic.md")
     def one(d, pattern):
         f = glob.glob(os.path.join(d, "**", pattern), recursive=True)
         if not f:
@@ -237,11 +243,16 @@ def summarize_profiles(kt_dir, pf_dir, pw_dir, command, name="step_square2048"):
     cw = max(write.get("__amd_rocclr_copyBuffer", [0.0]))
     sf = gib_kib / cf if cf > 0 else float("nan")
     sw = gib_kib / cw if cw > 0 else float("nan")
-    lines = [f"# HBM traffic per dispatch: {title}",
+    lines = [f"# L2 fetch and write traffic per dispatch: {title}",
              "",
              "FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the dispatches of the run),",
              "each scaled by what the same counter reads for a plain 1 GiB device-to-device copy",
-             "(1 GiB read, 1 GiB written).  Scaled MB = raw KiB x 1024 x scale / 1e6.",
+             "(1 GiB read, 1 GiB written).  Scaled MB = raw KiB x 1024 x scale / 1e6.  These are",
+             "the bytes the L2 caches fetch from and write to the memory side.  For streaming",
+             "kernels that is HBM traffic; for the random gathers of q (67 MB) most fetched lines",
+             "are served by the 256 MB last-level cache (MALL) in front of HBM, so the fetch",
+             "figures of gather kernels are L2-miss line traffic, not HBM traffic (they can",
+             "exceed what HBM could deliver in the kernel's time).",
              "",
              f"source-sha256: {sh}  (sha256 of {', '.join(PROFILE_SOURCES[name])})",
              "",
@@ -272,14 +283,17 @@ def algorithmic_bytes(nq, nme, nnz):
         "assemble_rows": me + q + w + 7 * vals,            # the same pass, kernel alone
         "elas_pattern": 4 * (nq + 1) + 4 * nnz + 4 * (2 * nq + 1) + 16 * nnz,
         "stiff_mass": me + q + 2 * vals,
+        "stiff_mass_full": me + q + 4 * (nq + 1) + 4 * nnz + 2 * vals,
     }
 
 
 def design_bytes(nq, nme, nnz):
     """Bytes the row-owner kernels stream by design: their index arrays
-    (row_ptr, inc_ptr, col_idx, inc_pos), the unique inputs and the outputs
-    (each once); the packed (x, y, w, 0) copy for Mw is written and read."""
-    idx = 4 * (nq + 1) * 2 + 4 * nnz + 4 * 3 * nme
+    (row_ptr, the fan codes, col_idx; every row of these meshes has a fan
+    code, so inc_ptr and inc_pos are not read), the unique inputs and the
+    outputs (each once); the packed (x, y, w, 0) copy for Mw is written and
+    read."""
+    idx = 4 * (nq + 1) + 8 * nq + 4 * nnz
     q, vals = 16 * nq, 8 * nnz
     return {
         "assemble": idx + q + 8 * nq + 2 * 32 * nq + 7 * vals,
@@ -416,6 +430,10 @@ def run_main(torch, fem, args):
     # the stiffness + mass pair alone (not part of the step), warm and with the
     # 256 MB last-level cache flushed (a 1 GiB write) before every call
     us["stiff_mass"] = time_calls(torch, st.stiff_mass, args.steps)
+    # like-for-like with the CPU baseline's full assembly: pattern (with the
+    # fan codes) and then the stiffness + mass pair
+    us["stiff_mass_full"] = time_calls(torch, lambda: (st.pattern(), st.stiff_mass()),
+                                       max(args.steps // 2, 3))
     st.assemble()
     us["assemble_rows"] = time_calls(torch, st.assemble_rows, args.steps)
     flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")
@@ -457,6 +475,61 @@ def run_main(torch, fem, args):
     log(f"[bench] step {ms_per_step:.3f} ms; " +
         ", ".join(f"{p} {kern[p]['us']:.0f}us" for p in kern))
     return m, st, ms_per_step, kern
+
+
+def run_gather_floor(torch, fem, st, reps):
+    """The random accesses of the row-owner kernels alone (fem_gather_probe):
+    the column stream of the step's pattern gathering the 16-byte records of
+    q with no arithmetic, in the relabelled order (random lines) and in
+    stream order (the same loads with perfect locality)."""
+    lib = st.lib
+    sink = torch.empty(int(lib.fem_gather_probe_threads()), dtype=torch.float64, device="cuda:0")
+    s = torch.cuda.current_stream().cuda_stream
+
+    def probe(mode):
+        fem._lib.check(lib.fem_gather_probe(st.nnz, st.nq, st.col_idx.data_ptr(), st.q.data_ptr(),
+                                            mode, sink.data_ptr(), s))
+
+    t_rand = time_calls(torch, lambda: probe(0), reps)
+    t_seq = time_calls(torch, lambda: probe(1), reps)
+    out = {"gathers": st.nnz, "record_bytes": 16,
+           "random_us": round(t_rand, 1), "stream_order_us": round(t_seq, 1),
+           "random_Ggathers_per_s": round(st.nnz / t_rand / 1e3, 1),
+           "note": "col_idx read in order, q[col_idx[e]] gathered (random on the relabelled mesh) "
+                   "or q[e mod nq] (stream order); the fan kernels gather the nnz - nq off-diagonal "
+                   "records per call"}
+    log(f"[bench] gather probe: {st.nnz} random gathers {t_rand:.0f}us, in stream order {t_seq:.0f}us")
+    return out
+
+
+def run_local(torch, fem, args):
+    """The same kernels on the 2048 x 2048 square without the vertex
+    relabelling (vertices numbered row by row, as a mesh generator emits
+    them): the gathers of q are then local, and the kernels' own streams
+    bound them."""
+    from paper_1305_3122_amd import meshgen as mg
+    lib = fem._lib.load()
+    m = mg.unit_square(2048, seed=mg.BASE_SEED + 2, permute=False)
+    w = mg.weight_quadratic(m.q)
+    st = Step(fem, lib, torch, m, w, 1.0, 0.5)
+    st.assemble()
+    t_sm = time_calls(torch, st.stiff_mass, args.steps)
+    t_rows = time_calls(torch, st.assemble_rows, args.steps)
+    t_pat = time_calls(torch, st.pattern, max(args.steps // 4, 3))
+    ab = algorithmic_bytes(m.nq, m.nme, st.nnz)
+    out = {"workload": "unit square 2048x2048 cells, jitter 0.2h, vertices numbered row by row "
+                       "(no relabelling); same kernels and calls as the step",
+           "nnz": st.nnz}
+    for key, t in (("stiff_mass", t_sm), ("assemble_rows", t_rows)):
+        gbs = ab[key] / (t * 1e-6) / 1e9
+        out[key] = {"kernel": CALL_KERNEL[key], "us": round(t, 1), "alg_bytes": ab[key],
+                    "achieved_GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out["pattern_us"] = round(t_pat, 1)
+    log(f"[bench] unrelabelled square: M+S {t_sm:.0f}us ({out['stiff_mass']['frac']:.3f}), "
+        f"four operators {t_rows:.0f}us ({out['assemble_rows']['frac']:.3f}), pattern {t_pat:.0f}us")
+    del st
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_batched(torch, fem, args):
@@ -602,7 +675,8 @@ def run_adjoint(torch, fem, args):
 
     def bwd():
         fem._lib.check(lib.fem_adjoint_stiff_wmass(
-            m.nq, pat.nme, pat.nnz, q.data_ptr(), wd.data_ptr(), *P, pat.tpos.data_ptr(),
+            m.nq, pat.nme, pat.nnz, q.data_ptr(), wd.data_ptr(), *P, pat.fan.data_ptr(),
+            pat.tpos.data_ptr(),
             G.data_ptr(), G.data_ptr(), dq.data_ptr(), dw.data_ptr(), awork.data_ptr(),
             awork.numel(), fem._lib.FEM_PACKED_QW, s))
 
@@ -644,7 +718,8 @@ def run_adjoint(torch, fem, args):
 
     def ebwd():
         fem._lib.check(lib.fem_adjoint_elas(
-            m.nq, pat.nme, pat.nnz, q.data_ptr(), *P, pat.tpos.data_ptr(), lam, mu, GK.data_ptr(),
+            m.nq, pat.nme, pat.nnz, q.data_ptr(), *P, pat.fan.data_ptr(), pat.tpos.data_ptr(), lam,
+            mu, GK.data_ptr(),
             dq.data_ptr(), dlm.data_ptr(), ework.data_ptr(), ework.numel(), 0, s))
 
     ef = t(efwd)
@@ -887,27 +962,53 @@ def run_p2(torch, fem, args):
     return out
 
 
-def run_cpu_baseline(args):
-    """The oracle, as it stands, on a bounded sample: the same recipe at
-    1448 x 1448 cells (half of the workload), one full step."""
+def run_cpu_baseline(args, m):
+    """The oracle, as it stands, on the step's mesh (the 2048 x 2048 square):
+    (i) the full assembly of stiffness + mass, the paper's OptV2 scope
+    (pattern from the triangles, then both value arrays), single-threaded,
+    median of 3; (ii) the oracle's numeric phase alone given that pattern,
+    median of 5; (iii) the numeric phase on every host core (OpenMP over the
+    rows, a separate C file beside the oracle), median of 5."""
     import oracle
-    from paper_1305_3122_amd import meshgen as mg
-    n = args.cpu_cells
-    m = mg.unit_square(n, seed=mg.BASE_SEED + 2)
-    w = mg.weight_quadratic(m.q)
-    t0 = time.perf_counter()
+    from oracle import cpu_baseline as cb
+
+    def full():
+        P = oracle.pattern(m.nq, m.me)
+        oracle.assemble("stiff", m.q, m.me, P.slot, P.nnz)
+        oracle.assemble("mass", m.q, m.me, P.slot, P.nnz)
+        return P
+
+    def timed(fn, reps):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), ts
+
+    t_full, ts_full = timed(full, args.cpu_reps_full)
     P = oracle.pattern(m.nq, m.me)
-    oracle.assemble("stiff", m.q, m.me, P.slot, P.nnz)
-    oracle.assemble("mass", m.q, m.me, P.slot, P.nnz)
-    oracle.assemble("wmass", m.q, m.me, P.slot, P.nnz, w=w)
-    rpe, cie, se = oracle.pattern_elas(m.nq, m.me)
-    oracle.assemble("elas", m.q, m.me, se, int(rpe[-1]), lam=1.0, mu=0.5)
-    dt = time.perf_counter() - t0
-    log(f"[bench] cpu oracle {n}x{n}: {dt:.2f}s")
-    return {"value": round(m.nme / dt / 1e6, 4), "unit": "Mtri/s", "cores": 1, "kind": "oracle",
-            "sample": f"same recipe at {n}x{n} cells ({m.nme} triangles), one full step "
-                      f"(pattern, S, M, Mw, elasticity pattern and values), {dt:.2f} s wall, "
-                      f"single-threaded C (-O2 -ffp-contract=off)"}
+    t_num, _ = timed(lambda: (oracle.assemble("stiff", m.q, m.me, P.slot, P.nnz),
+                              oracle.assemble("mass", m.q, m.me, P.slot, P.nnz)), 5)
+    S = np.empty(P.nnz)
+    M = np.empty(P.nnz)
+    cb.stiff_mass_rows(m.q, m.me, P, S, M)
+    t_omp, _ = timed(lambda: cb.stiff_mass_rows(m.q, m.me, P, S, M), 5)
+    cores = cb.threads()
+    log(f"[bench] cpu oracle square2048: full S+M {t_full:.2f}s, numeric {t_num:.2f}s, "
+        f"numeric on {cores} threads {t_omp:.3f}s")
+    return {"value": round(m.nme / t_full / 1e6, 4), "unit": "Mtri/s", "cores": 1, "kind": "oracle",
+            "sample": f"the step's mesh (2048x2048 cells, {m.nme} triangles): stiffness + mass "
+                      f"assembled from the triangles (pattern, then both value arrays; the OptV2 "
+                      f"scope) by the single-threaded C oracle (-O2 -ffp-contract=off), median of "
+                      f"{len(ts_full)} runs ({', '.join(f'{t:.2f}' for t in ts_full)} s)",
+            "numeric_only": {"value": round(m.nme / t_num / 1e6, 4), "unit": "Mtri/s", "cores": 1,
+                             "seconds": round(t_num, 3),
+                             "sample": "the oracle's S + M values given its pattern, median of 5"},
+            "all_cores": {"value": round(m.nme / t_omp / 1e6, 4), "unit": "Mtri/s", "cores": cores,
+                          "cpu_count": os.cpu_count(), "seconds": round(t_omp, 4),
+                          "sample": "S + M values given the oracle's pattern, OpenMP over the rows "
+                                    "(oracle/cpu_rows_omp.c, not the oracle), median of 5"}}
 
 
 def main():
@@ -917,7 +1018,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--cpu-cells", type=int, default=1448)
+    ap.add_argument("--cpu-reps-full", type=int, default=3)
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for counter scaling)")
     ap.add_argument("--summarize", nargs=3, metavar=("KT", "PF", "PW"),
@@ -954,8 +1055,9 @@ def main():
         print(json.dumps({args.only: fn(torch, fem, args)}), flush=True)
         return
     m, st, ms, kern = run_main(torch, fem, args)
-    extras = {}
+    extras = {"gather_floor": run_gather_floor(torch, fem, st, args.steps)}
     if not args.no_extras:
+        extras["roofline_local"] = run_local(torch, fem, args)
         extras["batched"] = run_batched(torch, fem, args)
         extras["adjoint"] = run_adjoint(torch, fem, args)
         extras["sparse"] = run_sparse(torch, fem, args)
@@ -975,6 +1077,9 @@ def main():
             r["traffic_fetch"] = int(round(fb))
             r["traffic_write"] = int(round(wb))
             r["traffic_GBps"] = round((fb + wb) / (k["us"] * 1e-6) / 1e9, 1)
+            r["traffic_kind"] = ("L2 fetch + write bytes (FETCH_SIZE, WRITE_SIZE, copy-calibrated); "
+                                 "the fetches of random gathers are mostly served by the MALL, "
+                                 "so this is L2-miss line traffic, not HBM traffic")
         return r
 
     line = {
@@ -1001,7 +1106,7 @@ def main():
     }
     line.update(extras)
     if not args.no_cpu:
-        line["cpu_baseline"] = run_cpu_baseline(args)
+        line["cpu_baseline"] = run_cpu_baseline(args, m)
     print(json.dumps(line), flush=True)
 
 

@@ -253,6 +253,16 @@ int fem_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q,
                  double *vals_K, void *work, size_t work_bytes, const struct fem_tune *tune,
                  int flags, void *stream);
 
+/* Measurement aid (not part of the assembly): the random accesses of the
+ * row-owner kernels without their arithmetic.  Reads col_idx[e] and the
+ * 16-byte vertex record q[col_idx[e]] for every e < nnz (mode 0), or q[e mod
+ * nq] in stream order (mode 1); writes one partial sum per thread to sink
+ * [fem_gather_probe_threads()].  The time of mode 0 is the floor that
+ * random gathers set on a relabelled mesh. */
+int fem_gather_probe_threads(void);
+int fem_gather_probe(int64_t nnz, int32_t nq, const int32_t *col_idx, const double *q, int mode,
+                     double *sink, void *stream);
+
 /* fem_assemble for callers that cannot allocate device memory (code being
  * captured into a HIP graph, tight serving loops, harnesses that forbid
  * allocation): the same arguments and results without the workspace.  The
@@ -493,14 +503,16 @@ int fem_adjoint_workspace(int32_t nq, int64_t nnz, size_t *bytes /* HOST */);
  * stored at the transposed places, which it must name), or NULL (then
  * found by search).  Patterns of fem_pattern are symmetric, so their map
  * has no -1; an entry whose map is -1 (no transposed entry) has no place
- * and its partial derivative is dropped, never stored out of bounds.  flags: FEM_ACCUMULATE,
+ * and its partial derivative is dropped, never stored out of bounds.  fan:
+ * the codes of fem_fan_plan for this pattern, or NULL (the order of
+ * additions follows them as in the forward calls).  flags: FEM_ACCUMULATE,
  * FEM_PACKED_QW.  Deterministic: two passes over the rows, no atomics; the
  * result does not depend on tpos, FEM_PACKED_QW or the launch shape. */
 int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                             const double *w, const int32_t *row_ptr, const int32_t *col_idx,
-                            const int32_t *inc_ptr, const uint32_t *inc_pos, const int32_t *tpos,
-                            const double *GS, const double *GM, double *dq, double *dw,
-                            void *work, size_t work_bytes, int flags, void *stream);
+                            const int32_t *inc_ptr, const uint32_t *inc_pos, const uint64_t *fan,
+                            const int32_t *tpos, const double *GS, const double *GM, double *dq,
+                            double *dw, void *work, size_t work_bytes, int flags, void *stream);
 
 /* HOST ONLY.  Bytes of device workspace for fem_adjoint_elas: per-row
  * partial sums (at most 16 nq) and per-entry partial derivatives (16 nnz). */
@@ -511,15 +523,15 @@ int fem_adjoint_elas_workspace(int32_t nq, int64_t nnz, size_t *bytes /* HOST */
  * in its interleaved 2x2-block layout).
  *   dq [nq][2] (overwritten, or added to with FEM_ACCUMULATE)
  *   dlm [2] device or NULL: (dL/dlambda, dL/dmu), likewise
- * Pattern arrays as for fem_assemble (FEM_DETERMINISTIC); tpos: the map that
- * fem_transpose_map wrote for this pattern, or NULL (search), as for
- * fem_adjoint_stiff_wmass.  Two passes over the rows plus a
- * fixed-order reduction; no atomics, bitwise reproducible. */
+ * Pattern arrays (and fan codes, or NULL) as for fem_assemble
+ * (FEM_DETERMINISTIC); tpos: the map that fem_transpose_map wrote for this
+ * pattern, or NULL (search), as for fem_adjoint_stiff_wmass.  Two passes over
+ * the rows plus a fixed-order reduction; no atomics, bitwise reproducible. */
 int fem_adjoint_elas(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                      const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
-                     const uint32_t *inc_pos, const int32_t *tpos, double lambda, double mu,
-                     const double *G, double *dq, double *dlm, void *work, size_t work_bytes,
-                     int flags, void *stream);
+                     const uint32_t *inc_pos, const uint64_t *fan, const int32_t *tpos,
+                     double lambda, double mu, const double *G, double *dq, double *dlm, void *work,
+                     size_t work_bytes, int flags, void *stream);
 
 #ifdef __cplusplus
 }

@@ -34,11 +34,13 @@ class OracleError(RuntimeError):
 
 
 def build() -> str:
-    """Compile liboracle.so (always)."""
+    """Compile liboracle.so (always), and the CPU-baseline library beside it."""
     tmp = LIB + ".tmp"
     subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-Wall", "-fPIC",
                     "-shared", "-o", tmp, SRC, "-lm"], check=True)
     os.replace(tmp, LIB)
+    from . import cpu_baseline
+    cpu_baseline.build()
     return LIB
 
 

@@ -586,7 +586,8 @@ def fem_adjoint_stiff_wmass(pat: Pattern, q, w, GS, GM, *, dq=None, dw=None, fla
         flags |= _lib.FEM_PACKED_QW
     _lib.check(lib.fem_adjoint_stiff_wmass(pat.nq, pat.nme, pat.nnz, _ptr(q), _ptr(w),
                                            _ptr(pat.row_ptr), _ptr(pat.col_idx), _ptr(pat.inc_ptr),
-                                           _ptr(pat.inc_pos), _ptr(pat.tpos), _ptr(GS), _ptr(GM),
+                                           _ptr(pat.inc_pos), _ptr(pat.fan), _ptr(pat.tpos),
+                                           _ptr(GS), _ptr(GM),
                                            _ptr(dq), _ptr(dw), _ptr(work),
                                            work.numel() * work.element_size(), flags,
                                            _stream(stream)))
@@ -609,7 +610,8 @@ def fem_adjoint_elas(pat: Pattern, q, lam: float, mu: float, G, *, dq=None, dlm=
     work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
     _lib.check(lib.fem_adjoint_elas(pat.nq, pat.nme, pat.nnz, _ptr(q), _ptr(pat.row_ptr),
                                     _ptr(pat.col_idx), _ptr(pat.inc_ptr), _ptr(pat.inc_pos),
-                                    _ptr(pat.tpos), float(lam), float(mu), _ptr(G), _ptr(dq),
+                                    _ptr(pat.fan), _ptr(pat.tpos), float(lam), float(mu), _ptr(G),
+                                    _ptr(dq),
                                     _ptr(dlm), _ptr(work), int(ws.value), flags, _stream(stream)))
     return dq, dlm
 

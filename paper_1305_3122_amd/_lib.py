@@ -73,6 +73,8 @@ SIGNATURES = {
     "fem_assemble_noalloc": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                     _vp, _dbl, _dbl, _vp, _vp, _vp, _vp, C.POINTER(fem_tune), _int,
                                     _vp]),
+    "fem_gather_probe_threads": (_int, []),
+    "fem_gather_probe": (_int, [_i64, _i32, _vp, _vp, _int, _vp, _vp]),
     "fem_assemble_mass": (_int, _NUM_HEAD + _PAT + [_vp, _int, _vp]),
     "fem_assemble_wmass": (_int, _NUM_HEAD + _PAT + [_vp, _vp, _int, _vp]),
     "fem_assemble_stiff": (_int, _NUM_HEAD + _PAT + [_vp, _int, _vp]),
@@ -105,11 +107,11 @@ SIGNATURES = {
     "fem_p2_assemble": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                C.c_size_t, _int, _vp]),
     "fem_adjoint_elas_workspace": (_int, [_i32, _i64, _szp]),
-    "fem_adjoint_elas": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _vp, _vp,
-                                _vp, _vp, C.c_size_t, _int, _vp]),
+    "fem_adjoint_elas": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _vp,
+                                _vp, _vp, _vp, C.c_size_t, _int, _vp]),
     "fem_adjoint_workspace": (_int, [_i32, _i64, _szp]),
     "fem_adjoint_stiff_wmass": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                       _vp, _vp, _vp, _vp, C.c_size_t, _int, _vp]),
+                                       _vp, _vp, _vp, _vp, _vp, C.c_size_t, _int, _vp]),
 }
 
 _lib = None

@@ -13,7 +13,11 @@
 // tpos, pass 1 stores H[i, j] at the place of entry (j, i), so pass 2 reads
 // row u in place; without it, pass 1 stores H in row order and pass 2 finds
 // each transposed entry by search.  Either way the same values are added in
-// the same order.  No atomics; every sum has a fixed order, so the result is
+// the same order.  With the fan codes of fem_fan_plan, pass 1 walks a row's
+// triangles in the order met around i, as the forward kernels do: each
+// H[i, j] is then the sum of the two steps that share the edge (i, j), the
+// diagonal part sums in walk order, and no slot of the row is searched per
+// triangle.  No atomics; every sum has a fixed order, so the result is
 // bitwise reproducible.
 //
 // Derivatives for the triangle (x0, x1, x2) (cyclic rotation starting at i),
@@ -268,6 +272,180 @@ __global__ __launch_bounds__(WAVE) void k_adj_rows(int32_t nq, const double4 *__
                 const double4 x1 = qw[cr[p1]], x2 = qw[cr[p2]];
                 AdjGrad o;
                 adj_tau<HS, HM>(xi.x, xi.y, x1.x, x1.y, x2.x, x2.y, xi.z, x1.z, x2.z, g0,
+                                HS ? GS[rs + p1] : 0.0, HS ? GS[rs + p2] : 0.0, h0,
+                                HM ? GM[rs + p1] : 0.0, HM ? GM[rs + p2] : 0.0, o);
+                ox += o.gx[0];
+                oy += o.gy[0];
+                ow += o.gw[0];
+                hadd(p1, o.gx[1], o.gy[1], o.gw[1]);
+                hadd(p2, o.gx[2], o.gy[2], o.gw[2]);
+            }
+            hadd(pd, ox, oy, ow);
+        }
+    }
+}
+
+// Pass 1 over fan codes: tile of 64 rows, one per lane.  LDS: the tile's GS
+// and GM values (read coalesced) and the H records (x, y, w) of the tile;
+// each lane gathers its neighbours' (x, y, w) records in walk order into
+// registers, walks the fan, and writes every H value into LDS as soon as it
+// is complete (slot s_j after step j, s_0 and the last slot at the end);
+// then H is stored as in k_adj_rows.  Rows without a fan code, with more
+// than N neighbours or in a tile too large for LDS take the per-lane
+// global-memory path of k_adj_rows (ascending triangles).
+template <bool HS, bool HM, int U, int N>
+__global__ __launch_bounds__(WAVE) void k_adj_rows_fan(int32_t nq, const double4 *__restrict__ qw,
+                                                       const int32_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col_idx,
+                                                       const int32_t *__restrict__ inc_ptr,
+                                                       const uint32_t *__restrict__ inc_pos,
+                                                       const uint64_t *__restrict__ fan,
+                                                       const int32_t *__restrict__ tpos,
+                                                       const double *__restrict__ GS,
+                                                       const double *__restrict__ GM,
+                                                       double4 *__restrict__ H, int64_t ntiles) {
+    constexpr int EB = U * WAVE;
+    extern __shared__ double smem[];
+    double *s_gs = smem;            // [EB]
+    double *s_gm = smem + EB;       // [EB]
+    double *s_h = smem + 2 * EB;    // [3 EB]: (x, y, w) per entry
+    const int lane = threadIdx.x;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * WAVE;
+        const int64_t r1 = (r0 + WAVE < nq) ? r0 + WAVE : nq;
+        const int64_t i = r0 + lane;
+        const bool active = i < nq;
+        const int32_t E0 = row_ptr[r0], E1 = row_ptr[r1], Ew = E1 - E0;
+        const int32_t rs = active ? row_ptr[i] : 0;
+        const int32_t len = active ? row_ptr[i + 1] - rs : 0;
+        const uint64_t code = active ? fan[i] : 0;
+        const int n = fan_n(code);
+        const bool closed = fan_closed(code);
+        const bool tile_fits = Ew <= EB;
+        const bool in_regs = tile_fits && active && n >= 2 && n <= N && len == n + 1;
+        const bool zero_row = !in_regs && active && len > 0;
+        const int32_t off = rs - E0;
+        if (tile_fits) {
+            double gsv[U], gmv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                gsv[u] = (HS && e < Ew) ? __builtin_nontemporal_load(GS + E0 + e) : 0.0;
+                gmv[u] = (HM && e < Ew) ? __builtin_nontemporal_load(GM + E0 + e) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                if (e < Ew) {
+                    if constexpr (HS) s_gs[e] = gsv[u];
+                    if constexpr (HM) s_gm[e] = gmv[u];
+                }
+            }
+        }
+        // the neighbours' records in walk order, the row's own one
+        int32_t cj[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) cj[j] = (in_regs && j < n) ? col_idx[rs + fan_slot(code, j)] : -1;
+        double4 x[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) x[j] = cj[j] >= 0 ? qw[cj[j]] : make_double4(0.0, 0.0, 0.0, 0.0);
+        const double4 xi = in_regs ? qw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+        if (tile_fits) __syncthreads();   // G staged
+        if (in_regs) {
+            const int32_t pd = fan_pd(code);
+            const double g0 = HS ? s_gs[off + pd] : 0.0, h0 = HM ? s_gm[off + pd] : 0.0;
+            auto put = [&](int sl, double hx, double hy, double hw) {
+                double *p = s_h + 3 * (off + sl);
+                p[0] = hx;
+                p[1] = hy;
+                p[2] = hw;
+            };
+            double ox = 0.0, oy = 0.0, ow = 0.0;
+            double cx = 0.0, cy = 0.0, cw = 0.0, fx = 0.0, fy = 0.0, fw = 0.0;
+            const int d = closed ? n : n - 1;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                if (j < d) {
+                    const bool wrap = j + 1 >= n;
+                    const int jn = j + 1 < N ? j + 1 : 0;
+                    const int32_t a = off + fan_slot(code, j);
+                    const int32_t b = off + (wrap ? fan_slot(code, 0) : fan_slot(code, jn));
+                    const double4 x2 = wrap ? x[0] : x[jn];
+                    AdjGrad o;
+                    adj_tau<HS, HM>(xi.x, xi.y, x[j].x, x[j].y, x2.x, x2.y, xi.z, x[j].z, x2.z, g0,
+                                    HS ? s_gs[a] : 0.0, HS ? s_gs[b] : 0.0, h0,
+                                    HM ? s_gm[a] : 0.0, HM ? s_gm[b] : 0.0, o);
+                    ox += o.gx[0];
+                    oy += o.gy[0];
+                    ow += o.gw[0];
+                    if (j == 0) {
+                        fx = o.gx[1];
+                        fy = o.gy[1];
+                        fw = o.gw[1];
+                        if (!closed) put(fan_slot(code, 0), fx, fy, fw);
+                    } else {
+                        put(fan_slot(code, j), cx + o.gx[1], cy + o.gy[1], cw + o.gw[1]);
+                    }
+                    cx = o.gx[2];
+                    cy = o.gy[2];
+                    cw = o.gw[2];
+                }
+            }
+            if (closed) put(fan_slot(code, 0), fx + cx, fy + cy, fw + cw);
+            else put(fan_slot(code, n - 1), cx, cy, cw);
+            put(pd, ox, oy, ow);
+        } else if (tile_fits && zero_row) {
+            for (int k = 0; k < 3 * len; ++k) s_h[3 * off + k] = 0.0;
+        }
+        if (tile_fits) {
+            __syncthreads();
+            // with tpos, each value goes to the place of its transposed entry
+            int32_t dst[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                dst[u] = e < Ew ? (tpos ? tpos[E0 + e] : E0 + e) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                if (e < Ew && dst[u] >= 0)   // tpos -1: no transposed entry, no place
+                    H[dst[u]] = make_double4(s_h[3 * e], s_h[3 * e + 1], s_h[3 * e + 2], 0.0);
+            }
+            __syncthreads();
+        }
+        if (zero_row) {
+            // ascending triangles from global memory, as in k_adj_rows (each
+            // entry at its own place, transposed with tpos; tpos -1 skipped)
+            auto hat = [&](int32_t e) -> int32_t { return tpos ? tpos[rs + e] : rs + e; };
+            auto hadd = [&](int32_t e, double gx, double gy, double gw) {
+                const int32_t dd = hat(e);
+                if (dd < 0) return;
+                double4 h = H[dd];
+                h.x += gx;
+                h.y += gy;
+                h.z += gw;
+                H[dd] = h;
+            };
+            if (!tile_fits) {
+                for (int e = 0; e < len; ++e) {
+                    const int32_t dd = hat(e);
+                    if (dd >= 0) H[dd] = make_double4(0.0, 0.0, 0.0, 0.0);
+                }
+            }
+            const int32_t is = inc_ptr[i], ie = inc_ptr[i + 1];
+            const int32_t *cr = col_idx + rs;
+            int32_t pd = 0;
+            while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
+            const double4 x0 = qw[i];
+            const double g0 = HS ? GS[rs + pd] : 0.0, h0 = HM ? GM[rs + pd] : 0.0;
+            double ox = 0.0, oy = 0.0, ow = 0.0;
+            for (int32_t t = is; t < ie; ++t) {
+                const uint32_t pp = inc_pos[t];
+                const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
+                const double4 x1 = qw[cr[p1]], x2 = qw[cr[p2]];
+                AdjGrad o;
+                adj_tau<HS, HM>(x0.x, x0.y, x1.x, x1.y, x2.x, x2.y, x0.z, x1.z, x2.z, g0,
                                 HS ? GS[rs + p1] : 0.0, HS ? GS[rs + p2] : 0.0, h0,
                                 HM ? GM[rs + p1] : 0.0, HM ? GM[rs + p2] : 0.0, o);
                 ox += o.gx[0];
@@ -701,6 +879,200 @@ __global__ __launch_bounds__(WAVE) void k_adj_elas_rows(
     }
 }
 
+// Pass 1 of the elasticity adjoint over fan codes (as k_adj_rows_fan): LDS
+// holds the tile's 4 Ew values of G and its H records (x, y); each lane
+// gathers its neighbours' coordinates in walk order and writes every H value
+// into LDS once complete.  The tile's dtau/dlambda, dtau/dmu sums go to
+// lm[tile] (walk order inside a row).  Other rows: the per-lane global-memory
+// path of k_adj_elas_rows.
+template <int U, int N>
+__global__ __launch_bounds__(WAVE) void k_adj_elas_rows_fan(
+    int32_t nq, const double *__restrict__ q, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ col_idx, const int32_t *__restrict__ inc_ptr,
+    const uint32_t *__restrict__ inc_pos, const uint64_t *__restrict__ fan,
+    const int32_t *__restrict__ tpos, const double *__restrict__ G, double lam, double mu,
+    double2 *__restrict__ H, double2 *__restrict__ lm, int64_t ntiles) {
+    constexpr int EB = U * WAVE;
+    extern __shared__ double smem[];
+    double *s_g = smem;             // [4 EB]: the tile's G in the elasticity layout
+    double *s_h = smem + 4 * EB;    // [2 EB]: (x, y) per entry
+    const int lane = threadIdx.x;
+    const double2 *q2 = reinterpret_cast<const double2 *>(q);
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * WAVE;
+        const int64_t r1 = (r0 + WAVE < nq) ? r0 + WAVE : nq;
+        const int64_t i = r0 + lane;
+        const bool active = i < nq;
+        const int32_t E0 = row_ptr[r0], E1 = row_ptr[r1], Ew = E1 - E0;
+        const int32_t rs = active ? row_ptr[i] : 0;
+        const int32_t len = active ? row_ptr[i + 1] - rs : 0;
+        const uint64_t code = active ? fan[i] : 0;
+        const int n = fan_n(code);
+        const bool closed = fan_closed(code);
+        const bool tile_fits = Ew <= EB;
+        const bool in_regs = tile_fits && active && n >= 2 && n <= N && len == n + 1;
+        const bool zero_row = !in_regs && active && len > 0;
+        const int32_t off = rs - E0;
+        if (tile_fits) {
+            // the tile's 4 Ew values of G, eight loads in flight per lane
+            const double *gt = G + 4 * (int64_t)E0;
+            for (int e0 = 0; e0 < 4 * Ew; e0 += 8 * WAVE) {
+                double gv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + lane + u * WAVE;
+                    gv[u] = e < 4 * Ew ? __builtin_nontemporal_load(gt + e) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + lane + u * WAVE;
+                    if (e < 4 * Ew) s_g[e] = gv[u];
+                }
+            }
+        }
+        int32_t cj[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) cj[j] = (in_regs && j < n) ? col_idx[rs + fan_slot(code, j)] : -1;
+        double2 xn[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) xn[j] = cj[j] >= 0 ? q2[cj[j]] : make_double2(0.0, 0.0);
+        const double2 xi = in_regs ? q2[i] : make_double2(0.0, 0.0);
+        if (tile_fits) __syncthreads();   // G staged
+        double sl = 0.0, sm = 0.0;
+        if (in_regs) {
+            const int32_t pd = fan_pd(code);
+            const double *gr = s_g + 4 * off;   // row 2i at gr[2k + beta], row 2i+1 at gr[2len + 2k + beta]
+            auto gblock = [&](int sl_, double (&g)[4]) {
+                g[0] = gr[2 * sl_];
+                g[1] = gr[2 * sl_ + 1];
+                g[2] = gr[2 * len + 2 * sl_];
+                g[3] = gr[2 * len + 2 * sl_ + 1];
+            };
+            auto put = [&](int sl_, double hx, double hy) {
+                s_h[2 * (off + sl_)] = hx;
+                s_h[2 * (off + sl_) + 1] = hy;
+            };
+            double x[3][2], g[3][4];
+            x[0][0] = xi.x;
+            x[0][1] = xi.y;
+            gblock(pd, g[0]);
+            double ox = 0.0, oy = 0.0, cx = 0.0, cy = 0.0, fx = 0.0, fy = 0.0;
+            const int d = closed ? n : n - 1;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                if (j < d) {
+                    const bool wrap = j + 1 >= n;
+                    const int jn = j + 1 < N ? j + 1 : 0;
+                    const double2 x2 = wrap ? xn[0] : xn[jn];
+                    x[1][0] = xn[j].x;
+                    x[1][1] = xn[j].y;
+                    x[2][0] = x2.x;
+                    x[2][1] = x2.y;
+                    gblock(fan_slot(code, j), g[1]);
+                    gblock(wrap ? fan_slot(code, 0) : fan_slot(code, jn), g[2]);
+                    ElasTau o;
+                    elas_tau(x, g, lam, mu, o);
+                    ox += o.d[0][0];
+                    oy += o.d[0][1];
+                    sl += o.nl;
+                    sm += o.nm;
+                    if (j == 0) {
+                        fx = o.d[1][0];
+                        fy = o.d[1][1];
+                        if (!closed) put(fan_slot(code, 0), fx, fy);
+                    } else {
+                        put(fan_slot(code, j), cx + o.d[1][0], cy + o.d[1][1]);
+                    }
+                    cx = o.d[2][0];
+                    cy = o.d[2][1];
+                }
+            }
+            if (closed) put(fan_slot(code, 0), fx + cx, fy + cy);
+            else put(fan_slot(code, n - 1), cx, cy);
+            put(pd, ox, oy);
+        } else if (tile_fits && zero_row) {
+            for (int k = 0; k < 2 * len; ++k) s_h[2 * off + k] = 0.0;
+        }
+        if (tile_fits) {
+            __syncthreads();
+            // with tpos, each value goes to the place of its transposed entry
+            int32_t dst[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                dst[u] = e < Ew ? (tpos ? tpos[E0 + e] : E0 + e) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + u * WAVE;
+                if (e < Ew && dst[u] >= 0)   // tpos -1: no transposed entry, no place
+                    H[dst[u]] = make_double2(s_h[2 * e], s_h[2 * e + 1]);
+            }
+            __syncthreads();
+        }
+        if (zero_row) {
+            // ascending triangles from global memory, as in k_adj_elas_rows
+            auto hat = [&](int32_t e) -> int32_t { return tpos ? tpos[rs + e] : rs + e; };
+            auto hadd = [&](int32_t e, double gx, double gy) {
+                const int32_t dd = hat(e);
+                if (dd < 0) return;
+                double2 h = H[dd];
+                h.x += gx;
+                h.y += gy;
+                H[dd] = h;
+            };
+            if (!tile_fits) {
+                for (int e = 0; e < len; ++e) {
+                    const int32_t dd = hat(e);
+                    if (dd >= 0) H[dd] = make_double2(0.0, 0.0);
+                }
+            }
+            const int32_t is = inc_ptr[i], ie = inc_ptr[i + 1];
+            const int32_t *cr = col_idx + rs;
+            int32_t pd = 0;
+            while (pd < len - 1 && cr[pd] != (int32_t)i) ++pd;
+            const double *gr = G + 4 * (int64_t)rs;
+            double x[3][2], g[3][4];
+            x[0][0] = q[2 * i];
+            x[0][1] = q[2 * i + 1];
+            g[0][0] = gr[2 * pd];
+            g[0][1] = gr[2 * pd + 1];
+            g[0][2] = gr[2 * len + 2 * pd];
+            g[0][3] = gr[2 * len + 2 * pd + 1];
+            double ox = 0.0, oy = 0.0;
+            for (int32_t t = is; t < ie; ++t) {
+                const uint32_t pp = inc_pos[t];
+                const int32_t p1 = (int32_t)(pp & 0xffffu), p2 = (int32_t)(pp >> 16);
+                const int64_t j1 = cr[p1], j2 = cr[p2];
+                x[1][0] = q[2 * j1];
+                x[1][1] = q[2 * j1 + 1];
+                x[2][0] = q[2 * j2];
+                x[2][1] = q[2 * j2 + 1];
+                g[1][0] = gr[2 * p1];
+                g[1][1] = gr[2 * p1 + 1];
+                g[1][2] = gr[2 * len + 2 * p1];
+                g[1][3] = gr[2 * len + 2 * p1 + 1];
+                g[2][0] = gr[2 * p2];
+                g[2][1] = gr[2 * p2 + 1];
+                g[2][2] = gr[2 * len + 2 * p2];
+                g[2][3] = gr[2 * len + 2 * p2 + 1];
+                ElasTau o;
+                elas_tau(x, g, lam, mu, o);
+                ox += o.d[0][0];
+                oy += o.d[0][1];
+                sl += o.nl;
+                sm += o.nm;
+                hadd(p1, o.d[1][0], o.d[1][1]);
+                hadd(p2, o.d[2][0], o.d[2][1]);
+            }
+            hadd(pd, ox, oy);
+        }
+        // the tile's dtau/dlambda, dtau/dmu sums (a fixed shuffle tree)
+        const double tl = wave_sum(sl), tm = wave_sum(sm);
+        if (lane == 0) lm[tile] = make_double2(tl, tm);
+    }
+}
+
 // Pass 2 of the elasticity adjoint: dq[u] = sum over row u of H at the
 // transposed positions, ascending position.  With tpos, pass 1 has already
 // stored every value at the place of its transposed entry, so row u is read
@@ -815,11 +1187,21 @@ constexpr int ADJ_U = 8;
 
 constexpr int ADJ_LMAX = 8;
 
+constexpr int ADJ_FAN = 8;   // neighbour slots walked in registers by k_adj_rows_fan
+
 template <bool HS, bool HM>
 int launch_adj(int32_t nq, const double4 *qw, const int32_t *row_ptr, const int32_t *col_idx,
-               const int32_t *inc_ptr, const uint32_t *inc_pos, const int32_t *tpos, const double *GS,
-               const double *GM, double4 *H, hipStream_t s) {
+               const int32_t *inc_ptr, const uint32_t *inc_pos, const uint64_t *fan,
+               const int32_t *tpos, const double *GS, const double *GM, double4 *H, hipStream_t s) {
     const int64_t ntiles = (nq + WAVE - 1) / WAVE;
+    if (fan) {
+        const size_t lds = (size_t)ADJ_U * WAVE * 5 * 8;
+        hipLaunchKernelGGL((k_adj_rows_fan<HS, HM, ADJ_U, ADJ_FAN>), dim3((unsigned)ntiles), dim3(WAVE),
+                           lds, s, nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, fan, tpos, GS, GM, H,
+                           ntiles);
+        FEM_LAUNCH_CHECK();
+        return FEM_OK;
+    }
     const size_t lds = (size_t)ADJ_U * WAVE * (5 * 8 + 4);
     hipLaunchKernelGGL((k_adj_rows<HS, HM, ADJ_U, ADJ_LMAX>), dim3((unsigned)ntiles), dim3(WAVE), lds,
                        s, nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, tpos, GS, GM, H, ntiles);
@@ -844,8 +1226,9 @@ extern "C" int fem_adjoint_workspace(int32_t nq, int64_t nnz, size_t *bytes) {
 extern "C" int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                                        const double *w, const int32_t *row_ptr,
                                        const int32_t *col_idx, const int32_t *inc_ptr,
-                                       const uint32_t *inc_pos, const int32_t *tpos,
-                                       const double *GS, const double *GM, double *dq, double *dw,
+                                       const uint32_t *inc_pos, const uint64_t *fan,
+                                       const int32_t *tpos, const double *GS, const double *GM,
+                                       double *dq, double *dw,
                                        void *work, size_t work_bytes, int flags, void *stream) {
     clear_error();
     FEM_REQUIRE(nq >= 1 && nme >= 0 && nnz >= 0 && nnz <= INT32_MAX, FEM_EINVAL,
@@ -870,11 +1253,11 @@ extern "C" int fem_adjoint_stiff_wmass(int32_t nq, int32_t nme, int64_t nnz, con
     }
     int st;
     if (GS && GM)
-        st = launch_adj<true, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, tpos, GS, GM, H, s);
+        st = launch_adj<true, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, fan, tpos, GS, GM, H, s);
     else if (GS)
-        st = launch_adj<true, false>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, tpos, GS, GM, H, s);
+        st = launch_adj<true, false>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, fan, tpos, GS, GM, H, s);
     else if (GM)
-        st = launch_adj<false, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, tpos, GS, GM, H, s);
+        st = launch_adj<false, true>(nq, qw, row_ptr, col_idx, inc_ptr, inc_pos, fan, tpos, GS, GM, H, s);
     else st = fill_f64(reinterpret_cast<double *>(H), 4 * nnz, 0.0, s);
     if (st) return st;
     const int acc = (flags & FEM_ACCUMULATE) ? 1 : 0;
@@ -899,9 +1282,10 @@ extern "C" int fem_adjoint_elas_workspace(int32_t nq, int64_t nnz, size_t *bytes
 
 extern "C" int fem_adjoint_elas(int32_t nq, int32_t nme, int64_t nnz, const double *q,
                                 const int32_t *row_ptr, const int32_t *col_idx,
-                                const int32_t *inc_ptr, const uint32_t *inc_pos, const int32_t *tpos,
-                                double lambda, double mu, const double *G, double *dq, double *dlm,
-                                void *work, size_t work_bytes, int flags, void *stream) {
+                                const int32_t *inc_ptr, const uint32_t *inc_pos, const uint64_t *fan,
+                                const int32_t *tpos, double lambda, double mu, const double *G,
+                                double *dq, double *dlm, void *work, size_t work_bytes, int flags,
+                                void *stream) {
     clear_error();
     FEM_REQUIRE(nq >= 1 && nme >= 0 && nnz >= 0 && 4 * nnz <= INT32_MAX, FEM_EINVAL,
                 "fem_adjoint_elas: bad sizes");
@@ -917,9 +1301,16 @@ extern "C" int fem_adjoint_elas(int32_t nq, int32_t nme, int64_t nnz, const doub
     double2 *lm = static_cast<double2 *>(work);
     double2 *H = reinterpret_cast<double2 *>(static_cast<char *>(work) + align256(sizeof(double2) * (size_t)nq));
     const int64_t ntiles = (nq + WAVE - 1) / WAVE;
-    const size_t lds = (size_t)ADJ_U * WAVE * (6 * 8 + 4);
-    hipLaunchKernelGGL((k_adj_elas_rows<ADJ_U, ADJ_LMAX>), dim3((unsigned)ntiles), dim3(WAVE), lds, s, nq,
-                       q, row_ptr, col_idx, inc_ptr, inc_pos, tpos, G, lambda, mu, H, lm, ntiles);
+    if (fan) {
+        const size_t lds = (size_t)ADJ_U * WAVE * 6 * 8;
+        hipLaunchKernelGGL((k_adj_elas_rows_fan<ADJ_U, ADJ_FAN>), dim3((unsigned)ntiles), dim3(WAVE), lds,
+                           s, nq, q, row_ptr, col_idx, inc_ptr, inc_pos, fan, tpos, G, lambda, mu, H,
+                           lm, ntiles);
+    } else {
+        const size_t lds = (size_t)ADJ_U * WAVE * (6 * 8 + 4);
+        hipLaunchKernelGGL((k_adj_elas_rows<ADJ_U, ADJ_LMAX>), dim3((unsigned)ntiles), dim3(WAVE), lds, s,
+                           nq, q, row_ptr, col_idx, inc_ptr, inc_pos, tpos, G, lambda, mu, H, lm, ntiles);
+    }
     FEM_LAUNCH_CHECK();
     const int acc = (flags & FEM_ACCUMULATE) ? 1 : 0;
     hipLaunchKernelGGL(k_adj_elas_cols<ADJ_U>, dim3((unsigned)(ntiles + (dlm ? 1 : 0))), dim3(WAVE), 0, s,

@@ -702,20 +702,32 @@ __global__ __launch_bounds__(WAVE) void k_rows_reg(
 // finished values for coalesced stores.  Rows without a fan code are summed
 // per lane in ascending triangle order (the chunk path of k_rows_reg).
 
-// One walk over the fan: v[m][j] = value of operator m at slot s_j,
-// dg[m] = diagonal value (zeros when `on` is false).
-template <int PM, int N>
-__device__ __forceinline__ void fan_walk(bool on, int n, bool closed, double2 xi, double wi,
-                                         const double2 (&x)[N], const double (&wn)[N], Lame L,
-                                         double (&v)[Ops<PM>::NV][N], double (&dg)[Ops<PM>::NV]) {
+// One walk over the fan of the lane's row, each value written into the LDS
+// transposition buffer as soon as it is complete: slot s_j (j >= 1) after
+// step j (c2 of step j-1 plus c1 of step j), s_0 at the end (closed fans:
+// c1 of step 0 plus c2 of the last step) or after step 0 (open fans, where
+// the last slot gets the last c2 alone), the diagonal at the end.  Scalar
+// operator m of PM goes to buf[m EB + off + slot]; the elasticity block of
+// a slot to buf[4 off + 2 slot + beta] (row 2i) and buf[4 off + 2 len +
+// 2 slot + beta] (row 2i+1).
+template <int PM, int N, int EB>
+__device__ __forceinline__ void fan_walk_lds(uint64_t code, int n, bool closed, double2 xi, double wi,
+                                             const double2 (&x)[N], const double (&wn)[N], Lame L,
+                                             double *buf, int32_t off, int32_t len) {
     using O = Ops<PM>;
+    constexpr int NV = O::NV;
+    auto put_lds = [&](int sl, const double (&val)[NV]) {
 #pragma unroll
-    for (int m = 0; m < O::NV; ++m) {
-        dg[m] = 0.0;
+        for (int m = 0; m < O::NS; ++m) buf[m * EB + off + sl] = val[m];
+        if constexpr (O::K) {
+            *reinterpret_cast<double2 *>(buf + 4 * off + 2 * sl) = make_double2(val[O::NS], val[O::NS + 1]);
+            *reinterpret_cast<double2 *>(buf + 4 * off + 2 * len + 2 * sl) =
+                make_double2(val[O::NS + 2], val[O::NS + 3]);
+        }
+    };
+    double dg[NV], carry[NV], first[NV];
 #pragma unroll
-        for (int j = 0; j < N; ++j) v[m][j] = 0.0;
-    }
-    if (!on) return;
+    for (int m = 0; m < NV; ++m) dg[m] = carry[m] = first[m] = 0.0;
     const int d = closed ? n : n - 1;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -727,24 +739,44 @@ __device__ __forceinline__ void fan_walk(bool on, int n, bool closed, double2 xi
             double c[O::NS > 0 ? O::NS : 1][3];
             double ce[3][4];
             elem_row<PM>(xi.x, xi.y, x[j].x, x[j].y, x2.x, x2.y, wi, wn[j], w2, L, c, ce);
+            double c1[NV], c2[NV];
 #pragma unroll
             for (int m = 0; m < O::NS; ++m) {
                 dg[m] += c[m][0];
-                v[m][j] += c[m][1];
-                if (j + 1 < N && !wrap) v[m][jn] = c[m][2];
-                if (wrap) v[m][0] += c[m][2];
+                c1[m] = c[m][1];
+                c2[m] = c[m][2];
             }
             if constexpr (O::K) {
 #pragma unroll
                 for (int z = 0; z < 4; ++z) {
                     dg[O::NS + z] += ce[0][z];
-                    v[O::NS + z][j] += ce[1][z];
-                    if (j + 1 < N && !wrap) v[O::NS + z][jn] = ce[2][z];
-                    if (wrap) v[O::NS + z][0] += ce[2][z];
+                    c1[O::NS + z] = ce[1][z];
+                    c2[O::NS + z] = ce[2][z];
                 }
             }
+            if (j == 0) {
+#pragma unroll
+                for (int m = 0; m < NV; ++m) first[m] = c1[m];
+                if (!closed) put_lds(fan_slot(code, 0), first);
+            } else {
+                double val[NV];
+#pragma unroll
+                for (int m = 0; m < NV; ++m) val[m] = carry[m] + c1[m];
+                put_lds(fan_slot(code, j), val);
+            }
+#pragma unroll
+            for (int m = 0; m < NV; ++m) carry[m] = c2[m];
         }
     }
+    if (closed) {
+        double val[NV];
+#pragma unroll
+        for (int m = 0; m < NV; ++m) val[m] = first[m] + carry[m];
+        put_lds(fan_slot(code, 0), val);
+    } else {
+        put_lds(fan_slot(code, n - 1), carry);
+    }
+    put_lds(fan_pd(code), dg);
 }
 
 // Stores one value of the lane's own row (fallback paths).
@@ -755,7 +787,7 @@ __device__ __forceinline__ void put(double *o, int64_t e, double v, int accumula
 
 // The fan walk of one row from global memory, every value stored directly
 // (fan rows longer than the register walk, or in a tile too large for LDS).
-// Same steps and order of additions as fan_walk.
+// Same steps and order of additions as fan_walk_lds.
 template <int MASK>
 __device__ void fan_row_global(int64_t i, int32_t rs, int32_t len, uint64_t code,
                                const double2 *__restrict__ q2, const double *__restrict__ w,
@@ -847,8 +879,8 @@ __global__ __launch_bounds__(WAVE) void k_rows_fan(
     constexpr int MS = MASK & (M_BIT | W_BIT | S_BIT);   // scalar operators (phase 1)
     constexpr int NS = O::NS;
     constexpr int EB = U * WAVE;
-    // LDS: the transposition buffer, EB doubles (one scalar operator at a
-    // time), 4 EB with K (the 2 x 2 blocks of the tile).
+    // LDS: the transposition buffer, NS EB doubles for the scalar operators
+    // (all at once) and 4 EB for the 2 x 2 blocks of K.
     extern __shared__ double smem[];
     const int lane = threadIdx.x;
     const double2 *q2 = reinterpret_cast<const double2 *>(q);
@@ -904,58 +936,41 @@ __global__ __launch_bounds__(WAVE) void k_rows_fan(
         const bool zero_row = !in_regs && active && len > 0;
 
         if constexpr (MS != 0) {
-            // ---- phase 1: scalar operators, one transposition each
-            double v[NS][N], dg[NS];
-            fan_walk<MS, N>(in_regs, n, closed, xi, wi, x, wn, L, v, dg);
+            // ---- phase 1: the scalar operators, all transposed at once
             if (tile_fits) {
-                double *s_t = smem;
+                if (in_regs) {
+                    fan_walk_lds<MS, N, EB>(code, n, closed, xi, wi, x, wn, L, smem, off, len);
+                } else if (zero_row) {
+#pragma unroll
+                    for (int m = 0; m < NS; ++m)
+                        for (int k = 0; k < len; ++k) smem[m * EB + off + k] = 0.0;
+                }
+                __syncthreads();
 #pragma unroll
                 for (int m = 0; m < NS; ++m) {
-                    if (in_regs) {
-#pragma unroll
-                        for (int j = 0; j < N; ++j)
-                            if (j < n) s_t[off + fan_slot(code, j)] = v[m][j];
-                        s_t[off + fan_pd(code)] = dg[m];
-                    } else if (zero_row) {
-                        for (int k = 0; k < len; ++k) s_t[off + k] = 0.0;
-                    }
-                    __syncthreads();
                     double *o = out.o[m] + E0;
                     for (int e = lane; e < Ew; e += WAVE) {
-                        const double val = s_t[e];
+                        const double val = smem[m * EB + e];
                         if (accumulate) o[e] += val;
                         else __builtin_nontemporal_store(val, o + e);
                     }
-                    __syncthreads();
                 }
+                __syncthreads();
             }
         }
         if constexpr (O::K) {
             // ---- phase 2: elasticity 2 x 2 blocks.  Row 2i: [4 off + 2 s + beta],
             // row 2i+1: [4 off + 2 len + 2 s + beta]
-            double v[4][N], dg[4];
-            fan_walk<K_BIT, N>(in_regs, n, closed, xi, wi, x, wn, L, v, dg);
             if (tile_fits) {
-                double *s_k = smem;
                 if (in_regs) {
-#pragma unroll
-                    for (int j = 0; j <= N; ++j) {
-                        if (j < n || j == N) {
-                            const int sl = j < N ? fan_slot(code, j) : fan_pd(code);
-                            const double a0 = j < N ? v[0][j] : dg[0], a1 = j < N ? v[1][j] : dg[1];
-                            const double a2 = j < N ? v[2][j] : dg[2], a3 = j < N ? v[3][j] : dg[3];
-                            *reinterpret_cast<double2 *>(s_k + 4 * off + 2 * sl) = make_double2(a0, a1);
-                            *reinterpret_cast<double2 *>(s_k + 4 * off + 2 * len + 2 * sl) =
-                                make_double2(a2, a3);
-                        }
-                    }
+                    fan_walk_lds<K_BIT, N, EB>(code, n, closed, xi, wi, x, wn, L, smem, off, len);
                 } else if (zero_row) {
-                    for (int k = 0; k < 4 * len; ++k) s_k[4 * off + k] = 0.0;
+                    for (int k = 0; k < 4 * len; ++k) smem[4 * off + k] = 0.0;
                 }
                 __syncthreads();
                 double *o = out.o[3] + 4 * (int64_t)E0;
                 for (int e = lane; e < 4 * Ew; e += WAVE) {
-                    const double val = s_k[e];
+                    const double val = smem[e];
                     if (accumulate) o[e] += val;
                     else __builtin_nontemporal_store(val, o + e);
                 }
@@ -1143,7 +1158,8 @@ int launch_fan_u(const Args &a, const double4 *qw, int grid_blocks) {
     const int64_t ntiles = (a.nq + WAVE - 1) / WAVE;
     const int64_t grid = grid_blocks > 0 ? (grid_blocks < ntiles ? grid_blocks : ntiles) : ntiles;
     FEM_REQUIRE(grid <= INT32_MAX, FEM_EOVERFLOW, "too many tiles");
-    const size_t lds = (size_t)U * WAVE * (Ops<MASK>::K ? 32 : 8);
+    constexpr int NS = Ops<MASK>::NS;
+    const size_t lds = (size_t)U * WAVE * 8 * (Ops<MASK>::K ? (NS > 4 ? NS : 4) : NS);
     hipLaunchKernelGGL((k_rows_fan<MASK, U, FAN_REG>), dim3((unsigned)grid), dim3(WAVE), lds, a.s,
                        a.nq, a.q, a.w, qw, a.row_ptr, a.col_idx, a.inc_ptr, a.inc_pos, a.fan,
                        outs_for(a), a.L, (a.flags & FEM_ACCUMULATE) ? 1 : 0, ntiles);
@@ -1360,6 +1376,53 @@ extern "C" int fem_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const
     Args a = make_args(ops, nq, nme, nnz, q, w, me, row_ptr, col_idx, inc_ptr, inc_pos, fan, slot,
                        lambda, mu, vals_M, vals_Mw, vals_S, vals_K, work, work_bytes, flags, stream);
     return run("fem_assemble", a, tune);
+}
+
+// ------------------------------------------------------------ gather probe
+//
+// Measurement aid: the random accesses of the row-owner kernels without
+// their arithmetic.  Every entry e of the column stream reads col_idx[e] and
+// the 16-byte record q[col_idx[e]] (mode 0), or the record q[e mod nq] in
+// stream order instead (mode 1: the same loads with perfect locality); the
+// sums go to one double per thread so that no load is dropped.
+namespace fem {
+__global__ __launch_bounds__(256) void k_gather_probe(int64_t nnz, int32_t nq,
+                                                      const int32_t *__restrict__ col_idx,
+                                                      const double2 *__restrict__ q, int mode,
+                                                      double *__restrict__ sink) {
+    constexpr int H = 8;   // loads in flight per thread
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    double acc = 0.0;
+    for (int64_t e0 = tid; e0 < nnz; e0 += H * nth) {
+        int32_t c[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int64_t e = e0 + h * nth;
+            c[h] = e < nnz ? (mode == 0 ? col_idx[e] : (int32_t)(e % nq)) : -1;
+        }
+        double2 x[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) x[h] = c[h] >= 0 ? q[c[h]] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int h = 0; h < H; ++h) acc += x[h].x + x[h].y;
+    }
+    sink[tid] = acc;
+}
+}  // namespace fem
+
+extern "C" int fem_gather_probe_threads(void) { return 2048 * 256; }
+
+extern "C" int fem_gather_probe(int64_t nnz, int32_t nq, const int32_t *col_idx, const double *q,
+                                int mode, double *sink, void *stream) {
+    clear_error();
+    FEM_REQUIRE(nnz >= 0 && nq >= 1 && (mode == 0 || mode == 1), FEM_EINVAL,
+                "fem_gather_probe: bad arguments");
+    FEM_REQUIRE(q && sink && (nnz == 0 || col_idx), FEM_EINVAL, "fem_gather_probe: NULL array");
+    hipLaunchKernelGGL(k_gather_probe, dim3(2048), dim3(256), 0, as_stream(stream), nnz, nq, col_idx,
+                       reinterpret_cast<const double2 *>(q), mode, sink);
+    FEM_LAUNCH_CHECK();
+    return FEM_OK;
 }
 
 // ------------------------------------------------------------ allocation-free variant

@@ -102,7 +102,7 @@ def test_host_validation_before_any_launch(lib):
     assert lib.fem_graph_begin(None) == _lib.FEM_EINVAL
     assert lib.fem_graph_destroy(None) == 0
     # adjoint: the GM term needs w and dw
-    st = lib.fem_adjoint_stiff_wmass(4, 2, 10, fake, None, fake, fake, fake, fake, None, None,
+    st = lib.fem_adjoint_stiff_wmass(4, 2, 10, fake, None, fake, fake, fake, fake, None, None, None,
                                      fake, fake, None, fake, 1000, 0, None)
     assert st == _lib.FEM_EINVAL
 
