@@ -33,10 +33,20 @@ class OracleError(RuntimeError):
     pass
 
 
+def sanitize_flags() -> list:
+    """With FEM_ORACLE_SANITIZE=1 the oracle is built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (then run Python with libasan preloaded; see
+    the sanitizer command in the repository's design notes)."""
+    if os.environ.get("FEM_ORACLE_SANITIZE") == "1":
+        return ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                "-fno-omit-frame-pointer", "-g"]
+    return []
+
+
 def build() -> str:
     """Compile liboracle.so (always), and the CPU-baseline library beside it."""
     tmp = LIB + ".tmp"
-    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-Wall", "-fPIC",
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-Wall", "-fPIC", *sanitize_flags(),
                     "-shared", "-o", tmp, SRC, "-lm"], check=True)
     os.replace(tmp, LIB)
     from . import cpu_baseline

@@ -26,8 +26,9 @@ _f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
 
 def build() -> str:
     tmp = LIB + ".tmp"
+    from . import sanitize_flags
     subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-std=c99", "-Wall", "-fPIC",
-                    "-shared", "-o", tmp, SRC, "-lm"], check=True)
+                    *sanitize_flags(), "-shared", "-o", tmp, SRC, "-lm"], check=True)
     os.replace(tmp, LIB)
     return LIB
 
