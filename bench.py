@@ -3,8 +3,8 @@
 Step (timed): the whole assembly of the 2048 x 2048-cell unit square
 (8,388,608 triangles, jitter 0.2 h, random vertex relabelling, FP64 values,
 int32 indices) from (q, me) resident in HBM:
-    fem_pattern        symbolic phase (CSR pattern + triangle lists)
-    fem_fan_plan       the order of each row's triangles around its vertex
+    fem_pattern        symbolic phase (CSR pattern, triangle lists, and the
+                       order of each row's triangles around its vertex)
     fem_assemble       mass M, weighted mass Mw (w = 1 + x^2 + y^2),
                        stiffness S and elasticity K (lambda = 1, mu = 0.5),
                        all four in one pass over the rows
@@ -345,12 +345,9 @@ class Step:
         s = self.torch.cuda.current_stream().cuda_stream
         self.fem._lib.check(self.lib.fem_pattern(
             self.nq, self.nme, self.me.data_ptr(), self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
-            self.cap, self.inc_ptr.data_ptr(), self.inc.data_ptr(), self.inc_pos.data_ptr(), None,
-            self.work.data_ptr(), self.ws, C.byref(n), s))
+            self.cap, self.inc_ptr.data_ptr(), self.inc.data_ptr(), self.inc_pos.data_ptr(),
+            self.fan.data_ptr(), None, self.work.data_ptr(), self.ws, C.byref(n), s))
         self.nnz = int(n.value)
-        self.fem._lib.check(self.lib.fem_fan_plan(
-            self.nq, self.nme, self.row_ptr.data_ptr(), self.inc_ptr.data_ptr(),
-            self.inc_pos.data_ptr(), self.fan.data_ptr(), s))
 
     def _pat(self):
         return (self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.inc_ptr.data_ptr(),

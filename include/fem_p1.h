@@ -124,6 +124,9 @@ int64_t fem_nnz_bound(int32_t nq, int32_t nme);
  *   inc_pos [3 nme]      for the same entries, the positions inside row v
  *                        (relative to row_ptr[v]) of me[k][(a+1)%3] (low 16
  *                        bits) and me[k][(a+2)%3] (high 16 bits)
+ *   fan     [nq]         optional (NULL to skip): the fan code of every row,
+ *                        as fem_fan_plan writes it (computed here from the
+ *                        rows just built, without a pass of its own)
  *   slot    [9][nme]     optional (NULL to skip): slot[(3b+a) nme + k] is the
  *                        CSR position of entry (me[k][a], me[k][b]) -- local
  *                        entry r = 3b + a of the column-wise element matrix
@@ -139,7 +142,7 @@ int64_t fem_nnz_bound(int32_t nq, int32_t nme);
 int fem_pattern(int32_t nq, int32_t nme, const int32_t *me,
                 int32_t *row_ptr, int32_t *col_idx, int64_t col_cap,
                 int32_t *inc_ptr, int32_t *inc, uint32_t *inc_pos,
-                int32_t *slot,
+                uint64_t *fan, int32_t *slot,
                 void *work, size_t work_bytes,
                 int64_t *nnz_out /* HOST */, void *stream);
 
@@ -174,8 +177,8 @@ int fem_transpose_map(int32_t nq, int64_t nnz, const int32_t *row_ptr, const int
  * entry receives exactly the two terms of consecutive steps and the numeric
  * kernels need no search of the row per triangle.  Built from the arrays
  * fem_pattern wrote (row_ptr, inc_ptr, inc_pos; no other input), once per
- * mesh.  A row gets code 0 -- and is then summed in ascending triangle
- * order -- unless its triangles form a single consistently oriented fan
+ * mesh (fem_pattern writes the same codes when given its fan argument).  A
+ * row gets code 0 -- and is then summed in ascending triangle order -- unless its triangles form a single consistently oriented fan
  * (closed around an inner vertex, open at a boundary vertex) of at most 13
  * neighbours; so on a mesh whose triangles are all counter-clockwise (or all
  * clockwise) every manifold row with up to 13 neighbours has one.  Layout:

@@ -101,7 +101,7 @@ class Pattern:
 
 
 def fem_pattern(me, nq: int, *, slot: bool = False, fan: bool = True, stream=None) -> Pattern:
-    """Symbolic phase (C: fem_pattern, then fem_fan_plan unless fan=False).
+    """Symbolic phase (C: fem_pattern), with the fan codes unless fan=False.
     me: [nme][3] int32 on the GPU."""
     torch = _torch()
     lib = _lib.load()
@@ -120,17 +120,15 @@ def fem_pattern(me, nq: int, *, slot: bool = False, fan: bool = True, stream=Non
     inc = torch.empty(max(3 * nme, 1), **i32)
     inc_pos = torch.empty(max(3 * nme, 1), **i32)
     sl = torch.empty(max(9 * nme, 1), **i32) if slot else None
+    fn = torch.empty(nq, dtype=torch.int64, device=dev) if fan else None
     work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
     nnz = C.c_int64(0)
     _lib.check(lib.fem_pattern(int(nq), nme, _ptr(me), _ptr(row_ptr), _ptr(col_buf), cap,
-                               _ptr(inc_ptr), _ptr(inc), _ptr(inc_pos), _ptr(sl), _ptr(work),
+                               _ptr(inc_ptr), _ptr(inc), _ptr(inc_pos), _ptr(fn), _ptr(sl), _ptr(work),
                                int(ws.value), C.byref(nnz), _stream(stream)))
     n = int(nnz.value)
-    pat = Pattern(int(nq), nme, n, me, row_ptr, col_buf[:n], inc_ptr, inc[:3 * nme],
-                  inc_pos[:3 * nme], None if sl is None else sl[:9 * nme].view(9, nme))
-    if fan:
-        fem_fan_plan(pat, stream=stream)
-    return pat
+    return Pattern(int(nq), nme, n, me, row_ptr, col_buf[:n], inc_ptr, inc[:3 * nme],
+                   inc_pos[:3 * nme], None if sl is None else sl[:9 * nme].view(9, nme), fan=fn)
 
 
 def fem_fan_plan(pat: Pattern, *, stream=None):

@@ -60,8 +60,8 @@ SIGNATURES = {
     "fem_version": (_int, []),
     "fem_pattern_workspace": (_int, [_i32, _i32, _szp]),
     "fem_nnz_bound": (_i64, [_i32, _i32]),
-    "fem_pattern": (_int, [_i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, C.c_size_t,
-                           C.POINTER(_i64), _vp]),
+    "fem_pattern": (_int, [_i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                           C.c_size_t, C.POINTER(_i64), _vp]),
     "fem_pattern_set_path": (_int, [_int]),
     "fem_transpose_map": (_int, [_i32, _i64, _vp, _vp, _vp, _vp]),
     "fem_fan_plan": (_int, [_i32, _i32, _vp, _vp, _vp, _vp, _vp]),

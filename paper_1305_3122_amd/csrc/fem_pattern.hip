@@ -326,6 +326,72 @@ __device__ inline int32_t lower_bound(const int32_t *a, int32_t n, int32_t x) {
     return lo;
 }
 
+// Fan code of a row (layout in fem_internal.h) from its d triangles in
+// ascending order and the row length: pos(t) gives triangle t's packed
+// positions p1 | p2 << 16 (next and previous vertex in the triangle's own
+// order), so triangle t links slot p1 -> p2 and the fan is the chain of these
+// links.  The code is nonzero only if every slot is left by at most one
+// triangle and entered by at most one, the links form one closed cycle or
+// one open path through all d triangles, and every off-diagonal slot is on
+// it; otherwise (inconsistent orientation, several fans meeting at the
+// vertex, a non-manifold edge, more than FAN_NMAX neighbours) it is 0.  A
+// closed fan starts at the first triangle's p1, an open one at its only slot
+// that no triangle enters.
+template <typename Pos>
+__device__ inline uint64_t fan_code(int d, int32_t len, Pos pos) {
+    if (!(d >= 1 && d <= FAN_NMAX && len >= 3 && len <= FAN_NMAX + 1)) return 0;
+    uint64_t succ = 0, p2t = 0;   // nibble tables: slot -> triangle, triangle -> p2
+    uint32_t outm = 0, inm = 0;
+    bool ok = true;
+    for (int t = 0; t < d && ok; ++t) {
+        const uint32_t pp = pos(t);
+        const uint32_t p1 = pp & 0xffffu, p2 = pp >> 16;
+        ok = p1 < 16 && p2 < 16 && !((outm >> p1) & 1u) && !((inm >> p2) & 1u);
+        if (ok) {
+            outm |= 1u << p1;
+            inm |= 1u << p2;
+            succ |= (uint64_t)t << (4 * p1);
+            p2t |= (uint64_t)p2 << (4 * t);
+        }
+    }
+    const uint32_t used = outm | inm, starts = outm & ~inm;
+    const bool closed = starts == 0;
+    ok = ok && __builtin_popcount(used) + 1 == len &&
+         (closed ? outm == inm
+                 : (__builtin_popcount(starts) == 1 && __builtin_popcount(inm & ~outm) == 1));
+    if (!ok) return 0;
+    const int s0 = closed ? (int)(pos(0) & 0xffffu) : __builtin_ctz(starts);
+    int s = s0, n = 0;
+    uint64_t slots = 0;
+    for (int j = 0; j < d && ok; ++j) {
+        // every step leaves its slot; a closed walk meets s0 again only at the end
+        ok = ((outm >> s) & 1u) && !(j > 0 && s == s0);
+        if (ok) {
+            slots |= (uint64_t)s << (4 * n++);
+            s = (int)((p2t >> (4 * ((succ >> (4 * s)) & 15u))) & 15u);
+        }
+    }
+    if (!ok) return 0;
+    if (closed) ok = s == s0;
+    else slots |= (uint64_t)s << (4 * n++);
+    if (!(ok && n + 1 == len && n <= FAN_NMAX)) return 0;
+    const int pd = __builtin_ctz(~used);
+    return (uint64_t)n | ((uint64_t)(closed ? 1 : 0) << 4) | ((uint64_t)pd << 5) | (slots << 9);
+}
+
+// Fan code of every row from the triangle lists (patterns of the coarse
+// and atomic paths, or built elsewhere).
+__global__ __launch_bounds__(256) void k_fan_plan(int32_t nq, const int32_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ inc_ptr,
+                                                  const uint32_t *__restrict__ inc_pos,
+                                                  uint64_t *__restrict__ fan) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const int32_t is = inc_ptr[i], d = inc_ptr[i + 1] - is;
+    const int32_t len = row_ptr[i + 1] - row_ptr[i];
+    fan[i] = fan_code(d, len, [&](int t) { return inc_pos[is + t]; });
+}
+
 // Bitonic sorting networks on register arrays (all indices static after
 // unrolling, so the arrays stay in VGPRs).  sort_kv: key + two payloads.
 template <int N>
@@ -403,11 +469,12 @@ __device__ inline int32_t block_exclusive_scan_i32(int32_t v, int32_t *s_wsum, i
 // more than FINE_DMAX triangles, sets ERR_BUCKET: the host then rebuilds with
 // the coarse path.
 template <bool PK>
-__global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
+__global__ __launch_bounds__(BKT_THREADS) __attribute__((amdgpu_waves_per_eu(6))) void k_bkt_rows(
     int32_t nq, int32_t nbkt, int32_t nblk, const int32_t *__restrict__ offs,
     const int32_t *__restrict__ total_ptr, const int32_t *__restrict__ ent, int32_t *__restrict__ inc_ptr,
-    int32_t *__restrict__ inc, uint32_t *__restrict__ inc_pos, int32_t *__restrict__ rowoff,
-    int32_t *__restrict__ btot, int32_t *__restrict__ stage, PatternCounters *cnt) {
+    int32_t *__restrict__ inc, uint32_t *__restrict__ inc_pos, uint64_t *__restrict__ fan,
+    int32_t *__restrict__ rowoff, int32_t *__restrict__ btot, int32_t *__restrict__ stage,
+    PatternCounters *cnt) {
     __shared__ int32_t s_cur[FINE_V];
     __shared__ int32_t s_key[FINE_CAP], s_n1[FINE_CAP], s_n2[FINE_CAP];
     __shared__ int32_t s_wsum[BKT_THREADS / WAVE];
@@ -581,6 +648,17 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
             out[lds_rank((int32_t)v)] = (int32_t)v;
             for (int t = 0; t < d; ++t) s_n1[is + t] = static_cast<int32_t>(POS_DIRECT);
         }
+    }
+    // the fan code, from the positions in the vertex's LDS slice (register
+    // path) or in inc_pos (LDS path); computed once the rows are out, when
+    // the sort's registers are free
+    if (fan && v < nq) {
+        uint64_t code = 0;
+        if (!bad && d > 0) {
+            if (in_regs) code = fan_code(d, L, [&](int t) { return static_cast<uint32_t>(s_n1[is + t]); });
+            else code = fan_code(d, L, [&](int t) { return inc_pos[ib + t]; });
+        }
+        fan[v] = code;
     }
     __syncthreads();
     if (fits) {
@@ -951,72 +1029,6 @@ __global__ __launch_bounds__(256) void k_transpose(int32_t nq, const int32_t *__
     }
 }
 
-// Fan code of every row (layout in fem_internal.h) from the triangle lists:
-// triangle t of vertex i links its two neighbour slots p1 -> p2 (next and
-// previous vertex in the triangle's own order), and the fan is the chain of
-// these links.  A row gets a code only if every slot is left by at most one
-// triangle and entered by at most one, the links form one closed cycle or
-// one open path through all of the row's triangles, and every off-diagonal
-// slot is on it; otherwise (inconsistent orientation, several fans meeting
-// at the vertex, a non-manifold edge, more than FAN_NMAX neighbours) it
-// gets 0.  A closed fan starts at the first triangle's p1 (lowest id), an
-// open one at its only slot that no triangle enters.
-__global__ __launch_bounds__(256) void k_fan_plan(int32_t nq, const int32_t *__restrict__ row_ptr,
-                                                  const int32_t *__restrict__ inc_ptr,
-                                                  const uint32_t *__restrict__ inc_pos,
-                                                  uint64_t *__restrict__ fan) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= nq) return;
-    const int32_t is = inc_ptr[i], d = inc_ptr[i + 1] - is;
-    const int32_t len = row_ptr[i + 1] - row_ptr[i];
-    uint64_t code = 0;
-    if (d >= 1 && d <= FAN_NMAX && len >= 3 && len <= FAN_NMAX + 1) {
-        uint64_t succ = 0, p2t = 0;   // nibble tables: slot -> triangle, triangle -> p2
-        uint32_t outm = 0, inm = 0;
-        bool ok = true;
-        for (int t = 0; t < d && ok; ++t) {
-            const uint32_t pp = inc_pos[is + t];
-            const uint32_t p1 = pp & 0xffffu, p2 = pp >> 16;
-            ok = p1 < 16 && p2 < 16 && !((outm >> p1) & 1u) && !((inm >> p2) & 1u);
-            if (ok) {
-                outm |= 1u << p1;
-                inm |= 1u << p2;
-                succ |= (uint64_t)t << (4 * p1);
-                p2t |= (uint64_t)p2 << (4 * t);
-            }
-        }
-        const uint32_t used = outm | inm, starts = outm & ~inm;
-        const bool closed = starts == 0;
-        ok = ok && __builtin_popcount(used) + 1 == len &&
-             (closed ? outm == inm
-                     : (__builtin_popcount(starts) == 1 && __builtin_popcount(inm & ~outm) == 1));
-        if (ok) {
-            const int s0 = closed ? (int)(inc_pos[is] & 0xffffu) : __builtin_ctz(starts);
-            int s = s0, n = 0;
-            uint64_t slots = 0;
-            for (int j = 0; j < d && ok; ++j) {
-                // every step leaves its slot; a closed walk meets s0 again only at the end
-                ok = ((outm >> s) & 1u) && !(j > 0 && s == s0);
-                if (ok) {
-                    slots |= (uint64_t)s << (4 * n++);
-                    s = (int)((p2t >> (4 * ((succ >> (4 * s)) & 15u))) & 15u);
-                }
-            }
-            if (ok) {
-                if (closed) ok = s == s0;
-                else slots |= (uint64_t)s << (4 * n++);
-                ok = ok && n + 1 == len && n <= FAN_NMAX;
-            }
-            if (ok) {
-                const int pd = __builtin_ctz(~used);
-                code = (uint64_t)n | ((uint64_t)(closed ? 1 : 0) << 4) | ((uint64_t)pd << 5) |
-                       (slots << 9);
-            }
-        }
-    }
-    fan[i] = code;
-}
-
 constexpr int ELAS_STAGE = 8 * WAVE;   // scalar entries of a tile staged in LDS (2 + 8 KiB)
 
 // Tile of 64 scalar rows = a contiguous slice of Ew scalar entries and of
@@ -1238,8 +1250,8 @@ extern "C" int fem_pattern_workspace(int32_t nq, int32_t nme, size_t *bytes) {
 
 extern "C" int fem_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *row_ptr,
                            int32_t *col_idx, int64_t col_cap, int32_t *inc_ptr, int32_t *inc,
-                           uint32_t *inc_pos, int32_t *slot, void *work, size_t work_bytes,
-                           int64_t *nnz_out, void *stream) {
+                           uint32_t *inc_pos, uint64_t *fan, int32_t *slot, void *work,
+                           size_t work_bytes, int64_t *nnz_out, void *stream) {
     clear_error();
     FEM_REQUIRE(nq >= 1, FEM_EINVAL, "fem_pattern: nq must be >= 1 (got %d)", nq);
     FEM_REQUIRE(nme >= 0, FEM_EINVAL, "fem_pattern: nme must be >= 0 (got %d)", nme);
@@ -1281,11 +1293,11 @@ extern "C" int fem_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *
         if (packed)
             hipLaunchKernelGGL(k_bkt_rows<true>, dim3(W.fine.nbkt), dim3(BKT_THREADS), 0, s, nq,
                                W.fine.nbkt, W.fine.nblk, W.counts, W.counts + W.fine.ncounts(), W.ent,
-                               inc_ptr, inc, inc_pos, W.rowlen, W.btot, fstage, W.cnt);
+                               inc_ptr, inc, inc_pos, fan, W.rowlen, W.btot, fstage, W.cnt);
         else
             hipLaunchKernelGGL(k_bkt_rows<false>, dim3(W.fine.nbkt), dim3(BKT_THREADS), 0, s, nq,
                                W.fine.nbkt, W.fine.nblk, W.counts, W.counts + W.fine.ncounts(), W.ent,
-                               inc_ptr, inc, inc_pos, W.rowlen, W.btot, fstage, W.cnt);
+                               inc_ptr, inc, inc_pos, fan, W.rowlen, W.btot, fstage, W.cnt);
         FEM_LAUNCH_CHECK();
         if ((st = exclusive_scan_i32(W.btot, W.bptr, W.fine.nbkt, W.part, &W.cnt->total[1],
                                      &W.cnt->err, s)))
@@ -1344,6 +1356,11 @@ extern "C" int fem_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *
         hipLaunchKernelGGL(k_copy_cols, dim3(grid_for(nq, WAVE)), dim3(WAVE), 0, s, nq, row_ptr,
                            inc_ptr, W.stage, col_idx);
         FEM_LAUNCH_CHECK();
+        if (fan) {
+            hipLaunchKernelGGL(k_fan_plan, dim3(grid_for(nq, 256)), dim3(256), 0, s, nq, row_ptr,
+                               inc_ptr, inc_pos, fan);
+            FEM_LAUNCH_CHECK();
+        }
     }
     const int64_t nnz = h.total[1];
     FEM_REQUIRE(!(h.err & ERR_NOSPC) && nnz <= col_cap, FEM_ENOSPC,

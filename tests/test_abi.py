@@ -50,16 +50,16 @@ def test_host_validation_before_any_launch(lib):
     nnz = C.c_int64(0)
     fake = C.c_void_p(0x1000)  # never dereferenced: the checks fail first
     # nq < 1
-    st = lib.fem_pattern(0, 1, fake, fake, fake, 10, fake, fake, fake, None, fake, 1 << 20,
+    st = lib.fem_pattern(0, 1, fake, fake, fake, 10, fake, fake, fake, None, None, fake, 1 << 20,
                          C.byref(nnz), None)
     assert st == _lib.FEM_EINVAL
     assert b"nq" in lib.fem_last_error()
     # nq + 6 nme beyond int32
-    st = lib.fem_pattern(10, 400_000_000, fake, fake, fake, 10, fake, fake, fake, None, fake,
+    st = lib.fem_pattern(10, 400_000_000, fake, fake, fake, 10, fake, fake, fake, None, None, fake,
                          1 << 20, C.byref(nnz), None)
     assert st == _lib.FEM_EOVERFLOW
     # workspace too small
-    st = lib.fem_pattern(10, 4, fake, fake, fake, 100, fake, fake, fake, None, fake, 16,
+    st = lib.fem_pattern(10, 4, fake, fake, fake, 100, fake, fake, fake, None, None, fake, 16,
                          C.byref(nnz), None)
     assert st == _lib.FEM_ENOSPC
     # elasticity: lambda + mu must be positive (elasticity section)

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_1305_3122_amd import meshgen as mg
-from tests.helpers import fan_mesh
+from tests.helpers import check_fan_codes, fan_mesh
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -83,6 +83,13 @@ def test_paths_bit_exact(name, m, path, path_reset):
     rs = P.row_ptr[v]
     np.testing.assert_array_equal(P.col_idx[rs + (pos & 0xFFFF)], m.me[k, (a + 1) % 3])
     np.testing.assert_array_equal(P.col_idx[rs + (pos >> 16)], m.me[k, (a + 2) % 3])
+    # the fan codes fem_pattern writes on this path: valid walks, and the same
+    # as fem_fan_plan computes from the finished pattern
+    fan_inline = pat.fan.clone()
+    fem.fem_fan_plan(pat)
+    torch.cuda.synchronize()
+    assert torch.equal(fan_inline, pat.fan)
+    check_fan_codes(_np(pat.fan), P.row_ptr, P.col_idx, m.me)
 
 
 def test_paths_agree_on_full_size_mesh(path_reset):
@@ -99,7 +106,7 @@ def test_paths_agree_on_full_size_mesh(path_reset):
     # Euler: nnz = nq + 2 E with E = nq + nme - 1 edges on a simply connected mesh
     assert ref.nnz == m.nq + 2 * (m.nq + m.nme - 1)
     for name in ("coarse", "atomic"):
-        for f in ("row_ptr", "col_idx", "inc_ptr", "inc", "inc_pos"):
+        for f in ("row_ptr", "col_idx", "inc_ptr", "inc", "inc_pos", "fan"):
             assert torch.equal(getattr(res[name], f), getattr(ref, f)), (name, f)
 
 
@@ -124,7 +131,7 @@ def test_col_cap_too_small(path, path_reset):
     for cap, ok in ((P.nnz - 1, False), (P.nnz, True)):
         col = torch.full((cap + 64,), -7, **i32)
         st = lib.fem_pattern(nq, nme, me.data_ptr(), row_ptr.data_ptr(), col.data_ptr(), cap,
-                             inc_ptr.data_ptr(), inc.data_ptr(), inc_pos.data_ptr(), None,
+                             inc_ptr.data_ptr(), inc.data_ptr(), inc_pos.data_ptr(), None, None,
                              work.data_ptr(), int(ws.value), C.byref(nnz), stream)
         torch.cuda.synchronize()
         assert (st == 0) == ok, (cap, st)
