@@ -439,7 +439,7 @@ __device__ __forceinline__ void bitonic_sort(int32_t (&k)[N]) {
 constexpr int REG_MAX = 8;
 
 // Exclusive scan of one int per thread over a workgroup of BKT_THREADS.
-__device__ inline int32_t block_exclusive_scan_i32(int32_t v, int32_t *s_wsum, int32_t *total) {
+__device__ __noinline__ int32_t block_exclusive_scan_i32(int32_t v, int32_t *s_wsum, int32_t *total) {
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int32_t incl = wave_inclusive_scan(v);
     if (lane == WAVE - 1) s_wsum[wid] = incl;
@@ -469,7 +469,7 @@ __device__ inline int32_t block_exclusive_scan_i32(int32_t v, int32_t *s_wsum, i
 // more than FINE_DMAX triangles, sets ERR_BUCKET: the host then rebuilds with
 // the coarse path.
 template <bool PK>
-__global__ __launch_bounds__(BKT_THREADS) __attribute__((amdgpu_waves_per_eu(6))) void k_bkt_rows(
+__global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
     int32_t nq, int32_t nbkt, int32_t nblk, const int32_t *__restrict__ offs,
     const int32_t *__restrict__ total_ptr, const int32_t *__restrict__ ent, int32_t *__restrict__ inc_ptr,
     int32_t *__restrict__ inc, uint32_t *__restrict__ inc_pos, uint64_t *__restrict__ fan,
@@ -649,17 +649,6 @@ __global__ __launch_bounds__(BKT_THREADS) __attribute__((amdgpu_waves_per_eu(6))
             for (int t = 0; t < d; ++t) s_n1[is + t] = static_cast<int32_t>(POS_DIRECT);
         }
     }
-    // the fan code, from the positions in the vertex's LDS slice (register
-    // path) or in inc_pos (LDS path); computed once the rows are out, when
-    // the sort's registers are free
-    if (fan && v < nq) {
-        uint64_t code = 0;
-        if (!bad && d > 0) {
-            if (in_regs) code = fan_code(d, L, [&](int t) { return static_cast<uint32_t>(s_n1[is + t]); });
-            else code = fan_code(d, L, [&](int t) { return inc_pos[ib + t]; });
-        }
-        fan[v] = code;
-    }
     __syncthreads();
     if (fits) {
         const int32_t n = static_cast<int32_t>(e1 - e0);
@@ -679,6 +668,17 @@ __global__ __launch_bounds__(BKT_THREADS) __attribute__((amdgpu_waves_per_eu(6))
     if ((tid & (WAVE - 1)) == 0) {
         max_into(&cnt->max_row_len, mr);
         max_into(&cnt->max_inc, mi);
+    }
+    // ---- the fan code, last, when the sort's registers are free: from the
+    // positions in the vertex's LDS slice (register path; the copy-out above
+    // only read it) or in inc_pos (LDS path)
+    if (fan && v < nq) {
+        uint64_t code = 0;
+        if (!bad && d > 0) {
+            if (in_regs) code = fan_code(d, L, [&](int t) { return static_cast<uint32_t>(s_n1[is + t]); });
+            else code = fan_code(d, L, [&](int t) { return inc_pos[ib + t]; });
+        }
+        fan[v] = code;
     }
 }
 
