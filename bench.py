@@ -150,8 +150,9 @@ PROFILE_TITLES = {
                       "counters."),
     "tet_cube128": ("P1 tetrahedra on the 128^3-cell unit cube",
                     "Workload: 12,582,912 Kuhn tetrahedra, 2,146,689 vertices (jitter 0.1h, random\n"
-                    "relabelling), nnz 31,802,497; 5 patterns (201M triplets), 11 mass + stiffness\n"
-                    "assemblies; FP64 values, int32 indices.  The 1 GiB fill and copy calibrate the\n"
+                    "relabelling), nnz 31,802,497; 5 patterns (50.3M incidences in 128-vertex\n"
+                    "buckets), 11 mass + stiffness assemblies (one lane per row);"
+                    " FP64 values, int32 indices.  The 1 GiB fill and copy calibrate the\n"
                     "counters."),
     "adjoint_square512": ("the adjoints on the 512x512-cell unit square",
                           "Workload: 524,288 triangles, 263,169 vertices (jitter 0.2h, random vertex\n"
@@ -801,7 +802,8 @@ def run_sparse(torch, fem, args):
 
 def run_tet(torch, fem, args):
     """P1 tetrahedra: the 128^3-cell unit cube (Kuhn, 12.6M tetrahedra, jitter
-    0.1h, random relabelling), pattern and fused mass + stiffness."""
+    0.1h, random relabelling), pattern and fused mass + stiffness (one lane
+    per row)."""
     from paper_1305_3122_amd import meshgen as mg
     lib = fem._lib.load()
     dev = torch.device("cuda:0")
@@ -812,33 +814,32 @@ def run_tet(torch, fem, args):
     ws = C.c_size_t(0)
     fem._lib.check(lib.fem_tet_pattern_workspace(m.nq, m.nme, C.byref(ws)))
     work = torch.empty(int(ws.value), dtype=torch.uint8, device=dev)
-    cap = 16 * m.nme
+    cap = int(lib.fem_tet_nnz_bound(m.nq, m.nme))
     i32 = dict(dtype=torch.int32, device=dev)
     row_ptr = torch.empty(m.nq + 1, **i32)
     col = torch.empty(cap, **i32)
-    cptr = torch.empty(cap + 1, **i32)
-    ctb = torch.empty(cap, **i32)
+    inc_ptr = torch.empty(m.nq + 1, **i32)
+    inc = torch.empty(4 * m.nme, **i32)
+    inc_pos = torch.empty(4 * m.nme, **i32)
     s = torch.cuda.current_stream().cuda_stream
     nnz = C.c_int64(0)
 
     def pattern():
         fem._lib.check(lib.fem_tet_pattern(m.nq, m.nme, me.data_ptr(), row_ptr.data_ptr(),
-                                           col.data_ptr(), cap, cptr.data_ptr(), ctb.data_ptr(),
-                                           work.data_ptr(), int(ws.value), C.byref(nnz), s))
+                                           col.data_ptr(), cap, inc_ptr.data_ptr(), inc.data_ptr(),
+                                           inc_pos.data_ptr(), work.data_ptr(), int(ws.value),
+                                           C.byref(nnz), s))
 
     pattern()
     k = int(nnz.value)
     ops = fem.FEM_OP_MASS | fem.FEM_OP_STIFF
-    aw = C.c_size_t(0)
-    fem._lib.check(lib.fem_tet_assemble_workspace(m.nme, ops, C.byref(aw)))
-    awork = torch.empty(int(aw.value), dtype=torch.uint8, device=dev)
     M = torch.empty(k, dtype=torch.float64, device=dev)
     S = torch.empty_like(M)
 
     def assemble():
-        fem._lib.check(lib.fem_tet_assemble(ops, m.nq, m.nme, k, q.data_ptr(), me.data_ptr(),
-                                            cptr.data_ptr(), ctb.data_ptr(), M.data_ptr(),
-                                            S.data_ptr(), awork.data_ptr(), awork.numel(), 0, s))
+        fem._lib.check(lib.fem_tet_assemble(ops, m.nq, m.nme, k, q.data_ptr(), row_ptr.data_ptr(),
+                                            col.data_ptr(), inc_ptr.data_ptr(), inc_pos.data_ptr(),
+                                            M.data_ptr(), S.data_ptr(), 0, s))
 
     def timed(fn, reps):
         fn()
@@ -856,7 +857,10 @@ def run_tet(torch, fem, args):
 
     tp = timed(pattern, 3)
     ta = timed(assemble, 10)
-    alg = 24 * m.nq + 16 * m.nme + 16 * k
+    # design bytes of the row kernel: q (24 per vertex), row_ptr and inc_ptr
+    # (8 per vertex), col_idx (4 per entry), inc_pos (4 per incidence, 16 per
+    # tetrahedron), M and S (16 per entry)
+    alg = 32 * m.nq + 16 * m.nme + 20 * k
     out = {"workload": "unit cube 128^3 cells, 6 Kuhn tetrahedra per cell (12.6M), jitter 0.1h, "
                        "random relabelling; P1 mass + stiffness FP64",
            "nq": m.nq, "nme": m.nme, "nnz": k, "pattern_us": round(tp, 1),

@@ -394,36 +394,53 @@ int fem_sparse_values(int64_t nnz, const int32_t *contrib_ptr, const int32_t *co
 /* HOST ONLY.  Bytes of device workspace fem_tet_pattern needs. */
 int fem_tet_pattern_workspace(int32_t nq, int32_t nme, size_t *bytes /* HOST */);
 
-/* Pattern of the P1 tetrahedron matrices (the 3D extension named in the
- * Conclusion), built the OptV2 way: the index arrays of all 16 local entries,
- * triplet t = r nme + k for entry r = 4 b + a of element k (row me[k][a],
- * column me[k][b]), compressed by fem_sparse.
- *   me [nme][4] int32, 16-byte aligned; row_ptr [nq+1], col_idx [col_cap]
- *   contrib_ptr [col_cap+1], contrib [16 nme]: the triplets of each entry,
- *                ascending (what fem_tet_assemble sums)
- *   work [work_bytes] >= fem_tet_pattern_workspace(nq, nme); nnz_out HOST
- * Requires 16 nme <= 2^31 - 1.  FEM_ERANGE / FEM_EDEGEN for an invalid me,
- * FEM_ENOSPC if col_cap < nnz.  Synchronises `stream`. */
-int fem_tet_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *row_ptr,
-                    int32_t *col_idx, int64_t col_cap, int32_t *contrib_ptr, int32_t *contrib,
-                    void *work, size_t work_bytes, int64_t *nnz_out /* HOST */, void *stream);
+/* HOST ONLY.  nq + 12 nme: an upper bound of the tetrahedron pattern's nnz
+ * (a vertex in d tetrahedra has at most 3 d neighbours); a safe col_cap. */
+int64_t fem_tet_nnz_bound(int32_t nq, int32_t nme);
 
-/* HOST ONLY.  Bytes of device workspace fem_tet_assemble needs (per
- * tetrahedron: 1 value for the mass, 10 for the stiffness). */
-int fem_tet_assemble_workspace(int32_t nme, int ops, size_t *bytes /* HOST */);
+/* Pattern of the P1 tetrahedron matrices (the 3D extension named in the
+ * Conclusion): the CSR pattern of sparse(Ig, Jg, .) over the 16 local entries
+ * of every element (Section 6; entry (a, b) of element k lies at row
+ * me[k][a], column me[k][b]), and per vertex its tetrahedra with the row
+ * slots of their other vertices, which is what fem_tet_assemble reads.
+ *   me [nme][4] int32, 16-byte aligned, 0-based vertex ids
+ *   row_ptr [nq+1], col_idx [col_cap]: rows ascending, columns ascending; a
+ *                vertex in no tetrahedron has an empty row
+ *   inc_ptr [nq+1], inc [4 nme]: the tetrahedra of vertex v as 4 k + a
+ *                (me[k][a] == v), ascending, at inc[inc_ptr[v] ..
+ *                inc_ptr[v+1])
+ *   inc_pos [4 nme]: for inc[i] = 4 k + a in row v, the row slots (offsets
+ *                from row_ptr[v]) of me[k][(a+1)%4], me[k][(a+2)%4] and
+ *                me[k][(a+3)%4] in bits 0-9, 10-19 and 20-29
+ *   work [work_bytes] >= fem_tet_pattern_workspace(nq, nme); nnz_out HOST
+ * All outputs are device memory owned by the caller.  Requires 16 nme <=
+ * 2^31 - 1 and rows of at most 1024 entries (FEM_EUNSUPPORTED otherwise).
+ * FEM_ERANGE / FEM_EDEGEN for an invalid me, FEM_ENOSPC if col_cap < nnz
+ * (fem_tet_nnz_bound is always enough).  Synchronises `stream`. */
+int fem_tet_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *row_ptr,
+                    int32_t *col_idx, int64_t col_cap, int32_t *inc_ptr, int32_t *inc,
+                    uint32_t *inc_pos, void *work, size_t work_bytes, int64_t *nnz_out /* HOST */,
+                    void *stream);
+
+/* HOST ONLY.  Grouping of fem_tet_pattern: FEM_PATTERN_AUTO (buckets of 128
+ * vertices in LDS, the general path for meshes beyond their limits) or
+ * FEM_PATTERN_COARSE (always the general path: fem_sparse over the 16 nme
+ * triplets).  Both give the same arrays bit for bit; for tests. */
+int fem_tet_pattern_set_path(int path);
 
 /* P1 tetrahedron mass (FEM_OP_MASS: |K| (1 + delta_ab) / 20) and / or
- * stiffness (FEM_OP_STIFF: |K| grad lambda_a . grad lambda_b) on the pattern
- * of fem_tet_pattern: what the element matrices of every tetrahedron hold
- * (the paper's Kg, reduced to |K| / 20 and the 10 distinct stiffness entries),
- * then for every entry the sum of its contributors in ascending t (bitwise
- * reproducible).
- *   q [nq][3] f64; me [nme][4] int32 (16-byte aligned); vals_M / vals_S [nnz]
- *   work [work_bytes] >= fem_tet_assemble_workspace(nme, ops), 16-byte aligned
- * flags: 0 or FEM_ACCUMULATE. */
+ * stiffness (FEM_OP_STIFF: |K| grad lambda_a . grad lambda_b), the 3D
+ * counterparts of the element matrices of Section 3, summed over the
+ * elements as sparse() does (Section 6), on the pattern of fem_tet_pattern.
+ * One lane per row; every entry is the sum of its element terms in ascending
+ * tetrahedron order (bitwise reproducible).
+ *   q [nq][3] f64; row_ptr, col_idx, inc_ptr, inc_pos from fem_tet_pattern
+ *   vals_M / vals_S [nnz] device, caller-owned
+ * flags: 0 or FEM_ACCUMULATE.  A degenerate (flat) tetrahedron gives
+ * non-finite stiffness values, as the element formula does. */
 int fem_tet_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q,
-                     const int32_t *me, const int32_t *contrib_ptr, const int32_t *contrib,
-                     double *vals_M, double *vals_S, void *work, size_t work_bytes, int flags,
+                     const int32_t *row_ptr, const int32_t *col_idx, const int32_t *inc_ptr,
+                     const uint32_t *inc_pos, double *vals_M, double *vals_S, int flags,
                      void *stream);
 
 /* ------------------------------------------------------------------------ */

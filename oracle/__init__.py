@@ -220,6 +220,18 @@ def assemble_tet(op: str, q, me):
     return row_ptr, col_idx[:nnz].copy(), vals[:nnz].copy()
 
 
+def tet_incidence(nq: int, me):
+    """The tetrahedra of every vertex (the transpose of me): vertex v's are
+    the ids 4 k + a with me[k][a] == v, ascending, at inc[inc_ptr[v] ..
+    inc_ptr[v+1]).  Returns (inc_ptr [nq+1], inc [4 nme]) int32."""
+    me = _i32(me)
+    v = me.reshape(-1).astype(np.int64)          # entry 4 k + a of the flat array
+    inc = np.argsort(v, kind="stable").astype(np.int32)
+    inc_ptr = np.zeros(nq + 1, np.int32)
+    inc_ptr[1:] = np.cumsum(np.bincount(v, minlength=nq))
+    return inc_ptr, inc
+
+
 def elem_p2_mass(area_: float):
     """6x6 P2 mass matrix [a][b] (vertices 0..2, then the edge opposite each)."""
     E = np.zeros(36)

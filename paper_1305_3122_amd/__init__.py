@@ -33,7 +33,7 @@ __all__ = [
     "fem_assemble_wmass", "fem_assemble_stiff", "fem_assemble_stiff_mass",
     "fem_assemble_stiff_wmass", "fem_assemble_elas", "fem_batch_globalize",
     "fem_assemble_stiff_mass_batched", "Graph", "SparseCSR", "fem_sparse", "fem_sparse_values",
-    "TetPattern", "fem_tet_pattern", "fem_tet_assemble", "P2Pattern", "fem_p2_pattern", "fem_p2_assemble",
+    "TetPattern", "fem_tet_pattern", "fem_tet_pattern_set_path", "fem_tet_assemble", "P2Pattern", "fem_p2_pattern", "fem_p2_assemble",
     "fem_adjoint_workspace", "fem_adjoint_stiff_wmass", "fem_adjoint_elas",
     "AssembleStiffWMass", "AssembleElas",
     "library_path",
@@ -403,12 +403,18 @@ class TetPattern:
     me: object               # [nme][4] int32
     row_ptr: object          # [nq+1] int32
     col_idx: object          # [nnz] int32
-    contrib_ptr: object      # [nnz+1] int32
-    contrib: object          # [16 nme] int32
+    inc_ptr: object          # [nq+1] int32
+    inc: object              # [4 nme] int32: 4 k + a, ascending per vertex
+    inc_pos: object          # [4 nme] int32 (uint32 bits): three 10-bit row slots
 
     def csr(self, values):
         torch = _torch()
         return torch.sparse_csr_tensor(self.row_ptr, self.col_idx, values, (self.nq, self.nq))
+
+
+def fem_tet_pattern_set_path(path: int) -> None:
+    """FEM_PATTERN_AUTO or FEM_PATTERN_COARSE (the general path), for tests."""
+    _lib.check(_lib.load().fem_tet_pattern_set_path(int(path)))
 
 
 def fem_tet_pattern(me, nq: int, *, stream=None) -> TetPattern:
@@ -423,22 +429,24 @@ def fem_tet_pattern(me, nq: int, *, stream=None) -> TetPattern:
     ws = C.c_size_t(0)
     _lib.check(lib.fem_tet_pattern_workspace(int(nq), nme, C.byref(ws)))
     work = torch.empty(max(int(ws.value), 1), dtype=torch.uint8, device=dev)
-    cap = 16 * nme
+    cap = int(lib.fem_tet_nnz_bound(int(nq), nme))
     i32 = dict(dtype=torch.int32, device=dev)
     row_ptr = torch.empty(int(nq) + 1, **i32)
+    inc_ptr = torch.empty(int(nq) + 1, **i32)
     col = torch.empty(max(cap, 1), **i32)
-    cptr = torch.empty(cap + 1, **i32)
-    ctb = torch.empty(max(cap, 1), **i32)
+    inc = torch.empty(max(4 * nme, 1), **i32)
+    inc_pos = torch.empty(max(4 * nme, 1), **i32)
     nnz = C.c_int64(0)
-    _lib.check(lib.fem_tet_pattern(int(nq), nme, _ptr(me), _ptr(row_ptr), _ptr(col), cap, _ptr(cptr),
-                                   _ptr(ctb), _ptr(work), int(ws.value), C.byref(nnz),
-                                   _stream(stream)))
+    _lib.check(lib.fem_tet_pattern(int(nq), nme, _ptr(me), _ptr(row_ptr), _ptr(col), cap,
+                                   _ptr(inc_ptr), _ptr(inc), _ptr(inc_pos), _ptr(work),
+                                   int(ws.value), C.byref(nnz), _stream(stream)))
     k = int(nnz.value)
-    return TetPattern(int(nq), nme, k, me, row_ptr, col[:k], cptr[:k + 1], ctb[:cap])
+    return TetPattern(int(nq), nme, k, me, row_ptr, col[:k], inc_ptr, inc[:4 * nme],
+                      inc_pos[:4 * nme])
 
 
 def fem_tet_assemble(pat: TetPattern, q, ops: int = FEM_OP_MASS | FEM_OP_STIFF, *, out=None,
-                     work=None, flags: int = 0, stream=None):
+                     flags: int = 0, stream=None):
     """P1 tetrahedron mass / stiffness values on `pat` (C: fem_tet_assemble).
     q: [nq][3] float64 on the GPU.  Returns {"M": ..., "S": ...} for the
     requested operators."""
@@ -451,14 +459,10 @@ def fem_tet_assemble(pat: TetPattern, q, ops: int = FEM_OP_MASS | FEM_OP_STIFF, 
     for key, bit in (("M", FEM_OP_MASS), ("S", FEM_OP_STIFF)):
         if ops & bit and key not in out:
             out[key] = torch.empty(max(pat.nnz, 1), **f64)[:pat.nnz]
-    if work is None:
-        ws = C.c_size_t(0)
-        _lib.check(lib.fem_tet_assemble_workspace(pat.nme, int(ops), C.byref(ws)))
-        work = torch.empty(max(int(ws.value), 16), dtype=torch.uint8, device=dev)
-    _lib.check(lib.fem_tet_assemble(int(ops), pat.nq, pat.nme, pat.nnz, _ptr(q), _ptr(pat.me),
-                                    _ptr(pat.contrib_ptr), _ptr(pat.contrib), _ptr(out.get("M")),
-                                    _ptr(out.get("S")), _ptr(work), work.numel() * work.element_size(),
-                                    flags, _stream(stream)))
+    _lib.check(lib.fem_tet_assemble(int(ops), pat.nq, pat.nme, pat.nnz, _ptr(q), _ptr(pat.row_ptr),
+                                    _ptr(pat.col_idx), _ptr(pat.inc_ptr), _ptr(pat.inc_pos),
+                                    _ptr(out.get("M")), _ptr(out.get("S")), flags,
+                                    _stream(stream)))
     return out
 
 

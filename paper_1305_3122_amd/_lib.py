@@ -93,11 +93,12 @@ SIGNATURES = {
                           C.c_size_t, C.POINTER(_i64), _vp]),
     "fem_sparse_values": (_int, [_i64, _vp, _vp, _vp, _vp, _int, _vp]),
     "fem_tet_pattern_workspace": (_int, [_i32, _i32, _szp]),
-    "fem_tet_pattern": (_int, [_i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t,
+    "fem_tet_nnz_bound": (_i64, [_i32, _i32]),
+    "fem_tet_pattern": (_int, [_i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, C.c_size_t,
                                C.POINTER(_i64), _vp]),
-    "fem_tet_assemble_workspace": (_int, [_i32, _int, _szp]),
-    "fem_tet_assemble": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                C.c_size_t, _int, _vp]),
+    "fem_tet_pattern_set_path": (_int, [_int]),
+    "fem_tet_assemble": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _int,
+                                _vp]),
     "fem_p2_dofs_workspace": (_int, [_i32, _i32, _szp]),
     "fem_p2_dofs": (_int, [_i32, _i32, _vp, _vp, _vp, _i64, _vp, C.c_size_t, C.POINTER(_i64), _vp]),
     "fem_p2_pattern_workspace": (_int, [_i32, _i32, _szp]),

@@ -123,15 +123,22 @@ def test_extension_size_limits_before_any_launch(lib):
                                None) == _lib.FEM_EOVERFLOW
     big_tet = 140_000_000       # 16 nme > 2^31 - 1
     assert lib.fem_tet_pattern_workspace(10, big_tet, C.byref(ws)) == _lib.FEM_EOVERFLOW
-    assert lib.fem_tet_pattern(10, big_tet, fake, fake, fake, 0, fake, fake, fake, 1 << 20, C.byref(out),
-                               None) == _lib.FEM_EOVERFLOW
+    assert lib.fem_tet_pattern(10, big_tet, fake, fake, fake, 0, fake, fake, fake, fake, 1 << 20,
+                               C.byref(out), None) == _lib.FEM_EOVERFLOW
     assert lib.fem_sparse_workspace(10, 10, 1 << 31, C.byref(ws)) == _lib.FEM_EOVERFLOW
     assert lib.fem_sparse(10, 10, 1 << 31, fake, fake, None, fake, fake, None, 0, None, None, fake,
                           1 << 20, C.byref(out), None) == _lib.FEM_EOVERFLOW
     # and the workspace queries at sizes that fit answer
     assert lib.fem_p2_dofs_workspace(10, 1000, C.byref(ws)) == _lib.FEM_OK and ws.value > 0
-    assert lib.fem_tet_assemble_workspace(1000, 5, C.byref(ws)) == _lib.FEM_OK
-    assert ws.value >= 8 * 11 * 1000
+    assert lib.fem_tet_pattern_workspace(1000, 5000, C.byref(ws)) == _lib.FEM_OK
+    assert ws.value >= 4 * 16 * 5000
+    assert lib.fem_tet_nnz_bound(1000, 5000) == 1000 + 12 * 5000
+    # the tetrahedron values refuse bad operator sets and flags on the host
+    assert lib.fem_tet_assemble(2, 10, 5, 10, fake, fake, fake, fake, fake, fake, fake, 0,
+                                None) == _lib.FEM_EINVAL
+    assert lib.fem_tet_assemble(5, 10, 5, 10, fake, fake, fake, fake, fake, fake, fake,
+                                _lib.FEM_ATOMIC, None) == _lib.FEM_EINVAL
+    assert lib.fem_tet_pattern_set_path(_lib.FEM_PATTERN_ATOMIC) == _lib.FEM_EINVAL
 
 
 def test_python_binding_refuses_cpu_tensors():

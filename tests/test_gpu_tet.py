@@ -1,8 +1,14 @@
 """GPU P1 tetrahedra (mass, stiffness) against the oracle, through the C ABI.
 
-Pattern and contributor lists bit-exact; values within 1e-13 per row (max
-norm): both sides add the same triplets in the same order (ascending t) and
-differ only in the rounding of the element formulas."""
+Pattern bit-exact: row_ptr and col_idx against the oracle's sparse() of the
+16 nme triplets, inc_ptr and inc against the oracle's transpose of me, and
+inc_pos by what it must name (the other three vertices of each tetrahedron,
+in the order a+1, a+2, a+3 mod 4, inside the row).  The bucket path and the
+general path give the same arrays bit for bit and the same values bit for
+bit.  Values within 1e-13 per row (max norm) of the oracle's triplet sums:
+the GPU adds each entry's element terms in ascending tetrahedron order, the
+oracle in ascending triplet order, and the element formulas round
+differently."""
 import numpy as np
 import pytest
 
@@ -30,43 +36,89 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def tet_triplets(me):
-    """Ig, Jg of the 16 local entries, t = r nme + k, r = 4 b + a."""
-    a = np.tile(np.arange(4), 4)
-    b = np.repeat(np.arange(4), 4)
-    return (me[:, a].T.reshape(-1).astype(np.int32), me[:, b].T.reshape(-1).astype(np.int32))
+def _check_inc(pat, me, rp, ci):
+    """inc_ptr / inc equal the oracle's transpose of me; inc_pos names the
+    other three vertices of each tetrahedron inside the row."""
+    nq = pat.nq
+    inc_ptr, inc = oracle.tet_incidence(nq, me)
+    np.testing.assert_array_equal(_np(pat.inc_ptr), inc_ptr)
+    np.testing.assert_array_equal(_np(pat.inc), inc)
+    pos = _np(pat.inc_pos).view(np.uint32).astype(np.int64)
+    assert np.all(pos >> 30 == 0)
+    v = np.repeat(np.arange(nq), np.diff(inc_ptr))
+    k, a = inc // 4, inc % 4
+    rs = rp[v].astype(np.int64)
+    L = (rp[v + 1] - rp[v]).astype(np.int64)
+    for j in (1, 2, 3):
+        p = (pos >> (10 * (j - 1))) & 1023
+        assert np.all(p < L)
+        np.testing.assert_array_equal(ci[rs + p], me[k, (a + j) % 4])
 
 
-def _check(m, contrib=True):
-    pat = fem.fem_tet_pattern(_up(m.me), m.nq)
+def _run(m, path):
+    fem.fem_tet_pattern_set_path(path)
+    try:
+        pat = fem.fem_tet_pattern(_up(m.me), m.nq)
+    finally:
+        fem.fem_tet_pattern_set_path(fem.FEM_PATTERN_AUTO)
     q = _up(m.q)
     both = fem.fem_tet_assemble(pat, q)
     onlyM = fem.fem_tet_assemble(pat, q, fem.FEM_OP_MASS)["M"]
     onlyS = fem.fem_tet_assemble(pat, q, fem.FEM_OP_STIFF)["S"]
     torch.cuda.synchronize()
-    rp, ci, M = oracle.assemble_tet("mass", m.q, m.me)
-    _, _, S = oracle.assemble_tet("stiff", m.q, m.me)
-    assert pat.nnz == ci.shape[0]
-    np.testing.assert_array_equal(_np(pat.row_ptr), rp)
-    np.testing.assert_array_equal(_np(pat.col_idx), ci)
-    if contrib:
-        I, J = tet_triplets(m.me)
-        _, _, pos = oracle.sparse_positions(I, J, m.nq, m.nq)
-        np.testing.assert_array_equal(_np(pat.contrib), np.argsort(pos, kind="stable"))
-        np.testing.assert_array_equal(
-            _np(pat.contrib_ptr), np.concatenate([[0], np.cumsum(np.bincount(pos, minlength=pat.nnz))]))
-    assert row_rel_err(rp, _np(both["M"]), M) <= RTOL_ROW
-    assert row_rel_err(rp, _np(both["S"]), S) <= RTOL_ROW
     # one pass for both operators adds the same terms as the single ones
     assert torch.equal(both["M"], onlyM) and torch.equal(both["S"], onlyS)
     return pat, both
 
 
+def _check(m, paths=(fem.FEM_PATTERN_AUTO, fem.FEM_PATTERN_COARSE)):
+    rp, ci, M = oracle.assemble_tet("mass", m.q, m.me)
+    _, _, S = oracle.assemble_tet("stiff", m.q, m.me)
+    first = None
+    for path in paths:
+        pat, vals = _run(m, path)
+        assert pat.nnz == ci.shape[0]
+        np.testing.assert_array_equal(_np(pat.row_ptr), rp)
+        np.testing.assert_array_equal(_np(pat.col_idx), ci)
+        _check_inc(pat, m.me, rp, ci)
+        assert row_rel_err(rp, _np(vals["M"]), M) <= RTOL_ROW
+        assert row_rel_err(rp, _np(vals["S"]), S) <= RTOL_ROW
+        if first is None:
+            first = (pat, vals)
+        else:
+            # the two groupings: the same arrays, the same sums
+            p0, v0 = first
+            for f in ("row_ptr", "col_idx", "inc_ptr", "inc", "inc_pos"):
+                assert torch.equal(getattr(p0, f), getattr(pat, f)), f
+            assert torch.equal(v0["M"], vals["M"]) and torch.equal(v0["S"], vals["S"])
+    return first
+
+
+def star_mesh(n_ring: int, seed: int = 0):
+    """n_ring tetrahedra (0, 1, r_i, r_{i+1}) around the axis from vertex 0 to
+    vertex 1, closed: vertex 0 lies in n_ring tetrahedra and has n_ring + 1
+    neighbours (rows beyond the LDS slots of the value kernel, and beyond the
+    bucket path's limits once n_ring > 26); vertices relabelled at random."""
+    rng = np.random.default_rng(seed)
+    ang = 2 * np.pi * np.arange(n_ring) / n_ring
+    r = 1.0 + 0.1 * rng.uniform(-1, 1, n_ring)
+    q = np.vstack([[0.0, 0.0, -0.2], [0.0, 0.0, 1.0],
+                   np.column_stack([r * np.cos(ang), r * np.sin(ang), 0.1 * rng.uniform(-1, 1, n_ring)])])
+    me = np.array([[0, 1, 2 + i, 2 + (i + 1) % n_ring] for i in range(n_ring)], np.int32)
+    perm = rng.permutation(q.shape[0])
+    q2 = np.empty_like(q)
+    q2[perm] = q
+    return mg.Mesh(q2, perm[me].astype(np.int32), f"star{n_ring}")
+
+
 def _cases():
     out = [("cube1", mg.unit_cube(1, seed=1)), ("cube3_flat", mg.unit_cube(3, jitter=0.0, seed=2)),
-           ("cube5", mg.unit_cube(5, seed=3)), ("cube12", mg.unit_cube(12, seed=4))]
+           ("cube5", mg.unit_cube(5, seed=3)), ("cube12", mg.unit_cube(12, seed=4)),
+           ("cube9_ordered", mg.unit_cube(9, seed=5, permute=False)),
+           ("star12", star_mesh(12, 1)), ("star20", star_mesh(20, 2)), ("star30", star_mesh(30, 3)),
+           ("star40", star_mesh(40, 4))]
     rng = np.random.default_rng(77)
-    for s in range(3):
+    for s in range(4):
         out.append((f"soup{s}", mg.random_tiny_tet_mesh(np.random.default_rng(rng.integers(1 << 30)), 30)))
     return out
 
@@ -80,10 +132,27 @@ def test_tet_matches_oracle(name, m):
     _check(m)
 
 
+def test_tet_accumulate():
+    m = mg.unit_cube(6, seed=9)
+    print(f"[case] tet accumulate nq={m.nq} nme={m.nme}", flush=True)
+    pat, vals = _run(m, fem.FEM_PATTERN_AUTO)
+    q = _up(m.q)
+    acc = {k: v.clone() for k, v in vals.items()}
+    fem.fem_tet_assemble(pat, q, out=acc, flags=fem.FEM_ACCUMULATE)
+    s = star_mesh(24, 6)                   # a long row takes the global-memory sums
+    ps, vs = _run(s, fem.FEM_PATTERN_AUTO)
+    accs = {k: v.clone() for k, v in vs.items()}
+    fem.fem_tet_assemble(ps, _up(s.q), out=accs, flags=fem.FEM_ACCUMULATE)
+    torch.cuda.synchronize()
+    for k in ("M", "S"):
+        assert torch.equal(acc[k], 2 * vals[k]), k     # x + x = 2 x exactly
+        assert torch.equal(accs[k], 2 * vs[k]), k
+
+
 def test_tet_cube48_full_parity():
     m = mg.unit_cube(48, seed=mg.BASE_SEED + 48)
     print(f"[case] tet cube48 nq={m.nq} nme={m.nme}", flush=True)
-    _check(m, contrib=False)
+    _check(m)
 
 
 def _row_ids(pat):
@@ -91,17 +160,30 @@ def _row_ids(pat):
     return torch.repeat_interleave(torch.arange(pat.nq, device=DEV), rp[1:] - rp[:-1])
 
 
-def test_tet_full_size_properties():
-    # the 128^3 cube (12.6M tetrahedra, 201M triplets): Euler's count of the
-    # entries, the volume, the null space of S and the energy of a linear field
+def _cube128():
+    return mg.unit_cube(128, seed=mg.BASE_SEED + 128)
+
+
+def test_tet_full_size_pattern_and_properties():
+    # the 128^3 cube (12.6M tetrahedra, 50M incidences): inc and inc_pos
+    # against the oracle's transpose of me, Euler's count of the entries, the
+    # volume, the null space of S and the energy of a linear field
     n = 128
-    m = mg.unit_cube(n, seed=mg.BASE_SEED + 128)
+    m = _cube128()
     print(f"[case] tet cube128 nq={m.nq} nme={m.nme}", flush=True)
     pat = fem.fem_tet_pattern(_up(m.me), m.nq)
     vals = fem.fem_tet_assemble(pat, _up(m.q))
     torch.cuda.synchronize()
     edges = 3 * n * (n + 1) ** 2 + 3 * n * n * (n + 1) + n ** 3
     assert pat.nnz == m.nq + 2 * edges
+    rp, ci = _np(pat.row_ptr), _np(pat.col_idx)
+    assert np.all(np.diff(rp) >= 1)
+    # rows ascending and distinct
+    rows_np = np.repeat(np.arange(m.nq), np.diff(rp))
+    same = rows_np[1:] == rows_np[:-1]
+    assert np.all(ci[1:][same] > ci[:-1][same])
+    del rows_np, same
+    _check_inc(pat, m.me, rp, ci)
     M, S = vals["M"], vals["S"]
     assert float(M.sum()) == pytest.approx(1.0, rel=1e-11)
     rows = _row_ids(pat)
@@ -122,9 +204,9 @@ def test_tet_full_size_properties():
 
 
 def test_tet_full_size_sampled_rows():
-    # 32 rows of the 128^3 cube recomputed one by one from the oracle's
+    # 64 rows of the 128^3 cube recomputed one by one from the oracle's
     # element matrices, summed in ascending t = (4 b + a) nme + k
-    m = mg.unit_cube(128, seed=mg.BASE_SEED + 128)
+    m = _cube128()
     print(f"[case] tet cube128 sampled rows nq={m.nq} nme={m.nme}", flush=True)
     pat = fem.fem_tet_pattern(_up(m.me), m.nq)
     vals = fem.fem_tet_assemble(pat, _up(m.q))
@@ -132,10 +214,11 @@ def test_tet_full_size_sampled_rows():
     rp, ci = _np(pat.row_ptr), _np(pat.col_idx)
     Mh, Sh = _np(vals["M"]), _np(vals["S"])
     rng = np.random.default_rng(128)
-    for v in rng.choice(m.nq, 32, replace=False):
-        ks, As = np.nonzero(m.me == v)
+    inc_ptr, inc = oracle.tet_incidence(m.nq, m.me)
+    for v in rng.choice(m.nq, 64, replace=False):
         trip = []
-        for k, a in zip(ks, As):
+        for key in inc[inc_ptr[v]:inc_ptr[v + 1]]:
+            k, a = divmod(int(key), 4)
             x = [m.q[m.me[k, c]] for c in range(4)]
             EM = oracle.elem_tet_mass(abs(oracle.tet_det(*x)) / 6)
             ES = oracle.elem_tet_stiff(*x)
@@ -156,16 +239,27 @@ def test_tet_full_size_sampled_rows():
 
 def test_tet_errors_and_empty():
     q = np.zeros((5, 3))
+    for path in (fem.FEM_PATTERN_AUTO, fem.FEM_PATTERN_COARSE):
+        fem.fem_tet_pattern_set_path(path)
+        try:
+            with pytest.raises(fem.FemError) as e:
+                fem.fem_tet_pattern(_up(np.array([[0, 1, 2, 5]], np.int32)), 5)
+            assert e.value.status == _lib.FEM_ERANGE
+            with pytest.raises(fem.FemError) as e:
+                fem.fem_tet_pattern(_up(np.array([[0, 1, 2, 3], [0, 1, 1, 4]], np.int32)), 5)
+            assert e.value.status == _lib.FEM_EDEGEN
+        finally:
+            fem.fem_tet_pattern_set_path(fem.FEM_PATTERN_AUTO)
     with pytest.raises(fem.FemError) as e:
-        fem.fem_tet_pattern(_up(np.array([[0, 1, 2, 5]], np.int32)), 5)
-    assert e.value.status == _lib.FEM_ERANGE
-    with pytest.raises(fem.FemError) as e:
-        fem.fem_tet_pattern(_up(np.array([[0, 1, 2, 3], [0, 1, 1, 4]], np.int32)), 5)
-    assert e.value.status == _lib.FEM_EDEGEN
+        fem.fem_tet_pattern_set_path(fem.FEM_PATTERN_ATOMIC)
+    assert e.value.status == _lib.FEM_EINVAL
     pat = fem.fem_tet_pattern(torch.zeros((0, 4), dtype=torch.int32, device=DEV), 5)
     vals = fem.fem_tet_assemble(pat, _up(q))
     torch.cuda.synchronize()
     assert pat.nnz == 0 and vals["M"].numel() == 0
     np.testing.assert_array_equal(_np(pat.row_ptr), np.zeros(6, np.int32))
-    # and the library keeps working
-    _check(mg.unit_cube(2, seed=8))
+    np.testing.assert_array_equal(_np(pat.inc_ptr), np.zeros(6, np.int32))
+    # vertices in no tetrahedron have empty rows; and the library keeps working
+    m = mg.unit_cube(2, seed=8)
+    q2 = np.vstack([m.q, np.full((3, 3), 5.0)])
+    _check(mg.Mesh(q2, m.me, "cube2_isolated"))

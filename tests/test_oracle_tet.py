@@ -165,3 +165,32 @@ def test_cube_generator_volumes_and_worst_case_jitter():
         worst = min(worst, np.linalg.det(np.stack([W[:, 1] - W[:, 0], W[:, 2] - W[:, 0],
                                                     W[:, 3] - W[:, 0]], axis=1)).min())
     assert worst >= 0.4 - 1e-12
+
+
+def test_tet_incidence_brute_force_and_kuhn_degrees():
+    # the transpose of me against a per-vertex scan of every (k, a)
+    rng = np.random.default_rng(5)
+    for m in (mg.unit_cube(2, seed=11), mg.random_tiny_tet_mesh(rng, 20),
+              mg.random_tiny_tet_mesh(rng, 30)):
+        inc_ptr, inc = oracle.tet_incidence(m.nq, m.me)
+        assert inc_ptr[0] == 0 and inc_ptr[-1] == 4 * m.nme
+        for v in range(m.nq):
+            want = [4 * k + a for k in range(m.nme) for a in range(4) if m.me[k, a] == v]
+            np.testing.assert_array_equal(inc[inc_ptr[v]:inc_ptr[v + 1]], want)
+    # Kuhn cube: an interior vertex lies in 24 tetrahedra; a corner on the
+    # main diagonal in the 6 of its one cell, and each of the six other
+    # corners in 2 (the monotone paths through it); every vertex's incidences
+    # name it
+    n = 4
+    m = mg.unit_cube(n, jitter=0.0, seed=None, permute=False)
+    inc_ptr, inc = oracle.tet_incidence(m.nq, m.me)
+    deg = np.diff(inc_ptr)
+    idx = np.arange(m.nq)
+    i, j, k = idx % (n + 1), (idx // (n + 1)) % (n + 1), idx // (n + 1) ** 2
+    interior = (i > 0) & (i < n) & (j > 0) & (j < n) & (k > 0) & (k < n)
+    assert np.all(deg[interior] == 24)
+    assert deg[0] == 6 and deg[m.nq - 1] == 6
+    corners = [c for c in range(m.nq) if i[c] in (0, n) and j[c] in (0, n) and k[c] in (0, n)]
+    assert sorted(deg[corners].tolist()) == [2, 2, 2, 2, 2, 2, 6, 6]
+    v_of = np.repeat(idx, deg)
+    np.testing.assert_array_equal(m.me.reshape(-1)[inc], v_of)
