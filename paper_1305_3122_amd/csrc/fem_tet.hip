@@ -527,46 +527,56 @@ struct TetRow {
     double sd, s1, s2, s3;    // stiffness: diagonal, towards x1, x2, x3
 };
 
+// Cross and dot products with explicit fused multiply-adds (the library is
+// built without contraction, so every kernel that calls tet_row rounds the
+// same way).
+__device__ __forceinline__ void cross_fma(const double (&a)[3], const double (&b)[3], double (&o)[3]) {
+    o[0] = fma(a[1], b[2], -(a[2] * b[1]));
+    o[1] = fma(a[2], b[0], -(a[0] * b[2]));
+    o[2] = fma(a[0], b[1], -(a[1] * b[0]));
+}
+
+__device__ __forceinline__ double dot_fma(const double (&a)[3], const double (&b)[3]) {
+    return fma(a[0], b[0], fma(a[1], b[1], a[2] * b[2]));
+}
+
 template <int MASK>
 __device__ __forceinline__ TetRow tet_row(const double (&e1)[3], const double (&e2)[3],
                                           const double (&e3)[3]) {
-    double c1[3], c2[3], c3[3], c0[3];
-    c1[0] = e2[1] * e3[2] - e2[2] * e3[1];
-    c1[1] = e2[2] * e3[0] - e2[0] * e3[2];
-    c1[2] = e2[0] * e3[1] - e2[1] * e3[0];
-    const double D = e1[0] * c1[0] + e1[1] * c1[1] + e1[2] * c1[2];
-    const double aD = fabs(D);
+    double c1[3];
+    cross_fma(e2, e3, c1);
+    const double aD = fabs(dot_fma(e1, c1));
     TetRow r{};
     if constexpr ((MASK & TET_M) != 0) {
-        r.mo = aD / 120.0;
-        r.md = aD / 60.0;
+        r.mo = aD * (1.0 / 120.0);
+        r.md = r.mo + r.mo;
     }
     if constexpr ((MASK & TET_S) != 0) {
-        c2[0] = e3[1] * e1[2] - e3[2] * e1[1];
-        c2[1] = e3[2] * e1[0] - e3[0] * e1[2];
-        c2[2] = e3[0] * e1[1] - e3[1] * e1[0];
-        c3[0] = e1[1] * e2[2] - e1[2] * e2[1];
-        c3[1] = e1[2] * e2[0] - e1[0] * e2[2];
-        c3[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        double c2[3], c3[3], c0[3];
+        cross_fma(e3, e1, c2);
+        cross_fma(e1, e2, c3);
 #pragma unroll
         for (int i = 0; i < 3; ++i) c0[i] = -(c1[i] + c2[i] + c3[i]);
         const double s6 = 1.0 / (6.0 * aD);
-        r.sd = (c0[0] * c0[0] + c0[1] * c0[1] + c0[2] * c0[2]) * s6;
-        r.s1 = (c0[0] * c1[0] + c0[1] * c1[1] + c0[2] * c1[2]) * s6;
-        r.s2 = (c0[0] * c2[0] + c0[1] * c2[1] + c0[2] * c2[2]) * s6;
-        r.s3 = (c0[0] * c3[0] + c0[1] * c3[1] + c0[2] * c3[2]) * s6;
+        r.sd = dot_fma(c0, c0) * s6;
+        r.s1 = dot_fma(c0, c1) * s6;
+        r.s2 = dot_fma(c0, c2) * s6;
+        r.s3 = dot_fma(c0, c3) * s6;
     }
     return r;
 }
 
 constexpr int TROW_LM = 16;   // row slots a lane keeps in LDS
-constexpr int TROW_H = 8;     // loads in flight per lane
+constexpr int TROW_IP = 32;   // tetrahedra per row whose slots are loaded up front
 
 // One lane per row, one wave per workgroup.  LDS: X [LM][3][WAVE] the row's
 // vertices relative to the row's own, A [NA][LM][WAVE] the per-slot sums
-// (through which the wave's rows leave, coalesced).  A row longer than LM is
-// summed by its lane one slot at a time from global memory (same terms, same
-// order, so the same values bit for bit).
+// (through which the wave's rows leave, coalesced).  Three dependent rounds
+// of loads, each issued whole: the row and tetrahedron ranges; the row's
+// vertex ids and its first TROW_IP tetrahedra's slots; the coordinates.
+// The sums then read registers and LDS only.  A row longer than LM is
+// summed by its lane one slot at a time from global memory (same terms,
+// same order, so the same values bit for bit).
 template <int MASK>
 __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__restrict__ q,
                                                    const int32_t *__restrict__ row_ptr,
@@ -605,65 +615,90 @@ __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__r
     auto XA = [&](int p, int c) -> double & { return X[(p * 3 + c) * WAVE + lane]; };
     auto AM = [&](int p) -> double & { return A[MI < 0 ? 0 : MI][p * WAVE + lane]; };
     auto AS = [&](int p) -> double & { return A[SI][p * WAVE + lane]; };
+    // the most tetrahedra of a row summed in LDS, over the wave (all lanes
+    // take part; the others count 0)
+    int32_t dmax = (fast && L > 0) ? d : 0;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, WAVE));
     int32_t pd = 0;
     if (fast && L > 0) {
+        int32_t u[LM];   // unused slots read vertex 0, so that no load branches
 #pragma unroll
-        for (int p0 = 0; p0 < LM; p0 += TROW_H) {
-            if (p0 < L) {
-                int32_t u[TROW_H];
+        for (int p = 0; p < LM; ++p) u[p] = p < L ? col_idx[rs + p] : 0;
+        uint32_t pp[TROW_IP];
 #pragma unroll
-                for (int j = 0; j < TROW_H; ++j) u[j] = p0 + j < L ? col_idx[rs + p0 + j] : v;
-                double y[TROW_H][3];
+        for (int t = 0; t < TROW_IP; ++t) pp[t] = t < d ? inc_pos[is + t] : 0u;
+        // a vertex's three coordinates in two loads (16 + 8 bytes; the
+        // 16-byte one is 8-byte aligned, which global loads accept)
+        double y[LM][3];
 #pragma unroll
-                for (int j = 0; j < TROW_H; ++j)
+        for (int p = 0; p < LM; ++p) {
+            const double *qu = q + 3 * (int64_t)u[p];
+            double2 xy;
+            __builtin_memcpy(&xy, qu, sizeof(double2));
+            y[p][0] = xy.x;
+            y[p][1] = xy.y;
+            y[p][2] = qu[2];
+        }
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) y[j][c] = q[3 * (int64_t)u[j] + c];
+        for (int p = 0; p < LM; ++p) {
+            if (p < L) {
 #pragma unroll
-                for (int j = 0; j < TROW_H; ++j) {
-                    const int p = p0 + j;
-                    if (p < L) {
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) XA(p, c) = y[j][c] - x0[c];
-                        if (u[j] == v) pd = p;
-                        if constexpr (HM) AM(p) = 0.0;
-                        if constexpr (HS) AS(p) = 0.0;
-                    }
-                }
+                for (int c = 0; c < 3; ++c) XA(p, c) = y[p][c] - x0[c];
+                if (u[p] == v) pd = p;
+                if constexpr (HM) AM(p) = 0.0;
+                if constexpr (HS) AS(p) = 0.0;
             }
         }
+        // one step per tetrahedron: its three slots are distinct, so the
+        // six accumulators are read together with the coordinates and
+        // written back together (one LDS round trip); a lane past its last
+        // tetrahedron keeps its values, so that the steps need no branch
+        // and pairs of them can overlap
         double dM = 0.0, dS = 0.0;
-        for (int32_t t0 = 0; t0 < d; t0 += TROW_H) {
-            uint32_t pp[TROW_H];
+        auto step = [&](uint32_t w, bool on) {
+            const int p1 = w & (ROW_MAX - 1), p2 = (w >> POS_BITS) & (ROW_MAX - 1),
+                      p3 = (w >> (2 * POS_BITS)) & (ROW_MAX - 1);
+            double e1[3], e2[3], e3[3];
 #pragma unroll
-            for (int j = 0; j < TROW_H; ++j) pp[j] = t0 + j < d ? inc_pos[is + t0 + j] : 0u;
+            for (int c = 0; c < 3; ++c) {
+                e1[c] = XA(p1, c);
+                e2[c] = XA(p2, c);
+                e3[c] = XA(p3, c);
+            }
+            double m1 = 0.0, m2 = 0.0, m3 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            if constexpr (HM) {
+                m1 = AM(p1);
+                m2 = AM(p2);
+                m3 = AM(p3);
+            }
+            if constexpr (HS) {
+                s1 = AS(p1);
+                s2 = AS(p2);
+                s3 = AS(p3);
+            }
+            const TetRow r = tet_row<MASK>(e1, e2, e3);
+            if constexpr (HM) {
+                dM = on ? dM + r.md : dM;
+                AM(p1) = on ? m1 + r.mo : m1;
+                AM(p2) = on ? m2 + r.mo : m2;
+                AM(p3) = on ? m3 + r.mo : m3;
+            }
+            if constexpr (HS) {
+                dS = on ? dS + r.sd : dS;
+                AS(p1) = on ? s1 + r.s1 : s1;
+                AS(p2) = on ? s2 + r.s2 : s2;
+                AS(p3) = on ? s3 + r.s3 : s3;
+            }
+        };
 #pragma unroll
-            for (int j = 0; j < TROW_H; ++j) {
-                if (t0 + j < d) {
-                    const int p1 = pp[j] & (ROW_MAX - 1), p2 = (pp[j] >> POS_BITS) & (ROW_MAX - 1),
-                              p3 = (pp[j] >> (2 * POS_BITS)) & (ROW_MAX - 1);
-                    double e1[3], e2[3], e3[3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        e1[c] = XA(p1, c);
-                        e2[c] = XA(p2, c);
-                        e3[c] = XA(p3, c);
-                    }
-                    const TetRow r = tet_row<MASK>(e1, e2, e3);
-                    if constexpr (HM) {
-                        dM += r.md;
-                        AM(p1) += r.mo;
-                        AM(p2) += r.mo;
-                        AM(p3) += r.mo;
-                    }
-                    if constexpr (HS) {
-                        dS += r.sd;
-                        AS(p1) += r.s1;
-                        AS(p2) += r.s2;
-                        AS(p3) += r.s3;
-                    }
-                }
+        for (int t = 0; t < TROW_IP; t += 2) {
+            if (t < dmax) {
+                step(pp[t], t < d);
+                step(pp[t + 1], t + 1 < d);
             }
         }
+        for (int32_t t = TROW_IP; t < dmax; ++t) step(t < d ? inc_pos[is + t] : 0u, t < d);
         if constexpr (HM) AM(pd) = dM;
         if constexpr (HS) AS(pd) = dS;
     } else if (!fast) {
@@ -673,17 +708,17 @@ __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__r
         for (int32_t p = 0; p < L; ++p) {
             double sm = 0.0, ss = 0.0;
             for (int32_t t = 0; t < d; ++t) {
-                const uint32_t pp = inc_pos[is + t];
-                const int p1 = pp & (ROW_MAX - 1), p2 = (pp >> POS_BITS) & (ROW_MAX - 1),
-                          p3 = (pp >> (2 * POS_BITS)) & (ROW_MAX - 1);
+                const uint32_t w = inc_pos[is + t];
+                const int p1 = w & (ROW_MAX - 1), p2 = (w >> POS_BITS) & (ROW_MAX - 1),
+                          p3 = (w >> (2 * POS_BITS)) & (ROW_MAX - 1);
                 if (!(p == pd || p == p1 || p == p2 || p == p3)) continue;
                 double e[3][3];
                 const int ps[3] = {p1, p2, p3};
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    const int64_t u = row[ps[i]];
+                    const int64_t uu = row[ps[i]];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) e[i][c] = q[3 * u + c] - x0[c];
+                    for (int c = 0; c < 3; ++c) e[i][c] = q[3 * uu + c] - x0[c];
                 }
                 const TetRow r = tet_row<MASK>(e[0], e[1], e[2]);
                 if (p == pd) {
@@ -698,10 +733,12 @@ __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__r
             if constexpr (HS) vs[rs + p] = accumulate ? vs[rs + p] + ss : ss;
         }
     }
-    __syncthreads();
-    // the wave's rows leave as one contiguous range: entry g belongs to the
+    // the workgroup is one wave, whose LDS accesses complete in program
+    // order: a scheduling barrier orders the sums before the write-out.
+    // The wave's rows leave as one contiguous range: entry g belongs to the
     // last row whose start is <= g (empty rows share the next start); the
     // search reads the starts from the other lanes, all lanes taking part
+    __builtin_amdgcn_wave_barrier();
     const int32_t R0 = __shfl(rsv, 0, WAVE);
     for (int32_t base = R0; base < R1; base += WAVE) {
         const int32_t g = base + lane;
