@@ -569,14 +569,24 @@ __device__ __forceinline__ TetRow tet_row(const double (&e1)[3], const double (&
 constexpr int TROW_LM = 16;   // row slots a lane keeps in LDS
 constexpr int TROW_IP = 32;   // tetrahedra per row whose slots are loaded up front
 
-// One lane per row, one wave per workgroup.  LDS: X [LM][3][WAVE] the row's
-// vertices relative to the row's own, A [NA][LM][WAVE] the per-slot sums
-// (through which the wave's rows leave, coalesced).  Three dependent rounds
-// of loads, each issued whole: the row and tetrahedron ranges; the row's
-// vertex ids and its first TROW_IP tetrahedra's slots; the coordinates.
-// The sums then read registers and LDS only.  A row longer than LM is
-// summed by its lane one slot at a time from global memory (same terms,
-// same order, so the same values bit for bit).
+// What a lane holds of its row in one group of WAVE consecutive rows.
+struct TetRowLoad {
+    int32_t v, rs, L, is, d;
+    double x0[3];
+    int32_t u[TROW_LM];       // the row's vertex ids (unused slots: vertex 0)
+    uint32_t pp[TROW_IP];     // its first tetrahedra's slots
+    double y[TROW_LM][3];     // the coordinates of its vertices
+};
+
+// One lane per row, one wave (a group of WAVE consecutive rows) per
+// workgroup.  LDS: X [LM][3][WAVE] the row's vertices relative to the row's
+// own, A [NA][LM][WAVE] the per-slot sums (through which the group's rows
+// leave, coalesced).  The loads come in three dependent rounds, each issued
+// whole: the row and tetrahedron ranges; the row's vertex ids and its first
+// TROW_IP tetrahedra's slots; the coordinates.  The sums read registers and
+// LDS only.  A row longer than LM is summed by its lane one slot at a time
+// from global memory (same terms, same order, so the same values bit for
+// bit).
 template <int MASK>
 __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__restrict__ q,
                                                    const int32_t *__restrict__ row_ptr,
@@ -586,182 +596,255 @@ __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__r
                                                    double *__restrict__ vm, double *__restrict__ vs,
                                                    int accumulate) {
     constexpr bool HM = (MASK & TET_M) != 0, HS = (MASK & TET_S) != 0;
-    constexpr int LM = TROW_LM;
+    constexpr int LM = TROW_LM, IP = TROW_IP;
     __shared__ double X[LM * 3 * WAVE];
     __shared__ double A[(HM ? 1 : 0) + (HS ? 1 : 0)][LM * WAVE];
     const int lane = threadIdx.x;
-    const int32_t r0 = blockIdx.x * WAVE;
-    const int32_t v = r0 + lane;
-    const bool valid = v < nq;
-    int32_t rs = 0, L = 0, is = 0, d = 0;
-    if (valid) {
-        rs = row_ptr[v];
-        L = row_ptr[v + 1] - rs;
-        is = inc_ptr[v];
-        d = inc_ptr[v + 1] - is;
-    }
-    // the wave's row starts (rows past nq start at the end) and its range
-    const int32_t rsv = valid ? rs : row_ptr[nq];
-    const int32_t R1 = r0 + WAVE < nq ? row_ptr[r0 + WAVE] : row_ptr[nq];
-    const bool fast = L <= LM;
-    const uint64_t longmask = __ballot(!fast);
-    double x0[3] = {0.0, 0.0, 0.0};
-    if (valid) {
-        x0[0] = q[3 * (int64_t)v];
-        x0[1] = q[3 * (int64_t)v + 1];
-        x0[2] = q[3 * (int64_t)v + 2];
-    }
     constexpr int MI = HM ? 0 : -1, SI = (HM && HS) ? 1 : 0;
     auto XA = [&](int p, int c) -> double & { return X[(p * 3 + c) * WAVE + lane]; };
     auto AM = [&](int p) -> double & { return A[MI < 0 ? 0 : MI][p * WAVE + lane]; };
     auto AS = [&](int p) -> double & { return A[SI][p * WAVE + lane]; };
-    // the most tetrahedra of a row summed in LDS, over the wave (all lanes
-    // take part; the others count 0)
-    int32_t dmax = (fast && L > 0) ? d : 0;
+    const int32_t nnz_all = row_ptr[nq], ninc_all = inc_ptr[nq];
+
+    // round 1: ranges and the row's own vertex
+    auto load_head = [&](int32_t r0, TetRowLoad &g) {
+        g.v = r0 + lane;
+        g.rs = g.L = g.is = g.d = 0;
+        g.x0[0] = g.x0[1] = g.x0[2] = 0.0;
+        if (g.v < nq) {
+            g.rs = row_ptr[g.v];
+            g.L = row_ptr[g.v + 1] - g.rs;
+            g.is = inc_ptr[g.v];
+            g.d = inc_ptr[g.v + 1] - g.is;
+            g.x0[0] = q[3 * (int64_t)g.v];
+            g.x0[1] = q[3 * (int64_t)g.v + 1];
+            g.x0[2] = q[3 * (int64_t)g.v + 2];
+        }
+    };
+    // round 2: vertex ids and slots, 16 bytes per load (4-byte aligned,
+    // which global loads accept) where the arrays reach that far
+    auto load_ids = [&](TetRowLoad &g) {
+        const bool on = g.L <= LM && g.L > 0;
+        if (on && g.rs + LM <= nnz_all) {
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, WAVE));
-    int32_t pd = 0;
-    if (fast && L > 0) {
-        int32_t u[LM];   // unused slots read vertex 0, so that no load branches
+            for (int j = 0; j < LM; j += 4) {
+                int4 w;
+                __builtin_memcpy(&w, col_idx + g.rs + j, sizeof(int4));
+                g.u[j] = w.x;
+                g.u[j + 1] = w.y;
+                g.u[j + 2] = w.z;
+                g.u[j + 3] = w.w;
+            }
+        } else {
 #pragma unroll
-        for (int p = 0; p < LM; ++p) u[p] = p < L ? col_idx[rs + p] : 0;
-        uint32_t pp[TROW_IP];
+            for (int p = 0; p < LM; ++p) g.u[p] = (on && p < g.L) ? col_idx[g.rs + p] : 0;
+        }
+        if (on && g.is + IP <= ninc_all) {
 #pragma unroll
-        for (int t = 0; t < TROW_IP; ++t) pp[t] = t < d ? inc_pos[is + t] : 0u;
-        // a vertex's three coordinates in two loads (16 + 8 bytes; the
-        // 16-byte one is 8-byte aligned, which global loads accept)
-        double y[LM][3];
+            for (int j = 0; j < IP; j += 4) {
+                uint4 w;
+                __builtin_memcpy(&w, inc_pos + g.is + j, sizeof(uint4));
+                g.pp[j] = w.x;
+                g.pp[j + 1] = w.y;
+                g.pp[j + 2] = w.z;
+                g.pp[j + 3] = w.w;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < IP; ++t) g.pp[t] = (on && t < g.d) ? inc_pos[g.is + t] : 0u;
+        }
+#pragma unroll
+        for (int p = 0; p < LM; ++p) g.u[p] = (on && p < g.L) ? g.u[p] : 0;
+#pragma unroll
+        for (int t = 0; t < IP; ++t) g.pp[t] = (on && t < g.d) ? g.pp[t] : 0u;
+    };
+    // round 3: a vertex's three coordinates in two loads (16 + 8 bytes; the
+    // 16-byte one is 8-byte aligned), no branch (unused slots read vertex 0)
+    auto load_coords = [&](TetRowLoad &g) {
 #pragma unroll
         for (int p = 0; p < LM; ++p) {
-            const double *qu = q + 3 * (int64_t)u[p];
+            const double *qu = q + 3 * (int64_t)g.u[p];
             double2 xy;
             __builtin_memcpy(&xy, qu, sizeof(double2));
-            y[p][0] = xy.x;
-            y[p][1] = xy.y;
-            y[p][2] = qu[2];
+            g.y[p][0] = xy.x;
+            g.y[p][1] = xy.y;
+            g.y[p][2] = qu[2];
         }
+    };
+
+    // the sums of one group, then its rows out
+    auto run_group = [&](int32_t r0, const TetRowLoad &g) {
+        const bool valid = g.v < nq;
+        const bool fast = g.L <= LM;
+        const uint64_t longmask = __ballot(!fast);
+        const int32_t rsv = valid ? g.rs : nnz_all;   // rows past nq start at the end
+        const int32_t R1 = r0 + WAVE < nq ? row_ptr[r0 + WAVE] : nnz_all;
+        // the most tetrahedra of a row summed in LDS, over the wave (all
+        // lanes take part; the others count 0)
+        int32_t dmax = (fast && g.L > 0) ? g.d : 0;
 #pragma unroll
-        for (int p = 0; p < LM; ++p) {
-            if (p < L) {
+        for (int o = WAVE / 2; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, WAVE));
+        int32_t pd = 0;
+        if (fast && g.L > 0) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) XA(p, c) = y[p][c] - x0[c];
-                if (u[p] == v) pd = p;
-                if constexpr (HM) AM(p) = 0.0;
-                if constexpr (HS) AS(p) = 0.0;
-            }
-        }
-        // one step per tetrahedron: its three slots are distinct, so the
-        // six accumulators are read together with the coordinates and
-        // written back together (one LDS round trip); a lane past its last
-        // tetrahedron keeps its values, so that the steps need no branch
-        // and pairs of them can overlap
-        double dM = 0.0, dS = 0.0;
-        auto step = [&](uint32_t w, bool on) {
-            const int p1 = w & (ROW_MAX - 1), p2 = (w >> POS_BITS) & (ROW_MAX - 1),
-                      p3 = (w >> (2 * POS_BITS)) & (ROW_MAX - 1);
-            double e1[3], e2[3], e3[3];
+            for (int p = 0; p < LM; ++p) {
+                if (p < g.L) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                e1[c] = XA(p1, c);
-                e2[c] = XA(p2, c);
-                e3[c] = XA(p3, c);
+                    for (int c = 0; c < 3; ++c) XA(p, c) = g.y[p][c] - g.x0[c];
+                    if (g.u[p] == g.v) pd = p;
+                    if constexpr (HM) AM(p) = 0.0;
+                    if constexpr (HS) AS(p) = 0.0;
+                }
             }
-            double m1 = 0.0, m2 = 0.0, m3 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            if constexpr (HM) {
-                m1 = AM(p1);
-                m2 = AM(p2);
-                m3 = AM(p3);
-            }
-            if constexpr (HS) {
-                s1 = AS(p1);
-                s2 = AS(p2);
-                s3 = AS(p3);
-            }
-            const TetRow r = tet_row<MASK>(e1, e2, e3);
-            if constexpr (HM) {
-                dM = on ? dM + r.md : dM;
-                AM(p1) = on ? m1 + r.mo : m1;
-                AM(p2) = on ? m2 + r.mo : m2;
-                AM(p3) = on ? m3 + r.mo : m3;
-            }
-            if constexpr (HS) {
-                dS = on ? dS + r.sd : dS;
-                AS(p1) = on ? s1 + r.s1 : s1;
-                AS(p2) = on ? s2 + r.s2 : s2;
-                AS(p3) = on ? s3 + r.s3 : s3;
-            }
-        };
-#pragma unroll
-        for (int t = 0; t < TROW_IP; t += 2) {
-            if (t < dmax) {
-                step(pp[t], t < d);
-                step(pp[t + 1], t + 1 < d);
-            }
-        }
-        for (int32_t t = TROW_IP; t < dmax; ++t) step(t < d ? inc_pos[is + t] : 0u, t < d);
-        if constexpr (HM) AM(pd) = dM;
-        if constexpr (HS) AS(pd) = dS;
-    } else if (!fast) {
-        // long row: slot by slot, the terms of that slot in ascending order
-        const int32_t *row = col_idx + rs;
-        pd = find_in_row(row, L, v);
-        for (int32_t p = 0; p < L; ++p) {
-            double sm = 0.0, ss = 0.0;
-            for (int32_t t = 0; t < d; ++t) {
-                const uint32_t w = inc_pos[is + t];
+            // one step per tetrahedron: its three slots are distinct, so
+            // the six accumulators are read together with the coordinates
+            // and written back together (one LDS round trip); a lane past
+            // its last tetrahedron keeps its values, so that the steps need
+            // no branch and pairs of them can overlap
+            double dM = 0.0, dS = 0.0;
+            auto step = [&](uint32_t w, bool on) {
                 const int p1 = w & (ROW_MAX - 1), p2 = (w >> POS_BITS) & (ROW_MAX - 1),
                           p3 = (w >> (2 * POS_BITS)) & (ROW_MAX - 1);
-                if (!(p == pd || p == p1 || p == p2 || p == p3)) continue;
-                double e[3][3];
-                const int ps[3] = {p1, p2, p3};
+                double e1[3], e2[3], e3[3];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const int64_t uu = row[ps[i]];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) e[i][c] = q[3 * uu + c] - x0[c];
+                for (int c = 0; c < 3; ++c) {
+                    e1[c] = XA(p1, c);
+                    e2[c] = XA(p2, c);
+                    e3[c] = XA(p3, c);
                 }
-                const TetRow r = tet_row<MASK>(e[0], e[1], e[2]);
-                if (p == pd) {
-                    sm += r.md;
-                    ss += r.sd;
-                } else {
-                    sm += r.mo;
-                    ss += p == p1 ? r.s1 : (p == p2 ? r.s2 : r.s3);
+                double m1 = 0.0, m2 = 0.0, m3 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                if constexpr (HM) {
+                    m1 = AM(p1);
+                    m2 = AM(p2);
+                    m3 = AM(p3);
+                }
+                if constexpr (HS) {
+                    s1 = AS(p1);
+                    s2 = AS(p2);
+                    s3 = AS(p3);
+                }
+                const TetRow r = tet_row<MASK>(e1, e2, e3);
+                if constexpr (HM) {
+                    dM = on ? dM + r.md : dM;
+                    AM(p1) = on ? m1 + r.mo : m1;
+                    AM(p2) = on ? m2 + r.mo : m2;
+                    AM(p3) = on ? m3 + r.mo : m3;
+                }
+                if constexpr (HS) {
+                    dS = on ? dS + r.sd : dS;
+                    AS(p1) = on ? s1 + r.s1 : s1;
+                    AS(p2) = on ? s2 + r.s2 : s2;
+                    AS(p3) = on ? s3 + r.s3 : s3;
+                }
+            };
+#pragma unroll
+            for (int t = 0; t < IP; t += 2) {
+                if (t < dmax) {
+                    step(g.pp[t], t < g.d);
+                    step(g.pp[t + 1], t + 1 < g.d);
                 }
             }
-            if constexpr (HM) vm[rs + p] = accumulate ? vm[rs + p] + sm : sm;
-            if constexpr (HS) vs[rs + p] = accumulate ? vs[rs + p] + ss : ss;
-        }
-    }
-    // the workgroup is one wave, whose LDS accesses complete in program
-    // order: a scheduling barrier orders the sums before the write-out.
-    // The wave's rows leave as one contiguous range: entry g belongs to the
-    // last row whose start is <= g (empty rows share the next start); the
-    // search reads the starts from the other lanes, all lanes taking part
-    __builtin_amdgcn_wave_barrier();
-    const int32_t R0 = __shfl(rsv, 0, WAVE);
-    for (int32_t base = R0; base < R1; base += WAVE) {
-        const int32_t g = base + lane;
-        int lo = 0;
+            for (int32_t t = IP; t < dmax; ++t) step(t < g.d ? inc_pos[g.is + t] : 0u, t < g.d);
+            if constexpr (HM) AM(pd) = dM;
+            if constexpr (HS) AS(pd) = dS;
+        } else if (!fast) {
+            // long row: slot by slot, the terms of that slot in ascending order
+            const int32_t *row = col_idx + g.rs;
+            pd = find_in_row(row, g.L, g.v);
+            for (int32_t p = 0; p < g.L; ++p) {
+                double sm = 0.0, ss = 0.0;
+                for (int32_t t = 0; t < g.d; ++t) {
+                    const uint32_t w = inc_pos[g.is + t];
+                    const int p1 = w & (ROW_MAX - 1), p2 = (w >> POS_BITS) & (ROW_MAX - 1),
+                              p3 = (w >> (2 * POS_BITS)) & (ROW_MAX - 1);
+                    if (!(p == pd || p == p1 || p == p2 || p == p3)) continue;
+                    double e[3][3];
+                    const int ps[3] = {p1, p2, p3};
 #pragma unroll
-        for (int step = WAVE / 2; step > 0; step >>= 1) {
-            const int cand = lo + step;
-            const int32_t sc = __shfl(rsv, cand < WAVE ? cand : WAVE - 1, WAVE);
-            if (cand < WAVE && sc <= g) lo = cand;
+                    for (int i = 0; i < 3; ++i) {
+                        const int64_t uu = row[ps[i]];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) e[i][c] = q[3 * uu + c] - g.x0[c];
+                    }
+                    const TetRow r = tet_row<MASK>(e[0], e[1], e[2]);
+                    if (p == pd) {
+                        sm += r.md;
+                        ss += r.sd;
+                    } else {
+                        sm += r.mo;
+                        ss += p == p1 ? r.s1 : (p == p2 ? r.s2 : r.s3);
+                    }
+                }
+                if constexpr (HM) vm[g.rs + p] = accumulate ? vm[g.rs + p] + sm : sm;
+                if constexpr (HS) vs[g.rs + p] = accumulate ? vs[g.rs + p] + ss : ss;
+            }
         }
-        // every lane reads its row's start before any lane leaves the pass
-        const int32_t rlo = __shfl(rsv, lo, WAVE);
-        const int p = g - rlo;
-        if (g >= R1 || ((longmask >> lo) & 1u) || p >= LM) continue;
-        if constexpr (HM) {
-            const double a = A[MI < 0 ? 0 : MI][p * WAVE + lo];
-            vm[g] = accumulate ? vm[g] + a : a;
+        // the workgroup is one wave, whose LDS accesses complete in program
+        // order: a scheduling barrier orders the sums before the write-out.
+        // The group's rows leave as one contiguous range.
+        __builtin_amdgcn_wave_barrier();
+        const int32_t R0 = __shfl(rsv, 0, WAVE);
+        auto put = [&](int32_t e, int o, int p) {
+            if constexpr (HM) {
+                const double a = A[MI < 0 ? 0 : MI][p * WAVE + o];
+                vm[e] = accumulate ? vm[e] + a : a;
+            }
+            if constexpr (HS) {
+                const double a = A[SI][p * WAVE + o];
+                vs[e] = accumulate ? vs[e] + a : a;
+            }
+        };
+        if (longmask == 0) {
+            // every row of the group has at most LM entries (the range at
+            // most LM * WAVE): each lane copies its sums in CSR order into
+            // the coordinate LDS (no longer needed), and the range is then
+            // written in order; both sides touch consecutive words
+            constexpr int NA = (HM ? 1 : 0) + (HS ? 1 : 0);
+            double *T = X;   // [NA][LM * WAVE]
+            for (int p = 0; p < g.L; ++p) {
+                if constexpr (HM) T[g.rs - R0 + p] = AM(p);
+                if constexpr (HS) T[(NA - 1) * LM * WAVE + g.rs - R0 + p] = AS(p);
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int32_t e = R0 + lane; e < R1; e += WAVE) {
+                if constexpr (HM) {
+                    const double a = T[e - R0];
+                    vm[e] = accumulate ? vm[e] + a : a;
+                }
+                if constexpr (HS) {
+                    const double a = T[(NA - 1) * LM * WAVE + e - R0];
+                    vs[e] = accumulate ? vs[e] + a : a;
+                }
+            }
+        } else {
+            // entry e belongs to the last row whose start is <= e (empty
+            // rows share the next start); the search reads the starts from
+            // the other lanes, all lanes taking part
+            for (int32_t base = R0; base < R1; base += WAVE) {
+                const int32_t e = base + lane;
+                int lo = 0;
+#pragma unroll
+                for (int stp = WAVE / 2; stp > 0; stp >>= 1) {
+                    const int cand = lo + stp;
+                    const int32_t sc = __shfl(rsv, cand < WAVE ? cand : WAVE - 1, WAVE);
+                    if (cand < WAVE && sc <= e) lo = cand;
+                }
+                // every lane reads its row's start before any lane leaves the pass
+                const int32_t rlo = __shfl(rsv, lo, WAVE);
+                const int p = e - rlo;
+                if (e >= R1 || ((longmask >> lo) & 1u) || p >= LM) continue;
+                put(e, lo, p);
+            }
         }
-        if constexpr (HS) {
-            const double a = A[SI][p * WAVE + lo];
-            vs[g] = accumulate ? vs[g] + a : a;
-        }
-    }
+        __builtin_amdgcn_wave_barrier();   // the rows have left LDS
+    };
+
+    const int32_t r0 = blockIdx.x * WAVE;
+    TetRowLoad g;
+    load_head(r0, g);
+    load_ids(g);
+    load_coords(g);
+    run_group(r0, g);
 }
 
 // ------------------------------------------------------------------ workspace
