@@ -32,6 +32,8 @@
 // lengths and k_copy_cols.  Beyond 4096 * HIST_MAX (about 151M) vertices the
 // grouping is a global-atomic count and fill (k_count, k_fill) instead.
 //   slot    one lane per triangle: binary search of its 9 entries
+#include <type_traits>
+
 #include "fem_internal.h"
 
 namespace fem {
@@ -435,6 +437,25 @@ __device__ __forceinline__ void bitonic_sort(int32_t (&k)[N]) {
             }
 }
 
+// Sorting network over unsigned words (ascending).
+template <int N, typename T>
+__device__ __forceinline__ void bitonic_sort_u(T (&k)[N]) {
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ stride;
+                if (l > i) {
+                    const bool up = (i & size) == 0;
+                    const T a = k[i], b = k[l];
+                    k[i] = up ? (a < b ? a : b) : (a < b ? b : a);
+                    k[l] = up ? (a < b ? b : a) : (a < b ? a : b);
+                }
+            }
+}
+
 // Triangles per vertex handled entirely in registers by k_rows.
 constexpr int REG_MAX = 8;
 
@@ -521,8 +542,14 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
     // ---- 3 per vertex: triangles by id, distinct neighbours, row length
     bool bad = !fits;
     int32_t L = 0;
-    int32_t key[REG_MAX], n1[REG_MAX], n2[REG_MAX], c[2 * REG_MAX];
-    bool f[2 * REG_MAX];
+    // register path (d <= REG_MAX): candidate words (neighbour << 4 |
+    // origin), origin 2 t or 2 t + 1 for the first or second neighbour of
+    // slice entry t; sorted, equal neighbours are adjacent and fm flags the
+    // first of each
+    using CW = typename std::conditional<PK, uint32_t, uint64_t>::type;
+    constexpr CW CW_NONE = ~CW(0);
+    CW c[2 * REG_MAX];
+    uint32_t fm = 0;
     // LDS path (REG_MAX < d <= FINE_DMAX): candidate u is entry u % 2 of the
     // neighbour pair of triangle u / 2; m0, m1 flag the first occurrences
     uint64_t m0 = 0, m1 = 0;
@@ -533,12 +560,6 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
         for (int u = 0; u < 2 * d; ++u) r += (first(u) && cand(u) < y) ? 1 : 0;
         return r;
     };
-    auto reg_rank = [&](int32_t y) {
-        int32_t r = (int32_t)v < y ? 1 : 0;
-#pragma unroll
-        for (int k = 0; k < 2 * REG_MAX; ++k) r += (f[k] && c[k] < y) ? 1 : 0;
-        return r;
-    };
     if (!fits || v >= nq) {
         d = 0;
     }
@@ -546,35 +567,54 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
     if (in_regs) {
 #pragma unroll
         for (int t = 0; t < REG_MAX; ++t) {
-            key[t] = n1[t] = n2[t] = INT32_MAX;
+            c[2 * t] = c[2 * t + 1] = CW_NONE;
             if (t < d) {
-                key[t] = s_key[is + t];
-                n1[t] = s_n1[is + t];
-                n2[t] = s_n2[is + t];
+                c[2 * t] = ((CW)s_n1[is + t] << 4) | (CW)(2 * t);
+                c[2 * t + 1] = ((CW)s_n2[is + t] << 4) | (CW)(2 * t + 1);
             }
         }
-        bitonic_sort_kv<REG_MAX>(key, n1, n2);
-#pragma unroll
-        for (int t = 0; t < REG_MAX; ++t) {
-            c[2 * t] = n1[t];
-            c[2 * t + 1] = n2[t];
-        }
-        bitonic_sort<2 * REG_MAX>(c);
+        bitonic_sort_u<2 * REG_MAX>(c);
+        // a candidate's distinct index is the running count of first
+        // occurrences; its row position adds 1 past v; each origin's
+        // position goes back to the slice (first neighbour to s_n1, second
+        // to s_n2: both have been read)
         int32_t nd = 0;
 #pragma unroll
         for (int k = 0; k < 2 * REG_MAX; ++k) {
-            f[k] = c[k] != INT32_MAX && (k == 0 || c[k] != c[k - 1]);
-            nd += f[k] ? 1 : 0;
+            if (c[k] != CW_NONE) {
+                const int32_t y = (int32_t)(c[k] >> 4);
+                const bool f = k == 0 || y != (int32_t)(c[k - 1] >> 4);
+                fm |= f ? 1u << k : 0u;
+                nd += f ? 1 : 0;
+                const int o = (int)(c[k] & 15u);
+                const int32_t pos = nd - 1 + (y > (int32_t)v ? 1 : 0);
+                if (o & 1) s_n2[is + (o >> 1)] = pos;
+                else s_n1[is + (o >> 1)] = pos;
+            }
         }
         L = d > 0 ? nd + 1 : 0;
-        // sorted triangles and the positions of their two neighbours in the
-        // row, back into the vertex's own LDS slice (copied out in step 5)
+        // the triangles by id (words key << 3 | slice entry), and their
+        // position pairs, back into the vertex's own LDS slice in that order
+        // (copied out in step 5)
+        uint64_t kt[REG_MAX];
 #pragma unroll
         for (int t = 0; t < REG_MAX; ++t)
-            if (t < d) {
-                s_key[is + t] = key[t];
-                s_n1[is + t] = static_cast<int32_t>(static_cast<uint32_t>(reg_rank(n1[t])) |
-                                                    (static_cast<uint32_t>(reg_rank(n2[t])) << 16));
+            kt[t] = t < d ? ((uint64_t)(uint32_t)s_key[is + t] << 3) | (uint64_t)t : ~uint64_t(0);
+        bitonic_sort_u<REG_MAX>(kt);
+        uint32_t pk[REG_MAX];
+#pragma unroll
+        for (int j = 0; j < REG_MAX; ++j) {
+            pk[j] = 0;
+            if (j < d) {
+                const int t = (int)(kt[j] & 7u);
+                pk[j] = (uint32_t)s_n1[is + t] | ((uint32_t)s_n2[is + t] << 16);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < REG_MAX; ++j)
+            if (j < d) {
+                s_key[is + j] = (int32_t)(kt[j] >> 3);
+                s_n1[is + j] = (int32_t)pk[j];
             }
     } else if (d <= FINE_DMAX) {
         // insertion sort of the vertex's LDS slice by triangle
@@ -632,12 +672,13 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
             bool vdone = false;
 #pragma unroll
             for (int k = 0; k < 2 * REG_MAX; ++k) {
-                if (f[k]) {
-                    if (!vdone && c[k] > (int32_t)v) {
+                if ((fm >> k) & 1u) {
+                    const int32_t y = (int32_t)(c[k] >> 4);
+                    if (!vdone && y > (int32_t)v) {
                         out[below] = (int32_t)v;
                         vdone = true;
                     }
-                    out[below + (vdone ? 1 : 0)] = c[k];
+                    out[below + (vdone ? 1 : 0)] = y;
                     ++below;
                 }
             }
