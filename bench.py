@@ -175,7 +175,7 @@ PROFILE_RUNS = {
     "step_square2048": ("step", "--steps 5 --warmup 1 --no-cpu --no-extras --calib"),
     "sparse_optv2_square2048": ("sparse", "--only sparse --calib"),
     "p2_square2048": ("p2", "--only p2 --calib"),
-    "tet_cube128": ("tet", "--only tet --calib"),
+    "tet_cube128": ("tet", "--only tet --no-local --calib"),
     "adjoint_square512": ("adjoint", "--only adjoint --calib"),
     "batched_512meshes": ("batched", "--only batched --calib"),
 }
@@ -859,17 +859,19 @@ def run_tet(torch, fem, args):
     ta = timed(assemble, 10)
     # context: the same cube without the random relabelling (vertex ids in
     # grid order, so a row's neighbours are near it in memory)
-    mo = mg.unit_cube(n, seed=mg.BASE_SEED + 128, permute=False)
-    me_o = torch.from_numpy(mo.me).to(dev)
-    q_o = torch.from_numpy(mo.q).to(dev)
-    pat_o = fem.fem_tet_pattern(me_o, mo.nq)
-    vo = fem.fem_tet_assemble(pat_o, q_o)
+    ta_o = None
+    if not getattr(args, "no_local", False):
+        mo = mg.unit_cube(n, seed=mg.BASE_SEED + 128, permute=False)
+        me_o = torch.from_numpy(mo.me).to(dev)
+        q_o = torch.from_numpy(mo.q).to(dev)
+        pat_o = fem.fem_tet_pattern(me_o, mo.nq)
+        vo = fem.fem_tet_assemble(pat_o, q_o)
 
-    def assemble_o():
-        fem.fem_tet_assemble(pat_o, q_o, out=vo)
+        def assemble_o():
+            fem.fem_tet_assemble(pat_o, q_o, out=vo)
 
-    ta_o = timed(assemble_o, 10)
-    del pat_o, vo, me_o, q_o
+        ta_o = timed(assemble_o, 10)
+        del pat_o, vo, me_o, q_o
     # design bytes of the row kernel: q (24 per vertex), row_ptr and inc_ptr
     # (8 per vertex), col_idx (4 per entry), inc_pos (4 per incidence, 16 per
     # tetrahedron), M and S (16 per entry)
@@ -880,9 +882,10 @@ def run_tet(torch, fem, args):
            "assemble_us": round(ta, 1), "Mtets_per_s_assemble": round(m.nme / ta, 1),
            "Mtets_per_s_total": round(m.nme / (tp + ta), 1),
            "assemble_alg_bytes": alg, "assemble_alg_GBps": round(alg / (ta * 1e-6) / 1e9, 1),
-           "assemble_us_unrelabelled": round(ta_o, 1)}
+           "assemble_us_unrelabelled": None if ta_o is None else round(ta_o, 1)}
     log(f"[bench] tet cube128 nme={m.nme}: pattern {tp:.0f}us, mass+stiffness {ta:.0f}us "
-        f"({m.nme / ta:.0f} Mtets/s); unrelabelled mass+stiffness {ta_o:.0f}us")
+        f"({m.nme / ta:.0f} Mtets/s); unrelabelled mass+stiffness "
+        + ("skipped" if ta_o is None else f"{ta_o:.0f}us"))
     return out
 
 
@@ -1042,6 +1045,8 @@ def main():
                     help="command text recorded by --summarize (default: that of the profile)")
     ap.add_argument("--profile-name", default="step_square2048", choices=sorted(PROFILE_TITLES),
                     help="which summary --summarize writes")
+    ap.add_argument("--no-local", action="store_true",
+                    help="tetrahedra: skip the unrelabelled cube (profiles of the relabelled one)")
     ap.add_argument("--only", choices=("sparse", "adjoint", "batched", "tet", "p2"),
                     help="run one of the extra measurements alone and print its JSON (profiling)")
     args = ap.parse_args()

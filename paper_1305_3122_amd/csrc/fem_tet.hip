@@ -227,7 +227,11 @@ __global__ __launch_bounds__(TB_V) void k_tbkt_rows(int32_t nq, int32_t nbkt, in
                                                    int32_t *__restrict__ btot,
                                                    int32_t *__restrict__ stage, PatternCounters *cnt) {
     __shared__ int32_t s_cur[TB_V];
-    __shared__ int32_t s_key[TB_CAP], s_n1[TB_CAP], s_n2[TB_CAP], s_n3[TB_CAP];
+    // the vertices' slices of the records, each slice start moved on by the
+    // vertex's index (one word of padding per vertex): slices of about 24
+    // words would otherwise start on a few banks only
+    __shared__ int32_t s_key[TB_CAP + TB_V], s_n1[TB_CAP + TB_V], s_n2[TB_CAP + TB_V],
+        s_n3[TB_CAP + TB_V];
     __shared__ uint32_t s_hash[TB_HS * TB_V];   // [slot][vertex]
     __shared__ int32_t s_wsum[TB_V / WAVE];
     const int tid = threadIdx.x;
@@ -254,7 +258,8 @@ __global__ __launch_bounds__(TB_V) void k_tbkt_rows(int32_t nq, int32_t nbkt, in
     int32_t d = s_cur[tid];
     int32_t unused;
     const int32_t is = tb_block_scan(d, s_wsum, &unused);
-    s_cur[tid] = is;
+    const int32_t js = is + tid;   // the slice in LDS (padded)
+    s_cur[tid] = js;
     if (v < nq) inc_ptr[v] = static_cast<int32_t>(e0) + is;
     if (b == nbkt - 1 && tid == 0) inc_ptr[nq] = static_cast<int32_t>(total);
     __syncthreads();
@@ -295,9 +300,9 @@ __global__ __launch_bounds__(TB_V) void k_tbkt_rows(int32_t nq, int32_t nbkt, in
     };
     if (!bad) {
         for (int t = 0; t < d && !bad; ++t) {
-            insert(s_n1[is + t]);
-            insert(s_n2[is + t]);
-            insert(s_n3[is + t]);
+            insert(s_n1[js + t]);
+            insert(s_n2[js + t]);
+            insert(s_n3[js + t]);
         }
     }
     if (bad) atomicOr(&cnt->err, TERR_BUCKET);
@@ -342,7 +347,7 @@ __global__ __launch_bounds__(TB_V) void k_tbkt_rows(int32_t nq, int32_t nbkt, in
         };
         // each tetrahedron's slots, packed into its record's first neighbour
         for (int t = 0; t < d; ++t) {
-            const int j = is + t;
+            const int j = js + t;
             s_n1[j] = (int32_t)(slot_of(s_n1[j]) | (slot_of(s_n2[j]) << POS_BITS) |
                                 (slot_of(s_n3[j]) << (2 * POS_BITS)));
         }
@@ -350,14 +355,14 @@ __global__ __launch_bounds__(TB_V) void k_tbkt_rows(int32_t nq, int32_t nbkt, in
         uint32_t sk[TB_DMAX];
 #pragma unroll
         for (int t = 0; t < TB_DMAX; ++t)
-            sk[t] = t < d ? ((uint32_t)(s_key[is + t] >> 2) << 5) | (uint32_t)t : HASH_EMPTY;
+            sk[t] = t < d ? ((uint32_t)(s_key[js + t] >> 2) << 5) | (uint32_t)t : HASH_EMPTY;
         bitonic_sort_u32<TB_DMAX>(sk);
         // the sorted order goes to the vertex's hash slots, no longer needed
 #pragma unroll
         for (int t = 0; t < TB_DMAX; ++t) hs[t * TB_V] = sk[t];
         const int64_t ib = e0 + is;
         for (int t = 0; t < d; ++t) {
-            const int j = is + (int)(hs[t * TB_V] & 31u);
+            const int j = js + (int)(hs[t * TB_V] & 31u);
             inc[ib + t] = s_key[j];
             inc_pos[ib + t] = (uint32_t)s_n1[j];
         }
