@@ -562,7 +562,12 @@ __device__ __forceinline__ TetRow tet_row(const double (&e1)[3], const double (&
         cross_fma(e1, e2, c3);
 #pragma unroll
         for (int i = 0; i < 3; ++i) c0[i] = -(c1[i] + c2[i] + c3[i]);
-        const double s6 = 1.0 / (6.0 * aD);
+        // 1 / (6 |D|): the hardware reciprocal and two Newton-Raphson steps
+        // (e = 1 - x r, r += r e), to within an ulp or two of the quotient
+        const double x6 = 6.0 * aD;
+        double s6 = __builtin_amdgcn_rcp(x6);
+        s6 = fma(s6, fma(-x6, s6, 1.0), s6);
+        s6 = fma(s6, fma(-x6, s6, 1.0), s6);
         r.sd = dot_fma(c0, c0) * s6;
         r.s1 = dot_fma(c0, c1) * s6;
         r.s2 = dot_fma(c0, c2) * s6;
@@ -703,11 +708,15 @@ __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__r
             }
             // one step per tetrahedron: its three slots are distinct, so
             // the six accumulators are read together with the coordinates
-            // and written back together (one LDS round trip); a lane past
-            // its last tetrahedron keeps its values, so that the steps need
-            // no branch and pairs of them can overlap
+            // and written back together (one LDS round trip).  A lane past
+            // its last tetrahedron steps on the diagonal slot, whose sum is
+            // overwritten at the end (only the diagonal sums keep their
+            // values), so that the steps need no branch and pairs of them
+            // can overlap
+            const uint32_t wpd = (uint32_t)pd | ((uint32_t)pd << POS_BITS) | ((uint32_t)pd << (2 * POS_BITS));
             double dM = 0.0, dS = 0.0;
             auto step = [&](uint32_t w, bool on) {
+                w = on ? w : wpd;
                 const int p1 = w & (ROW_MAX - 1), p2 = (w >> POS_BITS) & (ROW_MAX - 1),
                           p3 = (w >> (2 * POS_BITS)) & (ROW_MAX - 1);
                 double e1[3], e2[3], e3[3];
@@ -731,15 +740,15 @@ __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__r
                 const TetRow r = tet_row<MASK>(e1, e2, e3);
                 if constexpr (HM) {
                     dM = on ? dM + r.md : dM;
-                    AM(p1) = on ? m1 + r.mo : m1;
-                    AM(p2) = on ? m2 + r.mo : m2;
-                    AM(p3) = on ? m3 + r.mo : m3;
+                    AM(p1) = m1 + r.mo;
+                    AM(p2) = m2 + r.mo;
+                    AM(p3) = m3 + r.mo;
                 }
                 if constexpr (HS) {
                     dS = on ? dS + r.sd : dS;
-                    AS(p1) = on ? s1 + r.s1 : s1;
-                    AS(p2) = on ? s2 + r.s2 : s2;
-                    AS(p3) = on ? s3 + r.s3 : s3;
+                    AS(p1) = s1 + r.s1;
+                    AS(p2) = s2 + r.s2;
+                    AS(p3) = s3 + r.s3;
                 }
             };
 #pragma unroll
