@@ -145,9 +145,9 @@ PROFILE_TITLES = {
     "p2_square2048": ("P2 triangles on the 2048x2048-cell unit square",
                       "Workload: 8,388,608 triangles, 4,198,401 vertices + 12,587,008 edges = 16,785,409\n"
                       "P2 DOFs (jitter 0.2h, random vertex relabelling), nnz 192,970,753; 5 edge\n"
-                      "numberings (25.2M side triplets), 6 patterns (302M triplets), 11 mass + stiffness\n"
-                      "assemblies; FP64 values, int32 indices.  The 1 GiB fill and copy calibrate the\n"
-                      "counters."),
+                      "numberings (25.2M side triplets), 6 patterns (302M triplets, then the triangles\n"
+                      "of every DOF), 11 mass + stiffness assemblies (one lane per DOF row); FP64\n"
+                      "values, int32 indices.  The 1 GiB fill and copy calibrate the counters."),
     "tet_cube128": ("P1 tetrahedra on the 128^3-cell unit cube",
                     "Workload: 12,582,912 Kuhn tetrahedra, 2,146,689 vertices (jitter 0.1h, random\n"
                     "relabelling), nnz 31,802,497; 5 patterns (50.3M incidences in 128-vertex\n"
@@ -919,14 +919,15 @@ def run_p2(torch, fem, args):
     cap = ndof + 30 * m.nme
     row_ptr = torch.empty(ndof + 1, **i32)
     col = torch.empty(cap, **i32)
-    cptr = torch.empty(cap + 1, **i32)
-    ctb = torch.empty(36 * m.nme, **i32)
+    inc_ptr = torch.empty(ndof + 1, **i32)
+    inc = torch.empty(6 * m.nme, **i32)
+    inc_pos = torch.empty(6 * m.nme, dtype=torch.int64, device=dev)
     nnz = C.c_int64(0)
 
     def pattern():
         fem._lib.check(lib.fem_p2_pattern(ndof, m.nme, dofs.data_ptr(), row_ptr.data_ptr(), col.data_ptr(),
-                                          cap, cptr.data_ptr(), ctb.data_ptr(), pwork.data_ptr(),
-                                          int(pw.value), C.byref(nnz), s))
+                                          cap, inc_ptr.data_ptr(), inc.data_ptr(), inc_pos.data_ptr(),
+                                          pwork.data_ptr(), int(pw.value), C.byref(nnz), s))
 
     pattern()
     k = int(nnz.value)
@@ -938,8 +939,9 @@ def run_p2(torch, fem, args):
     S = torch.empty_like(M)
 
     def assemble():
-        fem._lib.check(lib.fem_p2_assemble(ops, m.nq, m.nme, k, q.data_ptr(), me.data_ptr(),
-                                           cptr.data_ptr(), ctb.data_ptr(), M.data_ptr(), S.data_ptr(),
+        fem._lib.check(lib.fem_p2_assemble(ops, m.nq, m.nme, ndof, k, q.data_ptr(), me.data_ptr(),
+                                           row_ptr.data_ptr(), inc_ptr.data_ptr(), inc.data_ptr(),
+                                           inc_pos.data_ptr(), M.data_ptr(), S.data_ptr(),
                                            awork.data_ptr(), awork.numel(), 0, s))
 
     def timed(fn, reps):
@@ -963,9 +965,10 @@ def run_p2(torch, fem, args):
     ta = timed(assemble, 10)
     # inputs once (me, q), outputs once (two value arrays)
     alg = 12 * m.nme + 16 * m.nq + 16 * k
-    # plus what the contributor design reads: contrib, contrib_ptr, the four
-    # numbers per triangle (written once, read back)
-    design = alg + 4 * 36 * m.nme + 4 * (k + 1) + 2 * 32 * m.nme
+    # plus what the row design reads: row_ptr and inc_ptr (8 per DOF), inc and
+    # inc_pos (12 per incidence, 72 per triangle), the four numbers per
+    # triangle (written once, read back once per incidence: 6 x 32 B)
+    design = alg + 8 * ndof + 72 * m.nme + 32 * m.nme + 6 * 32 * m.nme
     out = {"workload": "unit square 2048x2048 cells (8.4M triangles, jitter 0.2h, random relabelling); "
                        "P2 Lagrange, DOFs = vertices + edges; mass + stiffness FP64",
            "nq": m.nq, "ne": int(ne.value), "ndof": ndof, "nme": m.nme, "nnz": k,

@@ -471,20 +471,27 @@ int fem_p2_dofs(int32_t nq, int32_t nme, const int32_t *me, int32_t *dofs, int32
 /* HOST ONLY.  Bytes of device workspace fem_p2_pattern needs. */
 int fem_p2_pattern_workspace(int32_t ndof, int32_t nme, size_t *bytes /* HOST */);
 
-/* Pattern of the P2 matrices over ndof = nq + ne DOFs, built the OptV2 way:
- * the index arrays of all 36 local entries, triplet t = r nme + k for entry
- * r = 6 b + a of element k (row dofs[k][a], column dofs[k][b]), compressed by
- * fem_sparse.
+/* Pattern of the P2 matrices over ndof = nq + ne DOFs: the CSR pattern of
+ * sparse(Ig, Jg, .) over the 36 local entries of every element (Section 6;
+ * entry (a, b) of element k at row dofs[k][a], column dofs[k][b]), and per
+ * DOF its triangles with the row slots of their six DOFs, which is what
+ * fem_p2_assemble reads.
  *   dofs [nme][6] int32 from fem_p2_dofs (8-byte aligned)
  *   row_ptr [ndof+1], col_idx [col_cap]; nnz <= ndof + 30 nme
- *   contrib_ptr [col_cap+1], contrib [36 nme]: the triplets of each entry,
- *                ascending (what fem_p2_assemble sums)
+ *   inc_ptr [ndof+1], inc [6 nme]: the triangles of DOF i as 6 k + a
+ *                (dofs[k][a] == i), ascending, at inc[inc_ptr[i] ..
+ *                inc_ptr[i+1])
+ *   inc_pos [6 nme] uint64 (8-byte aligned): for inc[j] = 6 k + a in row i,
+ *                the row slot (offset from row_ptr[i]) of dofs[k][b] in bits
+ *                10 b .. 10 b + 9 (b = 0..5), and a in bits 60-62
  *   work [work_bytes] >= fem_p2_pattern_workspace(ndof, nme); nnz_out HOST
- * FEM_ERANGE for a DOF outside [0, ndof), FEM_ENOSPC if col_cap < nnz.
- * Synchronises `stream`. */
+ * All outputs are device memory owned by the caller.  FEM_ERANGE for a DOF
+ * outside [0, ndof), FEM_ENOSPC if col_cap < nnz, FEM_EUNSUPPORTED for a row
+ * over 1024 entries.  Synchronises `stream`. */
 int fem_p2_pattern(int32_t ndof, int32_t nme, const int32_t *dofs, int32_t *row_ptr,
-                   int32_t *col_idx, int64_t col_cap, int32_t *contrib_ptr, int32_t *contrib,
-                   void *work, size_t work_bytes, int64_t *nnz_out /* HOST */, void *stream);
+                   int32_t *col_idx, int64_t col_cap, int32_t *inc_ptr, int32_t *inc,
+                   uint64_t *inc_pos, void *work, size_t work_bytes, int64_t *nnz_out /* HOST */,
+                   void *stream);
 
 /* HOST ONLY.  Bytes of device workspace fem_p2_assemble needs (32 nme). */
 int fem_p2_assemble_workspace(int32_t nme, size_t *bytes /* HOST */);
@@ -492,19 +499,20 @@ int fem_p2_assemble_workspace(int32_t nme, size_t *bytes /* HOST */);
 /* P2 mass (FEM_OP_MASS: int phi_a phi_b) and / or stiffness (FEM_OP_STIFF:
  * int grad phi_a . grad phi_b) on the pattern of fem_p2_pattern, with the
  * basis phi_a = lambda_a (2 lambda_a - 1), phi_{3+a} = 4 lambda_b lambda_c
- * (the edge opposite vertex a).  Four numbers per triangle (|T| / 180 and
- * the three P1 off-diagonal stiffness entries / 3), then for every entry the
- * sum of its contributors in ascending t, each an integer combination of
- * those numbers (bitwise reproducible).
+ * (the edge opposite vertex a), summed over the elements as sparse() does
+ * (Section 6).  Four numbers per triangle (|T| / 180 and the three P1
+ * off-diagonal stiffness entries / 3), then one lane per DOF row adds its
+ * triangles' entries, each an integer combination of those numbers, in
+ * ascending triangle order (bitwise reproducible).
  *   q [nq][2] f64 (16-byte aligned); me [nme][3] int32 as validated by
- *   fem_p2_dofs; vals_M / vals_S [nnz]
+ *   fem_p2_dofs; row_ptr, inc_ptr, inc, inc_pos from fem_p2_pattern over
+ *   ndof DOFs; vals_M / vals_S [nnz] device, caller-owned
  *   work [work_bytes] >= fem_p2_assemble_workspace(nme), 32-byte aligned
- * flags: 0 or FEM_ACCUMULATE.  Contributors outside [0, 36 nme) are
- * skipped. */
-int fem_p2_assemble(int ops, int32_t nq, int32_t nme, int64_t nnz, const double *q,
-                    const int32_t *me, const int32_t *contrib_ptr, const int32_t *contrib,
-                    double *vals_M, double *vals_S, void *work, size_t work_bytes, int flags,
-                    void *stream);
+ * flags: 0 or FEM_ACCUMULATE. */
+int fem_p2_assemble(int ops, int32_t nq, int32_t nme, int32_t ndof, int64_t nnz, const double *q,
+                    const int32_t *me, const int32_t *row_ptr, const int32_t *inc_ptr,
+                    const int32_t *inc, const uint64_t *inc_pos, double *vals_M, double *vals_S,
+                    void *work, size_t work_bytes, int flags, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Adjoint                                                                   */

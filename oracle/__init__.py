@@ -232,6 +232,18 @@ def tet_incidence(nq: int, me):
     return inc_ptr, inc
 
 
+def p2_incidence(ndof: int, dofs):
+    """The triangles of every P2 DOF (the transpose of dofs): DOF i's are the
+    ids 6 k + a with dofs[k][a] == i, ascending, at inc[inc_ptr[i] ..
+    inc_ptr[i+1]).  Returns (inc_ptr [ndof+1], inc [6 nme]) int32."""
+    dofs = _i32(dofs)
+    v = dofs.reshape(-1).astype(np.int64)        # entry 6 k + a of the flat array
+    inc = np.argsort(v, kind="stable").astype(np.int32)
+    inc_ptr = np.zeros(ndof + 1, np.int32)
+    inc_ptr[1:] = np.cumsum(np.bincount(v, minlength=ndof))
+    return inc_ptr, inc
+
+
 def elem_p2_mass(area_: float):
     """6x6 P2 mass matrix [a][b] (vertices 0..2, then the edge opposite each)."""
     E = np.zeros(36)

@@ -479,8 +479,9 @@ class P2Pattern:
     edges: object            # [ne][2] int32
     row_ptr: object          # [ndof+1] int32
     col_idx: object          # [nnz] int32
-    contrib_ptr: object      # [nnz+1] int32
-    contrib: object          # [36 nme] int32
+    inc_ptr: object          # [ndof+1] int32
+    inc: object              # [6 nme] int32: 6 k + a, ascending per DOF
+    inc_pos: object          # [6 nme] int64 (uint64 bits): six 10-bit row slots, a in bits 60-62
 
     @property
     def ndof(self) -> int:
@@ -519,14 +520,16 @@ def fem_p2_pattern(me, nq: int, *, stream=None) -> P2Pattern:
     cap = min(36 * nme, ndof + 30 * nme)
     row_ptr = torch.empty(ndof + 1, **i32)
     col = torch.empty(max(cap, 1), **i32)
-    cptr = torch.empty(cap + 1, **i32)
-    ctb = torch.empty(max(36 * nme, 1), **i32)
+    inc_ptr = torch.empty(ndof + 1, **i32)
+    inc = torch.empty(max(6 * nme, 1), **i32)
+    inc_pos = torch.empty(max(6 * nme, 1), dtype=torch.int64, device=dev)
     nnz = C.c_int64(0)
-    _lib.check(lib.fem_p2_pattern(ndof, nme, _ptr(dofs), _ptr(row_ptr), _ptr(col), cap, _ptr(cptr),
-                                  _ptr(ctb), _ptr(work), int(ws.value), C.byref(nnz), _stream(stream)))
+    _lib.check(lib.fem_p2_pattern(ndof, nme, _ptr(dofs), _ptr(row_ptr), _ptr(col), cap, _ptr(inc_ptr),
+                                  _ptr(inc), _ptr(inc_pos), _ptr(work), int(ws.value), C.byref(nnz),
+                                  _stream(stream)))
     k = int(nnz.value)
-    return P2Pattern(int(nq), ne, nme, k, me, dofs, edges[:ne], row_ptr, col[:k], cptr[:k + 1],
-                     ctb[:36 * nme])
+    return P2Pattern(int(nq), ne, nme, k, me, dofs, edges[:ne], row_ptr, col[:k], inc_ptr,
+                     inc[:6 * nme], inc_pos[:6 * nme])
 
 
 def fem_p2_assemble(pat: P2Pattern, q, ops: int = FEM_OP_MASS | FEM_OP_STIFF, *, out=None,
@@ -547,10 +550,10 @@ def fem_p2_assemble(pat: P2Pattern, q, ops: int = FEM_OP_MASS | FEM_OP_STIFF, *,
         ws = C.c_size_t(0)
         _lib.check(lib.fem_p2_assemble_workspace(pat.nme, C.byref(ws)))
         work = torch.empty(max(int(ws.value), 32), dtype=torch.uint8, device=dev)
-    _lib.check(lib.fem_p2_assemble(int(ops), pat.nq, pat.nme, pat.nnz, _ptr(q), _ptr(pat.me),
-                                   _ptr(pat.contrib_ptr), _ptr(pat.contrib), _ptr(out.get("M")),
-                                   _ptr(out.get("S")), _ptr(work), work.numel() * work.element_size(),
-                                   flags, _stream(stream)))
+    _lib.check(lib.fem_p2_assemble(int(ops), pat.nq, pat.nme, pat.ndof, pat.nnz, _ptr(q), _ptr(pat.me),
+                                   _ptr(pat.row_ptr), _ptr(pat.inc_ptr), _ptr(pat.inc), _ptr(pat.inc_pos),
+                                   _ptr(out.get("M")), _ptr(out.get("S")), _ptr(work),
+                                   work.numel() * work.element_size(), flags, _stream(stream)))
     return out
 
 

@@ -102,11 +102,11 @@ SIGNATURES = {
     "fem_p2_dofs_workspace": (_int, [_i32, _i32, _szp]),
     "fem_p2_dofs": (_int, [_i32, _i32, _vp, _vp, _vp, _i64, _vp, C.c_size_t, C.POINTER(_i64), _vp]),
     "fem_p2_pattern_workspace": (_int, [_i32, _i32, _szp]),
-    "fem_p2_pattern": (_int, [_i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t,
+    "fem_p2_pattern": (_int, [_i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, C.c_size_t,
                               C.POINTER(_i64), _vp]),
     "fem_p2_assemble_workspace": (_int, [_i32, _szp]),
-    "fem_p2_assemble": (_int, [_int, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                               C.c_size_t, _int, _vp]),
+    "fem_p2_assemble": (_int, [_int, _i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                               _vp, C.c_size_t, _int, _vp]),
     "fem_adjoint_elas_workspace": (_int, [_i32, _i64, _szp]),
     "fem_adjoint_elas": (_int, [_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _vp,
                                 _vp, _vp, _vp, C.c_size_t, _int, _vp]),

@@ -117,10 +117,10 @@ def test_extension_size_limits_before_any_launch(lib):
     assert lib.fem_p2_dofs_workspace(10, big_p2, C.byref(ws)) == _lib.FEM_EOVERFLOW
     assert lib.fem_p2_dofs(10, big_p2, fake, fake, None, 0, fake, 1 << 20, C.byref(out),
                            None) == _lib.FEM_EOVERFLOW
-    assert lib.fem_p2_pattern(10, big_p2, fake, fake, fake, 0, fake, fake, fake, 1 << 20, C.byref(out),
-                              None) == _lib.FEM_EOVERFLOW
-    assert lib.fem_p2_assemble(5, 10, big_p2, 10, fake, fake, fake, fake, fake, fake, fake, 1 << 20, 0,
-                               None) == _lib.FEM_EOVERFLOW
+    assert lib.fem_p2_pattern(10, big_p2, fake, fake, fake, 0, fake, fake, fake, fake, 1 << 20,
+                              C.byref(out), None) == _lib.FEM_EOVERFLOW
+    assert lib.fem_p2_assemble(5, 10, big_p2, 20, 10, fake, fake, fake, fake, fake, fake, fake, fake, fake,
+                               1 << 20, 0, None) == _lib.FEM_EOVERFLOW
     big_tet = 140_000_000       # 16 nme > 2^31 - 1
     assert lib.fem_tet_pattern_workspace(10, big_tet, C.byref(ws)) == _lib.FEM_EOVERFLOW
     assert lib.fem_tet_pattern(10, big_tet, fake, fake, fake, 0, fake, fake, fake, fake, 1 << 20,

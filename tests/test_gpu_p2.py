@@ -1,8 +1,11 @@
 """GPU P2 triangles (mass, stiffness) against the oracle, through the C ABI.
 
-DOFs, edges, pattern and contributor lists bit-exact; values within 1e-13 per
-row (max norm): both sides add the same triplets in the same order
-(ascending t) and differ only in the rounding of the element matrices."""
+DOFs, edges, pattern, and the triangles of every DOF (inc_ptr, inc) bit-exact
+against the oracle; inc_pos checked entry by entry against what it must name
+(the triangle's six DOFs in the row); values within 1e-13 per row (max norm):
+the GPU adds each entry's element terms in ascending triangle order, the
+oracle in ascending triplet order, and the element formulas round
+differently."""
 import numpy as np
 import pytest
 
@@ -30,14 +33,25 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def p2_triplets(dofs):
-    """Ig, Jg of the 36 local entries, t = r nme + k, r = 6 b + a."""
-    a = np.tile(np.arange(6), 6)
-    b = np.repeat(np.arange(6), 6)
-    return dofs[:, a].T.reshape(-1).astype(np.int32), dofs[:, b].T.reshape(-1).astype(np.int32)
+def _check_inc(pat, dofs, rp, ci):
+    """inc_ptr / inc equal the oracle's transpose of dofs; inc_pos names each
+    triangle's six DOFs inside the row, and the row's own local index."""
+    inc_ptr, inc = oracle.p2_incidence(pat.ndof, dofs)
+    np.testing.assert_array_equal(_np(pat.inc_ptr), inc_ptr)
+    np.testing.assert_array_equal(_np(pat.inc), inc)
+    pos = _np(pat.inc_pos).view(np.uint64)
+    np.testing.assert_array_equal((pos >> np.uint64(60)).astype(np.int64), inc % 6)
+    v = np.repeat(np.arange(pat.ndof), np.diff(inc_ptr))
+    k = (inc // 6).astype(np.int64)
+    rs = rp[v].astype(np.int64)
+    L = (rp[v + 1] - rp[v]).astype(np.int64)
+    for b in range(6):
+        p = ((pos >> np.uint64(10 * b)) & np.uint64(1023)).astype(np.int64)
+        assert np.all(p < L)
+        np.testing.assert_array_equal(ci[rs + p], dofs[k, b])
 
 
-def _check(m, contrib=True):
+def _check(m):
     pat = fem.fem_p2_pattern(_up(m.me), m.nq)
     q = _up(m.q)
     both = fem.fem_p2_assemble(pat, q)
@@ -52,12 +66,7 @@ def _check(m, contrib=True):
     assert pat.nnz == ci.shape[0]
     np.testing.assert_array_equal(_np(pat.row_ptr), rp)
     np.testing.assert_array_equal(_np(pat.col_idx), ci)
-    if contrib:
-        I, J = p2_triplets(dofs)
-        _, _, pos = oracle.sparse_positions(I, J, pat.ndof, pat.ndof)
-        np.testing.assert_array_equal(_np(pat.contrib), np.argsort(pos, kind="stable"))
-        np.testing.assert_array_equal(
-            _np(pat.contrib_ptr), np.concatenate([[0], np.cumsum(np.bincount(pos, minlength=pat.nnz))]))
+    _check_inc(pat, dofs, rp, ci)
     assert row_rel_err(rp, _np(both["M"]), M) <= RTOL_ROW
     assert row_rel_err(rp, _np(both["S"]), S) <= RTOL_ROW
     # one pass for both operators adds the same terms as the single ones
@@ -90,7 +99,7 @@ def test_p2_square96_full_parity_and_accumulate():
     # several tiles of every kernel and a ragged tail (nnz not a multiple of 256)
     m = mg.unit_square(96, seed=mg.BASE_SEED + 96)
     print(f"[case] p2 square96 nq={m.nq} nme={m.nme}", flush=True)
-    pat, both = _check(m, contrib=False)
+    pat, both = _check(m)
     assert pat.nnz % 256 != 0
     out = {"M": both["M"].clone(), "S": both["S"].clone()}
     fem.fem_p2_assemble(pat, _up(m.q), out=out, flags=fem.FEM_ACCUMULATE)
@@ -144,11 +153,13 @@ def test_p2_full_size():
 
     assert float(u @ Mu) == pytest.approx(isq(c, c), rel=1e-11)
     assert float(u @ Su) == pytest.approx(isq(ux, ux) + isq(uy, uy), rel=1e-10)
-    # sampled rows, one by one, from the oracle's DOF numbering and element
-    # matrices, summed in ascending t = (6 b + a) nme + k
+    # the triangles of every DOF and their slots; sampled rows, one by one,
+    # from the oracle's DOF numbering and element matrices, summed in
+    # ascending t = (6 b + a) nme + k
     dofs, edges = oracle.p2_dofs(m.nq, m.me)
     np.testing.assert_array_equal(_np(pat.dofs), dofs)
     rph, cih = _np(pat.row_ptr), _np(pat.col_idx)
+    _check_inc(pat, dofs, rph, cih)
     Mh, Sh = _np(M), _np(S)
     rng = np.random.default_rng(2048)
     sample = np.concatenate([rng.choice(m.nq, 16, replace=False),
@@ -190,5 +201,6 @@ def test_p2_errors_and_empty():
     torch.cuda.synchronize()
     assert pat.ne == 0 and pat.nnz == 0 and vals["M"].numel() == 0
     np.testing.assert_array_equal(_np(pat.row_ptr), np.zeros(6, np.int32))
+    np.testing.assert_array_equal(_np(pat.inc_ptr), np.zeros(6, np.int32))
     # and the library keeps working
     _check(mg.unit_square(2, seed=8))

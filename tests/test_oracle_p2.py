@@ -251,3 +251,21 @@ def test_invalid_meshes_are_rejected():
         oracle.assemble_p2("mass", q, np.array([[0, 1, 4]], np.int32))
     with pytest.raises(oracle.OracleError):
         oracle.assemble_p2("mass", q, np.array([[0, 1, 1]], np.int32))
+
+
+def test_p2_incidence_brute_force():
+    # the transpose of dofs against a per-DOF scan of every (k, a); on the
+    # square and the disk (manifold meshes) each interior edge lies in two
+    # triangles and a boundary edge in one
+    rng = np.random.default_rng(13)
+    for m in (mg.unit_square(3, seed=5), mg.random_tiny_mesh(rng, 25), mg.unit_disk(3, seed=6)):
+        dofs, edges = oracle.p2_dofs(m.nq, m.me)
+        ndof = m.nq + edges.shape[0]
+        inc_ptr, inc = oracle.p2_incidence(ndof, dofs)
+        assert inc_ptr[0] == 0 and inc_ptr[-1] == 6 * m.nme
+        for i in range(ndof):
+            want = [6 * k + a for k in range(m.nme) for a in range(6) if dofs[k, a] == i]
+            np.testing.assert_array_equal(inc[inc_ptr[i]:inc_ptr[i + 1]], want)
+        if m.name != "tiny":
+            deg_edges = np.diff(inc_ptr)[m.nq:]
+            assert set(deg_edges.tolist()) == {1, 2}
