@@ -411,15 +411,17 @@ __device__ __forceinline__ void p2_term(uint32_t cw, const double4 &e, double &m
 
 // One lane per DOF row over rows [r_begin, r_end), one wave per workgroup;
 // vertex rows and edge rows go to separate launches with their own LM and
-// IP, so that the short edge rows need less LDS and fewer registers.  LDS:
-// A [NA][LM][WAVE] the per-slot sums, T [LM WAVE] the transposition of one
-// operator's rows into CSR order (the wave's rows leave as one contiguous,
-// coalesced range; written row by row from the lanes they took 1.4-1.6x as
-// long), and the coefficient table.  The row's first IP triangles' ids,
-// slots and records are loaded up front; per triangle, its six slots are
-// distinct, so the twelve accumulators are read together and written back
-// together.  A row longer than LM is summed by its lane slot by slot from
-// global memory (same terms, same order, so the same values bit for bit).
+// IP, so that the short edge rows need less LDS and fewer registers.  The
+// row's first IP triangles' ids, slots and records are loaded up front;
+// then one pass over them per operator: the per-slot sums in LDS (A
+// [LM][WAVE]; per triangle, its six slots are distinct, so the six sums are
+// read together and written back together), then the wave's rows leave as
+// one contiguous, coalesced range, each entry finding its lane and slot in
+// an owner table (LM WAVE ints; written row by row from the lanes the rows
+// took 1.4-1.6x as long).  One operator at a time halves the LDS, and the
+// owner table is half a transposition buffer of doubles, so a CU holds more
+// workgroups.  A row longer than LM is summed by its lane slot by slot from global
+// memory (same terms, same order, so the same values bit for bit).
 template <int MASK, int LM, int IP>
 __global__ __launch_bounds__(WAVE) void k_p2_rows(int32_t r_begin, int32_t r_end,
                                                   const int32_t *__restrict__ row_ptr,
@@ -431,9 +433,8 @@ __global__ __launch_bounds__(WAVE) void k_p2_rows(int32_t r_begin, int32_t r_end
                                                   int accumulate) {
     constexpr bool HM = (MASK & P2_M) != 0, HS = (MASK & P2_S) != 0;
     constexpr int NA = (HM ? 1 : 0) + (HS ? 1 : 0);
-    constexpr int MI = HM ? 0 : -1, SI = (HM && HS) ? 1 : 0;
-    __shared__ double A[NA][LM * WAVE];
-    __shared__ double T[LM * WAVE];
+    __shared__ double A[LM * WAVE];
+    __shared__ int32_t own[LM * WAVE];   // (lane << 8 | slot) of each entry of the range
     __shared__ uint32_t tab[36];
     const int lane = threadIdx.x;
     if (lane < 36) tab[lane] = P2_TABLE.w[lane];
@@ -452,47 +453,20 @@ __global__ __launch_bounds__(WAVE) void k_p2_rows(int32_t r_begin, int32_t r_end
     const int32_t R1 = r0 + WAVE < r_end ? row_ptr[r0 + WAVE] : end_all;
     const bool fast = L <= LM;
     const uint64_t longmask = __ballot(!fast);
-    auto AM = [&](int p) -> double & { return A[MI < 0 ? 0 : MI][p * WAVE + lane]; };
-    auto AS = [&](int p) -> double & { return A[SI][p * WAVE + lane]; };
+    auto AX = [&](int p) -> double & { return A[p * WAVE + lane]; };
     __syncthreads();   // the table
+    // the first IP triangles: ids and slots, then their records
+    int32_t kk[IP];
+    uint64_t ww[IP];
+    double4 ee[IP];
     if (fast && L > 0) {
-        // the first IP triangles: ids and slots, then their records
-        int32_t kk[IP];
-        uint64_t ww[IP];
 #pragma unroll
         for (int t = 0; t < IP; ++t) {
             kk[t] = t < d ? inc[is + t] / 6 : 0;
             ww[t] = t < d ? inc_pos[is + t] : 0ull;
         }
-        double4 ee[IP];
 #pragma unroll
         for (int t = 0; t < IP; ++t) ee[t] = ed[kk[t]];
-        for (int p = 0; p < L; ++p) {
-            if constexpr (HM) AM(p) = 0.0;
-            if constexpr (HS) AS(p) = 0.0;
-        }
-        auto step = [&](uint64_t w, const double4 &e) {
-            const int a = (int)(w >> 60);
-            int sl[6];
-            double om[6], os[6];
-#pragma unroll
-            for (int b = 0; b < 6; ++b) {
-                sl[b] = (int)((w >> (P2_POS_BITS * b)) & (P2_ROW_MAX - 1));
-                om[b] = HM ? AM(sl[b]) : 0.0;
-                os[b] = HS ? AS(sl[b]) : 0.0;
-            }
-#pragma unroll
-            for (int b = 0; b < 6; ++b) {
-                double m = 0.0, s = 0.0;
-                p2_term<MASK>(tab[6 * b + a], e, m, s);
-                if constexpr (HM) AM(sl[b]) = om[b] + m;
-                if constexpr (HS) AS(sl[b]) = os[b] + s;
-            }
-        };
-#pragma unroll
-        for (int t = 0; t < IP; ++t)
-            if (t < d) step(ww[t], ee[t]);
-        for (int32_t t = IP; t < d; ++t) step(inc_pos[is + t], ed[inc[is + t] / 6]);
     } else if (!fast) {
         // long row: slot by slot, the terms of that slot in ascending order
         for (int32_t p = 0; p < L; ++p) {
@@ -512,22 +486,51 @@ __global__ __launch_bounds__(WAVE) void k_p2_rows(int32_t r_begin, int32_t r_end
             if constexpr (HS) vs[rs + p] = accumulate ? vs[rs + p] + ss : ss;
         }
     }
-    // the workgroup is one wave, whose LDS accesses complete in program
-    // order: scheduling barriers order the sums, the transposition and the
-    // write-out
-    __builtin_amdgcn_wave_barrier();
     const int32_t R0 = __shfl(rsv, 0, WAVE);
+#pragma unroll
     for (int op = 0; op < NA; ++op) {
-        double *out = (op == 0 && HM) ? vm : vs;
-        const int ai = (op == 0 && HM) ? (MI < 0 ? 0 : MI) : SI;
+        // the operator of this pass: mass first when both are asked for
+        const bool is_m = HM && op == 0;
+        double *out = is_m ? vm : vs;
+        if (fast && L > 0) {
+            for (int p = 0; p < L; ++p) AX(p) = 0.0;
+            auto step = [&](uint64_t w, const double4 &e) {
+                const int a = (int)(w >> 60);
+                int sl[6];
+                double o[6];
+#pragma unroll
+                for (int b = 0; b < 6; ++b) {
+                    sl[b] = (int)((w >> (P2_POS_BITS * b)) & (P2_ROW_MAX - 1));
+                    o[b] = AX(sl[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < 6; ++b) {
+                    double m = 0.0, s = 0.0;
+                    if (is_m) p2_term<P2_M>(tab[6 * b + a], e, m, s);
+                    else p2_term<P2_S>(tab[6 * b + a], e, m, s);
+                    AX(sl[b]) = o[b] + (is_m ? m : s);
+                }
+            };
+#pragma unroll
+            for (int t = 0; t < IP; ++t)
+                if (t < d) step(ww[t], ee[t]);
+            for (int32_t t = IP; t < d; ++t) step(inc_pos[is + t], ed[inc[is + t] / 6]);
+        }
+        // the workgroup is one wave, whose LDS accesses complete in program
+        // order: scheduling barriers order the sums, the transposition and
+        // the write-out
+        __builtin_amdgcn_wave_barrier();
         if (longmask == 0) {
             // every row has at most LM entries (the range at most LM WAVE):
-            // each lane copies its sums in CSR order into T, and the range
-            // is then written in order
-            for (int p = 0; p < L; ++p) T[rs - R0 + p] = A[ai][p * WAVE + lane];
-            __builtin_amdgcn_wave_barrier();
+            // the owner table (written once, on the first pass) names each
+            // entry's lane and slot, and the range is written in order
+            if (op == 0) {
+                for (int p = 0; p < L; ++p) own[rs - R0 + p] = (lane << 8) | p;
+                __builtin_amdgcn_wave_barrier();
+            }
             for (int32_t e = R0 + lane; e < R1; e += WAVE) {
-                const double v = T[e - R0];
+                const int32_t o = own[e - R0];
+                const double v = A[(o & 255) * WAVE + (o >> 8)];
                 out[e] = accumulate ? out[e] + v : v;
             }
         } else {
@@ -545,7 +548,7 @@ __global__ __launch_bounds__(WAVE) void k_p2_rows(int32_t r_begin, int32_t r_end
                 const int32_t rlo = __shfl(rsv, lo, WAVE);
                 const int p = e - rlo;
                 if (e >= R1 || ((longmask >> lo) & 1u) || p >= LM) continue;
-                const double v = A[ai][p * WAVE + lo];
+                const double v = A[p * WAVE + lo];
                 out[e] = accumulate ? out[e] + v : v;
             }
         }
