@@ -103,6 +103,19 @@ struct Outs {
     double *o[4];   // M, Mw, S, K (K in the 2x2 block layout of fem_elas_pattern)
 };
 
+// Stores the n values of an LDS tile to o, coalesced: lane l takes entries
+// l, l + 64, ...  Overwrites are streaming stores (nothing reads the values
+// back in this pass); the accumulate path adds in place.  The two paths are
+// separate loops: merged into one store, the streaming hint would be dropped.
+__device__ __forceinline__ void tile_store(double *__restrict__ o, const double *src, int n, int lane,
+                                           int accumulate) {
+    if (!accumulate) {
+        for (int e = lane; e < n; e += WAVE) __builtin_nontemporal_store(src[e], o + e);
+    } else {
+        for (int e = lane; e < n; e += WAVE) o[e] += src[e];
+    }
+}
+
 // (x, y, w, 0) records, so that a vertex costs one random access.
 __global__ __launch_bounds__(256) void k_pack_qw(int32_t nq, const double2 *__restrict__ q,
                                                  const double *__restrict__ w,
@@ -599,12 +612,7 @@ __global__ __launch_bounds__(WAVE) void k_rows_reg(
                         for (int k = 0; k < len; ++k) s_t[off + k] = 0.0;
                     }
                     __syncthreads();
-                    double *o = out.o[m] + E0;
-                    for (int e = lane; e < Ew; e += WAVE) {
-                        const double v = s_t[e];
-                        if (accumulate) o[e] += v;
-                        else __builtin_nontemporal_store(v, o + e);
-                    }
+                    tile_store(out.o[m] + E0, s_t, Ew, lane, accumulate);
                     __syncthreads();
                 }
             }
@@ -629,12 +637,7 @@ __global__ __launch_bounds__(WAVE) void k_rows_reg(
                     for (int k = 0; k < 4 * len; ++k) s_stage[4 * off + k] = 0.0;
                 }
                 __syncthreads();
-                double *o = out.o[3] + 4 * (int64_t)E0;
-                for (int e = lane; e < 4 * Ew; e += WAVE) {
-                    const double v = s_stage[e];
-                    if (accumulate) o[e] += v;
-                    else __builtin_nontemporal_store(v, o + e);
-                }
+                tile_store(out.o[3] + 4 * (int64_t)E0, s_stage, 4 * Ew, lane, accumulate);
                 __syncthreads();
             }
         }
@@ -947,14 +950,7 @@ __global__ __launch_bounds__(WAVE) void k_rows_fan(
                 }
                 __syncthreads();
 #pragma unroll
-                for (int m = 0; m < NS; ++m) {
-                    double *o = out.o[m] + E0;
-                    for (int e = lane; e < Ew; e += WAVE) {
-                        const double val = smem[m * EB + e];
-                        if (accumulate) o[e] += val;
-                        else __builtin_nontemporal_store(val, o + e);
-                    }
-                }
+                for (int m = 0; m < NS; ++m) tile_store(out.o[m] + E0, smem + m * EB, Ew, lane, accumulate);
                 __syncthreads();
             }
         }
@@ -968,12 +964,7 @@ __global__ __launch_bounds__(WAVE) void k_rows_fan(
                     for (int k = 0; k < 4 * len; ++k) smem[4 * off + k] = 0.0;
                 }
                 __syncthreads();
-                double *o = out.o[3] + 4 * (int64_t)E0;
-                for (int e = lane; e < 4 * Ew; e += WAVE) {
-                    const double val = smem[e];
-                    if (accumulate) o[e] += val;
-                    else __builtin_nontemporal_store(val, o + e);
-                }
+                tile_store(out.o[3] + 4 * (int64_t)E0, smem, 4 * Ew, lane, accumulate);
                 __syncthreads();
             }
         }
