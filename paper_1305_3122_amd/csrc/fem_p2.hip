@@ -528,10 +528,16 @@ __global__ __launch_bounds__(WAVE) void k_p2_rows(int32_t r_begin, int32_t r_end
                 for (int p = 0; p < L; ++p) own[rs - R0 + p] = (lane << 8) | p;
                 __builtin_amdgcn_wave_barrier();
             }
-            for (int32_t e = R0 + lane; e < R1; e += WAVE) {
+            // overwrites are streaming stores (separate loops: merged with the
+            // accumulate path's store, the hint would be dropped)
+            auto owned = [&](int32_t e) {
                 const int32_t o = own[e - R0];
-                const double v = A[(o & 255) * WAVE + (o >> 8)];
-                out[e] = accumulate ? out[e] + v : v;
+                return A[(o & 255) * WAVE + (o >> 8)];
+            };
+            if (!accumulate) {
+                for (int32_t e = R0 + lane; e < R1; e += WAVE) __builtin_nontemporal_store(owned(e), out + e);
+            } else {
+                for (int32_t e = R0 + lane; e < R1; e += WAVE) out[e] += owned(e);
             }
         } else {
             // entry e belongs to the last row whose start is <= e (empty

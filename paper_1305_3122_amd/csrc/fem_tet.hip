@@ -820,14 +820,18 @@ __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__r
                 if constexpr (HS) T[(NA - 1) * LM * WAVE + g.rs - R0 + p] = AS(p);
             }
             __builtin_amdgcn_wave_barrier();
-            for (int32_t e = R0 + lane; e < R1; e += WAVE) {
-                if constexpr (HM) {
-                    const double a = T[e - R0];
-                    vm[e] = accumulate ? vm[e] + a : a;
+            // overwrites are streaming stores (separate loops: merged with the
+            // accumulate path's store, the hint would be dropped)
+            const double *TS = T + (NA - 1) * LM * WAVE;
+            if (!accumulate) {
+                for (int32_t e = R0 + lane; e < R1; e += WAVE) {
+                    if constexpr (HM) __builtin_nontemporal_store(T[e - R0], vm + e);
+                    if constexpr (HS) __builtin_nontemporal_store(TS[e - R0], vs + e);
                 }
-                if constexpr (HS) {
-                    const double a = T[(NA - 1) * LM * WAVE + e - R0];
-                    vs[e] = accumulate ? vs[e] + a : a;
+            } else {
+                for (int32_t e = R0 + lane; e < R1; e += WAVE) {
+                    if constexpr (HM) vm[e] += T[e - R0];
+                    if constexpr (HS) vs[e] += TS[e - R0];
                 }
             }
         } else {
