@@ -693,10 +693,12 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
     __syncthreads();
     if (fits) {
         const int32_t n = static_cast<int32_t>(e1 - e0);
+        // streaming stores: the row kernels read inc and inc_pos only for
+        // rows without a fan code
         for (int32_t p = tid; p < n; p += BKT_THREADS) {
-            inc[e0 + p] = s_key[p];
+            __builtin_nontemporal_store(s_key[p], inc + e0 + p);
             const uint32_t pp = static_cast<uint32_t>(s_n1[p]);
-            if (pp != POS_DIRECT) inc_pos[e0 + p] = pp;
+            if (pp != POS_DIRECT) __builtin_nontemporal_store(pp, inc_pos + e0 + p);
         }
     }
     // ---- maxima
