@@ -591,7 +591,7 @@ struct TetRowLoad {
 // One lane per row, one wave (a group of WAVE consecutive rows) per
 // workgroup.  LDS: X [LM][3][WAVE] the row's vertices relative to the row's
 // own, A [NA][LM][WAVE] the per-slot sums (through which the group's rows
-// leave, coalesced).  The loads come in three dependent rounds, each issued
+// leave, coalesced).  The loads come in three dependent stages, each issued
 // whole: the row and tetrahedron ranges; the row's vertex ids and its first
 // TROW_IP tetrahedra's slots; the coordinates.  The sums read registers and
 // LDS only.  A row longer than LM is summed by its lane one slot at a time
@@ -616,7 +616,7 @@ __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__r
     auto AS = [&](int p) -> double & { return A[SI][p * WAVE + lane]; };
     const int32_t nnz_all = row_ptr[nq], ninc_all = inc_ptr[nq];
 
-    // round 1: ranges and the row's own vertex
+    // load stage 1: ranges and the row's own vertex
     auto load_head = [&](int32_t r0, TetRowLoad &g) {
         g.v = r0 + lane;
         g.rs = g.L = g.is = g.d = 0;
@@ -631,7 +631,7 @@ __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__r
             g.x0[2] = q[3 * (int64_t)g.v + 2];
         }
     };
-    // round 2: vertex ids and slots, 16 bytes per load (4-byte aligned,
+    // load stage 2: vertex ids and slots, 16 bytes per load (4-byte aligned,
     // which global loads accept) where the arrays reach that far
     auto load_ids = [&](TetRowLoad &g) {
         const bool on = g.L <= LM && g.L > 0;
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(WAVE) void k_tet_rows(int32_t nq, const double *__r
 #pragma unroll
         for (int t = 0; t < IP; ++t) g.pp[t] = (on && t < g.d) ? g.pp[t] : 0u;
     };
-    // round 3: a vertex's three coordinates in two loads (16 + 8 bytes; the
+    // load stage 3: a vertex's three coordinates in two loads (16 + 8 bytes; the
     // 16-byte one is 8-byte aligned), no branch (unused slots read vertex 0)
     auto load_coords = [&](TetRowLoad &g) {
 #pragma unroll
