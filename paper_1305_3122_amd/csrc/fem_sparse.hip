@@ -716,13 +716,14 @@ __global__ __launch_bounds__(SP_THREADS) void k_sp_copy(
                 v[j] = (in && vals) ? stage_val[e0 + x] : 0.0;
                 cp[j] = (in && contrib_ptr) ? stage_cptr[e0 + x] : 0;
             }
+            // streaming stores: the outputs are not read again by this call
 #pragma unroll
             for (int j = 0; j < H; ++j) {
                 const int32_t x = x0 + j * SP_THREADS;
                 if (x >= T) continue;
-                col_idx[P + x] = c[j];
-                if (vals) vals[P + x] = v[j];
-                if (contrib_ptr) contrib_ptr[P + x] = cp[j];
+                __builtin_nontemporal_store(c[j], col_idx + P + x);
+                if (vals) __builtin_nontemporal_store(v[j], vals + P + x);
+                if (contrib_ptr) __builtin_nontemporal_store(cp[j], contrib_ptr + P + x);
             }
         }
     }
@@ -751,8 +752,8 @@ __global__ __launch_bounds__(256) void k_sp_values(int64_t nnz, const int32_t *_
         for (int j = 0; j < H; ++j)
             if (c[j] >= 0) acc += x[j];
     }
-    if (accumulate) vals[p] += acc;
-    else vals[p] = acc;
+    // a streaming store: nothing reads vals again in this call
+    __builtin_nontemporal_store(accumulate ? vals[p] + acc : acc, vals + p);
 }
 
 struct SparsePlan {
