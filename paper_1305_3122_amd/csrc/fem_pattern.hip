@@ -88,8 +88,9 @@ __device__ inline void max_into(int *dst, int v) {
 // ---------------------------------------------------------------- bucket sort
 //
 // Buckets are ranges of 2^bs consecutive vertex ids.  A first pass
-// partitions the incidences by bucket (k_bkt_count / scan / k_bkt_scatter:
-// each workgroup of triangles writes one contiguous run per bucket).  Then
+// partitions the incidences by bucket (k_bkt_count, k_bkt_colscan and a scan
+// of the bucket totals, k_bkt_scatter: each workgroup of triangles writes one
+// contiguous run per bucket).  Then
 // either
 //   fine buckets (512 vertices): k_bkt_rows does everything for a bucket in
 //     LDS -- counting sort by vertex, per-vertex rows -- and stages the
@@ -153,14 +154,13 @@ __device__ inline bool tri_ok(int32_t a, int32_t b, int32_t c, int32_t nq) {
            a != b && b != c && a != c;
 }
 
-// counts[b * nblk + blk] = incidences of workgroup blk (tpb triangles)
-// falling in bucket b; mesh checks.
+// counts[blk * nbkt + b] = incidences of workgroup blk (tpb triangles)
+// falling in bucket b (each workgroup writes one contiguous row); mesh checks.
 __global__ __launch_bounds__(BKT_THREADS) void k_bkt_count(int32_t nme, const int32_t *__restrict__ me,
                                                           int32_t nq, int bs, int32_t nbkt, int32_t tpb,
                                                           int32_t *__restrict__ counts,
                                                           PatternCounters *cnt) {
     extern __shared__ int32_t s_hist[];
-    const int32_t nblk = gridDim.x;
     for (int b = threadIdx.x; b < nbkt; b += BKT_THREADS) s_hist[b] = 0;
     __syncthreads();
     int bad = 0;
@@ -200,7 +200,47 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_count(int32_t nme, const in
     if (bad) atomicOr(&cnt->err, bad);
     __syncthreads();
     for (int b = threadIdx.x; b < nbkt; b += BKT_THREADS)
-        counts[(int64_t)b * nblk + blockIdx.x] = s_hist[b];
+        counts[(int64_t)blockIdx.x * nbkt + b] = s_hist[b];
+}
+
+// In place over counts[blk][b]: each entry becomes the number of bucket b's
+// incidences in workgroups before blk, and bsum[b] the bucket's total.  One
+// lane per bucket, the four waves of a workgroup over quarters of the
+// workgroup range (their partial sums meet in LDS); every read and write
+// covers 64 consecutive buckets.
+__global__ __launch_bounds__(256) void k_bkt_colscan(int32_t nbkt, int32_t nblk,
+                                                     int32_t *__restrict__ counts,
+                                                     int32_t *__restrict__ bsum) {
+    __shared__ int32_t s_part[4][WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int32_t b = blockIdx.x * WAVE + lane;
+    const bool ok = b < nbkt;
+    const int32_t Q = (nblk + 3) / 4;
+    const int32_t k0 = w * Q, k1 = (k0 + Q < nblk) ? k0 + Q : nblk;
+    constexpr int H = 8;   // loads in flight per lane
+    int32_t sum = 0;
+    for (int32_t k = k0; k < k1; k += H) {
+        int32_t c[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) c[j] = (ok && k + j < k1) ? counts[(int64_t)(k + j) * nbkt + b] : 0;
+#pragma unroll
+        for (int j = 0; j < H; ++j) sum += c[j];
+    }
+    s_part[w][lane] = sum;
+    __syncthreads();
+    int32_t run = 0;
+    for (int u = 0; u < w; ++u) run += s_part[u][lane];
+    for (int32_t k = k0; k < k1; k += H) {
+        int32_t c[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) c[j] = (ok && k + j < k1) ? counts[(int64_t)(k + j) * nbkt + b] : 0;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            if (ok && k + j < k1) counts[(int64_t)(k + j) * nbkt + b] = run;
+            run += c[j];
+        }
+    }
+    if (ok && w == 3) bsum[b] = run;
 }
 
 // Same triangles per workgroup as k_bkt_count: each incidence goes to the run
@@ -210,11 +250,13 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_scatter(int32_t nme, const 
                                                             int32_t nq, int bs, int32_t nbkt,
                                                             int32_t tpb,
                                                             const int32_t *__restrict__ offs,
+                                                            const int32_t *__restrict__ bstart,
                                                             int32_t *__restrict__ ent) {
     extern __shared__ int32_t s_cur[];
-    const int32_t nblk = gridDim.x;
-    for (int b = threadIdx.x; b < nbkt; b += BKT_THREADS)
-        s_cur[b] = offs[(int64_t)b * nblk + blockIdx.x];
+    // the run of (b, this workgroup) starts at the bucket's start plus the
+    // incidences of the workgroups before it (one contiguous row of offs)
+    const int32_t *row = offs + (int64_t)blockIdx.x * nbkt;
+    for (int b = threadIdx.x; b < nbkt; b += BKT_THREADS) s_cur[b] = bstart[b] + row[b];
     __syncthreads();
     const int64_t k0 = (int64_t)blockIdx.x * tpb;
     const int64_t k1 = (k0 + tpb < nme) ? k0 + tpb : nme;
@@ -248,9 +290,7 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_scatter(int32_t nme, const 
 // Coarse path: one workgroup per bucket of COARSE_V vertices: counting sort of
 // its incidences by vertex in LDS.  Writes inc_ptr for the bucket's vertices
 // and the (unordered within a vertex) triangle lists and neighbour pairs.
-__global__ __launch_bounds__(BKT_THREADS) void k_bkt_sort(int32_t nq, int32_t nblk,
-                                                         const int32_t *__restrict__ offs,
-                                                         const int32_t *__restrict__ total_ptr,
+__global__ __launch_bounds__(BKT_THREADS) void k_bkt_sort(int32_t nq, const int32_t *__restrict__ bstart,
                                                          const int32_t *__restrict__ ent_w,
                                                          int32_t *__restrict__ inc_ptr,
                                                          int32_t *__restrict__ inc,
@@ -259,9 +299,7 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_sort(int32_t nq, int32_t nb
     __shared__ int32_t s_wsum[BKT_THREADS / WAVE];
     const int4 *ent = reinterpret_cast<const int4 *>(ent_w);
     const int32_t b = blockIdx.x;
-    const int64_t total = *total_ptr;
-    const int64_t e0 = offs[(int64_t)b * nblk];
-    const int64_t e1 = (b + 1 < (int32_t)gridDim.x) ? offs[(int64_t)(b + 1) * nblk] : total;
+    const int64_t e0 = bstart[b], e1 = bstart[b + 1];
     const int32_t v0 = b << COARSE_SHIFT;
     for (int i = threadIdx.x; i < COARSE_V; i += BKT_THREADS) s_cnt[i] = 0;
     __syncthreads();
@@ -299,7 +337,7 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_sort(int32_t nq, int32_t nb
         if (v0 + lv < nq) inc_ptr[v0 + lv] = static_cast<int32_t>(e0) + run;
         run += loc[t];
     }
-    if (b == (int32_t)gridDim.x - 1 && threadIdx.x == 0) inc_ptr[nq] = static_cast<int32_t>(total);
+    if (b == (int32_t)gridDim.x - 1 && threadIdx.x == 0) inc_ptr[nq] = static_cast<int32_t>(e1);
     __syncthreads();
     for (int64_t e = e0 + threadIdx.x; e < e1; e += B8 * BKT_THREADS) {
         int4 x[B8];
@@ -491,8 +529,8 @@ __device__ __noinline__ int32_t block_exclusive_scan_i32(int32_t v, int32_t *s_w
 // the coarse path.
 template <bool PK>
 __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
-    int32_t nq, int32_t nbkt, int32_t nblk, const int32_t *__restrict__ offs,
-    const int32_t *__restrict__ total_ptr, const int32_t *__restrict__ ent, int32_t *__restrict__ inc_ptr,
+    int32_t nq, int32_t nbkt, const int32_t *__restrict__ bstart,
+    const int32_t *__restrict__ ent, int32_t *__restrict__ inc_ptr,
     int32_t *__restrict__ inc, uint32_t *__restrict__ inc_pos, uint64_t *__restrict__ fan,
     int32_t *__restrict__ rowoff, int32_t *__restrict__ btot, int32_t *__restrict__ stage,
     PatternCounters *cnt) {
@@ -501,9 +539,7 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
     __shared__ int32_t s_wsum[BKT_THREADS / WAVE];
     const int tid = threadIdx.x;
     const int32_t b = blockIdx.x;
-    const int64_t total = *total_ptr;
-    const int64_t e0 = offs[(int64_t)b * nblk];
-    const int64_t e1 = (b + 1 < nbkt) ? offs[(int64_t)(b + 1) * nblk] : total;
+    const int64_t e0 = bstart[b], e1 = bstart[b + 1];
     const bool fits = e1 - e0 <= FINE_CAP;
     const int32_t v0 = b << FINE_SHIFT;
     const int64_t v = (int64_t)v0 + tid;
@@ -527,7 +563,7 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
     is = block_exclusive_scan_i32(d, s_wsum, &unused);
     s_cur[tid] = is;
     if (v < nq) inc_ptr[v] = static_cast<int32_t>(e0) + is;
-    if (b == nbkt - 1 && tid == 0) inc_ptr[nq] = static_cast<int32_t>(total);
+    if (b == nbkt - 1 && tid == 0) inc_ptr[nq] = static_cast<int32_t>(e1);
     __syncthreads();
     // ---- 2 counting sort into LDS
 #pragma unroll
@@ -727,8 +763,8 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_rows(
 
 // Bucket b's rows, staged by k_bkt_rows, to col_idx at bptr[b] (the scan of
 // the bucket totals), and row_ptr of its vertices.
-__global__ __launch_bounds__(256) void k_bkt_copy(int32_t nq, int32_t nbkt, int32_t nblk,
-                                                 const int32_t *__restrict__ offs,
+__global__ __launch_bounds__(256) void k_bkt_copy(int32_t nq, int32_t nbkt,
+                                                 const int32_t *__restrict__ bstart,
                                                  const int32_t *__restrict__ bptr,
                                                  const int32_t *__restrict__ rowoff,
                                                  const int32_t *__restrict__ stage,
@@ -736,7 +772,7 @@ __global__ __launch_bounds__(256) void k_bkt_copy(int32_t nq, int32_t nbkt, int3
                                                  int32_t *__restrict__ col_idx, int64_t col_cap,
                                                  PatternCounters *cnt) {
     const int32_t b = blockIdx.x;
-    const int64_t e0 = offs[(int64_t)b * nblk];
+    const int64_t e0 = bstart[b];
     const int32_t v0 = b << FINE_SHIFT;
     const int32_t P = bptr[b], T = bptr[b + 1] - P;
     for (int t = threadIdx.x; t < FINE_V; t += 256)
@@ -1183,6 +1219,7 @@ struct PatternWork {
     PatternCounters *cnt;
     int32_t *btot, *bptr;                  // fine path: bucket totals and their scan
     int32_t *deg, *rowlen, *wide, *mid, *counts;
+    int32_t *bstart;                       // start of each bucket's incidences (+ the total)
     long long *part;
     int2 *nbr;
     int32_t *ent;                          // bucket records (12 or 16 B); the region
@@ -1216,6 +1253,8 @@ PatternWork carve(int32_t nq, int32_t nme, char *base) {
     w.wide = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nq));
     w.mid = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nq));
     w.counts = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(ncounts + 1)));
+    const int32_t nbkt_max = w.fine.nbkt > w.coarse.nbkt ? w.fine.nbkt : w.coarse.nbkt;
+    w.bstart = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(nbkt_max + 1)));
     w.part = reinterpret_cast<long long *>(take(sizeof(long long) * (size_t)scan_partials(nscan)));
     // nbr (coarse and atomic paths) doubles as the fine path's row staging
     // area, which must not alias the bucket records it is built from
@@ -1233,8 +1272,9 @@ PatternWork carve(int32_t nq, int32_t nme, char *base) {
 }
 
 // Partition the incidences into the buckets of plan P: counts per
-// (bucket, workgroup), their scan, and the scatter into ent_*.  The total
-// number of incidences stays on the device at counts[P.ncounts()].
+// (workgroup, bucket), per bucket their prefix over the workgroups and the
+// bucket totals, the scan of those into bstart (the total number of
+// incidences at bstart[P.nbkt]), and the scatter into ent_*.
 int partition(const PatternWork &W, const BucketPlan &P, bool packed, int32_t nq, int32_t nme,
               const int32_t *me, hipStream_t s) {
     const size_t hist_lds = sizeof(int32_t) * (size_t)P.nbkt;
@@ -1242,15 +1282,17 @@ int partition(const PatternWork &W, const BucketPlan &P, bool packed, int32_t nq
                        P.shift, P.nbkt, P.tpb, W.counts, W.cnt);
     FEM_LAUNCH_CHECK();
     int st;
-    if ((st = exclusive_scan_i32(W.counts, W.counts, P.ncounts(), W.part, &W.cnt->total[2],
-                                 &W.cnt->err, s)))
+    hipLaunchKernelGGL(k_bkt_colscan, dim3(grid_for(P.nbkt, WAVE)), dim3(256), 0, s, P.nbkt, P.nblk,
+                       W.counts, W.bstart);
+    FEM_LAUNCH_CHECK();
+    if ((st = exclusive_scan_i32(W.bstart, W.bstart, P.nbkt, W.part, &W.cnt->total[2], &W.cnt->err, s)))
         return st;
     if (packed)
         hipLaunchKernelGGL(k_bkt_scatter<true>, dim3(P.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me,
-                           nq, P.shift, P.nbkt, P.tpb, W.counts, W.ent);
+                           nq, P.shift, P.nbkt, P.tpb, W.counts, W.bstart, W.ent);
     else
         hipLaunchKernelGGL(k_bkt_scatter<false>, dim3(P.nblk), dim3(BKT_THREADS), hist_lds, s, nme, me,
-                           nq, P.shift, P.nbkt, P.tpb, W.counts, W.ent);
+                           nq, P.shift, P.nbkt, P.tpb, W.counts, W.bstart, W.ent);
     FEM_LAUNCH_CHECK();
     return FEM_OK;
 }
@@ -1335,18 +1377,18 @@ extern "C" int fem_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *
         int32_t *fstage = reinterpret_cast<int32_t *>(W.nbr);
         if (packed)
             hipLaunchKernelGGL(k_bkt_rows<true>, dim3(W.fine.nbkt), dim3(BKT_THREADS), 0, s, nq,
-                               W.fine.nbkt, W.fine.nblk, W.counts, W.counts + W.fine.ncounts(), W.ent,
+                               W.fine.nbkt, W.bstart, W.ent,
                                inc_ptr, inc, inc_pos, fan, W.rowlen, W.btot, fstage, W.cnt);
         else
             hipLaunchKernelGGL(k_bkt_rows<false>, dim3(W.fine.nbkt), dim3(BKT_THREADS), 0, s, nq,
-                               W.fine.nbkt, W.fine.nblk, W.counts, W.counts + W.fine.ncounts(), W.ent,
+                               W.fine.nbkt, W.bstart, W.ent,
                                inc_ptr, inc, inc_pos, fan, W.rowlen, W.btot, fstage, W.cnt);
         FEM_LAUNCH_CHECK();
         if ((st = exclusive_scan_i32(W.btot, W.bptr, W.fine.nbkt, W.part, &W.cnt->total[1],
                                      &W.cnt->err, s)))
             return st;
         hipLaunchKernelGGL(k_bkt_copy, dim3(W.fine.nbkt), dim3(256), 0, s, nq, W.fine.nbkt,
-                           W.fine.nblk, W.counts, W.bptr, W.rowlen, fstage, row_ptr, col_idx, col_cap,
+                           W.bstart, W.bptr, W.rowlen, fstage, row_ptr, col_idx, col_cap,
                            W.cnt);
         FEM_LAUNCH_CHECK();
         if ((st = read_counters())) return st;
@@ -1360,9 +1402,8 @@ extern "C" int fem_pattern(int32_t nq, int32_t nme, const int32_t *me, int32_t *
         if (W.coarse.nbkt > 0 && path != FEM_PATTERN_ATOMIC) {
             // group the incidences by vertex: two-level counting sort, no global atomics
             if ((st = partition(W, W.coarse, false, nq, nme, me, s))) return st;
-            hipLaunchKernelGGL(k_bkt_sort, dim3(W.coarse.nbkt), dim3(BKT_THREADS), 0, s, nq,
-                               W.coarse.nblk, W.counts, W.counts + W.coarse.ncounts(), W.ent,
-                               inc_ptr, inc, W.nbr);
+            hipLaunchKernelGGL(k_bkt_sort, dim3(W.coarse.nbkt), dim3(BKT_THREADS), 0, s, nq, W.bstart,
+                               W.ent, inc_ptr, inc, W.nbr);
             FEM_LAUNCH_CHECK();
         } else {
             if ((st = fill_i32(W.deg, nq, 0, s))) return st;
