@@ -7,7 +7,9 @@
 // buckets of 128 consecutive vertex ids (no global atomics):
 //   1 bucket count    about 256 workgroups over contiguous ranges of
 //                     tetrahedra: mesh checks and an LDS histogram
-//   2 scan            bucket-major offsets of every (bucket, workgroup) run
+//   2 offsets         per bucket, the prefix of its counts over the
+//                     workgroups (k_bkt_colscan), and the scan of the bucket
+//                     totals: the start of every (bucket, workgroup) run
 //   3 bucket scatter  one 16-byte record per incidence: (4 k + a, the other
 //                     three vertices in the order a+1, a+2, a+3 mod 4, and
 //                     the vertex relative to its bucket)
@@ -91,14 +93,14 @@ __device__ inline int tet_err(const int (&v)[4], int32_t nq) {
 
 // ------------------------------------------------------------------ partition
 
-// counts[b * nblk + blk] = incidences of workgroup blk (tpb tetrahedra)
-// whose vertex falls in bucket b; mesh checks.
+// counts[blk * nbkt + b] = incidences of workgroup blk (tpb tetrahedra)
+// whose vertex falls in bucket b (each workgroup writes one contiguous row);
+// mesh checks.
 __global__ __launch_bounds__(TB_PART_THREADS) void k_tbkt_count(int32_t nme, const int4 *__restrict__ me,
                                                                int32_t nq, int32_t nbkt, int32_t tpb,
                                                                int32_t *__restrict__ counts,
                                                                PatternCounters *cnt) {
     extern __shared__ int32_t s_hist[];
-    const int32_t nblk = gridDim.x;
     for (int b = threadIdx.x; b < nbkt; b += TB_PART_THREADS) s_hist[b] = 0;
     __syncthreads();
     int bad = 0;
@@ -128,7 +130,7 @@ __global__ __launch_bounds__(TB_PART_THREADS) void k_tbkt_count(int32_t nme, con
     if (bad) atomicOr(&cnt->err, bad);
     __syncthreads();
     for (int b = threadIdx.x; b < nbkt; b += TB_PART_THREADS)
-        counts[(int64_t)b * nblk + blockIdx.x] = s_hist[b];
+        counts[(int64_t)blockIdx.x * nbkt + b] = s_hist[b];
 }
 
 // Same tetrahedra per workgroup as k_tbkt_count: each incidence (k, a) goes
@@ -137,11 +139,13 @@ __global__ __launch_bounds__(TB_PART_THREADS) void k_tbkt_count(int32_t nme, con
 __global__ __launch_bounds__(TB_PART_THREADS) void k_tbkt_scatter(int32_t nme, const int4 *__restrict__ me,
                                                                  int32_t nq, int32_t nbkt, int32_t tpb,
                                                                  const int32_t *__restrict__ offs,
+                                                                 const int32_t *__restrict__ bstart,
                                                                  int4 *__restrict__ ent) {
     extern __shared__ int32_t s_cur[];
-    const int32_t nblk = gridDim.x;
-    for (int b = threadIdx.x; b < nbkt; b += TB_PART_THREADS)
-        s_cur[b] = offs[(int64_t)b * nblk + blockIdx.x];
+    // the run of (b, this workgroup): the bucket's start plus the incidences
+    // of the workgroups before it (one contiguous row of offs)
+    const int32_t *row = offs + (int64_t)blockIdx.x * nbkt;
+    for (int b = threadIdx.x; b < nbkt; b += TB_PART_THREADS) s_cur[b] = bstart[b] + row[b];
     __syncthreads();
     const int64_t k0 = (int64_t)blockIdx.x * tpb;
     const int64_t k1 = (k0 + tpb < nme) ? k0 + tpb : nme;
@@ -216,9 +220,8 @@ __device__ __forceinline__ uint32_t tb_hash(int32_t u) {
 // entries); k_tbkt_copy moves them once the bucket totals are scanned.  A
 // bucket or vertex beyond the limits sets TERR_BUCKET and the host runs the
 // general path instead.
-__global__ __launch_bounds__(TB_V) void k_tbkt_rows(int32_t nq, int32_t nbkt, int32_t nblk,
-                                                   const int32_t *__restrict__ offs,
-                                                   const int32_t *__restrict__ total_ptr,
+__global__ __launch_bounds__(TB_V) void k_tbkt_rows(int32_t nq, int32_t nbkt,
+                                                   const int32_t *__restrict__ bstart,
                                                    const int4 *__restrict__ ent,
                                                    int32_t *__restrict__ inc_ptr,
                                                    int32_t *__restrict__ inc,
@@ -236,9 +239,7 @@ __global__ __launch_bounds__(TB_V) void k_tbkt_rows(int32_t nq, int32_t nbkt, in
     __shared__ int32_t s_wsum[TB_V / WAVE];
     const int tid = threadIdx.x;
     const int32_t b = blockIdx.x;
-    const int64_t total = *total_ptr;
-    const int64_t e0 = offs[(int64_t)b * nblk];
-    const int64_t e1 = (b + 1 < nbkt) ? offs[(int64_t)(b + 1) * nblk] : total;
+    const int64_t e0 = bstart[b], e1 = bstart[b + 1];
     const bool fits = e1 - e0 <= TB_CAP;
     const int32_t v0 = b << TB_SHIFT;
     const int32_t v = v0 + tid;
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(TB_V) void k_tbkt_rows(int32_t nq, int32_t nbkt, in
     const int32_t js = is + tid;   // the slice in LDS (padded)
     s_cur[tid] = js;
     if (v < nq) inc_ptr[v] = static_cast<int32_t>(e0) + is;
-    if (b == nbkt - 1 && tid == 0) inc_ptr[nq] = static_cast<int32_t>(total);
+    if (b == nbkt - 1 && tid == 0) inc_ptr[nq] = static_cast<int32_t>(e1);
     __syncthreads();
     // ---- counting sort into LDS
 #pragma unroll
@@ -383,8 +384,8 @@ __global__ __launch_bounds__(TB_V) void k_tbkt_rows(int32_t nq, int32_t nbkt, in
 }
 
 // Bucket b's staged rows to col_idx at bptr[b], and row_ptr of its vertices.
-__global__ __launch_bounds__(256) void k_tbkt_copy(int32_t nq, int32_t nbkt, int32_t nblk,
-                                                  const int32_t *__restrict__ offs,
+__global__ __launch_bounds__(256) void k_tbkt_copy(int32_t nq, int32_t nbkt,
+                                                  const int32_t *__restrict__ bstart,
                                                   const int32_t *__restrict__ bptr,
                                                   const int32_t *__restrict__ rowoff,
                                                   const int32_t *__restrict__ stage,
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(256) void k_tbkt_copy(int32_t nq, int32_t nbkt, int
                                                   int32_t *__restrict__ col_idx, int64_t col_cap,
                                                   PatternCounters *cnt) {
     const int32_t b = blockIdx.x;
-    const int64_t e0 = offs[(int64_t)b * nblk];
+    const int64_t e0 = bstart[b];
     const int32_t v0 = b << TB_SHIFT;
     const int32_t P = bptr[b], T = bptr[b + 1] - P;
     for (int t = threadIdx.x; t < TB_V; t += 256)
@@ -890,7 +891,7 @@ TetBucketPlan plan_tet_buckets(int32_t nq, int32_t nme) {
 struct TetPatternWork {
     PatternCounters *cnt;
     TetBucketPlan plan;
-    int32_t *counts, *btot, *bptr, *rowoff, *stage;
+    int32_t *counts, *bstart, *btot, *bptr, *rowoff, *stage;
     long long *part;
     int4 *ent;
     int32_t *I, *J, *cptr, *contrib, *deg;
@@ -929,6 +930,7 @@ TetPatternWork carve_tet(int32_t nq, int32_t nme, char *base, int *st) {
     if (w.plan.nbkt > 0) {
         const int64_t nc = w.plan.ncounts();
         w.counts = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(nc + 1)));
+        w.bstart = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(w.plan.nbkt + 1)));
         w.part = reinterpret_cast<long long *>(take(sizeof(long long) * (size_t)scan_partials(nc)));
         w.btot = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(w.plan.nbkt + 1)));
         w.bptr = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(w.plan.nbkt + 1)));
@@ -1025,20 +1027,22 @@ extern "C" int fem_tet_pattern(int32_t nq, int32_t nme, const int32_t *me, int32
         hipLaunchKernelGGL(k_tbkt_count, dim3(P.nblk), dim3(TB_PART_THREADS), hist_lds, s, nme, me4, nq,
                            P.nbkt, P.tpb, W.counts, W.cnt);
         FEM_LAUNCH_CHECK();
-        if ((st = exclusive_scan_i32(W.counts, W.counts, P.ncounts(), W.part, &W.cnt->total[2],
-                                     &W.cnt->err, s)))
+        hipLaunchKernelGGL(k_bkt_colscan, dim3(grid_for(P.nbkt, WAVE)), dim3(256), 0, s, P.nbkt, P.nblk,
+                           W.counts, W.bstart);
+        FEM_LAUNCH_CHECK();
+        if ((st = exclusive_scan_i32(W.bstart, W.bstart, P.nbkt, W.part, &W.cnt->total[2], &W.cnt->err,
+                                     s)))
             return st;
         hipLaunchKernelGGL(k_tbkt_scatter, dim3(P.nblk), dim3(TB_PART_THREADS), hist_lds, s, nme, me4,
-                           nq, P.nbkt, P.tpb, W.counts, W.ent);
+                           nq, P.nbkt, P.tpb, W.counts, W.bstart, W.ent);
         FEM_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_tbkt_rows, dim3(P.nbkt), dim3(TB_V), 0, s, nq, P.nbkt, P.nblk, W.counts,
-                           W.counts + P.ncounts(), W.ent, inc_ptr, inc, inc_pos, W.rowoff, W.btot,
-                           W.stage, W.cnt);
+        hipLaunchKernelGGL(k_tbkt_rows, dim3(P.nbkt), dim3(TB_V), 0, s, nq, P.nbkt, W.bstart, W.ent,
+                           inc_ptr, inc, inc_pos, W.rowoff, W.btot, W.stage, W.cnt);
         FEM_LAUNCH_CHECK();
         if ((st = exclusive_scan_i32(W.btot, W.bptr, P.nbkt, W.part, &W.cnt->total[1], &W.cnt->err, s)))
             return st;
-        hipLaunchKernelGGL(k_tbkt_copy, dim3(P.nbkt), dim3(256), 0, s, nq, P.nbkt, P.nblk, W.counts,
-                           W.bptr, W.rowoff, W.stage, row_ptr, col_idx, col_cap, W.cnt);
+        hipLaunchKernelGGL(k_tbkt_copy, dim3(P.nbkt), dim3(256), 0, s, nq, P.nbkt, W.bstart, W.bptr,
+                           W.rowoff, W.stage, row_ptr, col_idx, col_cap, W.cnt);
         FEM_LAUNCH_CHECK();
         if ((st = read_counters())) return st;
         if ((st = tet_check_errors(h, nq))) return st;
