@@ -76,7 +76,7 @@ PROFILE_SOURCES = {
     "step_square2048": ("fem_common.hip", "fem_internal.h", "fem_pattern.hip", "fem_numeric.hip"),
     "sparse_optv2_square2048": ("fem_common.hip", "fem_internal.h", "fem_sparse.hip"),
     "p2_square2048": ("fem_common.hip", "fem_internal.h", "fem_sparse.hip", "fem_p2.hip"),
-    "tet_cube128": ("fem_common.hip", "fem_internal.h", "fem_sparse.hip", "fem_tet.hip"),
+    "tet_cube128": ("fem_common.hip", "fem_internal.h", "fem_pattern.hip", "fem_sparse.hip", "fem_tet.hip"),
     "adjoint_square512": ("fem_common.hip", "fem_internal.h", "fem_pattern.hip", "fem_numeric.hip",
                           "fem_adjoint.hip"),
     "batched_512meshes": ("fem_common.hip", "fem_internal.h", "fem_pattern.hip", "fem_numeric.hip"),

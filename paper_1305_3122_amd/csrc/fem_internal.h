@@ -107,7 +107,9 @@ __device__ inline T wave_sum(T v) {
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v);
 // Bucket partitions: in place over counts[blk][b] (nblk rows of nbkt), each
 // entry becomes the count of bucket b in the rows before blk; bsum[b] gets
-// the column total.  256 threads per workgroup, 64 buckets per workgroup.
+// the column total.  COLSCAN_WAVES * 64 threads per workgroup, 64 buckets per
+// workgroup.
+constexpr int COLSCAN_WAVES = 16;
 __global__ void k_bkt_colscan(int32_t nbkt, int32_t nblk, int32_t *counts, int32_t *bsum);
 __global__ void k_fill_f64(double *p, int64_t n, double v);
 

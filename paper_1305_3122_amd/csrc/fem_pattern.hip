@@ -205,17 +205,18 @@ __global__ __launch_bounds__(BKT_THREADS) void k_bkt_count(int32_t nme, const in
 
 // In place over counts[blk][b]: each entry becomes the number of bucket b's
 // incidences in workgroups before blk, and bsum[b] the bucket's total.  One
-// lane per bucket, the four waves of a workgroup over quarters of the
-// workgroup range (their partial sums meet in LDS); every read and write
+// lane per bucket, the COLSCAN_WAVES waves of a workgroup over equal parts of
+// the workgroup range (their partial sums meet in LDS); every read and write
 // covers 64 consecutive buckets.
-__global__ __launch_bounds__(256) void k_bkt_colscan(int32_t nbkt, int32_t nblk,
-                                                     int32_t *__restrict__ counts,
-                                                     int32_t *__restrict__ bsum) {
-    __shared__ int32_t s_part[4][WAVE];
+__global__ __launch_bounds__(COLSCAN_WAVES * WAVE) void k_bkt_colscan(int32_t nbkt, int32_t nblk,
+                                                                     int32_t *__restrict__ counts,
+                                                                     int32_t *__restrict__ bsum) {
+    constexpr int NW = COLSCAN_WAVES;
+    __shared__ int32_t s_part[NW][WAVE];
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const int32_t b = blockIdx.x * WAVE + lane;
     const bool ok = b < nbkt;
-    const int32_t Q = (nblk + 3) / 4;
+    const int32_t Q = (nblk + NW - 1) / NW;
     const int32_t k0 = w * Q, k1 = (k0 + Q < nblk) ? k0 + Q : nblk;
     constexpr int H = 8;   // loads in flight per lane
     int32_t sum = 0;
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(256) void k_bkt_colscan(int32_t nbkt, int32_t nblk,
             run += c[j];
         }
     }
-    if (ok && w == 3) bsum[b] = run;
+    if (ok && w == NW - 1) bsum[b] = run;
 }
 
 // Same triangles per workgroup as k_bkt_count: each incidence goes to the run
@@ -1282,8 +1283,8 @@ int partition(const PatternWork &W, const BucketPlan &P, bool packed, int32_t nq
                        P.shift, P.nbkt, P.tpb, W.counts, W.cnt);
     FEM_LAUNCH_CHECK();
     int st;
-    hipLaunchKernelGGL(k_bkt_colscan, dim3(grid_for(P.nbkt, WAVE)), dim3(256), 0, s, P.nbkt, P.nblk,
-                       W.counts, W.bstart);
+    hipLaunchKernelGGL(k_bkt_colscan, dim3(grid_for(P.nbkt, WAVE)), dim3(COLSCAN_WAVES * WAVE), 0, s,
+                       P.nbkt, P.nblk, W.counts, W.bstart);
     FEM_LAUNCH_CHECK();
     if ((st = exclusive_scan_i32(W.bstart, W.bstart, P.nbkt, W.part, &W.cnt->total[2], &W.cnt->err, s)))
         return st;

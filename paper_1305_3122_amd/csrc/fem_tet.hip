@@ -1027,8 +1027,8 @@ extern "C" int fem_tet_pattern(int32_t nq, int32_t nme, const int32_t *me, int32
         hipLaunchKernelGGL(k_tbkt_count, dim3(P.nblk), dim3(TB_PART_THREADS), hist_lds, s, nme, me4, nq,
                            P.nbkt, P.tpb, W.counts, W.cnt);
         FEM_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_bkt_colscan, dim3(grid_for(P.nbkt, WAVE)), dim3(256), 0, s, P.nbkt, P.nblk,
-                           W.counts, W.bstart);
+        hipLaunchKernelGGL(k_bkt_colscan, dim3(grid_for(P.nbkt, WAVE)), dim3(COLSCAN_WAVES * WAVE), 0, s,
+                           P.nbkt, P.nblk, W.counts, W.bstart);
         FEM_LAUNCH_CHECK();
         if ((st = exclusive_scan_i32(W.bstart, W.bstart, P.nbkt, W.part, &W.cnt->total[2], &W.cnt->err,
                                      s)))
